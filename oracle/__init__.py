@@ -1,0 +1,242 @@
+"""CPU oracle for the relational hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain definitions of filter, stable sort, equi-join, join ranges, group-by
+aggregation and whole queries, in C (``tqp_oracle.c``, built with gcc) behind
+ctypes.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark import this package; the GPU library never does, and the two share
+no code.  All inputs are numpy arrays; all outputs are numpy arrays.
+
+Conventions (the paper states SQL semantics only, Sections 2.2-2.3):
+  * filter keeps rows in ascending row-id order;
+  * sort is stable and ascending on the signed value;
+  * join returns every (i, j) with L[i] == R[j], ordered by (key, i, j);
+  * group-by emits the groups that occur, ascending by key, SUM mod 2**64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tqp_oracle.c")
+_LIB = os.path.join(_HERE, "libtqp_oracle.so")
+
+DT = {np.dtype(np.int8): 1, np.dtype(np.int32): 2, np.dtype(np.int64): 3}
+OPS = {"<": 0, "<=": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
+AGG_SUM, AGG_COUNT, AGG_SUM_PRODUCT = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compiles the oracle with gcc into ``oracle/libtqp_oracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        _lib.orc_filter.restype = i64
+        _lib.orc_filter.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp]
+        _lib.orc_gather.restype = None
+        _lib.orc_gather.argtypes = [i64, vp, i32, vp, vp]
+        _lib.orc_sort.restype = i32
+        _lib.orc_sort.argtypes = [i64, vp, i32, vp, vp]
+        _lib.orc_join.restype = i64
+        _lib.orc_join.argtypes = [i64, vp, i64, vp, i32, i64, vp, vp]
+        _lib.orc_join_ranges.restype = i64
+        _lib.orc_join_ranges.argtypes = [i64, vp, i64, vp, i32, i64, vp, vp, vp,
+                                         vp, vp, vp, vp]
+        _lib.orc_groupby.restype = i64
+        _lib.orc_groupby.argtypes = [i64, vp, i32, vp, vp, i32, vp, vp, vp, i64,
+                                     vp, vp, vp]
+        _lib.orc_q1.restype = i64
+        _lib.orc_q1.argtypes = [i64, vp, vp, vp, i64, i64, vp, vp, i64, vp, vp,
+                                vp, vp]
+        _lib.orc_q2.restype = i32
+        _lib.orc_q2.argtypes = [i64, vp, vp, vp, vp, vp, i64, i64, vp, vp,
+                                i64, vp, vp, vp, vp, vp,
+                                i64, vp, vp, vp, vp, vp]
+        _lib.orc_q3.restype = i64
+        _lib.orc_q3.argtypes = [i64, vp, vp, vp, vp, vp,
+                                i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
+                                i64, i64, vp, vp, vp, vp]
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype=dtype))
+    return a
+
+
+def _ptr_array(arrs):
+    return (ctypes.c_void_p * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+
+
+def filter_rows(cols, preds) -> np.ndarray:
+    """Row ids (int32, ascending) where every predicate holds.
+
+    cols: list of 1-D int8/int32/int64 arrays of equal length.
+    preds: list of (col_index, op_string, literal).
+    """
+    cols = [_c(c) for c in cols]
+    n = len(cols[0]) if cols else 0
+    dts = np.array([DT[c.dtype] for c in cols], dtype=np.int32)
+    pc = np.array([p[0] for p in preds], dtype=np.int32)
+    po = np.array([OPS[p[1]] for p in preds], dtype=np.int32)
+    pl = np.array([int(p[2]) for p in preds], dtype=np.int64)
+    out = np.empty(max(n, 1), dtype=np.int32)
+    ptrs = _ptr_array(cols)
+    cnt = lib().orc_filter(n, ptrs, _p(dts), len(preds), _p(pc), _p(po), _p(pl), _p(out))
+    return out[:cnt].copy()
+
+
+def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    src = _c(src)
+    idx = _c(idx, np.int32)
+    out = np.empty(len(idx), dtype=src.dtype)
+    lib().orc_gather(len(idx), _p(src), DT[src.dtype], _p(idx), _p(out))
+    return out
+
+
+def sort(keys: np.ndarray):
+    """Stable ascending sort. Returns (sorted_keys, perm int32)."""
+    keys = _c(keys)
+    n = len(keys)
+    ok = np.empty(max(n, 1), dtype=keys.dtype)
+    perm = np.empty(max(n, 1), dtype=np.int32)
+    rc = lib().orc_sort(n, _p(keys), DT[keys.dtype], _p(ok), _p(perm))
+    assert rc == 0
+    return ok[:n].copy(), perm[:n].copy()
+
+
+def join(lk: np.ndarray, rk: np.ndarray, cap: int | None = None):
+    """Inner equi-join pairs (L row, R row) in (key, i, j) order.
+
+    Returns (count, out_l, out_r); the arrays are empty if count > cap.
+    """
+    lk = _c(lk)
+    rk = _c(rk)
+    assert lk.dtype == rk.dtype
+    if cap is None:
+        cnt = lib().orc_join(len(lk), _p(lk), len(rk), _p(rk), DT[lk.dtype], 0,
+                             None, None)
+        cap = cnt
+    ol = np.empty(max(cap, 1), dtype=np.int32)
+    orr = np.empty(max(cap, 1), dtype=np.int32)
+    cnt = lib().orc_join(len(lk), _p(lk), len(rk), _p(rk), DT[lk.dtype], cap,
+                         _p(ol), _p(orr))
+    if cnt > cap:
+        return cnt, np.empty(0, np.int32), np.empty(0, np.int32)
+    return cnt, ol[:cnt].copy(), orr[:cnt].copy()
+
+
+def join_ranges(lk: np.ndarray, rk: np.ndarray):
+    """Per matched key: key, lstart, lcnt, rstart, rcnt (int64) and the total."""
+    lk = _c(lk)
+    rk = _c(rk)
+    cap = min(len(lk), len(rk))
+    bufs = [np.empty(max(cap, 1), dtype=np.int64) for _ in range(5)]
+    total = ctypes.c_int64(0)
+    ovf = ctypes.c_int(0)
+    m = lib().orc_join_ranges(len(lk), _p(lk), len(rk), _p(rk), DT[lk.dtype], cap,
+                              *[_p(b) for b in bufs], ctypes.byref(total),
+                              ctypes.byref(ovf))
+    out = {k: b[:m].copy() for k, b in zip(("key", "lstart", "lcnt", "rstart", "rcnt"), bufs)}
+    out["total"] = total.value
+    out["total_overflow"] = bool(ovf.value)
+    return out
+
+
+def groupby(keys: np.ndarray, vals, aggs):
+    """GROUP BY keys.  aggs: list of ("sum", a) | ("count",) | ("sum_product", a, b).
+
+    Returns (unique_keys int64, [agg arrays int64], overflow flag).
+    """
+    keys = _c(keys)
+    vals = [_c(v) for v in vals]
+    n = len(keys)
+    op = np.array([{"sum": AGG_SUM, "count": AGG_COUNT, "sum_product": AGG_SUM_PRODUCT}[a[0]]
+                   for a in aggs], dtype=np.int32)
+    aa = np.array([a[1] if len(a) > 1 else 0 for a in aggs], dtype=np.int32)
+    ab = np.array([a[2] if len(a) > 2 else 0 for a in aggs], dtype=np.int32)
+    vdt = np.array([DT[v.dtype] for v in vals] or [3], dtype=np.int32)
+    ok = np.empty(max(n, 1), dtype=np.int64)
+    outs = [np.empty(max(n, 1), dtype=np.int64) for _ in aggs]
+    ovf = ctypes.c_int(0)
+    ng = lib().orc_groupby(n, _p(keys), DT[keys.dtype], _ptr_array(vals), _p(vdt),
+                           len(aggs), _p(op), _p(aa), _p(ab), n, _p(ok),
+                           _ptr_array(outs), ctypes.byref(ovf))
+    return ok[:ng].copy(), [o[:ng].copy() for o in outs], bool(ovf.value)
+
+
+def q1(fact: dict, dim: dict, day_cut: int):
+    """SELECT cat, SUM(qty), COUNT(*) ... WHERE day < day_cut GROUP BY cat."""
+    fk, qty, day = _c(fact["fk"], np.int32), _c(fact["qty"], np.int64), _c(fact["day"], np.int32)
+    pk, cat = _c(dim["pk"], np.int32), _c(dim["cat"], np.int32)
+    cap = max(len(pk), 1)
+    k, s, c = (np.empty(cap, np.int64) for _ in range(3))
+    ovf = ctypes.c_int(0)
+    ng = lib().orc_q1(len(fk), _p(fk), _p(qty), _p(day), day_cut, len(pk), _p(pk),
+                      _p(cat), cap, _p(k), _p(s), _p(c), ctypes.byref(ovf))
+    return {"key": k[:ng].copy(), "sum_qty": s[:ng].copy(), "count": c[:ng].copy(),
+            "overflow": bool(ovf.value)}
+
+
+def q2(fact: dict, dim: dict, day_cut: int):
+    """Skewed star query: low-cardinality and per-fk group-bys after the join."""
+    fk = _c(fact["fk"], np.int32)
+    qty = _c(fact["qty"], np.int64)
+    price = _c(fact["price"], np.int64)
+    flag = _c(fact["flag"], np.int8)
+    day = _c(fact["day"], np.int32)
+    pk, cat = _c(dim["pk"], np.int32), _c(dim["cat"], np.int32)
+    capa = 1024
+    capb = max(len(pk), 1)
+    a = [np.empty(capa, np.int64) for _ in range(4)]
+    b = [np.empty(capb, np.int64) for _ in range(3)]
+    nga, ngb = ctypes.c_int64(0), ctypes.c_int64(0)
+    ovf = ctypes.c_int(0)
+    lib().orc_q2(len(fk), _p(fk), _p(qty), _p(price), _p(flag), _p(day), day_cut,
+                 len(pk), _p(pk), _p(cat), capa, *[_p(x) for x in a], ctypes.byref(nga),
+                 capb, *[_p(x) for x in b], ctypes.byref(ngb), ctypes.byref(ovf))
+    na, nb = nga.value, ngb.value
+    return {"a_key": a[0][:na].copy(), "a_qty": a[1][:na].copy(),
+            "a_price": a[2][:na].copy(), "a_count": a[3][:na].copy(),
+            "b_key": b[0][:nb].copy(), "b_qty": b[1][:nb].copy(),
+            "b_count": b[2][:nb].copy(), "overflow": bool(ovf.value)}
+
+
+def q3(cfg: dict):
+    """Star join over three filtered dims, GROUP BY d1.cat * 5 + d2.cat."""
+    f, d1, d2, d3 = cfg["fact"], cfg["d1"], cfg["d2"], cfg["d3"]
+    fk1, fk2, fk3 = (_c(f[k], np.int32) for k in ("fk1", "fk2", "fk3"))
+    qty, price = _c(f["qty"], np.int64), _c(f["price"], np.int64)
+    a1 = [_c(d1[k], np.int32) for k in ("pk", "cat", "attr")]
+    a2 = [_c(d2[k], np.int32) for k in ("pk", "cat", "attr")]
+    a3 = [_c(d3[k], np.int32) for k in ("pk", "attr")]
+    cap = 1 << 16
+    k, s, c = (np.empty(cap, np.int64) for _ in range(3))
+    ovf = ctypes.c_int(0)
+    ng = lib().orc_q3(len(fk1), _p(fk1), _p(fk2), _p(fk3), _p(qty), _p(price),
+                      len(a1[0]), *[_p(x) for x in a1], len(a2[0]), *[_p(x) for x in a2],
+                      len(a3[0]), *[_p(x) for x in a3], cfg["attr_cut"], cap,
+                      _p(k), _p(s), _p(c), ctypes.byref(ovf))
+    return {"key": k[:ng].copy(), "sum_qp": s[:ng].copy(), "count": c[:ng].copy(),
+            "overflow": bool(ovf.value)}

@@ -1,0 +1,333 @@
+"""Pins for the CPU oracle: each check compares it with something other than
+itself -- brute-force loops over tiny tables, numpy library routines with the
+same definition, closed forms and invariants.
+
+The paper prints no result values (its figures carry only speed-ups,
+Section 2.3), so the pins are the SQL definitions of the operators (Sections
+2.2-2.3) evaluated independently, plus the invariants the method must keep:
+join cardinality equals the sum over keys of count_L * count_R, and group
+sums conserve the filtered total.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import tqp_datagen as dg
+
+I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
+I64_MIN, I64_MAX = -(2 ** 63), 2 ** 63 - 1
+OPS = {"<": lambda a, b: a < b, "<=": lambda a, b: a <= b, ">": lambda a, b: a > b,
+       ">=": lambda a, b: a >= b, "==": lambda a, b: a == b, "!=": lambda a, b: a != b}
+
+
+def rng_cols(seed, n, dom=50):
+    return [
+        dg.uniform_int(seed, 1, n, -dom, dom, np.int8),
+        dg.uniform_int(seed, 2, n, -dom, dom, np.int32),
+        dg.uniform_int(seed, 3, n, -dom, dom, np.int64),
+    ]
+
+
+# ----------------------------------------------------------------- filter ----
+
+@pytest.mark.parametrize("seed", range(6))
+def test_filter_brute_force(seed):
+    n = 300 + 37 * seed
+    cols = rng_cols(seed, n, dom=20)
+    opnames = list(OPS)
+    for trial in range(12):
+        k = 1 + trial % 4
+        preds = []
+        for q in range(k):
+            c = (trial + q) % 3
+            op = opnames[(trial * 7 + q * 3 + seed) % 6]
+            lit = int(cols[c][(trial * 13 + q) % n])      # literal on a data value
+            preds.append((c, op, lit))
+        got = oracle.filter_rows(cols, preds)
+        want = [i for i in range(n)
+                if all(OPS[op](int(cols[c][i]), lit) for c, op, lit in preds)]
+        assert got.tolist() == want, preds
+
+
+def test_filter_literal_outside_column_range():
+    c8 = np.array([-128, -1, 0, 1, 127], np.int8)
+    # mathematical comparison: nothing in int8 is >= 200, everything is > -1000
+    assert oracle.filter_rows([c8], [(0, ">=", 200)]).tolist() == []
+    assert oracle.filter_rows([c8], [(0, ">", -1000)]).tolist() == [0, 1, 2, 3, 4]
+    c32 = np.array([I32_MIN, 0, I32_MAX], np.int32)
+    assert oracle.filter_rows([c32], [(0, "<", I32_MAX)]).tolist() == [0, 1]
+    c64 = np.array([I64_MIN, 0, I64_MAX], np.int64)
+    assert oracle.filter_rows([c64], [(0, "<=", I64_MIN)]).tolist() == [0]
+    assert oracle.filter_rows([c64], [(0, ">=", I64_MAX)]).tolist() == [2]
+
+
+def test_filter_matches_numpy_mask_and_complement():
+    day = dg.uniform_int(0, 3, 200_000, 0, dg.DAY_DOMAIN, np.int32)
+    lt = oracle.filter_rows([day], [(0, "<", 1278)])
+    ge = oracle.filter_rows([day], [(0, ">=", 1278)])
+    assert np.array_equal(lt, np.nonzero(day < 1278)[0].astype(np.int32))
+    assert len(lt) + len(ge) == len(day)
+    assert np.array_equal(np.sort(np.concatenate([lt, ge])), np.arange(len(day)))
+    assert np.all(np.diff(lt) > 0)
+
+
+def test_filter_empty_and_all():
+    x = np.arange(10, dtype=np.int32)
+    assert oracle.filter_rows([x], [(0, "<", 0)]).tolist() == []
+    assert oracle.filter_rows([x], [(0, ">=", 0)]).tolist() == list(range(10))
+    assert oracle.filter_rows([x[:0]], [(0, "<", 5)]).tolist() == []
+
+
+# ------------------------------------------------------------------- sort ----
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("dom", [3, 1000, None])
+def test_sort_matches_numpy_stable_argsort(dtype, dom):
+    n = 5000
+    if dom is None:
+        info = np.iinfo(dtype)
+        keys = dg.raw_u64(9, 1, n).view(np.int64)
+        keys = keys.astype(dtype) if dtype == np.int64 else (keys >> 32).astype(np.int32)
+        keys[:4] = [info.min, info.max, 0, -1]
+    else:
+        keys = dg.uniform_int(1, 1, n, -dom, dom, dtype)
+    sk, perm = oracle.sort(keys)
+    want = np.argsort(keys, kind="stable")
+    assert np.array_equal(perm, want.astype(np.int32))
+    assert np.array_equal(sk, keys[want])
+
+
+def test_sort_brute_force_tiny():
+    keys = np.array([3, -1, 3, 0, -1, 7, 3, -5], np.int64)
+    # stable order by (key, position), written out by hand
+    want = [7, 1, 4, 3, 0, 2, 6, 5]
+    sk, perm = oracle.sort(keys)
+    assert perm.tolist() == want
+    assert sk.tolist() == [-5, -1, -1, 0, 3, 3, 3, 7]
+    for n in range(0, 7):
+        for ks in itertools.product([-1, 0, 2], repeat=n):
+            a = np.array(ks, np.int32)
+            _, p = oracle.sort(a)
+            brute = sorted(range(n), key=lambda i: (ks[i], i))
+            assert p.tolist() == brute
+
+
+# ------------------------------------------------------------------- join ----
+
+def brute_join(lk, rk):
+    pairs = [(int(lk[i]), i, j) for i in range(len(lk)) for j in range(len(rk))
+             if lk[i] == rk[j]]
+    pairs.sort()
+    return [(i, j) for _, i, j in pairs]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_join_brute_force(seed):
+    nl, nr = 150 + 31 * seed, 90 + 17 * seed
+    dom = [1, 3, 20, 200][seed % 4]
+    dt = np.int32 if seed % 2 else np.int64
+    lk = dg.uniform_int(seed, 1, nl, -dom, dom, dt)
+    rk = dg.uniform_int(seed, 2, nr, -dom, dom, dt)
+    cnt, ol, orr = oracle.join(lk, rk)
+    want = brute_join(lk, rk)
+    assert cnt == len(want)
+    assert list(zip(ol.tolist(), orr.tolist())) == want
+
+
+def test_join_cardinality_and_checksum_closed_form():
+    lk = dg.uniform_int(3, 1, 40_000, 0, 3000, np.int32)
+    rk = dg.uniform_int(3, 2, 9_000, 0, 3000, np.int32)
+    cnt, ol, orr = oracle.join(lk, rk)
+    ul, cl = np.unique(lk, return_counts=True)
+    ur, cr = np.unique(rk, return_counts=True)
+    common, il, ir = np.intersect1d(ul, ur, return_indices=True)
+    assert cnt == int(np.sum(cl[il].astype(np.int64) * cr[ir]))
+    # checksum: sum over pairs of (A*i + B*j) = sum over keys (A*cR*sum_i + B*cL*sum_j)
+    A, B = 3, 7
+    suml = np.bincount(lk, weights=np.arange(len(lk), dtype=np.float64), minlength=3000)
+    sumr = np.bincount(rk, weights=np.arange(len(rk), dtype=np.float64), minlength=3000)
+    cntl = np.bincount(lk, minlength=3000).astype(np.int64)
+    cntr = np.bincount(rk, minlength=3000).astype(np.int64)
+    closed = int(np.sum(A * cntr * suml.astype(np.int64) + B * cntl * sumr.astype(np.int64)))
+    assert int(np.sum(A * ol.astype(np.int64) + B * orr.astype(np.int64))) == closed
+    assert np.all(lk[ol] == rk[orr])
+
+
+def test_join_edge_cases():
+    e32 = np.zeros(0, np.int32)
+    assert oracle.join(e32, np.arange(5, dtype=np.int32))[0] == 0
+    assert oracle.join(np.arange(5, dtype=np.int32), e32)[0] == 0
+    assert oracle.join(np.arange(5, dtype=np.int32), np.arange(5, 10, dtype=np.int32))[0] == 0
+    k = np.full(50, 7, np.int64)
+    cnt, ol, orr = oracle.join(k, k[:30])
+    assert cnt == 1500
+    assert ol.tolist() == [i for i in range(50) for _ in range(30)]
+    assert orr.tolist() == list(range(30)) * 50
+    ext = np.array([I64_MIN, I64_MAX, 0, I64_MIN], np.int64)
+    assert oracle.join(ext, ext)[0] == 6
+
+
+def test_join_ranges_definition():
+    lk = dg.uniform_int(5, 1, 3000, -40, 40, np.int64)
+    rk = dg.uniform_int(5, 2, 800, -60, 20, np.int64)
+    r = oracle.join_ranges(lk, rk)
+    sl, sr = np.sort(lk, kind="stable"), np.sort(rk, kind="stable")
+    keys = sorted(set(lk.tolist()) & set(rk.tolist()))
+    assert r["key"].tolist() == keys
+    for q, k in enumerate(keys):
+        assert r["lstart"][q] == int(np.sum(lk < k))
+        assert r["lcnt"][q] == int(np.sum(lk == k))
+        assert r["rstart"][q] == int(np.sum(rk < k))
+        assert r["rcnt"][q] == int(np.sum(rk == k))
+        assert np.all(sl[r["lstart"][q]:r["lstart"][q] + r["lcnt"][q]] == k)
+        assert np.all(sr[r["rstart"][q]:r["rstart"][q] + r["rcnt"][q]] == k)
+    assert r["total"] == oracle.join(lk, rk)[0]
+
+
+# ---------------------------------------------------------------- group-by ---
+
+@pytest.mark.parametrize("seed", range(5))
+def test_groupby_matches_numpy_unique_add_at(seed):
+    n = 20_000
+    dom = [1, 6, 125, 5000, 10 ** 6][seed]
+    keys = dg.uniform_int(seed, 1, n, -dom // 2 - 1, dom // 2 + 1, np.int32)
+    a = dg.uniform_int(seed, 2, n, 1, 5001, np.int64)
+    b = dg.uniform_int(seed, 3, n, 100, 10_000_001, np.int64)
+    uk, (s, c, sp), ovf = oracle.groupby(keys, [a, b], [("sum", 0), ("count",), ("sum_product", 0, 1)])
+    nk, inv = np.unique(keys, return_inverse=True)
+    ws = np.zeros(len(nk), np.int64)
+    np.add.at(ws, inv, a)
+    wc = np.bincount(inv, minlength=len(nk)).astype(np.int64)
+    wp = np.zeros(len(nk), np.int64)
+    np.add.at(wp, inv, a * b)
+    assert not ovf
+    assert np.array_equal(uk, nk.astype(np.int64))
+    assert np.array_equal(s, ws)
+    assert np.array_equal(c, wc)
+    assert np.array_equal(sp, wp)
+    assert int(s.sum()) == int(a.sum())          # conservation
+    assert int(c.sum()) == n
+
+
+def test_groupby_brute_force_tiny():
+    keys = np.array([5, -2, 5, 0, -2, 5], np.int64)
+    vals = np.array([1, 10, 100, 1000, 10000, 100000], np.int64)
+    uk, (s, c), _ = oracle.groupby(keys, [vals], [("sum", 0), ("count",)])
+    assert uk.tolist() == [-2, 0, 5]
+    assert s.tolist() == [10010, 1000, 100101]
+    assert c.tolist() == [2, 1, 3]
+
+
+def test_groupby_wraps_mod_2_64_and_flags_overflow():
+    keys = np.zeros(3, np.int32)
+    vals = np.array([I64_MAX, I64_MAX, 5], np.int64)
+    uk, (s,), ovf = oracle.groupby(keys, [vals], [("sum", 0)])
+    assert ovf
+    exact = I64_MAX * 2 + 5
+    assert int(s[0]) == (exact + 2 ** 63) % 2 ** 64 - 2 ** 63
+    assert oracle.groupby(np.zeros(0, np.int32), [np.zeros(0, np.int64)], [("sum", 0)])[0].size == 0
+
+
+# ------------------------------------------------------------ whole query ----
+
+def composed_q1(fact, dim, cut):
+    """Q1 from the operator oracles: filter -> join -> gather -> group-by."""
+    rows = oracle.filter_rows([fact["day"]], [(0, "<", cut)])
+    fk = oracle.gather(fact["fk"], rows)
+    cnt, li, ri = oracle.join(fk, dim["pk"])
+    cat = oracle.gather(dim["cat"], ri)
+    qty = oracle.gather(oracle.gather(fact["qty"], rows), li)
+    uk, (s, c), _ = oracle.groupby(cat, [qty], [("sum", 0), ("count",)])
+    return uk, s, c
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_q1_whole_query_equals_composed_and_invariants(seed):
+    c = dg.config1(seed, n_fact=200_000, n_dim=2_000)
+    r = oracle.q1(c["fact"], c["dim"], c["day_cut"])
+    uk, s, cnt = composed_q1(c["fact"], c["dim"], c["day_cut"])
+    assert np.array_equal(r["key"], uk)
+    assert np.array_equal(r["sum_qty"], s)
+    assert np.array_equal(r["count"], cnt)
+    keep = c["fact"]["day"] < c["day_cut"]
+    # pk is a permutation covering every fk, so the join keeps every filtered row
+    assert int(r["count"].sum()) == int(keep.sum())
+    assert int(r["sum_qty"].sum()) == int(c["fact"]["qty"][keep].sum())
+    # independent numpy statement: cat of each kept row via an inverse permutation
+    inv = np.empty(len(c["dim"]["pk"]), np.int64)
+    inv[c["dim"]["pk"]] = np.arange(len(c["dim"]["pk"]))
+    cats = c["dim"]["cat"][inv[c["fact"]["fk"][keep]]]
+    w = np.bincount(cats, weights=None, minlength=25)
+    assert np.array_equal(r["count"], w[w > 0])
+
+
+def brute_q1(fact, dim, cut):
+    g = {}
+    for i in range(len(fact["fk"])):
+        if fact["day"][i] < cut:
+            for j in range(len(dim["pk"])):
+                if dim["pk"][j] == fact["fk"][i]:
+                    k = int(dim["cat"][j])
+                    s, c = g.get(k, (0, 0))
+                    g[k] = (s + int(fact["qty"][i]), c + 1)
+    ks = sorted(g)
+    return ks, [g[k][0] for k in ks], [g[k][1] for k in ks]
+
+
+def test_q1_brute_force_with_duplicate_dim_keys():
+    fact = {"fk": dg.uniform_int(4, 1, 400, 0, 30, np.int32),
+            "qty": dg.uniform_int(4, 2, 400, 1, 5001, np.int64),
+            "day": dg.uniform_int(4, 3, 400, 0, 10, np.int32)}
+    dim = {"pk": dg.uniform_int(4, 4, 40, 0, 35, np.int32),   # duplicates + misses
+           "cat": dg.uniform_int(4, 5, 40, 0, 7, np.int32)}
+    r = oracle.q1(fact, dim, 5)
+    ks, s, c = brute_q1(fact, dim, 5)
+    assert r["key"].tolist() == ks and r["sum_qty"].tolist() == s and r["count"].tolist() == c
+    uk, s2, c2 = composed_q1(fact, dim, 5)
+    assert uk.tolist() == ks and s2.tolist() == s and c2.tolist() == c
+
+
+def test_q2_matches_composed_operators():
+    c = dg.config2(0, n_fact=300_000, n_dim=20_000)
+    f, d = c["fact"], c["dim"]
+    r = oracle.q2(f, d, c["day_cut"])
+    rows = oracle.filter_rows([f["day"]], [(0, "<", c["day_cut"])])
+    fk = oracle.gather(f["fk"], rows)
+    cnt, li, ri = oracle.join(fk, d["pk"])
+    frow = rows[li]
+    key = f["flag"][frow].astype(np.int64) * 2 + (d["cat"][ri] % 2)
+    uk, (sq, sp, sc), _ = oracle.groupby(key, [f["qty"][frow], f["price"][frow]],
+                                         [("sum", 0), ("sum", 1), ("count",)])
+    assert np.array_equal(r["a_key"], uk)
+    assert np.array_equal(r["a_qty"], sq) and np.array_equal(r["a_price"], sp)
+    assert np.array_equal(r["a_count"], sc)
+    ub, (bq, bc), _ = oracle.groupby(f["fk"][frow], [f["qty"][frow]], [("sum", 0), ("count",)])
+    assert np.array_equal(r["b_key"], ub)
+    assert np.array_equal(r["b_qty"], bq) and np.array_equal(r["b_count"], bc)
+    assert int(r["a_count"].sum()) == cnt == len(rows)
+    assert int(r["b_qty"].sum()) == int(f["qty"][rows].sum())
+    assert len(r["b_key"]) == len(np.unique(f["fk"][rows]))
+
+
+def test_q3_matches_numpy_statement():
+    c = dg.config3(0, n_fact=200_000, dims=(5_000, 800, 25))
+    r = oracle.q3(c)
+    f = c["fact"]
+    cut = c["attr_cut"]
+    inv = []
+    for d in (c["d1"], c["d2"], c["d3"]):
+        x = np.empty(len(d["pk"]), np.int64)
+        x[d["pk"]] = np.arange(len(d["pk"]))
+        inv.append(x)
+    j1, j2, j3 = inv[0][f["fk1"]], inv[1][f["fk2"]], inv[2][f["fk3"]]
+    keep = ((c["d1"]["attr"][j1] < cut) & (c["d2"]["attr"][j2] < cut)
+            & (c["d3"]["attr"][j3] < cut))
+    key = c["d1"]["cat"][j1[keep]].astype(np.int64) * 5 + c["d2"]["cat"][j2[keep]]
+    nk, ix = np.unique(key, return_inverse=True)
+    sp = np.zeros(len(nk), np.int64)
+    np.add.at(sp, ix, f["qty"][keep] * f["price"][keep])
+    assert np.array_equal(r["key"], nk)
+    assert np.array_equal(r["sum_qp"], sp)
+    assert np.array_equal(r["count"], np.bincount(ix).astype(np.int64))
