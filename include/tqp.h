@@ -1,0 +1,221 @@
+/*
+ * tqp.h -- C ABI of the MI355X relational hot path (libtqp.so).
+ *
+ * The operation set is the relational core of a tensor query processor
+ * (arXiv 2209.04579): tables are columnar, one contiguous (n x 1) device array
+ * per numeric column (Section 2.1), and the executor turns input columns into
+ * result columns (Section 2.2, "Execution").  The operators are the ones the
+ * paper's TPC-H workload exercises (Section 2.3): predicate filters, an
+ * equi-join and SUM/COUNT aggregation, here with a group-by (Fig. 4).  The sort
+ * is the step a sort-merge join and a sort-based group-by rest on.
+ *
+ * Conventions for every entry point:
+ *  - Every pointer to column data, row ids, counts, outputs and workspace is
+ *    DEVICE memory on the current HIP device, unless the argument is a
+ *    descriptor array (tqp_col*, tqp_pred*, tqp_agg*, tqp_keyterm*,
+ *    tqp_ranges*): those descriptor structs live in HOST memory and are read
+ *    before the call returns.
+ *  - The caller allocates and owns every buffer, including the workspace
+ *    (size from the matching *_workspace_bytes call).  The library keeps no
+ *    device memory between calls.  Input and output buffers must not overlap.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns without waiting, unless it says it synchronizes.
+ *    Result counts are written to device memory (int64_t *d_...), so calls can
+ *    be chained, and captured in a graph, without host round trips.
+ *  - `n` arguments are host-side capacities.  Where a `const int64_t *d_n`
+ *    is accepted and non-NULL, the actual count is min(*d_n, n), read on the
+ *    device; NULL means the count is n.
+ *  - Row ids are int32; a call accepts at most 2^31 - 1 rows (sort: 2^30 - 1).
+ *  - Return value: TQP_OK, or an error code with a message retrievable from
+ *    tqp_last_error() (thread-local).  Argument errors are reported before
+ *    anything is enqueued; nothing aborts the process.
+ */
+#ifndef TQP_H
+#define TQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TQP_OK        0
+#define TQP_EINVAL    1   /* bad argument: null pointer, size, dtype, flag   */
+#define TQP_ECAPACITY 2   /* an output or workspace buffer is too small       */
+#define TQP_EHIP      3   /* the HIP runtime reported an error                */
+
+/* Column element types.  Money is int64 fixed-point cents, so sums are exact. */
+typedef enum { TQP_INT8 = 1, TQP_INT32 = 2, TQP_INT64 = 3 } tqp_dtype;
+
+/* A non-owning 1-D device column: `len` elements of `dtype` at `data`. */
+typedef struct {
+    void    *data;
+    int64_t  len;
+    int32_t  dtype;
+    int32_t  reserved;
+} tqp_col;
+
+/* Predicate `cols[col] op literal`, compared as mathematical integers. */
+typedef enum { TQP_LT = 0, TQP_LE = 1, TQP_GT = 2, TQP_GE = 3, TQP_EQ = 4, TQP_NE = 5 } tqp_cmp;
+typedef struct {
+    int32_t col;
+    int32_t op;
+    int64_t literal;
+} tqp_pred;
+
+/* Aggregates over value columns: SUM(vals[a]), COUNT(*), SUM(vals[a]*vals[b]).
+ * Sums are int64 two's complement, i.e. exact modulo 2^64. */
+typedef enum { TQP_AGG_SUM = 0, TQP_AGG_COUNT = 1, TQP_AGG_SUM_PRODUCT = 2 } tqp_agg_op;
+typedef struct {
+    int32_t op;
+    int32_t a;
+    int32_t b;
+    int32_t reserved;
+} tqp_agg;
+
+/* One term of a packed key: mul * f(col[rows ? rows[i] : i]) where
+ * f(v) = v mod m in [0, m) when m > 0, and f(v) = v when m == 0. */
+typedef struct {
+    tqp_col        col;
+    const int32_t *rows;
+    int64_t        mod;
+    int64_t        mul;
+} tqp_keyterm;
+
+/* Join result in ranges form: five device int64 arrays of capacity range_cap. */
+typedef struct {
+    int64_t *key;
+    int64_t *lstart;
+    int64_t *lcnt;
+    int64_t *rstart;
+    int64_t *rcnt;
+} tqp_ranges;
+
+/* Thread-local text of the last error reported on this thread ("" if none). */
+const char *tqp_last_error(void);
+
+/* Library version string. */
+const char *tqp_version(void);
+
+/* ------------------------------------------------------------------------
+ * tqp_filter -- WHERE with stream compaction (Section 2.3: Q6's filters).
+ * Keeps row i of an n-row table when every predicate holds; n = cols[0].len
+ * and every cols[c] and pay_in[c] has len n.  npred in [1, 8], ncols in
+ * [1, 8], npay in [0, 8].
+ *   out_rows  : optional, capacity n; kept row ids, ascending.
+ *   pay_out[c]: optional payload columns (same dtype as pay_in[c], capacity
+ *               n): pay_out[c][k] = pay_in[c][out_rows[k]].
+ *   d_count   : required; receives the number of kept rows.
+ * Workspace: tqp_filter_workspace_bytes(n).
+ * ---------------------------------------------------------------------- */
+size_t tqp_filter_workspace_bytes(int64_t n);
+int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
+               const tqp_col *pay_in, const tqp_col *pay_out, int npay,
+               int32_t *out_rows, int64_t *d_count,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_gather -- out[i] = src[idx[i]] for i < count (Fig. 3's index_select).
+ * src and dst share a dtype; dst->len >= n.  An index outside [0, src->len)
+ * yields 0 instead of a read.
+ * ---------------------------------------------------------------------- */
+int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n,
+               const int64_t *d_n, const tqp_col *dst, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_pack_key -- out[i] = sum over terms of mul * f(col[row]) (int64, mod
+ * 2^64) for i < count: the packed multi-column group key, e.g.
+ * flag * 2 + (cat mod 2).  Each term's rows (if given) hold >= count entries.
+ * nterms in [1, 4].  Row ids outside the column read as 0.
+ * ---------------------------------------------------------------------- */
+int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n,
+                 const int64_t *d_n, int64_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_sort -- stable ascending sort of signed int32/int64 keys (LSD radix).
+ *   key      : input keys, key->len >= n (n = capacity, d_n = actual count).
+ *   in_rows  : optional row id carried with each key (NULL = 0, 1, 2, ...).
+ *   key_bits : 0 = derive the key range on the device and read it back
+ *              (this SYNCHRONIZES the stream); 1..64 = the caller guarantees
+ *              0 <= key - key_min < 2^key_bits for every key.
+ *   out_key  : sorted keys (capacity n), out_rows: carried row ids (capacity
+ *              n, required).  Ties keep input order.
+ * Workspace: tqp_sort_workspace_bytes(n, dtype).
+ * ---------------------------------------------------------------------- */
+size_t tqp_sort_workspace_bytes(int64_t n, int dtype);
+int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n,
+             const int64_t *d_n, int key_bits, int64_t key_min,
+             const tqp_col *out_key, int32_t *out_rows,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_join -- inner equi-join, bag semantics, sort-merge (Section 2.3: Q14).
+ *   lkey/rkey : same dtype (int32 or int64).  With TQP_JOIN_SORTED both are
+ *               ascending and lrows/rrows (optional; NULL = position) give the
+ *               row id of each position; without it the library sorts both
+ *               sides first (stable, key range derived on the device, which
+ *               synchronizes the stream) and lrows/rrows are the row ids of
+ *               the unsorted inputs.
+ *   Pairs     : every (i, j) with lkey[i] == rkey[j], ordered by (key, i, j)
+ *               over sorted positions, written as out_l = lrows[i],
+ *               out_r = rrows[j], out_pair_key (optional, key dtype) = key.
+ *               d_count (required) receives the pair count, even when it
+ *               exceeds cap; then pairs past cap are not written.  Pass
+ *               out_l = out_r = NULL to skip pairs.
+ *   Ranges    : with TQP_JOIN_RANGES, for each key present on both sides,
+ *               ascending: key, lstart, lcnt, rstart, rcnt, indexing the
+ *               sorted sides; d_nranges receives their number (at most
+ *               range_cap are written).
+ * Workspace: tqp_join_workspace_bytes(nl, nr, dtype, flags).
+ * ---------------------------------------------------------------------- */
+#define TQP_JOIN_SORTED 1u
+#define TQP_JOIN_RANGES 2u
+size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags);
+int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
+             const tqp_col *rkey, const int32_t *rrows, const int64_t *d_nr,
+             uint32_t flags,
+             int32_t *out_l, int32_t *out_r, void *out_pair_key, int64_t cap,
+             int64_t *d_count,
+             const tqp_ranges *ranges, int64_t range_cap, int64_t *d_nranges,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_groupby_agg -- GROUP BY key with SUM / COUNT / SUM of products
+ * (Section 2.3 aggregates; Fig. 4's group-by aggregate).
+ *   key       : int32/int64 keys, capacity key->len, actual count d_n.
+ *   vals      : nvals value columns (int8/int32/int64, each len >= count or
+ *               >= max row id + 1 when val_rows is given).
+ *   val_rows  : optional; the values of row i are vals[c][val_rows[i]].
+ *   aggs      : nagg in [1, 4] aggregates.
+ *   flags     : TQP_GB_SORTED  -- keys are already ascending (no sort);
+ *               TQP_GB_DENSE   -- the caller guarantees
+ *                                 key_lo <= key < key_lo + key_span with
+ *                                 key_span <= TQP_GB_DENSE_MAX: direct
+ *                                 aggregation, no sort.
+ *               otherwise the keys are sorted first; key_span > 0 bounds the
+ *               key range as above, key_span == 0 derives it on the device
+ *               (synchronizes the stream).
+ *   Output    : the groups that occur, ascending by key: out_key (capacity
+ *               out_key->len) and out_aggs[a] (int64, same capacity);
+ *               d_ngroups receives the group count.
+ * Workspace: tqp_groupby_workspace_bytes(n, key dtype, nagg, flags, key_span).
+ * ---------------------------------------------------------------------- */
+#define TQP_GB_SORTED 1u
+#define TQP_GB_DENSE  2u
+#define TQP_GB_DENSE_MAX 4096
+size_t tqp_groupby_workspace_bytes(int64_t n, int dtype, int nagg, uint32_t flags,
+                                   int64_t key_span);
+int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t flags,
+                    int64_t key_lo, int64_t key_span,
+                    const tqp_col *vals, int nvals, const int32_t *val_rows,
+                    const tqp_agg *aggs, int nagg,
+                    const tqp_col *out_key, int64_t *const *out_aggs,
+                    int64_t *d_ngroups,
+                    void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TQP_H */

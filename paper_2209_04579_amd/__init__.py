@@ -1,0 +1,325 @@
+"""Python binding of libtqp: the MI355X relational hot path.
+
+Argument marshalling only: every operator runs in the HIP kernels of
+``libtqp.so`` (built by ``paper_2209_04579_amd.build``).  Tensors are device
+memory from PyTorch; the stream is PyTorch's current HIP stream.  Importing the
+module does not need a GPU; calling an operator does, and fails loudly if the
+library is missing.
+
+Two layers:
+  * ``*_into`` functions take preallocated outputs and workspace, enqueue the
+    kernels and return immediately (counts stay on the device);
+  * convenience functions allocate, run, read the counts back and return
+    trimmed tensors (one synchronization).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "TqpError", "lib", "library_path", "filter", "filter_into", "gather_into", "gather",
+    "pack_key_into", "sort", "sort_into", "join", "join_into", "join_ranges",
+    "groupby_agg", "groupby_agg_into", "OPS", "DTYPES",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtqp.so")
+
+TQP_OK, TQP_EINVAL, TQP_ECAPACITY, TQP_EHIP = 0, 1, 2, 3
+DTYPES = {torch.int8: 1, torch.int32: 2, torch.int64: 3}
+OPS = {"<": 0, "<=": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
+AGGS = {"sum": 0, "count": 1, "sum_product": 2}
+JOIN_SORTED, JOIN_RANGES = 1, 2
+GB_SORTED, GB_DENSE = 1, 2
+GB_DENSE_MAX = 4096
+
+
+class TqpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libtqp error {code}: {msg}")
+        self.code = code
+
+
+class Col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("len", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("literal", ctypes.c_int64)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class KeyTerm(ctypes.Structure):
+    _fields_ = [("col", Col), ("rows", ctypes.c_void_p), ("mod", ctypes.c_int64),
+                ("mul", ctypes.c_int64)]
+
+
+class Ranges(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("lstart", ctypes.c_void_p),
+                ("lcnt", ctypes.c_void_p), ("rstart", ctypes.c_void_p),
+                ("rcnt", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Loads libtqp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: build it with paper_2209_04579_amd.build.build() "
+                "(the operators have no other implementation)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i64, i32, u32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_uint32, ctypes.c_size_t)
+        P = ctypes.POINTER
+        L.tqp_last_error.restype = ctypes.c_char_p
+        L.tqp_version.restype = ctypes.c_char_p
+        L.tqp_filter_workspace_bytes.restype = sz
+        L.tqp_filter_workspace_bytes.argtypes = [i64]
+        L.tqp_filter.restype = i32
+        L.tqp_filter.argtypes = [P(Col), i32, P(Pred), i32, P(Col), P(Col), i32, vp, vp,
+                                 vp, sz, vp]
+        L.tqp_gather.restype = i32
+        L.tqp_gather.argtypes = [P(Col), vp, i64, vp, P(Col), vp]
+        L.tqp_pack_key.restype = i32
+        L.tqp_pack_key.argtypes = [P(KeyTerm), i32, i64, vp, vp, vp]
+        L.tqp_sort_workspace_bytes.restype = sz
+        L.tqp_sort_workspace_bytes.argtypes = [i64, i32]
+        L.tqp_sort.restype = i32
+        L.tqp_sort.argtypes = [P(Col), vp, i64, vp, i32, i64, P(Col), vp, vp, sz, vp]
+        L.tqp_join_workspace_bytes.restype = sz
+        L.tqp_join_workspace_bytes.argtypes = [i64, i64, i32, u32]
+        L.tqp_join.restype = i32
+        L.tqp_join.argtypes = [P(Col), vp, vp, P(Col), vp, vp, u32, vp, vp, vp, i64, vp,
+                               P(Ranges), i64, vp, vp, sz, vp]
+        L.tqp_groupby_workspace_bytes.restype = sz
+        L.tqp_groupby_workspace_bytes.argtypes = [i64, i32, i32, u32, i64]
+        L.tqp_groupby_agg.restype = i32
+        L.tqp_groupby_agg.argtypes = [P(Col), vp, u32, i64, i64, P(Col), i32, vp, P(Agg), i32,
+                                      P(Col), P(vp), vp, vp, sz, vp]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers ----
+
+def _check(rc: int):
+    if rc != TQP_OK:
+        raise TqpError(rc, lib().tqp_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _col(t: torch.Tensor) -> Col:
+    if t.dtype not in DTYPES:
+        raise TypeError(f"unsupported column dtype {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+        raise ValueError("columns must be contiguous 1-D device tensors")
+    return Col(t.data_ptr(), t.numel(), DTYPES[t.dtype], 0)
+
+
+def _cols(ts):
+    arr = (Col * max(1, len(ts)))()
+    for i, t in enumerate(ts):
+        arr[i] = _col(t)
+    return arr
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def _dev(t):
+    return t.device
+
+
+# ----------------------------------------------------------------- filter ----
+
+def filter_into(cols, preds, payload_in, payload_out, out_rows, d_count, ws, stream=None):
+    """Enqueues WHERE + compaction.  preds: [(col_index, op, literal)]."""
+    pr = (Pred * len(preds))(*[Pred(c, OPS[op], int(lit)) for c, op, lit in preds])
+    pin = _cols(payload_in)
+    pout = _cols(payload_out)
+    _check(lib().tqp_filter(_cols(cols), len(cols), pr, len(preds), pin, pout,
+                            len(payload_in), _ptr(out_rows), _ptr(d_count), _ptr(ws),
+                            ws.numel(), _stream(stream)))
+
+
+def filter_workspace_bytes(n: int) -> int:
+    return lib().tqp_filter_workspace_bytes(n)
+
+
+def filter(cols, preds, payload=(), want_rows=True):
+    """Returns (row ids int32, [payload columns]) for rows where all preds hold."""
+    n = cols[0].numel()
+    dev = _dev(cols[0])
+    rows = torch.empty(n, dtype=torch.int32, device=dev) if want_rows else None
+    pout = [torch.empty(n, dtype=p.dtype, device=dev) for p in payload]
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = workspace(filter_workspace_bytes(n), dev)
+    filter_into(cols, preds, list(payload), pout, rows, cnt, ws)
+    k = int(cnt.item())
+    return (rows[:k] if rows is not None else None), [p[:k] for p in pout]
+
+
+# ----------------------------------------------------------------- gather ----
+
+def gather_into(src, idx, n, dst, d_n=None, stream=None):
+    _check(lib().tqp_gather(ctypes.byref(_col(src)), _ptr(idx), int(n), _ptr(d_n),
+                            ctypes.byref(_col(dst)), _stream(stream)))
+
+
+def gather(src, idx):
+    out = torch.empty(idx.numel(), dtype=src.dtype, device=src.device)
+    gather_into(src, idx, idx.numel(), out)
+    return out
+
+
+def pack_key_into(terms, n, out, d_n=None, stream=None):
+    """terms: [(column, rows or None, mod, mul)] -> out[i] = sum mul * f(col[row])."""
+    arr = (KeyTerm * len(terms))()
+    for i, (c, rows, mod, mul) in enumerate(terms):
+        arr[i] = KeyTerm(_col(c), _ptr(rows), int(mod), int(mul))
+    _check(lib().tqp_pack_key(arr, len(terms), int(n), _ptr(d_n), _ptr(out), _stream(stream)))
+
+
+# ------------------------------------------------------------------- sort ----
+
+def sort_workspace_bytes(n: int, dtype) -> int:
+    return lib().tqp_sort_workspace_bytes(n, DTYPES[dtype])
+
+
+def sort_into(key, in_rows, n, out_key, out_rows, ws, d_n=None, key_bits=0, key_min=0,
+              stream=None):
+    _check(lib().tqp_sort(ctypes.byref(_col(key)), _ptr(in_rows), int(n), _ptr(d_n),
+                          int(key_bits), int(key_min), ctypes.byref(_col(out_key)),
+                          _ptr(out_rows), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def sort(key, in_rows=None, key_bits=0, key_min=0):
+    """Stable ascending sort: returns (sorted keys, carried row ids)."""
+    n = key.numel()
+    ok = torch.empty_like(key)
+    orows = torch.empty(n, dtype=torch.int32, device=key.device)
+    ws = workspace(sort_workspace_bytes(n, key.dtype), key.device)
+    sort_into(key, in_rows, n, ok, orows, ws, key_bits=key_bits, key_min=key_min)
+    return ok, orows
+
+
+# ------------------------------------------------------------------- join ----
+
+def join_workspace_bytes(nl, nr, dtype, flags) -> int:
+    return lib().tqp_join_workspace_bytes(nl, nr, DTYPES[dtype], flags)
+
+
+def join_into(lkey, rkey, flags, out_l, out_r, out_key, cap, d_count, ws, lrows=None,
+              rrows=None, d_nl=None, d_nr=None, ranges=None, range_cap=0, d_nranges=None,
+              stream=None):
+    rg = None
+    if ranges is not None:
+        rg = Ranges(*[r.data_ptr() for r in ranges])
+    _check(lib().tqp_join(ctypes.byref(_col(lkey)), _ptr(lrows), _ptr(d_nl),
+                          ctypes.byref(_col(rkey)), _ptr(rrows), _ptr(d_nr), int(flags),
+                          _ptr(out_l), _ptr(out_r), _ptr(out_key), int(cap), _ptr(d_count),
+                          ctypes.byref(rg) if rg is not None else None, int(range_cap),
+                          _ptr(d_nranges), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def join(lkey, rkey, lrows=None, rrows=None, sorted_inputs=False, cap=None, with_key=False):
+    """Pairs (L row, R row[, key]) of the inner equi-join, in (key, i, j) order.
+
+    Re-runs once with the exact capacity when the first guess is too small.
+    """
+    dev = lkey.device
+    flags = JOIN_SORTED if sorted_inputs else 0
+    ws = workspace(join_workspace_bytes(lkey.numel(), rkey.numel(), lkey.dtype, flags), dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    cap = int(cap if cap is not None else max(lkey.numel(), rkey.numel(), 1))
+    for _ in range(2):
+        ol = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        orr = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        ok = torch.empty(max(cap, 1), dtype=lkey.dtype, device=dev) if with_key else None
+        join_into(lkey, rkey, flags, ol, orr, ok, cap, cnt, ws, lrows=lrows, rrows=rrows)
+        total = int(cnt.item())
+        if total <= cap:
+            out = (ol[:total], orr[:total])
+            return out + ((ok[:total],) if with_key else ())
+        cap = total
+    raise TqpError(TQP_ECAPACITY, "join output did not fit after a retry")
+
+
+def join_ranges(lkey_sorted, rkey_sorted):
+    """Ranges form over two ascending key columns: dict of int64 tensors + total."""
+    dev = lkey_sorted.device
+    flags = JOIN_SORTED | JOIN_RANGES
+    cap = max(1, min(lkey_sorted.numel(), rkey_sorted.numel()))
+    rng = [torch.empty(cap, dtype=torch.int64, device=dev) for _ in range(5)]
+    nr = torch.empty(1, dtype=torch.int64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = workspace(join_workspace_bytes(lkey_sorted.numel(), rkey_sorted.numel(),
+                                        lkey_sorted.dtype, flags), dev)
+    join_into(lkey_sorted, rkey_sorted, flags, None, None, None, 0, cnt, ws, ranges=rng,
+              range_cap=cap, d_nranges=nr)
+    m = int(nr.item())
+    out = {k: r[:m] for k, r in zip(("key", "lstart", "lcnt", "rstart", "rcnt"), rng)}
+    out["total"] = int(cnt.item())
+    return out
+
+
+# --------------------------------------------------------------- group-by ----
+
+def groupby_workspace_bytes(n, dtype, nagg, flags, key_span=0) -> int:
+    return lib().tqp_groupby_workspace_bytes(n, DTYPES[dtype], nagg, flags, key_span)
+
+
+def _aggs(aggs):
+    arr = (Agg * len(aggs))()
+    for i, a in enumerate(aggs):
+        arr[i] = Agg(AGGS[a[0]], a[1] if len(a) > 1 else 0, a[2] if len(a) > 2 else 0, 0)
+    return arr
+
+
+def groupby_agg_into(key, vals, aggs, out_key, out_aggs, d_ngroups, ws, flags=0, key_lo=0,
+                     key_span=0, val_rows=None, d_n=None, stream=None):
+    outs = (ctypes.c_void_p * len(out_aggs))(*[o.data_ptr() for o in out_aggs])
+    _check(lib().tqp_groupby_agg(ctypes.byref(_col(key)), _ptr(d_n), int(flags), int(key_lo),
+                                 int(key_span), _cols(vals), len(vals), _ptr(val_rows),
+                                 _aggs(aggs), len(aggs), ctypes.byref(_col(out_key)), outs,
+                                 _ptr(d_ngroups), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def groupby_agg(key, vals, aggs, flags=0, key_lo=0, key_span=0, val_rows=None, cap=None):
+    """GROUP BY key: returns (unique keys, [int64 aggregate tensors])."""
+    dev = key.device
+    n = key.numel()
+    cap = int(cap if cap is not None else max(n, 1))
+    ok = torch.empty(cap, dtype=key.dtype, device=dev)
+    outs = [torch.empty(cap, dtype=torch.int64, device=dev) for _ in aggs]
+    ng = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = workspace(groupby_workspace_bytes(n, key.dtype, len(aggs), flags, key_span), dev)
+    groupby_agg_into(key, list(vals), aggs, ok, outs, ng, ws, flags=flags, key_lo=key_lo,
+                     key_span=key_span, val_rows=val_rows)
+    g = int(ng.item())
+    return ok[:g], [o[:g] for o in outs]

@@ -1,0 +1,147 @@
+// Library-wide pieces: error text, fills, the key-range reduction.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "tqp_internal.hpp"
+
+namespace tqp {
+
+static thread_local char g_err[512];
+
+int set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(TQP_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return TQP_OK;
+}
+
+int dtype_size(int dtype) {
+    switch (dtype) {
+    case TQP_INT8: return 1;
+    case TQP_INT32: return 4;
+    case TQP_INT64: return 8;
+    default: return 0;
+    }
+}
+
+bool dtype_ok(int dtype) { return dtype_size(dtype) != 0; }
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+int fill_u64(void *dst, uint64_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return TQP_OK;
+    int64_t blocks = ceil_div(count, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       static_cast<uint64_t *>(dst), value, count);
+    return check_launch("fill_u64");
+}
+
+int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return TQP_OK;
+    int64_t blocks = ceil_div(count, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       static_cast<uint32_t *>(dst), value, count);
+    return check_launch("fill_u32");
+}
+
+// Min and max of the first count keys.  out[0], out[1] must hold INT64_MAX
+// and INT64_MIN beforehand.
+template <class K>
+__global__ __launch_bounds__(256) void k_minmax(const K *key, int64_t n,
+                                                const int64_t *d_n, int64_t *out) {
+    const int64_t cnt = count_of(d_n, n);
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cnt;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        int64_t v = key[i];
+        lo = v < lo ? v : lo;
+        hi = v > hi ? v : hi;
+    }
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        int64_t a = shfl_xor(lo, m), b = shfl_xor(hi, m);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    __shared__ int64_t slo[4], shi[4];
+    if (lane_id() == 0) { slo[wave_id()] = lo; shi[wave_id()] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) {
+            lo = slo[w] < lo ? slo[w] : lo;
+            hi = shi[w] > hi ? shi[w] : hi;
+        }
+        if (lo != INT64_MAX) atomicMin(reinterpret_cast<long long *>(&out[0]), (long long)lo);
+        if (hi != INT64_MIN) atomicMax(reinterpret_cast<long long *>(&out[1]), (long long)hi);
+    }
+}
+
+int launch_minmax(const void *key, int dtype, int64_t n, const int64_t *d_n,
+                  int64_t *out, hipStream_t s) {
+    int rc = fill_u64(out, uint64_t(INT64_MAX), 1, s);
+    if (rc) return rc;
+    rc = fill_u64(out + 1, uint64_t(INT64_MIN), 1, s);
+    if (rc) return rc;
+    if (n <= 0) return TQP_OK;
+    int64_t blocks = ceil_div(n, 256 * 16);
+    if (blocks > 2048) blocks = 2048;
+    if (dtype == TQP_INT32)
+        hipLaunchKernelGGL(k_minmax<int32_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
+                           static_cast<const int32_t *>(key), n, d_n, out);
+    else
+        hipLaunchKernelGGL(k_minmax<int64_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
+                           static_cast<const int64_t *>(key), n, d_n, out);
+    return check_launch("minmax");
+}
+
+int derive_key_range(const void *key, int dtype, int64_t n, const int64_t *d_n,
+                     void *scratch16, hipStream_t s, int64_t *key_min, int *key_bits) {
+    int64_t *dev = static_cast<int64_t *>(scratch16);
+    int rc = launch_minmax(key, dtype, n, d_n, dev, s);
+    if (rc) return rc;
+    int64_t host[2];
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return set_error(TQP_EHIP, "key range read-back: %s", hipGetErrorString(e));
+    if (host[0] > host[1]) {          // no keys
+        *key_min = 0;
+        *key_bits = 0;
+        return TQP_OK;
+    }
+    uint64_t span = uint64_t(host[1]) - uint64_t(host[0]);
+    int bits = 0;
+    while (bits < 64 && (span >> bits) != 0) bits++;
+    *key_min = host[0];
+    *key_bits = bits;
+    return TQP_OK;
+}
+
+}  // namespace tqp
+
+TQP_API const char *tqp_last_error(void) { return tqp::g_err; }
+
+TQP_API const char *tqp_version(void) { return "tqp-mi355x 0.1 (gfx950)"; }

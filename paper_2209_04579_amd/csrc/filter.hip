@@ -1,0 +1,221 @@
+// WHERE with stream compaction, single pass.
+//
+// Each workgroup takes a 4096-row tile (256 threads x 16 consecutive rows),
+// evaluates the predicate conjunction with wide vector loads, counts its kept
+// rows with a block scan, gets the tile's output offset from a decoupled
+// look-back over the tiles before it, and writes the kept row ids and the
+// payload columns at those offsets.  Every input byte is read once; output is
+// written once; the order of kept rows is ascending row id.
+#include "tqp_internal.hpp"
+
+namespace tqp {
+
+constexpr int kFilterNT = 256;
+constexpr int kFilterIPT = 16;
+constexpr int kFilterTile = kFilterNT * kFilterIPT;
+constexpr int kMaxPred = 8;
+constexpr int kMaxPay = 8;
+
+struct FilterArgs {
+    const void *pcol[kMaxPred];
+    int64_t plit[kMaxPred];
+    int32_t pdt[kMaxPred];
+    int32_t pop[kMaxPred];
+    int32_t pcolid[kMaxPred];
+    const void *pin[kMaxPay];
+    void *pout[kMaxPay];
+    int32_t paydt[kMaxPay];
+    int32_t npred;
+    int32_t npay;
+    int32_t vec;          // every column base is 16-byte aligned
+    int32_t *out_rows;
+    int64_t *d_count;
+    int64_t n;
+    uint32_t *ticket;
+    uint64_t *status;
+};
+
+// Loads 16 consecutive elements starting at row0 (sign-extended to int64).
+__device__ __forceinline__ void load16(const void *p, int dt, int64_t row0, int64_t n,
+                                       bool vec, int64_t (&v)[16]) {
+    if (vec && row0 + 16 <= n) {
+        if (dt == TQP_INT8) {
+            int4 x = *reinterpret_cast<const int4 *>(static_cast<const int8_t *>(p) + row0);
+            const int w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                v[r] = static_cast<int8_t>(static_cast<uint32_t>(w[r >> 2]) >> (8 * (r & 3)));
+        } else if (dt == TQP_INT32) {
+            const int4 *q = reinterpret_cast<const int4 *>(static_cast<const int32_t *>(p) + row0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                int4 x = q[k];
+                v[4 * k + 0] = x.x;
+                v[4 * k + 1] = x.y;
+                v[4 * k + 2] = x.z;
+                v[4 * k + 3] = x.w;
+            }
+        } else {
+            const longlong2 *q =
+                reinterpret_cast<const longlong2 *>(static_cast<const int64_t *>(p) + row0);
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                longlong2 x = q[k];
+                v[2 * k + 0] = x.x;
+                v[2 * k + 1] = x.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+            v[r] = (row0 + r < n) ? load_any(p, dt, row0 + r) : 0;
+    }
+}
+
+__device__ __forceinline__ bool cmp_holds(int64_t v, int op, int64_t lit) {
+    switch (op) {
+    case TQP_LT: return v < lit;
+    case TQP_LE: return v <= lit;
+    case TQP_GT: return v > lit;
+    case TQP_GE: return v >= lit;
+    case TQP_EQ: return v == lit;
+    default: return v != lit;
+    }
+}
+
+__global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
+    __shared__ int64_t s_tile;
+    __shared__ int64_t s_prefix;
+    __shared__ int32_t s_scan[kFilterNT / kWave];
+
+    const int64_t n = a.n;
+    const int64_t ntiles = ceil_div(n, kFilterTile);
+    const int64_t tile = take_tile(a.ticket, &s_tile);
+    if (tile >= ntiles) {
+        if (tile == 0 && threadIdx.x == 0) *a.d_count = 0;   // empty input
+        return;
+    }
+    const int64_t row0 = tile * kFilterTile + int64_t(threadIdx.x) * kFilterIPT;
+    const bool vec = a.vec != 0;
+
+    uint32_t mask = 0;
+#pragma unroll
+    for (int r = 0; r < 16; r++)
+        if (row0 + r < n) mask |= 1u << r;
+
+    int64_t v[16];
+    int loaded = -1;
+    for (int p = 0; p < a.npred; p++) {
+        if (a.pcolid[p] != loaded) {
+            load16(a.pcol[p], a.pdt[p], row0, n, vec, v);
+            loaded = a.pcolid[p];
+        }
+        const int op = a.pop[p];
+        const int64_t lit = a.plit[p];
+        uint32_t m = 0;
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+            if (cmp_holds(v[r], op, lit)) m |= 1u << r;
+        mask &= m;
+    }
+
+    int32_t total;
+    const int32_t excl = block_excl_scan<kFilterNT>(int32_t(__popc(mask)), &total, s_scan);
+    if (wave_id() == 0) {
+        int64_t pre = lookback_count(a.status, tile, total);
+        if (lane_id() == 0) s_prefix = pre;
+    }
+    __syncthreads();
+    const int64_t base = s_prefix + excl;
+    if (tile == ntiles - 1 && threadIdx.x == 0) *a.d_count = s_prefix + total;
+    if (mask == 0) return;
+
+    if (a.out_rows) {
+        int64_t q = base;
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+            if (mask & (1u << r)) a.out_rows[q++] = static_cast<int32_t>(row0 + r);
+    }
+    for (int c = 0; c < a.npay; c++) {
+        load16(a.pin[c], a.paydt[c], row0, n, vec, v);
+        const int dt = a.paydt[c];
+        void *out = a.pout[c];
+        int64_t q = base;
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+            if (mask & (1u << r)) store_any(out, dt, q++, v[r]);
+    }
+}
+
+static size_t filter_ws(int64_t n) {
+    Carver c(nullptr);
+    c.take<uint64_t>(1 + (n > 0 ? ceil_div(n, kFilterTile) : 1));
+    return c.bytes();
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+TQP_API size_t tqp_filter_workspace_bytes(int64_t n) { return filter_ws(n < 0 ? 0 : n); }
+
+TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
+                       const tqp_col *pay_in, const tqp_col *pay_out, int npay,
+                       int32_t *out_rows, int64_t *d_count, void *ws, size_t ws_bytes,
+                       void *stream) {
+    clear_error();
+    if (!cols || ncols < 1 || ncols > kMaxPred)
+        return set_error(TQP_EINVAL, "tqp_filter: ncols must be in [1, %d]", kMaxPred);
+    if (!preds || npred < 1 || npred > kMaxPred)
+        return set_error(TQP_EINVAL, "tqp_filter: npred must be in [1, %d]", kMaxPred);
+    if (npay < 0 || npay > kMaxPay || (npay > 0 && (!pay_in || !pay_out)))
+        return set_error(TQP_EINVAL, "tqp_filter: npay must be in [0, %d] with both arrays", kMaxPay);
+    if (!d_count) return set_error(TQP_EINVAL, "tqp_filter: d_count is required");
+    const int64_t n = cols[0].len;
+    if (n < 0 || n > INT32_MAX) return set_error(TQP_EINVAL, "tqp_filter: bad row count %lld", (long long)n);
+    FilterArgs a = {};
+    bool vec = true;
+    for (int c = 0; c < ncols; c++) {
+        if (!dtype_ok(cols[c].dtype) || cols[c].len != n || (n > 0 && !cols[c].data))
+            return set_error(TQP_EINVAL, "tqp_filter: column %d has a bad dtype, length or pointer", c);
+        vec = vec && (reinterpret_cast<uintptr_t>(cols[c].data) % 16 == 0);
+    }
+    for (int p = 0; p < npred; p++) {
+        if (preds[p].col < 0 || preds[p].col >= ncols || preds[p].op < TQP_LT || preds[p].op > TQP_NE)
+            return set_error(TQP_EINVAL, "tqp_filter: predicate %d is invalid", p);
+        a.pcol[p] = cols[preds[p].col].data;
+        a.pdt[p] = cols[preds[p].col].dtype;
+        a.pcolid[p] = preds[p].col;
+        a.pop[p] = preds[p].op;
+        a.plit[p] = preds[p].literal;
+    }
+    for (int c = 0; c < npay; c++) {
+        if (!dtype_ok(pay_in[c].dtype) || pay_in[c].dtype != pay_out[c].dtype ||
+            pay_in[c].len != n || pay_out[c].len < n || (n > 0 && (!pay_in[c].data || !pay_out[c].data)))
+            return set_error(TQP_EINVAL, "tqp_filter: payload %d has a bad dtype, length or pointer", c);
+        vec = vec && (reinterpret_cast<uintptr_t>(pay_in[c].data) % 16 == 0);
+        a.pin[c] = pay_in[c].data;
+        a.pout[c] = pay_out[c].data;
+        a.paydt[c] = pay_in[c].dtype;
+    }
+    const size_t need = filter_ws(n);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_filter: workspace needs %zu bytes", need);
+    hipStream_t s = as_stream(stream);
+    Carver cv(ws);
+    const int64_t ntiles = ceil_div(n, kFilterTile);
+    uint64_t *words = cv.take<uint64_t>(1 + (ntiles > 0 ? ntiles : 1));
+    int rc = fill_u64(words, 0, 1 + (ntiles > 0 ? ntiles : 1), s);
+    if (rc) return rc;
+    a.npred = npred;
+    a.npay = npay;
+    a.vec = vec ? 1 : 0;
+    a.out_rows = out_rows;
+    a.d_count = d_count;
+    a.n = n;
+    a.ticket = reinterpret_cast<uint32_t *>(words);
+    a.status = words + 1;
+    const unsigned grid = unsigned(ntiles > 0 ? ntiles : 1);
+    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
+    return check_launch("tqp_filter");
+}

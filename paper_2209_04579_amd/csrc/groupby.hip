@@ -1,0 +1,437 @@
+// GROUP BY with SUM / COUNT / SUM of products, int64 exact modulo 2^64.
+//
+// Sort-based path (general).  After the keys are sorted, every group is a run.
+// Because int64 addition modulo 2^64 is a group operation, the sum of a run
+// equals the difference of the running prefix sum at its last row and at the
+// last row of the run before it.  One single-pass scan over the sorted rows
+// (block scan + decoupled look-back carrying the head count and one running
+// sum per aggregate) writes, at every run end, the running sums and the
+// unique key; a second, small kernel over the groups takes adjacent
+// differences.  No atomics, so the output is the same bytes on every run.
+//
+// Dense path.  When the caller bounds the key to a small domain
+// [key_lo, key_lo + span), each workgroup accumulates into LDS counters
+// indexed by key - key_lo and adds its totals to device accumulators; a final
+// one-workgroup kernel emits the non-empty keys in ascending order.  Integer
+// addition is order-free, so this path is bit-identical to the sorted one.
+#include "tqp_internal.hpp"
+
+namespace tqp {
+
+constexpr int kGbNT = 256;
+constexpr int kGbIPT = 16;
+constexpr int kGbTile = kGbNT * kGbIPT;
+constexpr int kMaxAgg = 4;
+constexpr int kMaxVals = 8;
+constexpr int kNV = kMaxAgg + 1;        // head count + one running sum per aggregate
+
+struct AggArgs {
+    const void *val[kMaxVals];
+    int64_t vlen[kMaxVals];
+    int32_t vdt[kMaxVals];
+    int32_t op[kMaxAgg];
+    int32_t ia[kMaxAgg];
+    int32_t ib[kMaxAgg];
+    int32_t nagg;
+    const int32_t *val_rows;
+};
+
+__device__ __forceinline__ int64_t agg_term(const AggArgs &a, int g, int64_t row) {
+    if (a.op[g] == TQP_AGG_COUNT) return 1;
+    const int x = a.ia[g];
+    const int64_t vx = (row >= 0 && row < a.vlen[x]) ? load_any(a.val[x], a.vdt[x], row) : 0;
+    if (a.op[g] == TQP_AGG_SUM) return vx;
+    const int y = a.ib[g];
+    const int64_t vy = (row >= 0 && row < a.vlen[y]) ? load_any(a.val[y], a.vdt[y], row) : 0;
+    return int64_t(uint64_t(vx) * uint64_t(vy));
+}
+
+// Look-back over kNV int64 values.  flags[t]: 0 not ready, 1 aggregate,
+// 2 inclusive; the values sit in aggv / incv rows of kNV.  The value stores
+// are ordered before the flag by a release store, and read after an acquire
+// load of the flag, all at agent scope so every XCD sees the same data.
+__device__ __forceinline__ void lookback_multi(uint32_t *flags, int64_t *aggv, int64_t *incv,
+                                               int64_t tile, int nv, const int64_t (&agg)[kNV],
+                                               int64_t (&excl)[kNV]) {
+#pragma unroll
+    for (int k = 0; k < kNV; k++) excl[k] = 0;
+    if (tile == 0) {
+        if (lane_id() == 0) {
+            for (int k = 0; k < nv; k++) st_relaxed(&incv[k], agg[k]);
+            st_release(&flags[0], 2u);
+        }
+        return;
+    }
+    if (lane_id() == 0) {
+        for (int k = 0; k < nv; k++) st_relaxed(&aggv[tile * kNV + k], agg[k]);
+        st_release(&flags[tile], 1u);
+    }
+    int64_t base = tile - 1;
+    while (true) {
+        const int64_t idx = base - lane_id();
+        uint32_t f = 2;
+        int64_t v[kNV];
+#pragma unroll
+        for (int k = 0; k < kNV; k++) v[k] = 0;
+        if (idx >= 0) {
+            f = ld_acquire(&flags[idx]);
+            while (f == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                f = ld_acquire(&flags[idx]);
+            }
+            const int64_t *src = (f == 2 ? incv : aggv) + idx * kNV;
+            for (int k = 0; k < nv; k++) v[k] = ld_relaxed(&src[k]);
+        }
+        const uint64_t inc = ballot(f == 2);
+        const int stop = inc ? (__ffsll(static_cast<long long>(inc)) - 1) : (kWave - 1);
+#pragma unroll
+        for (int k = 0; k < kNV; k++) {
+            const int64_t x = lane_id() <= stop ? v[k] : 0;
+            excl[k] += wave_sum(x);
+        }
+        if (inc) break;
+        base -= kWave;
+    }
+    if (lane_id() == 0) {
+        for (int k = 0; k < nv; k++) st_relaxed(&incv[tile * kNV + k], excl[k] + agg[k]);
+        st_release(&flags[tile], 2u);
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, int64_t n,
+                                                   const int64_t *d_n, AggArgs a,
+                                                   K *__restrict__ out_key, int64_t key_cap,
+                                                   int64_t *__restrict__ ends /* [kMaxAgg][n] */,
+                                                   int64_t ends_stride, int64_t *d_ngroups,
+                                                   uint32_t *ticket, uint32_t *flags,
+                                                   int64_t *aggv, int64_t *incv) {
+    __shared__ int64_t s_tile;
+    __shared__ int64_t s_scan[kGbNT / kWave];
+    __shared__ int64_t s_excl[kNV];
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t ntiles = ceil_div(cnt, kGbTile);
+    const int64_t tile = take_tile(ticket, &s_tile);
+    if (tile >= ntiles) {
+        if (tile == 0 && threadIdx.x == 0) *d_ngroups = 0;
+        return;
+    }
+    const int nagg = a.nagg;
+    const int64_t row0 = tile * kGbTile + int64_t(threadIdx.x) * kGbIPT;
+    K v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+    const K before = row0 > 0 && row0 <= cnt ? keys[row0 - 1] : K(0);
+    const K after = row0 + 16 < cnt ? keys[row0 + 16] : K(0);
+    uint32_t head = 0, end = 0;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t i = row0 + r;
+        if (i < cnt) {
+            const K prv = r == 0 ? before : v[r - 1];
+            const K nxt = r == 15 ? after : v[r + 1];
+            if (i == 0 || v[r] != prv) head |= 1u << r;
+            if (i == cnt - 1 || v[r] != nxt) end |= 1u << r;
+        }
+    }
+    int64_t agg[kNV], excl[kNV], tot[kNV];
+    agg[0] = __popc(head);
+#pragma unroll
+    for (int g = 0; g < kMaxAgg; g++) agg[g + 1] = 0;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t i = row0 + r;
+        if (i < cnt) {
+            const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
+#pragma unroll
+            for (int g = 0; g < kMaxAgg; g++)
+                if (g < nagg) agg[g + 1] += agg_term(a, g, row);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNV; k++) excl[k] = block_excl_scan<kGbNT>(agg[k], &tot[k], s_scan);
+    if (wave_id() == 0) {
+        int64_t pre[kNV];
+        lookback_multi(flags, aggv, incv, tile, nagg + 1, tot, pre);
+        if (lane_id() == 0)
+            for (int k = 0; k < kNV; k++) s_excl[k] = pre[k];
+    }
+    __syncthreads();
+    if (tile == ntiles - 1 && threadIdx.x == 0) *d_ngroups = s_excl[0] + tot[0];
+    int64_t hc = s_excl[0] + excl[0];
+    int64_t run[kMaxAgg];
+#pragma unroll
+    for (int g = 0; g < kMaxAgg; g++) run[g] = s_excl[g + 1] + excl[g + 1];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t i = row0 + r;
+        if (i < cnt) {
+            if (head & (1u << r)) {
+                if (hc < key_cap) out_key[hc] = v[r];
+                hc++;
+            }
+            const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
+#pragma unroll
+            for (int g = 0; g < kMaxAgg; g++)
+                if (g < nagg) run[g] += agg_term(a, g, row);
+            if (end & (1u << r)) {
+#pragma unroll
+                for (int g = 0; g < kMaxAgg; g++)
+                    if (g < nagg) ends[g * ends_stride + (hc - 1)] = run[g];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gb_diff(const int64_t *__restrict__ ends,
+                                                 int64_t ends_stride, int nagg,
+                                                 const int64_t *d_ngroups, int64_t cap,
+                                                 int64_t *o0, int64_t *o1, int64_t *o2,
+                                                 int64_t *o3) {
+    const int64_t ng0 = *d_ngroups;
+    const int64_t ng = ng0 < cap ? ng0 : cap;
+    int64_t *outs[4] = {o0, o1, o2, o3};
+    for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < ng;
+         g += int64_t(gridDim.x) * blockDim.x) {
+        for (int k = 0; k < nagg; k++) {
+            const int64_t *e = ends + k * ends_stride;
+            const uint64_t hi = uint64_t(e[g]);
+            const uint64_t lo = g > 0 ? uint64_t(e[g - 1]) : 0;
+            outs[k][g] = int64_t(hi - lo);
+        }
+    }
+}
+
+// ---- dense key domain ------------------------------------------------------
+
+template <class K>
+__global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, int64_t n,
+                                                    const int64_t *d_n, int64_t key_lo,
+                                                    int64_t span, AggArgs a,
+                                                    unsigned long long *__restrict__ gacc) {
+    extern __shared__ unsigned long long s_acc[];   // [(nagg + 1)][span], count last
+    const int nagg = a.nagg;
+    const int64_t cells = int64_t(nagg + 1) * span;
+    for (int64_t i = threadIdx.x; i < cells; i += kGbNT) s_acc[i] = 0;
+    __syncthreads();
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t stride = int64_t(gridDim.x) * kGbNT;
+    for (int64_t i = blockIdx.x * int64_t(kGbNT) + threadIdx.x; i < cnt; i += stride) {
+        const uint64_t b = uint64_t(int64_t(keys[i])) - uint64_t(key_lo);
+        if (b >= uint64_t(span)) continue;
+        const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
+        for (int g = 0; g < nagg; g++)
+            atomicAdd(&s_acc[g * span + b], (unsigned long long)agg_term(a, g, row));
+        atomicAdd(&s_acc[nagg * span + b], 1ull);
+    }
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < span; c += kGbNT) {
+        if (s_acc[nagg * span + c] == 0) continue;
+        for (int g = 0; g <= nagg; g++) atomicAdd(&gacc[g * span + c], s_acc[g * span + c]);
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(1024) void k_gb_dense_emit(const unsigned long long *__restrict__ gacc,
+                                                        int64_t key_lo, int64_t span, int nagg,
+                                                        K *out_key, int64_t cap, int64_t *o0,
+                                                        int64_t *o1, int64_t *o2, int64_t *o3,
+                                                        int64_t *d_ngroups) {
+    // 1024 threads x 4 consecutive bins each covers span <= 4096.
+    __shared__ int64_t s_scan[1024 / kWave];
+    int64_t *outs[4] = {o0, o1, o2, o3};
+    const int64_t c0 = int64_t(threadIdx.x) * 4;
+    uint32_t live = 0;
+    for (int r = 0; r < 4; r++)
+        if (c0 + r < span && gacc[nagg * span + c0 + r] != 0) live |= 1u << r;
+    int64_t total;
+    int64_t q = block_excl_scan<1024>(int64_t(__popc(live)), &total, s_scan);
+    for (int r = 0; r < 4; r++) {
+        if (!(live & (1u << r))) continue;
+        if (q < cap) {
+            out_key[q] = K(key_lo + c0 + r);
+            for (int g = 0; g < nagg; g++) outs[g][q] = int64_t(gacc[g * span + c0 + r]);
+        }
+        q++;
+    }
+    if (threadIdx.x == 0) *d_ngroups = total;
+}
+
+struct GbLayout {
+    int64_t *scratch;
+    void *skey;
+    int32_t *srows;
+    void *sort_ws;
+    size_t sort_ws_bytes;
+    int64_t *ends;
+    uint32_t *words;          // ticket + flags
+    int64_t ntiles;
+    int64_t *aggv, *incv;
+    unsigned long long *gacc;
+    size_t bytes;
+};
+
+static bool dense_ok(uint32_t flags, int64_t span, int nagg) {
+    return (flags & TQP_GB_DENSE) && span > 0 && span <= TQP_GB_DENSE_MAX &&
+           int64_t(nagg + 1) * span * 8 <= 48 * 1024;
+}
+
+static GbLayout gb_layout(void *ws, int64_t n, int dtype, int nagg, uint32_t flags, int64_t span) {
+    GbLayout L = {};
+    Carver c(ws);
+    const int ks = dtype_size(dtype);
+    L.scratch = c.take<int64_t>(2);
+    if (dense_ok(flags, span, nagg)) {
+        L.gacc = c.take<unsigned long long>(size_t(nagg + 1) * span);
+        L.bytes = c.bytes();
+        return L;
+    }
+    const int64_t nn = n > 0 ? n : 1;
+    if (!(flags & TQP_GB_SORTED)) {
+        L.skey = c.take<char>(size_t(nn) * ks);
+        L.srows = c.take<int32_t>(size_t(nn));
+        L.sort_ws_bytes = sort_ws_bytes(nn, dtype, ks * 8);
+        L.sort_ws = c.take<char>(L.sort_ws_bytes);
+    }
+    L.ends = c.take<int64_t>(size_t(kMaxAgg) * nn);
+    L.ntiles = ceil_div(nn, kGbTile);
+    L.words = c.take<uint32_t>(size_t(2 + L.ntiles));
+    L.aggv = c.take<int64_t>(size_t(L.ntiles) * kNV);
+    L.incv = c.take<int64_t>(size_t(L.ntiles) * kNV);
+    L.bytes = c.bytes();
+    return L;
+}
+
+template <class K>
+static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags, int64_t key_lo,
+                         int64_t key_span, const AggArgs &args, const tqp_col *out_key,
+                         int64_t *const *out_aggs, int64_t *d_ngroups, void *ws, hipStream_t s) {
+    const int64_t n = key->len;
+    const int nagg = args.nagg;
+    GbLayout L = gb_layout(ws, n, key->dtype, nagg, flags, key_span);
+    int64_t *o[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int g = 0; g < nagg; g++) o[g] = out_aggs[g];
+    int rc;
+    if (dense_ok(flags, key_span, nagg)) {
+        rc = fill_u64(L.gacc, 0, int64_t(nagg + 1) * key_span, s);
+        if (rc) return rc;
+        if (n > 0) {
+            int64_t g = ceil_div(n, int64_t(kGbNT) * 64);
+            if (g > 2048) g = 2048;
+            const size_t lds = size_t(nagg + 1) * key_span * 8;
+            hipLaunchKernelGGL(k_gb_dense<K>, dim3(unsigned(g)), dim3(kGbNT), lds, s,
+                               static_cast<const K *>(key->data), n, d_n, key_lo, key_span, args,
+                               L.gacc);
+            if ((rc = check_launch("group-by dense"))) return rc;
+        }
+        hipLaunchKernelGGL(k_gb_dense_emit<K>, dim3(1), dim3(1024), 0, s, L.gacc, key_lo, key_span,
+                           nagg, static_cast<K *>(out_key->data), out_key->len, o[0], o[1], o[2],
+                           o[3], d_ngroups);
+        return check_launch("group-by dense emit");
+    }
+    const K *k = static_cast<const K *>(key->data);
+    AggArgs a = args;
+    if (!(flags & TQP_GB_SORTED)) {
+        int64_t kmin = key_lo;
+        int kbits = 0;
+        if (key_span > 0) {
+            while (kbits < 64 && (uint64_t(key_span - 1) >> kbits) != 0) kbits++;
+        } else {
+            rc = derive_key_range(k, key->dtype, n, d_n, L.scratch, s, &kmin, &kbits);
+            if (rc) return rc;
+        }
+        rc = sort_impl(k, key->dtype, args.val_rows, n, d_n, kbits, kmin, L.skey, L.srows,
+                       L.sort_ws, L.sort_ws_bytes, s);
+        if (rc) return rc;
+        k = static_cast<const K *>(L.skey);
+        a.val_rows = L.srows;
+    }
+    rc = fill_u32(L.words, 0, 2 + L.ntiles, s);
+    if (rc) return rc;
+    const unsigned grid = unsigned(L.ntiles);
+    hipLaunchKernelGGL(k_gb_scan<K>, dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a,
+                       static_cast<K *>(out_key->data), out_key->len, L.ends,
+                       n > 0 ? n : int64_t(1), d_ngroups, L.words, L.words + 2, L.aggv, L.incv);
+    if ((rc = check_launch("group-by scan"))) return rc;
+    int64_t g = ceil_div(out_key->len > 0 ? out_key->len : 1, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_gb_diff, dim3(unsigned(g)), dim3(256), 0, s, L.ends,
+                       n > 0 ? n : int64_t(1), nagg, d_ngroups, out_key->len, o[0], o[1], o[2],
+                       o[3]);
+    return check_launch("group-by diff");
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+TQP_API size_t tqp_groupby_workspace_bytes(int64_t n, int dtype, int nagg, uint32_t flags,
+                                           int64_t key_span) {
+    if (n < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64) || nagg < 1 || nagg > kMaxAgg)
+        return 0;
+    return gb_layout(nullptr, n, dtype, nagg, flags, key_span).bytes;
+}
+
+TQP_API int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t flags, int64_t key_lo,
+                            int64_t key_span, const tqp_col *vals, int nvals,
+                            const int32_t *val_rows, const tqp_agg *aggs, int nagg,
+                            const tqp_col *out_key, int64_t *const *out_aggs, int64_t *d_ngroups,
+                            void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!key || !out_key || !aggs || !out_aggs || !d_ngroups)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: null argument");
+    if (key->dtype != TQP_INT32 && key->dtype != TQP_INT64)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: keys must be int32 or int64");
+    if (out_key->dtype != key->dtype)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: out_key dtype must equal the key dtype");
+    if (nagg < 1 || nagg > kMaxAgg)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: nagg must be in [1, %d]", kMaxAgg);
+    if (nvals < 0 || nvals > kMaxVals || (nvals > 0 && !vals))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: nvals must be in [0, %d]", kMaxVals);
+    if (flags & ~(TQP_GB_SORTED | TQP_GB_DENSE))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: unknown flag bits");
+    if ((flags & TQP_GB_DENSE) && (key_span < 1 || key_span > TQP_GB_DENSE_MAX))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: dense needs 1 <= key_span <= %d",
+                         TQP_GB_DENSE_MAX);
+    if (key_span < 0) return set_error(TQP_EINVAL, "tqp_groupby_agg: negative key_span");
+    const int64_t n = key->len;
+    if (n < 0 || n > (int64_t(1) << 30) - 1)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: n must be in [0, 2^30 - 1]");
+    if ((n > 0 && !key->data) || (out_key->len > 0 && !out_key->data))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg: null key data");
+    AggArgs a = {};
+    for (int c = 0; c < nvals; c++) {
+        if (!dtype_ok(vals[c].dtype) || (vals[c].len > 0 && !vals[c].data))
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: value column %d is invalid", c);
+        if (!val_rows && vals[c].len < n)
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: value column %d is shorter than keys", c);
+        a.val[c] = vals[c].data;
+        a.vlen[c] = vals[c].len;
+        a.vdt[c] = vals[c].dtype;
+    }
+    for (int g = 0; g < nagg; g++) {
+        const tqp_agg &x = aggs[g];
+        if (x.op < TQP_AGG_SUM || x.op > TQP_AGG_SUM_PRODUCT)
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d has a bad op", g);
+        if (x.op != TQP_AGG_COUNT && (x.a < 0 || x.a >= nvals))
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d names a missing column", g);
+        if (x.op == TQP_AGG_SUM_PRODUCT && (x.b < 0 || x.b >= nvals))
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d names a missing column", g);
+        if (out_key->len > 0 && !out_aggs[g])
+            return set_error(TQP_EINVAL, "tqp_groupby_agg: output %d is null", g);
+        a.op[g] = x.op;
+        a.ia[g] = x.a;
+        a.ib[g] = x.b;
+    }
+    a.nagg = nagg;
+    a.val_rows = val_rows;
+    const size_t need = tqp_groupby_workspace_bytes(n, key->dtype, nagg, flags, key_span);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_groupby_agg: workspace needs %zu bytes", need);
+    hipStream_t s = as_stream(stream);
+    if (key->dtype == TQP_INT32)
+        return groupby_typed<int32_t>(key, d_n, flags, key_lo, key_span, a, out_key, out_aggs,
+                                      d_ngroups, ws, s);
+    return groupby_typed<int64_t>(key, d_n, flags, key_lo, key_span, a, out_key, out_aggs,
+                                  d_ngroups, ws, s);
+}

@@ -1,0 +1,441 @@
+// Sort-merge inner equi-join over two ascending key columns.
+//
+//  1. Run-length encode each sorted side: one single-pass compaction of the
+//     run heads gives (unique key, run start) and the number of runs.
+//  2. Match: for each left run, find the right run with the same key
+//     (binary search over the right run keys); a matched key becomes one range
+//     (key, lstart, lcnt, rstart, rcnt).  Two decoupled look-backs in the same
+//     kernel give each range its slot and its first output pair (the running
+//     sum of lcnt * rcnt), so the pair total is known on the device.
+//  3. Expand: output positions are split evenly over threads, whatever the
+//     key skew; each thread finds its range by binary search over the pair
+//     offsets, then walks (i, j) within the range in row-major order, which is
+//     the canonical (key, i, j) order.
+#include "tqp_internal.hpp"
+
+namespace tqp {
+
+constexpr int kJoinNT = 256;
+constexpr int kJoinIPT = 16;
+constexpr int kJoinTile = kJoinNT * kJoinIPT;
+constexpr int kExpandPer = 8;
+constexpr int kMatchIPT = 4;
+constexpr int kMatchTile = kJoinNT * kMatchIPT;
+
+template <class K>
+__device__ __forceinline__ void load_keys16(const K *p, int64_t row0, int64_t cnt, K (&v)[16]) {
+    if (row0 + 16 <= cnt) {
+        if (sizeof(K) == 4) {
+            const int4 *q = reinterpret_cast<const int4 *>(p + row0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                int4 x = q[k];
+                v[4 * k + 0] = K(x.x);
+                v[4 * k + 1] = K(x.y);
+                v[4 * k + 2] = K(x.z);
+                v[4 * k + 3] = K(x.w);
+            }
+        } else {
+            const longlong2 *q = reinterpret_cast<const longlong2 *>(p + row0);
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                longlong2 x = q[k];
+                v[2 * k + 0] = K(x.x);
+                v[2 * k + 1] = K(x.y);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) v[r] = row0 + r < cnt ? p[row0 + r] : K(0);
+    }
+}
+
+// Run heads of a sorted column -> (unique key, run start), count in *d_nu.
+template <class K>
+__global__ __launch_bounds__(kJoinNT) void k_rle(const K *__restrict__ keys, int64_t n,
+                                                 const int64_t *d_n, K *__restrict__ ukey,
+                                                 int32_t *__restrict__ ustart, int64_t *d_nu,
+                                                 uint32_t *ticket, uint64_t *status) {
+    __shared__ int64_t s_tile, s_prefix;
+    __shared__ int32_t s_scan[kJoinNT / kWave];
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t ntiles = ceil_div(cnt, kJoinTile);
+    const int64_t tile = take_tile(ticket, &s_tile);
+    if (tile >= ntiles) {
+        if (tile == 0 && threadIdx.x == 0) *d_nu = 0;
+        return;
+    }
+    const int64_t row0 = tile * kJoinTile + int64_t(threadIdx.x) * kJoinIPT;
+    K v[16];
+    if (reinterpret_cast<uintptr_t>(keys) % 16 == 0) {
+        load_keys16(keys, row0, cnt, v);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+    }
+    uint32_t head = 0;
+    K prev = row0 > 0 && row0 - 1 < cnt ? keys[row0 - 1] : K(0);
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t i = row0 + r;
+        if (i < cnt && (i == 0 || v[r] != prev)) head |= 1u << r;
+        prev = v[r];
+    }
+    int32_t total;
+    const int32_t excl = block_excl_scan<kJoinNT>(int32_t(__popc(head)), &total, s_scan);
+    if (wave_id() == 0) {
+        int64_t pre = lookback_count(status, tile, total);
+        if (lane_id() == 0) s_prefix = pre;
+    }
+    __syncthreads();
+    if (tile == ntiles - 1 && threadIdx.x == 0) *d_nu = s_prefix + total;
+    int64_t q = s_prefix + excl;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        if (head & (1u << r)) {
+            ukey[q] = v[r];
+            ustart[q] = int32_t(row0 + r);
+            q++;
+        }
+    }
+}
+
+struct MatchArgs {
+    const void *uL;
+    const int32_t *sL;
+    const int64_t *d_nuL;
+    const int64_t *d_nl;     // left row count (device), or null => nl
+    int64_t nl;
+    const void *uR;
+    const int32_t *sR;
+    const int64_t *d_nuR;
+    const int64_t *d_nr;
+    int64_t nr;
+    int64_t *rkey, *rls, *rlc, *rrs, *rrc;   // ranges (workspace), capacity min(nl, nr)
+    int64_t *off;                            // first pair of each range
+    int64_t *ukey, *uls, *ulc, *urs, *urc;   // optional user copies
+    int64_t ucap;
+    int64_t *d_nranges_ws;
+    int64_t *d_nranges_user;
+    int64_t *d_count;
+    uint32_t *ticket;
+    uint64_t *status_m;
+    uint64_t *status_p;
+};
+
+template <class K>
+__global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
+    __shared__ int64_t s_tile, s_pm, s_pp;
+    __shared__ int32_t s_scan32[kJoinNT / kWave];
+    __shared__ int64_t s_scan64[kJoinNT / kWave];
+    const int64_t nuL = count_of(a.d_nuL, a.nl);
+    const int64_t nuR = count_of(a.d_nuR, a.nr);
+    const int64_t nl = count_of(a.d_nl, a.nl);
+    const int64_t nr = count_of(a.d_nr, a.nr);
+    const int64_t ntiles = ceil_div(nuL, kMatchTile);
+    const int64_t tile = take_tile(a.ticket, &s_tile);
+    if (tile >= ntiles) {
+        if (tile == 0 && threadIdx.x == 0) {
+            *a.d_nranges_ws = 0;
+            if (a.d_nranges_user) *a.d_nranges_user = 0;
+            *a.d_count = 0;
+        }
+        return;
+    }
+    const K *uL = static_cast<const K *>(a.uL);
+    const K *uR = static_cast<const K *>(a.uR);
+    const int64_t u0 = tile * kMatchTile + int64_t(threadIdx.x) * kMatchIPT;
+    int64_t ls[kMatchIPT], lc[kMatchIPT], rs[kMatchIPT], rc[kMatchIPT];
+    K key[kMatchIPT];
+    uint32_t hit = 0;
+    int64_t pairs = 0;
+#pragma unroll
+    for (int r = 0; r < kMatchIPT; r++) {
+        const int64_t u = u0 + r;
+        ls[r] = lc[r] = rs[r] = rc[r] = 0;
+        key[r] = K(0);
+        if (u < nuL) {
+            const K k = uL[u];
+            key[r] = k;
+            ls[r] = a.sL[u];
+            lc[r] = (u + 1 < nuL ? int64_t(a.sL[u + 1]) : nl) - ls[r];
+            int64_t lo = 0, hi = nuR;             // lower_bound of k in uR
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (uR[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < nuR && uR[lo] == k) {
+                hit |= 1u << r;
+                rs[r] = a.sR[lo];
+                rc[r] = (lo + 1 < nuR ? int64_t(a.sR[lo + 1]) : nr) - rs[r];
+                pairs += lc[r] * rc[r];
+            }
+        }
+    }
+    int32_t tot_m;
+    int64_t tot_p;
+    const int32_t ex_m = block_excl_scan<kJoinNT>(int32_t(__popc(hit)), &tot_m, s_scan32);
+    const int64_t ex_p = block_excl_scan<kJoinNT>(pairs, &tot_p, s_scan64);
+    if (wave_id() == 0) {
+        int64_t pm = lookback_count(a.status_m, tile, tot_m);
+        int64_t pp = lookback_count(a.status_p, tile, tot_p);
+        if (lane_id() == 0) { s_pm = pm; s_pp = pp; }
+    }
+    __syncthreads();
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
+        *a.d_nranges_ws = s_pm + tot_m;
+        if (a.d_nranges_user) *a.d_nranges_user = s_pm + tot_m;
+        *a.d_count = s_pp + tot_p;
+    }
+    int64_t q = s_pm + ex_m;
+    int64_t o = s_pp + ex_p;
+#pragma unroll
+    for (int r = 0; r < kMatchIPT; r++) {
+        if (!(hit & (1u << r))) continue;
+        a.rkey[q] = int64_t(key[r]);
+        a.rls[q] = ls[r];
+        a.rlc[q] = lc[r];
+        a.rrs[q] = rs[r];
+        a.rrc[q] = rc[r];
+        a.off[q] = o;
+        if (a.ukey && q < a.ucap) {
+            a.ukey[q] = int64_t(key[r]);
+            a.uls[q] = ls[r];
+            a.ulc[q] = lc[r];
+            a.urs[q] = rs[r];
+            a.urc[q] = rc[r];
+        }
+        o += lc[r] * rc[r];
+        q++;
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(kJoinNT) void k_join_expand(
+    const int64_t *__restrict__ rkey, const int64_t *__restrict__ rls,
+    const int64_t *__restrict__ rlc, const int64_t *__restrict__ rrs,
+    const int64_t *__restrict__ rrc, const int64_t *__restrict__ off, const int64_t *d_nranges,
+    const int64_t *d_count, int64_t cap, const int32_t *__restrict__ lrows,
+    const int32_t *__restrict__ rrows, int32_t *__restrict__ out_l, int32_t *__restrict__ out_r,
+    K *__restrict__ out_key) {
+    const int64_t nranges = *d_nranges;
+    const int64_t total = *d_count;
+    const int64_t limit = total < cap ? total : cap;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * kExpandPer;
+    for (int64_t o0 = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) * kExpandPer; o0 < limit;
+         o0 += stride) {
+        int64_t lo = 0, hi = nranges;          // last m with off[m] <= o0
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= o0) lo = mid;
+            else hi = mid;
+        }
+        int64_t m = lo;
+        int64_t lstart = rls[m], lcnt = rlc[m], rstart = rrs[m], rcnt = rrc[m];
+        K key = K(rkey[m]);
+        const int64_t t = o0 - off[m];
+        int64_t i = t / rcnt;
+        int64_t j = t - i * rcnt;
+        const int64_t oend = o0 + kExpandPer < limit ? o0 + kExpandPer : limit;
+        for (int64_t o = o0; o < oend; o++) {
+            if (i == lcnt) {                    // next range
+                m++;
+                lstart = rls[m];
+                lcnt = rlc[m];
+                rstart = rrs[m];
+                rcnt = rrc[m];
+                key = K(rkey[m]);
+                i = 0;
+                j = 0;
+            }
+            const int64_t li = lstart + i, rj = rstart + j;
+            if (out_l) out_l[o] = lrows ? lrows[li] : int32_t(li);
+            if (out_r) out_r[o] = rrows ? rrows[rj] : int32_t(rj);
+            if (out_key) out_key[o] = key;
+            if (++j == rcnt) {
+                j = 0;
+                i++;
+            }
+        }
+    }
+}
+
+struct JoinLayout {
+    void *sl_key, *sr_key;
+    int32_t *sl_rows, *sr_rows;
+    void *sort_ws;
+    size_t sort_ws_bytes;
+    void *uL, *uR;
+    int32_t *sL, *sR;
+    int64_t *rng[5];
+    int64_t *off;
+    int64_t *counters;       // nuL, nuR, nranges
+    uint64_t *words;         // tickets + statuses
+    int64_t nwords;
+    uint64_t *stL, *stR, *stM, *stP;
+    size_t bytes;
+};
+
+static JoinLayout join_layout(void *ws, int64_t nl, int64_t nr, int dtype, uint32_t flags) {
+    JoinLayout L = {};
+    Carver c(ws);
+    const int ks = dtype_size(dtype);
+    if (!(flags & TQP_JOIN_SORTED)) {
+        L.sl_key = c.take<char>(size_t(nl) * ks);
+        L.sl_rows = c.take<int32_t>(size_t(nl));
+        L.sr_key = c.take<char>(size_t(nr) * ks);
+        L.sr_rows = c.take<int32_t>(size_t(nr));
+        const int64_t nmax = nl > nr ? nl : nr;
+        L.sort_ws_bytes = sort_ws_bytes(nmax, dtype, ks * 8);
+        L.sort_ws = c.take<char>(L.sort_ws_bytes);
+    }
+    L.uL = c.take<char>(size_t(nl > 0 ? nl : 1) * ks);
+    L.sL = c.take<int32_t>(size_t(nl > 0 ? nl : 1));
+    L.uR = c.take<char>(size_t(nr > 0 ? nr : 1) * ks);
+    L.sR = c.take<int32_t>(size_t(nr > 0 ? nr : 1));
+    const int64_t nm = (nl < nr ? nl : nr) > 0 ? (nl < nr ? nl : nr) : 1;
+    for (int k = 0; k < 5; k++) L.rng[k] = c.take<int64_t>(size_t(nm));
+    L.off = c.take<int64_t>(size_t(nm));
+    L.counters = c.take<int64_t>(4);
+    const int64_t tl = ceil_div(nl > 0 ? nl : 1, kJoinTile);
+    const int64_t tr = ceil_div(nr > 0 ? nr : 1, kJoinTile);
+    const int64_t tm = ceil_div(nl > 0 ? nl : 1, kMatchTile);
+    L.nwords = 4 + tl + tr + 2 * tm;
+    L.words = c.take<uint64_t>(size_t(L.nwords));
+    if (L.words) {
+        L.stL = L.words + 4;
+        L.stR = L.stL + tl;
+        L.stM = L.stR + tr;
+        L.stP = L.stM + tm;
+    }
+    L.bytes = c.bytes();
+    return L;
+}
+
+template <class K>
+static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
+                      const tqp_col *rkey, const int32_t *rrows, const int64_t *d_nr,
+                      uint32_t flags, int32_t *out_l, int32_t *out_r, void *out_pair_key,
+                      int64_t cap, int64_t *d_count, const tqp_ranges *ranges, int64_t range_cap,
+                      int64_t *d_nranges, void *ws, hipStream_t s) {
+    const int64_t nl = lkey->len, nr = rkey->len;
+    JoinLayout L = join_layout(ws, nl, nr, lkey->dtype, flags);
+    const K *lk = static_cast<const K *>(lkey->data);
+    const K *rk = static_cast<const K *>(rkey->data);
+    int rc;
+    if (!(flags & TQP_JOIN_SORTED)) {
+        int64_t kmin;
+        int kbits;
+        rc = derive_key_range(lk, lkey->dtype, nl, d_nl, L.sort_ws, s, &kmin, &kbits);
+        if (rc) return rc;
+        rc = sort_impl(lk, lkey->dtype, lrows, nl, d_nl, kbits, kmin, L.sl_key, L.sl_rows,
+                       L.sort_ws, L.sort_ws_bytes, s);
+        if (rc) return rc;
+        rc = derive_key_range(rk, rkey->dtype, nr, d_nr, L.sort_ws, s, &kmin, &kbits);
+        if (rc) return rc;
+        rc = sort_impl(rk, rkey->dtype, rrows, nr, d_nr, kbits, kmin, L.sr_key, L.sr_rows,
+                       L.sort_ws, L.sort_ws_bytes, s);
+        if (rc) return rc;
+        lk = static_cast<const K *>(L.sl_key);
+        rk = static_cast<const K *>(L.sr_key);
+        lrows = L.sl_rows;
+        rrows = L.sr_rows;
+    }
+    rc = fill_u64(L.words, 0, L.nwords, s);
+    if (rc) return rc;
+    uint32_t *tickets = reinterpret_cast<uint32_t *>(L.words);
+    const unsigned gl = unsigned(ceil_div(nl > 0 ? nl : 1, kJoinTile));
+    const unsigned gr = unsigned(ceil_div(nr > 0 ? nr : 1, kJoinTile));
+    hipLaunchKernelGGL(k_rle<K>, dim3(gl), dim3(kJoinNT), 0, s, lk, nl, d_nl,
+                       static_cast<K *>(L.uL), L.sL, &L.counters[0], tickets + 0, L.stL);
+    if ((rc = check_launch("join rle left"))) return rc;
+    hipLaunchKernelGGL(k_rle<K>, dim3(gr), dim3(kJoinNT), 0, s, rk, nr, d_nr,
+                       static_cast<K *>(L.uR), L.sR, &L.counters[1], tickets + 2, L.stR);
+    if ((rc = check_launch("join rle right"))) return rc;
+    MatchArgs a = {};
+    a.uL = L.uL;
+    a.sL = L.sL;
+    a.d_nuL = &L.counters[0];
+    a.d_nl = d_nl;
+    a.nl = nl;
+    a.uR = L.uR;
+    a.sR = L.sR;
+    a.d_nuR = &L.counters[1];
+    a.d_nr = d_nr;
+    a.nr = nr;
+    a.rkey = L.rng[0];
+    a.rls = L.rng[1];
+    a.rlc = L.rng[2];
+    a.rrs = L.rng[3];
+    a.rrc = L.rng[4];
+    a.off = L.off;
+    if (flags & TQP_JOIN_RANGES) {
+        a.ukey = ranges->key;
+        a.uls = ranges->lstart;
+        a.ulc = ranges->lcnt;
+        a.urs = ranges->rstart;
+        a.urc = ranges->rcnt;
+        a.ucap = range_cap;
+        a.d_nranges_user = d_nranges;
+    }
+    a.d_nranges_ws = &L.counters[2];
+    a.d_count = d_count;
+    a.ticket = tickets + 4;
+    a.status_m = L.stM;
+    a.status_p = L.stP;
+    const unsigned gm = unsigned(ceil_div(nl > 0 ? nl : 1, kMatchTile));
+    hipLaunchKernelGGL(k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
+    if ((rc = check_launch("join match"))) return rc;
+    if ((out_l || out_r || out_pair_key) && cap > 0) {
+        int64_t g = ceil_div(cap, int64_t(kJoinNT) * kExpandPer);
+        if (g > 65536) g = 65536;
+        hipLaunchKernelGGL(k_join_expand<K>, dim3(unsigned(g)), dim3(kJoinNT), 0, s, L.rng[0],
+                           L.rng[1], L.rng[2], L.rng[3], L.rng[4], L.off, &L.counters[2], d_count,
+                           cap, lrows, rrows, out_l, out_r, static_cast<K *>(out_pair_key));
+        if ((rc = check_launch("join expand"))) return rc;
+    }
+    return TQP_OK;
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+TQP_API size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags) {
+    if (nl < 0 || nr < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64)) return 0;
+    return join_layout(nullptr, nl, nr, dtype, flags).bytes;
+}
+
+TQP_API int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
+                     const tqp_col *rkey, const int32_t *rrows, const int64_t *d_nr,
+                     uint32_t flags, int32_t *out_l, int32_t *out_r, void *out_pair_key,
+                     int64_t cap, int64_t *d_count, const tqp_ranges *ranges, int64_t range_cap,
+                     int64_t *d_nranges, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!lkey || !rkey || !d_count) return set_error(TQP_EINVAL, "tqp_join: null argument");
+    if (lkey->dtype != rkey->dtype || (lkey->dtype != TQP_INT32 && lkey->dtype != TQP_INT64))
+        return set_error(TQP_EINVAL, "tqp_join: keys must share dtype int32 or int64");
+    if (flags & ~(TQP_JOIN_SORTED | TQP_JOIN_RANGES))
+        return set_error(TQP_EINVAL, "tqp_join: unknown flag bits");
+    const int64_t nl = lkey->len, nr = rkey->len;
+    if (nl < 0 || nr < 0 || nl > (int64_t(1) << 30) - 1 || nr > (int64_t(1) << 30) - 1)
+        return set_error(TQP_EINVAL, "tqp_join: sides must hold [0, 2^30 - 1] rows");
+    if ((nl > 0 && !lkey->data) || (nr > 0 && !rkey->data))
+        return set_error(TQP_EINVAL, "tqp_join: null key data");
+    if (cap < 0) return set_error(TQP_EINVAL, "tqp_join: negative cap");
+    if ((flags & TQP_JOIN_RANGES) &&
+        (!ranges || !d_nranges || range_cap < 0 ||
+         (range_cap > 0 && (!ranges->key || !ranges->lstart || !ranges->lcnt || !ranges->rstart ||
+                            !ranges->rcnt))))
+        return set_error(TQP_EINVAL, "tqp_join: ranges mode needs five arrays and d_nranges");
+    const size_t need = tqp_join_workspace_bytes(nl, nr, lkey->dtype, flags);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_join: workspace needs %zu bytes", need);
+    hipStream_t s = as_stream(stream);
+    if (lkey->dtype == TQP_INT32)
+        return join_typed<int32_t>(lkey, lrows, d_nl, rkey, rrows, d_nr, flags, out_l, out_r,
+                                   out_pair_key, cap, d_count, ranges, range_cap, d_nranges, ws, s);
+    return join_typed<int64_t>(lkey, lrows, d_nl, rkey, rrows, d_nr, flags, out_l, out_r,
+                               out_pair_key, cap, d_count, ranges, range_cap, d_nranges, ws, s);
+}

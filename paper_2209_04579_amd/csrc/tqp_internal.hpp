@@ -1,0 +1,237 @@
+// Internal helpers shared by the libtqp translation units: error reporting,
+// launch checks, wave64 primitives and the decoupled look-back used by every
+// single-pass scan (filter compaction, run-length encoding, join offsets,
+// group-by prefix sums, radix scatter).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "tqp.h"
+
+#define TQP_API extern "C" __attribute__((visibility("default")))
+
+namespace tqp {
+
+constexpr int kWave = 64;
+
+// ---- host side ---------------------------------------------------------
+
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+// Reports a failed launch (hipGetLastError) as TQP_EHIP.
+int check_launch(const char *what);
+int dtype_size(int dtype);
+bool dtype_ok(int dtype);
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Carves aligned sub-buffers out of a caller-provided workspace.  With a null
+// base it only measures.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T> T *take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (used + 255) & ~size_t(255); }
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Enqueues a fill of `count` 64-bit words (a kernel, not a memset node, so
+// that captured graphs replay it faithfully).
+int fill_u64(void *dst, uint64_t value, int64_t count, hipStream_t s);
+int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s);
+
+// Device-side min / max of a key column over min(*d_n, n) entries, written to
+// out[0] = min, out[1] = max (int64).
+int launch_minmax(const void *key, int dtype, int64_t n, const int64_t *d_n,
+                  int64_t *out, hipStream_t s);
+
+// Internal entry used by join and group-by: LSD radix sort with known range.
+int sort_impl(const void *key_in, int dtype, const int32_t *rows_in, int64_t n,
+              const int64_t *d_n, int key_bits, int64_t key_min, void *key_out,
+              int32_t *rows_out, void *ws, size_t ws_bytes, hipStream_t s);
+size_t sort_ws_bytes(int64_t n, int dtype, int key_bits);
+// Host-synchronizing derivation of (key_min, key_bits) for a column.
+int derive_key_range(const void *key, int dtype, int64_t n, const int64_t *d_n,
+                     void *scratch16, hipStream_t s, int64_t *key_min, int *key_bits);
+
+// ---- device side --------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int64_t count_of(const int64_t *d_n, int64_t n) {
+    if (d_n) {
+        int64_t v = *d_n;
+        return v < n ? (v < 0 ? 0 : v) : n;
+    }
+    return n;
+}
+
+template <class T> __device__ __forceinline__ T shfl_up(T v, int d) {
+    return __shfl_up(v, d, kWave);
+}
+template <> __device__ __forceinline__ int64_t shfl_up<int64_t>(int64_t v, int d) {
+    int lo = __shfl_up(static_cast<int>(v & 0xffffffff), d, kWave);
+    int hi = __shfl_up(static_cast<int>(v >> 32), d, kWave);
+    return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+}
+template <> __device__ __forceinline__ uint64_t shfl_up<uint64_t>(uint64_t v, int d) {
+    return static_cast<uint64_t>(shfl_up<int64_t>(static_cast<int64_t>(v), d));
+}
+template <class T> __device__ __forceinline__ T shfl_xor(T v, int m) {
+    return __shfl_xor(v, m, kWave);
+}
+template <> __device__ __forceinline__ int64_t shfl_xor<int64_t>(int64_t v, int m) {
+    int lo = __shfl_xor(static_cast<int>(v & 0xffffffff), m, kWave);
+    int hi = __shfl_xor(static_cast<int>(v >> 32), m, kWave);
+    return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+}
+template <class T> __device__ __forceinline__ T shfl(T v, int src) {
+    return __shfl(v, src, kWave);
+}
+template <> __device__ __forceinline__ int64_t shfl<int64_t>(int64_t v, int src) {
+    int lo = __shfl(static_cast<int>(v & 0xffffffff), src, kWave);
+    int hi = __shfl(static_cast<int>(v >> 32), src, kWave);
+    return (static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo);
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (wrapping arithmetic).
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = shfl_up(v, d);
+        if (lane_id() >= d) v += u;
+    }
+    return v;
+}
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += shfl_xor(v, m);
+    return v;
+}
+
+// Exclusive prefix sum across a block of NT threads.  `lds` holds NT/64
+// entries of T.  Returns the exclusive prefix; *total receives the block sum.
+template <int NT, class T>
+__device__ __forceinline__ T block_excl_scan(T v, T *total, T *lds) {
+    constexpr int NW = NT / kWave;
+    T inc = wave_incl_scan(v);
+    const int w = wave_id();
+    if (lane_id() == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+        T x = lds[i];
+        if (i < w) pre += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+// ---- agent-scope atomics ------------------------------------------------
+
+template <class T> __device__ __forceinline__ T ld_acquire(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ T ld_relaxed(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ void st_release(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ void st_relaxed(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Dynamic tile id: tiles are handed out in launch order, so every tile's
+// predecessors belong to workgroups that are already running.  That is what
+// lets a look-back wait on them without deadlock.
+__device__ __forceinline__ int64_t take_tile(uint32_t *ticket, int64_t *lds_slot) {
+    if (threadIdx.x == 0) *lds_slot = atomicAdd(ticket, 1u);
+    __syncthreads();
+    return *lds_slot;
+}
+
+// ---- decoupled look-back over one non-negative count -----------------------
+// status[t] = flag << 62 | value, flag 0 = not ready, 1 = tile aggregate,
+// 2 = inclusive prefix.  Called by all 64 lanes of one wave of tile `tile`
+// with the tile aggregate `agg` (< 2^62).  Returns the exclusive prefix of
+// the tile; publishes the inclusive prefix.
+constexpr uint64_t kFlagAgg = uint64_t(1) << 62;
+constexpr uint64_t kFlagInc = uint64_t(2) << 62;
+constexpr uint64_t kValMask = (uint64_t(1) << 62) - 1;
+
+__device__ __forceinline__ int64_t lookback_count(uint64_t *status, int64_t tile,
+                                                  int64_t agg) {
+    if (tile == 0) {
+        if (lane_id() == 0) st_relaxed(&status[0], kFlagInc | uint64_t(agg));
+        return 0;
+    }
+    if (lane_id() == 0) st_relaxed(&status[tile], kFlagAgg | uint64_t(agg));
+    int64_t excl = 0;
+    int64_t base = tile - 1;
+    while (true) {
+        const int64_t idx = base - lane_id();
+        uint64_t s = kFlagInc;
+        if (idx >= 0) {
+            s = ld_relaxed(&status[idx]);
+            while ((s >> 62) == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                s = ld_relaxed(&status[idx]);
+            }
+        }
+        const uint64_t inc = ballot((s >> 62) == 2);
+        const int stop = inc ? (__ffsll(static_cast<long long>(inc)) - 1) : (kWave - 1);
+        int64_t v = lane_id() <= stop ? int64_t(s & kValMask) : 0;
+        excl += wave_sum(v);
+        if (inc) break;
+        base -= kWave;
+    }
+    if (lane_id() == 0) st_relaxed(&status[tile], kFlagInc | uint64_t(excl + agg));
+    return excl;
+}
+
+// ---- key/value element access ------------------------------------------------
+
+template <class T> struct KeyTraits;
+template <> struct KeyTraits<int32_t> {
+    using U = uint32_t;
+    static constexpr int kBits = 32;
+};
+template <> struct KeyTraits<int64_t> {
+    using U = uint64_t;
+    static constexpr int kBits = 64;
+};
+
+__device__ __forceinline__ int64_t load_any(const void *p, int dtype, int64_t i) {
+    switch (dtype) {
+    case TQP_INT8: return static_cast<const int8_t *>(p)[i];
+    case TQP_INT32: return static_cast<const int32_t *>(p)[i];
+    default: return static_cast<const int64_t *>(p)[i];
+    }
+}
+__device__ __forceinline__ void store_any(void *p, int dtype, int64_t i, int64_t v) {
+    switch (dtype) {
+    case TQP_INT8: static_cast<int8_t *>(p)[i] = static_cast<int8_t>(v); break;
+    case TQP_INT32: static_cast<int32_t *>(p)[i] = static_cast<int32_t>(v); break;
+    default: static_cast<int64_t *>(p)[i] = v; break;
+    }
+}
+
+}  // namespace tqp

@@ -1,0 +1,265 @@
+"""GPU parity: every operator through the C ABI against the CPU oracle, bit
+for bit, on seeded inputs spanning several tiles, ragged tails and the edge
+cases of each operator (empty input, one row, all / no rows kept, one key,
+all keys distinct, extreme values, skew)."""
+import numpy as np
+import pytest
+
+import oracle
+import tqp_datagen as dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 63, 64, 65, 4095, 4096, 4097, 12_289, 100_003]
+I32 = np.iinfo(np.int32)
+I64 = np.iinfo(np.int64)
+
+
+@pytest.fixture(scope="module")
+def tqp():
+    import paper_2209_04579_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+# ----------------------------------------------------------------- filter ----
+
+@pytest.mark.parametrize("n", SIZES)
+def test_filter_single_predicate(tqp, n):
+    day = dg.uniform_int(n, 3, n, 0, dg.DAY_DOMAIN, np.int32)
+    qty = dg.uniform_int(n, 2, n, 1, 5001, np.int64)
+    rows, (q,) = tqp.filter([dev(day)], [(0, "<", 1278)], payload=[dev(qty)])
+    want = oracle.filter_rows([day], [(0, "<", 1278)])
+    assert np.array_equal(host(rows), want)
+    assert np.array_equal(host(q), oracle.gather(qty, want))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_conjunction_mixed_dtypes(tqp, seed):
+    n = 50_000 + 777 * seed
+    cols = [dg.uniform_int(seed, 1, n, -100, 100, np.int8),
+            dg.uniform_int(seed, 2, n, -1000, 1000, np.int32),
+            dg.uniform_int(seed, 3, n, -10 ** 6, 10 ** 6, np.int64)]
+    preds = [(0, ">=", -50 + seed), (1, "<", 500), (2, "!=", int(cols[2][7])), (0, "<=", 90),
+             (1, ">", -900 + seed)]
+    rows, pay = tqp.filter([dev(c) for c in cols], preds, payload=[dev(c) for c in cols])
+    want = oracle.filter_rows(cols, preds)
+    assert np.array_equal(host(rows), want)
+    for c, p in zip(cols, pay):
+        assert np.array_equal(host(p), oracle.gather(c, want))
+
+
+def test_filter_all_none_and_extremes(tqp):
+    x = np.array([I32.min, -1, 0, 1, I32.max] * 1000, np.int32)
+    for preds in ([(0, ">=", I32.min)], [(0, "<", I32.min)], [(0, ">", 2 ** 40)],
+                  [(0, "==", I32.max)], [(0, "<=", -(2 ** 40))]):
+        rows, _ = tqp.filter([dev(x)], preds)
+        assert np.array_equal(host(rows), oracle.filter_rows([x], preds)), preds
+    y = np.array([I64.min, I64.max, 0] * 3000, np.int64)
+    rows, _ = tqp.filter([dev(y)], [(0, "<", I64.max)])
+    assert np.array_equal(host(rows), oracle.filter_rows([y], [(0, "<", I64.max)]))
+
+
+def test_filter_is_deterministic_across_runs(tqp):
+    n = 3_000_000
+    day = dev(dg.uniform_int(11, 3, n, 0, dg.DAY_DOMAIN, np.int32))
+    a, _ = tqp.filter([day], [(0, "<", 1278)])
+    b, _ = tqp.filter([day], [(0, "<", 1278)])
+    assert torch.equal(a, b)
+    assert np.array_equal(host(a), np.nonzero(host(day) < 1278)[0].astype(np.int32))
+
+
+# ----------------------------------------------------------------- gather ----
+
+@pytest.mark.parametrize("dtype", [np.int8, np.int32, np.int64])
+def test_gather(tqp, dtype):
+    src = dg.uniform_int(1, 1, 70_001, -100, 100, dtype)
+    idx = dg.uniform_int(1, 2, 33_333, 0, 70_001, np.int32)
+    assert np.array_equal(host(tqp.gather(dev(src), dev(idx))), oracle.gather(src, idx))
+
+
+def test_pack_key(tqp):
+    n = 10_007
+    flag = dg.uniform_int(2, 1, n, 0, 3, np.int8)
+    cat = dg.uniform_int(2, 2, 5000, -30, 30, np.int32)
+    rows = dg.uniform_int(2, 3, n, 0, 5000, np.int32)
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    tqp.pack_key_into([(dev(flag), None, 0, 2), (dev(cat), dev(rows), 2, 1)], n, out)
+    want = flag.astype(np.int64) * 2 + np.mod(cat[rows], 2)
+    assert np.array_equal(host(out), want)
+
+
+# ------------------------------------------------------------------- sort ----
+
+def sort_case(n, dtype, kind, seed=0):
+    if kind == "dup":
+        return dg.uniform_int(seed, 1, n, -3, 4, dtype)
+    if kind == "dom":
+        return dg.uniform_int(seed, 1, n, 0, 10_000, dtype)
+    if kind == "neg":
+        return dg.uniform_int(seed, 1, n, -(2 ** 31), 2 ** 31 - 1, np.int64).astype(dtype)
+    if kind == "full":
+        u = dg.raw_u64(seed, 1, n).view(np.int64)
+        k = u if dtype == np.int64 else (u >> 32).astype(np.int32)
+        k = k.astype(dtype)
+        info = np.iinfo(dtype)
+        k[: min(n, 4)] = [info.min, info.max, 0, -1][: min(n, 4)]
+        return k
+    if kind == "zipf":
+        return (dg.zipf_ranks(seed, 1, n, 2_000_000, 1.0) - 1).astype(dtype)
+    if kind == "const":
+        return np.full(n, 42, dtype)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("kind", ["dup", "dom", "neg", "full", "zipf", "const"])
+@pytest.mark.parametrize("n", [0, 1, 65, 4096, 4097, 100_003])
+def test_sort_matches_oracle(tqp, dtype, kind, n):
+    keys = sort_case(n, dtype, kind)
+    sk, perm = tqp.sort(dev(keys))
+    ok, operm = oracle.sort(keys)
+    assert np.array_equal(host(perm), operm)
+    assert np.array_equal(host(sk), ok)
+
+
+def test_sort_carries_rows_and_explicit_bits(tqp):
+    n = 1_000_003
+    keys = dg.uniform_int(5, 1, n, 1000, 1000 + 2 ** 21, np.int32)
+    rows = dg.uniform_int(5, 2, n, 0, 2 ** 31 - 1, np.int32)
+    sk, r = tqp.sort(dev(keys), in_rows=dev(rows), key_bits=21, key_min=1000)
+    ok, perm = oracle.sort(keys)
+    assert np.array_equal(host(sk), ok)
+    assert np.array_equal(host(r), rows[perm])
+
+
+def test_sort_large_zipf_is_deterministic(tqp):
+    n = 30_000_000
+    keys = dev(sort_case(n, np.int32, "zipf", seed=3))
+    a = tqp.sort(keys, key_bits=21, key_min=0)
+    b = tqp.sort(keys, key_bits=21, key_min=0)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    want = np.argsort(host(keys), kind="stable").astype(np.int32)
+    assert np.array_equal(host(a[1]), want)
+
+
+# ------------------------------------------------------------------- join ----
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("nl,nr,dom", [(0, 10, 5), (10, 0, 5), (1, 1, 1), (5000, 3000, 1),
+                                       (5000, 3000, 7), (20_000, 7_000, 5000),
+                                       (100_003, 4097, 10 ** 6), (4096, 4096, 4096)])
+def test_join_pairs_match_oracle(tqp, dtype, nl, nr, dom):
+    lk = dg.uniform_int(nl + 1, 1, nl, -dom // 2, dom - dom // 2, dtype) if nl else np.zeros(0, dtype)
+    rk = dg.uniform_int(nr + 2, 2, nr, -dom // 2, dom - dom // 2, dtype) if nr else np.zeros(0, dtype)
+    cnt, ol, orr = oracle.join(lk, rk)
+    if cnt > 30_000_000:
+        pytest.skip("pair count too large for this test")
+    gl, gr, gk = tqp.join(dev(lk), dev(rk), cap=cnt, with_key=True)
+    assert gl.numel() == cnt
+    assert np.array_equal(host(gl), ol)
+    assert np.array_equal(host(gr), orr)
+    assert np.array_equal(host(gk), lk[ol])
+
+
+def test_join_extreme_and_disjoint_keys(tqp):
+    e = np.array([I64.min, I64.max, 0, I64.min, -1], np.int64)
+    cnt, ol, orr = oracle.join(e, e)
+    gl, gr = tqp.join(dev(e), dev(e))
+    assert np.array_equal(host(gl), ol) and np.array_equal(host(gr), orr)
+    a = np.arange(0, 10_000, 2, dtype=np.int32)
+    b = np.arange(1, 10_001, 2, dtype=np.int32)
+    gl, gr = tqp.join(dev(a), dev(b))
+    assert gl.numel() == 0
+
+
+def test_join_capacity_overflow_reports_count(tqp):
+    k = np.zeros(300, np.int32)
+    gl, gr = tqp.join(dev(k), dev(k), cap=1000)          # 90_000 pairs: retried
+    assert gl.numel() == 90_000
+    assert np.array_equal(host(gl), np.repeat(np.arange(300, dtype=np.int32), 300))
+
+
+def test_join_sorted_inputs_with_row_maps(tqp):
+    lk = dg.uniform_int(8, 1, 50_000, 0, 3000, np.int32)
+    rk = dg.uniform_int(8, 2, 9_000, 0, 3000, np.int32)
+    sl, pl = oracle.sort(lk)
+    sr, pr = oracle.sort(rk)
+    cnt, ol, orr = oracle.join(lk, rk)
+    gl, gr = tqp.join(dev(sl), dev(sr), lrows=dev(pl), rrows=dev(pr), sorted_inputs=True, cap=cnt)
+    assert np.array_equal(host(gl), ol) and np.array_equal(host(gr), orr)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_join_ranges_match_oracle(tqp, dtype):
+    lk = np.sort(dg.uniform_int(4, 1, 200_000, -5000, 5000, dtype))
+    rk = np.sort(dg.uniform_int(4, 2, 30_000, -2000, 9000, dtype))
+    want = oracle.join_ranges(lk, rk)
+    got = tqp.join_ranges(dev(lk), dev(rk))
+    for k in ("key", "lstart", "lcnt", "rstart", "rcnt"):
+        assert np.array_equal(host(got[k]), want[k]), k
+    assert got["total"] == want["total"]
+
+
+# --------------------------------------------------------------- group-by ----
+
+AGGS = [("sum", 0), ("count",), ("sum_product", 0, 1), ("sum", 1)]
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 100_003])
+@pytest.mark.parametrize("dom", [1, 6, 5000, 10 ** 7])
+def test_groupby_sort_path(tqp, dtype, n, dom):
+    keys = dg.uniform_int(n + dom, 1, n, -dom // 3, dom - dom // 3, dtype)
+    a = dg.uniform_int(n, 2, n, 1, 5001, np.int64)
+    b = dg.uniform_int(n, 3, n, -10 ** 7, 10 ** 7, np.int32)
+    uk, aggs = tqp.groupby_agg(dev(keys), [dev(a), dev(b)], AGGS)
+    wk, wa, _ = oracle.groupby(keys, [a, b], AGGS)
+    assert np.array_equal(host(uk).astype(np.int64), wk)
+    for g, w in zip(aggs, wa):
+        assert np.array_equal(host(g), w)
+
+
+@pytest.mark.parametrize("n", [0, 1, 100_003, 2_000_000])
+@pytest.mark.parametrize("span", [1, 6, 25, 125, 1024])
+def test_groupby_dense_path(tqp, n, span):
+    lo = -7
+    keys = dg.uniform_int(n + span, 1, n, lo, lo + span, np.int64)
+    a = dg.uniform_int(n, 2, n, 1, 5001, np.int64)
+    b = dg.uniform_int(n, 3, n, 100, 10 ** 7, np.int64)
+    uk, aggs = tqp.groupby_agg(dev(keys), [dev(a), dev(b)], AGGS[:3], flags=tqp.GB_DENSE,
+                               key_lo=lo, key_span=span)
+    wk, wa, _ = oracle.groupby(keys, [a, b], AGGS[:3])
+    assert np.array_equal(host(uk), wk)
+    for g, w in zip(aggs, wa):
+        assert np.array_equal(host(g), w)
+
+
+def test_groupby_sorted_flag_and_val_rows(tqp):
+    n = 300_000
+    keys = np.sort(dg.zipf_ranks(9, 1, n, 50_000, 1.0).astype(np.int32))
+    vals = dg.uniform_int(9, 2, 1_000_000, 1, 5001, np.int64)
+    rows = dg.uniform_int(9, 3, n, 0, 1_000_000, np.int32)
+    uk, (s, c) = tqp.groupby_agg(dev(keys), [dev(vals)], [("sum", 0), ("count",)],
+                                 flags=tqp.GB_SORTED, val_rows=dev(rows))
+    wk, (ws, wc), _ = oracle.groupby(keys, [vals[rows]], [("sum", 0), ("count",)])
+    assert np.array_equal(host(uk), wk) and np.array_equal(host(s), ws)
+    assert np.array_equal(host(c), wc)
+
+
+def test_groupby_wraps_modulo_2_64(tqp):
+    keys = np.zeros(10_000, np.int64)
+    vals = np.full(10_000, I64.max, np.int64)
+    uk, (s,) = tqp.groupby_agg(dev(keys), [dev(vals)], [("sum", 0)])
+    wk, (w,), ovf = oracle.groupby(keys, [vals], [("sum", 0)])
+    assert ovf and np.array_equal(host(s), w)
