@@ -98,6 +98,16 @@ const char *tqp_last_error(void);
 /* Library version string. */
 const char *tqp_version(void);
 
+/* Per-kernel timing, off by default.  While enabled, every kernel the library
+ * enqueues is bracketed by two HIP events on its stream.  tqp_profile_collect
+ * waits for the pending events, accumulates them and writes one line per
+ * kernel name, "name launches total_ms\n", into buf (HOST memory, truncated to
+ * len); it returns the length the full text needs, including the final NUL.
+ * tqp_profile_reset drops all pending and accumulated timings. */
+void tqp_profile_enable(int on);
+int tqp_profile_collect(char *buf, size_t len);
+void tqp_profile_reset(void);
+
 /* ------------------------------------------------------------------------
  * tqp_filter -- WHERE with stream compaction (Section 2.3: Q6's filters).
  * Keeps row i of an n-row table when every predicate holds; n = cols[0].len

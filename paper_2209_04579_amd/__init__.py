@@ -109,6 +109,12 @@ def lib():
                                P(Ranges), i64, vp, vp, sz, vp]
         L.tqp_groupby_workspace_bytes.restype = sz
         L.tqp_groupby_workspace_bytes.argtypes = [i64, i32, i32, u32, i64]
+        L.tqp_profile_enable.restype = None
+        L.tqp_profile_enable.argtypes = [i32]
+        L.tqp_profile_collect.restype = i32
+        L.tqp_profile_collect.argtypes = [ctypes.c_char_p, sz]
+        L.tqp_profile_reset.restype = None
+        L.tqp_profile_reset.argtypes = []
         L.tqp_groupby_agg.restype = i32
         L.tqp_groupby_agg.argtypes = [P(Col), vp, u32, i64, i64, P(Col), i32, vp, P(Agg), i32,
                                       P(Col), P(vp), vp, vp, sz, vp]
@@ -323,3 +329,27 @@ def groupby_agg(key, vals, aggs, flags=0, key_lo=0, key_span=0, val_rows=None, c
                      key_span=key_span, val_rows=val_rows)
     g = int(ng.item())
     return ok[:g], [o[:g] for o in outs]
+
+
+# -------------------------------------------------------------- profiling ----
+
+def profile_enable(on: bool = True):
+    """Brackets every library kernel launch with HIP events (see tqp.h)."""
+    lib().tqp_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().tqp_profile_reset()
+
+
+def profile_collect() -> dict:
+    """{kernel name: (launches, total ms)} accumulated since the last reset."""
+    L = lib()
+    need = L.tqp_profile_collect(None, 0)
+    buf = ctypes.create_string_buffer(need + 64)
+    L.tqp_profile_collect(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

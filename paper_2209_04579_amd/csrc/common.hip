@@ -53,7 +53,7 @@ int fill_u64(void *dst, uint64_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return TQP_OK;
     int64_t blocks = ceil_div(count, 256);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_u64, dim3(unsigned(blocks)), dim3(256), 0, s,
+    TQP_LAUNCH("fill_u64", k_fill_u64, dim3(unsigned(blocks)), dim3(256), 0, s,
                        static_cast<uint64_t *>(dst), value, count);
     return check_launch("fill_u64");
 }
@@ -62,7 +62,7 @@ int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s) {
     if (count <= 0) return TQP_OK;
     int64_t blocks = ceil_div(count, 256);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(blocks)), dim3(256), 0, s,
+    TQP_LAUNCH("fill_u32", k_fill_u32, dim3(unsigned(blocks)), dim3(256), 0, s,
                        static_cast<uint32_t *>(dst), value, count);
     return check_launch("fill_u32");
 }
@@ -109,10 +109,10 @@ int launch_minmax(const void *key, int dtype, int64_t n, const int64_t *d_n,
     int64_t blocks = ceil_div(n, 256 * 16);
     if (blocks > 2048) blocks = 2048;
     if (dtype == TQP_INT32)
-        hipLaunchKernelGGL(k_minmax<int32_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
+        TQP_LAUNCH("minmax", k_minmax<int32_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
                            static_cast<const int32_t *>(key), n, d_n, out);
     else
-        hipLaunchKernelGGL(k_minmax<int64_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
+        TQP_LAUNCH("minmax", k_minmax<int64_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
                            static_cast<const int64_t *>(key), n, d_n, out);
     return check_launch("minmax");
 }

@@ -216,6 +216,6 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
     a.ticket = reinterpret_cast<uint32_t *>(words);
     a.status = words + 1;
     const unsigned grid = unsigned(ntiles > 0 ? ntiles : 1);
-    hipLaunchKernelGGL(k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
+    TQP_LAUNCH("filter", k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
     return check_launch("tqp_filter");
 }

@@ -86,17 +86,17 @@ TQP_API int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n, const 
     const unsigned g = grid_for(n, 4);
     switch (src->dtype) {
     case TQP_INT8:
-        hipLaunchKernelGGL(k_gather<int8_t>, dim3(g), dim3(kGatherNT), 0, s,
+        TQP_LAUNCH("gather", k_gather<int8_t>, dim3(g), dim3(kGatherNT), 0, s,
                            static_cast<const int8_t *>(src->data), src->len, idx, n, d_n,
                            static_cast<int8_t *>(dst->data));
         break;
     case TQP_INT32:
-        hipLaunchKernelGGL(k_gather<int32_t>, dim3(g), dim3(kGatherNT), 0, s,
+        TQP_LAUNCH("gather", k_gather<int32_t>, dim3(g), dim3(kGatherNT), 0, s,
                            static_cast<const int32_t *>(src->data), src->len, idx, n, d_n,
                            static_cast<int32_t *>(dst->data));
         break;
     default:
-        hipLaunchKernelGGL(k_gather<int64_t>, dim3(g), dim3(kGatherNT), 0, s,
+        TQP_LAUNCH("gather", k_gather<int64_t>, dim3(g), dim3(kGatherNT), 0, s,
                            static_cast<const int64_t *>(src->data), src->len, idx, n, d_n,
                            static_cast<int64_t *>(dst->data));
         break;
@@ -126,7 +126,7 @@ TQP_API int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n, const 
     }
     a.nterms = nterms;
     if (n == 0) return TQP_OK;
-    hipLaunchKernelGGL(k_pack_key, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, as_stream(stream),
+    TQP_LAUNCH("pack_key", k_pack_key, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, as_stream(stream),
                        a, n, d_n, out);
     return check_launch("tqp_pack_key");
 }

@@ -319,12 +319,12 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
             int64_t g = ceil_div(n, int64_t(kGbNT) * 64);
             if (g > 2048) g = 2048;
             const size_t lds = size_t(nagg + 1) * key_span * 8;
-            hipLaunchKernelGGL(k_gb_dense<K>, dim3(unsigned(g)), dim3(kGbNT), lds, s,
+            TQP_LAUNCH("gb_dense", k_gb_dense<K>, dim3(unsigned(g)), dim3(kGbNT), lds, s,
                                static_cast<const K *>(key->data), n, d_n, key_lo, key_span, args,
                                L.gacc);
             if ((rc = check_launch("group-by dense"))) return rc;
         }
-        hipLaunchKernelGGL(k_gb_dense_emit<K>, dim3(1), dim3(1024), 0, s, L.gacc, key_lo, key_span,
+        TQP_LAUNCH("gb_dense_emit", k_gb_dense_emit<K>, dim3(1), dim3(1024), 0, s, L.gacc, key_lo, key_span,
                            nagg, static_cast<K *>(out_key->data), out_key->len, o[0], o[1], o[2],
                            o[3], d_ngroups);
         return check_launch("group-by dense emit");
@@ -349,13 +349,13 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
     rc = fill_u32(L.words, 0, 2 + L.ntiles, s);
     if (rc) return rc;
     const unsigned grid = unsigned(L.ntiles);
-    hipLaunchKernelGGL(k_gb_scan<K>, dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a,
+    TQP_LAUNCH("gb_scan", k_gb_scan<K>, dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a,
                        static_cast<K *>(out_key->data), out_key->len, L.ends,
                        n > 0 ? n : int64_t(1), d_ngroups, L.words, L.words + 2, L.aggv, L.incv);
     if ((rc = check_launch("group-by scan"))) return rc;
     int64_t g = ceil_div(out_key->len > 0 ? out_key->len : 1, 256);
     if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_gb_diff, dim3(unsigned(g)), dim3(256), 0, s, L.ends,
+    TQP_LAUNCH("gb_diff", k_gb_diff, dim3(unsigned(g)), dim3(256), 0, s, L.ends,
                        n > 0 ? n : int64_t(1), nagg, d_ngroups, out_key->len, o[0], o[1], o[2],
                        o[3]);
     return check_launch("group-by diff");

@@ -347,10 +347,10 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     uint32_t *tickets = reinterpret_cast<uint32_t *>(L.words);
     const unsigned gl = unsigned(ceil_div(nl > 0 ? nl : 1, kJoinTile));
     const unsigned gr = unsigned(ceil_div(nr > 0 ? nr : 1, kJoinTile));
-    hipLaunchKernelGGL(k_rle<K>, dim3(gl), dim3(kJoinNT), 0, s, lk, nl, d_nl,
+    TQP_LAUNCH("rle", k_rle<K>, dim3(gl), dim3(kJoinNT), 0, s, lk, nl, d_nl,
                        static_cast<K *>(L.uL), L.sL, &L.counters[0], tickets + 0, L.stL);
     if ((rc = check_launch("join rle left"))) return rc;
-    hipLaunchKernelGGL(k_rle<K>, dim3(gr), dim3(kJoinNT), 0, s, rk, nr, d_nr,
+    TQP_LAUNCH("rle", k_rle<K>, dim3(gr), dim3(kJoinNT), 0, s, rk, nr, d_nr,
                        static_cast<K *>(L.uR), L.sR, &L.counters[1], tickets + 2, L.stR);
     if ((rc = check_launch("join rle right"))) return rc;
     MatchArgs a = {};
@@ -385,12 +385,12 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     a.status_m = L.stM;
     a.status_p = L.stP;
     const unsigned gm = unsigned(ceil_div(nl > 0 ? nl : 1, kMatchTile));
-    hipLaunchKernelGGL(k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
+    TQP_LAUNCH("join_match", k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
     if ((rc = check_launch("join match"))) return rc;
     if ((out_l || out_r || out_pair_key) && cap > 0) {
         int64_t g = ceil_div(cap, int64_t(kJoinNT) * kExpandPer);
         if (g > 65536) g = 65536;
-        hipLaunchKernelGGL(k_join_expand<K>, dim3(unsigned(g)), dim3(kJoinNT), 0, s, L.rng[0],
+        TQP_LAUNCH("join_expand", k_join_expand<K>, dim3(unsigned(g)), dim3(kJoinNT), 0, s, L.rng[0],
                            L.rng[1], L.rng[2], L.rng[3], L.rng[4], L.off, &L.counters[2], d_count,
                            cap, lrows, rrows, out_l, out_r, static_cast<K *>(out_pair_key));
         if ((rc = check_launch("join expand"))) return rc;

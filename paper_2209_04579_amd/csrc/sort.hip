@@ -205,7 +205,7 @@ static int sort_typed(const K *key_in, const int32_t *rows_in, int64_t n, const 
     const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
     if (npass == 0) {
         unsigned g = grid_all > 4096 ? 4096 : grid_all;
-        hipLaunchKernelGGL(k_copy_sorted<K>, dim3(g), dim3(256), 0, s, key_in, rows_in, key_out,
+        TQP_LAUNCH("copy_sorted", k_copy_sorted<K>, dim3(g), dim3(256), 0, s, key_in, rows_in, key_out,
                            rows_out, n, d_n);
         return check_launch("sort copy");
     }
@@ -227,7 +227,7 @@ static int sort_typed(const K *key_in, const int32_t *rows_in, int64_t n, const 
     if (rc) return rc;
     {
         unsigned g = grid_all > 1024 ? 1024 : grid_all;
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(g), dim3(kSortNT), 0, s, key_in, n, d_n,
+        TQP_LAUNCH("radix_hist", k_radix_hist<K>, dim3(g), dim3(kSortNT), 0, s, key_in, n, d_n,
                            K(key_min), npass, ghist);
         rc = check_launch("radix histogram");
         if (rc) return rc;
@@ -238,7 +238,7 @@ static int sort_typed(const K *key_in, const int32_t *rows_in, int64_t n, const 
         const bool to_out = ((npass - 1 - p) % 2) == 0;
         K *dk = to_out ? key_out : tmp_keys;
         int32_t *dr = to_out ? rows_out : tmp_rows;
-        hipLaunchKernelGGL(k_onesweep<K>, dim3(grid_all), dim3(kSortNT), 0, s, src_k, src_r, dk,
+        TQP_LAUNCH("onesweep", k_onesweep<K>, dim3(grid_all), dim3(kSortNT), 0, s, src_k, src_r, dk,
                            dr, n, d_n, K(key_min), p * kRadixBits, ghist + p * kBins,
                            status + size_t(p) * ntiles * kBins, tickets + p);
         rc = check_launch("radix pass");

@@ -43,6 +43,26 @@ struct Carver {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Per-kernel timing (see profile.hip).  A scope records one event before and
+// one after the launches it encloses, on the launch stream, when enabled.
+bool profile_on();
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+  private:
+    const char *name_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// Launches a kernel inside a timing scope named after it.
+#define TQP_LAUNCH(name, kern, grid, block, lds, stream, ...)                  \
+    do {                                                                       \
+        ::tqp::ProfScope tqp_prof_scope_(name, stream);                        \
+        hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);       \
+    } while (0)
+
 // Enqueues a fill of `count` 64-bit words (a kernel, not a memset node, so
 // that captured graphs replay it faithfully).
 int fill_u64(void *dst, uint64_t value, int64_t count, hipStream_t s);
