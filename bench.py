@@ -54,18 +54,19 @@ def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
     if name == "radix_hist":
         return 4.0 * (kept + nd)
     if name == "onesweep":
-        # first pass reads key only (row ids are positions), later passes key + row
+        # every pass reads and writes each element once: the fact side moves
+        # fk (4) + qty (8) + price (8) + flag (1), the dim side pk (4) + cat (4)
         p = st["passes"]
-        return (kept + nd) * (12.0 + 16.0 * (p - 1))
+        return p * (kept * 2.0 * 21 + nd * 2.0 * 8)
     if name == "rle":
         return 4.0 * (kept + nd) + 8.0 * (ul + ur)
     if name == "join_match":
         return ul * (4 + 4 + 4 + 4 + 6 * 8)
     if name == "join_expand":
-        return pairs * (4 + 4 + 4 + 4 + 4)
+        return pairs * (4 + 4 + 4) + ul * 6 * 8
     if name == "pack_key":
         return pairs * (4 + 4 + 1 + 4 + 8)
-    if name == "gb_dense":
+    if name in ("gb_dense", "gb_tiny"):
         return pairs * (8 + 4 + 8 + 8)
     if name == "gb_scan":
         return pairs * (4 + 4 + 8) + gb * (4 + 16)
@@ -85,6 +86,7 @@ def source_sha(kernel_file: str) -> str:
 KERNEL_FILE = {"filter": "filter.hip", "onesweep": "sort.hip", "radix_hist": "sort.hip",
                "rle": "join.hip", "join_match": "join.hip", "join_expand": "join.hip",
                "pack_key": "gather.hip", "gb_dense": "groupby.hip", "gb_scan": "groupby.hip",
+               "gb_tiny": "groupby.hip",
                "gb_diff": "groupby.hip"}
 
 

@@ -143,20 +143,25 @@ int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n,
                  const int64_t *d_n, int64_t *out, void *stream);
 
 /* ------------------------------------------------------------------------
- * tqp_sort -- stable ascending sort of signed int32/int64 keys (LSD radix).
+ * tqp_sort -- stable ascending sort of signed int32/int64 keys (LSD radix),
+ * the step under the sort-merge join and the sort-based group-by.
  *   key      : input keys, key->len >= n (n = capacity, d_n = actual count).
  *   in_rows  : optional row id carried with each key (NULL = 0, 1, 2, ...).
  *   key_bits : 0 = derive the key range on the device and read it back
  *              (this SYNCHRONIZES the stream); 1..64 = the caller guarantees
  *              0 <= key - key_min < 2^key_bits for every key.
- *   out_key  : sorted keys (capacity n), out_rows: carried row ids (capacity
- *              n, required).  Ties keep input order.
- * Workspace: tqp_sort_workspace_bytes(n, dtype).
+ *   out_key  : sorted keys (capacity n).  Ties keep input order.
+ *   out_rows : optional (capacity n); the row id carried with each key.
+ *   pay_in / pay_out : npay in [0, 4] payload columns (any dtype, len >= n)
+ *              moved with the keys: pay_out[c][i] = pay_in[c][perm[i]].
+ * Workspace: tqp_sort_workspace_bytes(n, dtype, pay_bytes) where pay_bytes is
+ * the sum of the payload element sizes.
  * ---------------------------------------------------------------------- */
-size_t tqp_sort_workspace_bytes(int64_t n, int dtype);
+size_t tqp_sort_workspace_bytes(int64_t n, int dtype, int pay_bytes);
 int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n,
              const int64_t *d_n, int key_bits, int64_t key_min,
              const tqp_col *out_key, int32_t *out_rows,
+             const tqp_col *pay_in, const tqp_col *pay_out, int npay,
              void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
@@ -177,11 +182,13 @@ int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n,
  *               ascending: key, lstart, lcnt, rstart, rcnt, indexing the
  *               sorted sides; d_nranges receives their number (at most
  *               range_cap are written).
- * Workspace: tqp_join_workspace_bytes(nl, nr, dtype, flags).
+ * Workspace: tqp_join_workspace_bytes(nl, nr, dtype, flags, cap), with cap
+ * 0 when no pairs are requested.
  * ---------------------------------------------------------------------- */
 #define TQP_JOIN_SORTED 1u
 #define TQP_JOIN_RANGES 2u
-size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags);
+size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags,
+                                int64_t cap);
 int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
              const tqp_col *rkey, const int32_t *rrows, const int64_t *d_nr,
              uint32_t flags,

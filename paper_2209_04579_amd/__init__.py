@@ -99,11 +99,12 @@ def lib():
         L.tqp_pack_key.restype = i32
         L.tqp_pack_key.argtypes = [P(KeyTerm), i32, i64, vp, vp, vp]
         L.tqp_sort_workspace_bytes.restype = sz
-        L.tqp_sort_workspace_bytes.argtypes = [i64, i32]
+        L.tqp_sort_workspace_bytes.argtypes = [i64, i32, i32]
         L.tqp_sort.restype = i32
-        L.tqp_sort.argtypes = [P(Col), vp, i64, vp, i32, i64, P(Col), vp, vp, sz, vp]
+        L.tqp_sort.argtypes = [P(Col), vp, i64, vp, i32, i64, P(Col), vp, P(Col), P(Col), i32,
+                               vp, sz, vp]
         L.tqp_join_workspace_bytes.restype = sz
-        L.tqp_join_workspace_bytes.argtypes = [i64, i64, i32, u32]
+        L.tqp_join_workspace_bytes.argtypes = [i64, i64, i32, u32, i64]
         L.tqp_join.restype = i32
         L.tqp_join.argtypes = [P(Col), vp, vp, P(Col), vp, vp, u32, vp, vp, vp, i64, vp,
                                P(Ranges), i64, vp, vp, sz, vp]
@@ -213,31 +214,40 @@ def pack_key_into(terms, n, out, d_n=None, stream=None):
 
 # ------------------------------------------------------------------- sort ----
 
-def sort_workspace_bytes(n: int, dtype) -> int:
-    return lib().tqp_sort_workspace_bytes(n, DTYPES[dtype])
+def sort_workspace_bytes(n: int, dtype, pay_bytes: int = 0) -> int:
+    return lib().tqp_sort_workspace_bytes(n, DTYPES[dtype], int(pay_bytes))
+
+
+def pay_bytes_of(cols) -> int:
+    return sum(c.element_size() for c in cols)
 
 
 def sort_into(key, in_rows, n, out_key, out_rows, ws, d_n=None, key_bits=0, key_min=0,
-              stream=None):
+              pay_in=(), pay_out=(), stream=None):
     _check(lib().tqp_sort(ctypes.byref(_col(key)), _ptr(in_rows), int(n), _ptr(d_n),
                           int(key_bits), int(key_min), ctypes.byref(_col(out_key)),
-                          _ptr(out_rows), _ptr(ws), ws.numel(), _stream(stream)))
+                          _ptr(out_rows), _cols(list(pay_in)), _cols(list(pay_out)),
+                          len(pay_in), _ptr(ws), ws.numel(), _stream(stream)))
 
 
-def sort(key, in_rows=None, key_bits=0, key_min=0):
-    """Stable ascending sort: returns (sorted keys, carried row ids)."""
+def sort(key, in_rows=None, key_bits=0, key_min=0, payload=(), want_rows=True):
+    """Stable ascending sort: returns (sorted keys, carried row ids, [payloads])."""
     n = key.numel()
     ok = torch.empty_like(key)
-    orows = torch.empty(n, dtype=torch.int32, device=key.device)
-    ws = workspace(sort_workspace_bytes(n, key.dtype), key.device)
-    sort_into(key, in_rows, n, ok, orows, ws, key_bits=key_bits, key_min=key_min)
+    orows = torch.empty(n, dtype=torch.int32, device=key.device) if want_rows else None
+    pout = [torch.empty_like(p[:n]) for p in payload]
+    ws = workspace(sort_workspace_bytes(n, key.dtype, pay_bytes_of(payload)), key.device)
+    sort_into(key, in_rows, n, ok, orows, ws, key_bits=key_bits, key_min=key_min,
+              pay_in=payload, pay_out=pout)
+    if payload:
+        return ok, orows, pout
     return ok, orows
 
 
 # ------------------------------------------------------------------- join ----
 
-def join_workspace_bytes(nl, nr, dtype, flags) -> int:
-    return lib().tqp_join_workspace_bytes(nl, nr, DTYPES[dtype], flags)
+def join_workspace_bytes(nl, nr, dtype, flags, cap=0) -> int:
+    return lib().tqp_join_workspace_bytes(nl, nr, DTYPES[dtype], flags, int(cap))
 
 
 def join_into(lkey, rkey, flags, out_l, out_r, out_key, cap, d_count, ws, lrows=None,
@@ -260,10 +270,11 @@ def join(lkey, rkey, lrows=None, rrows=None, sorted_inputs=False, cap=None, with
     """
     dev = lkey.device
     flags = JOIN_SORTED if sorted_inputs else 0
-    ws = workspace(join_workspace_bytes(lkey.numel(), rkey.numel(), lkey.dtype, flags), dev)
     cnt = torch.empty(1, dtype=torch.int64, device=dev)
     cap = int(cap if cap is not None else max(lkey.numel(), rkey.numel(), 1))
     for _ in range(2):
+        ws = workspace(join_workspace_bytes(lkey.numel(), rkey.numel(), lkey.dtype, flags, cap),
+                       dev)
         ol = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         orr = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         ok = torch.empty(max(cap, 1), dtype=lkey.dtype, device=dev) if with_key else None

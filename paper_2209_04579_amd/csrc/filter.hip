@@ -87,16 +87,19 @@ __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
     __shared__ int64_t s_tile;
     __shared__ int64_t s_prefix;
     __shared__ int32_t s_scan[kFilterNT / kWave];
+    __shared__ int64_t s_stage[kFilterTile];
 
     const int64_t n = a.n;
     const int64_t ntiles = ceil_div(n, kFilterTile);
+    const bool vec = a.vec != 0;
+    // Persistent workgroups: each takes tiles in ticket order until none are left.
+    for (;;) {
     const int64_t tile = take_tile(a.ticket, &s_tile);
     if (tile >= ntiles) {
         if (tile == 0 && threadIdx.x == 0) *a.d_count = 0;   // empty input
-        return;
+        break;
     }
     const int64_t row0 = tile * kFilterTile + int64_t(threadIdx.x) * kFilterIPT;
-    const bool vec = a.vec != 0;
 
     uint32_t mask = 0;
 #pragma unroll
@@ -126,24 +129,53 @@ __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
         if (lane_id() == 0) s_prefix = pre;
     }
     __syncthreads();
-    const int64_t base = s_prefix + excl;
+    const int64_t base = s_prefix;
     if (tile == ntiles - 1 && threadIdx.x == 0) *a.d_count = s_prefix + total;
-    if (mask == 0) return;
 
+    // Each output column goes through LDS in kept order, then out with
+    // consecutive threads on consecutive addresses.
     if (a.out_rows) {
-        int64_t q = base;
+        int32_t *st = reinterpret_cast<int32_t *>(s_stage);
+        int q = excl;
 #pragma unroll
         for (int r = 0; r < 16; r++)
-            if (mask & (1u << r)) a.out_rows[q++] = static_cast<int32_t>(row0 + r);
+            if (mask & (1u << r)) st[q++] = static_cast<int32_t>(row0 + r);
+        __syncthreads();
+        for (int i = threadIdx.x; i < total; i += kFilterNT) a.out_rows[base + i] = st[i];
+        __syncthreads();
     }
     for (int c = 0; c < a.npay; c++) {
-        load16(a.pin[c], a.paydt[c], row0, n, vec, v);
         const int dt = a.paydt[c];
-        void *out = a.pout[c];
-        int64_t q = base;
+        if (mask) load16(a.pin[c], dt, row0, n, vec, v);
+        int q = excl;
+        if (dt == TQP_INT8) {
+            int8_t *st = reinterpret_cast<int8_t *>(s_stage);
 #pragma unroll
-        for (int r = 0; r < 16; r++)
-            if (mask & (1u << r)) store_any(out, dt, q++, v[r]);
+            for (int r = 0; r < 16; r++)
+                if (mask & (1u << r)) st[q++] = static_cast<int8_t>(v[r]);
+            __syncthreads();
+            int8_t *out = static_cast<int8_t *>(a.pout[c]);
+            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+        } else if (dt == TQP_INT32) {
+            int32_t *st = reinterpret_cast<int32_t *>(s_stage);
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (mask & (1u << r)) st[q++] = static_cast<int32_t>(v[r]);
+            __syncthreads();
+            int32_t *out = static_cast<int32_t *>(a.pout[c]);
+            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+        } else {
+            int64_t *st = reinterpret_cast<int64_t *>(s_stage);
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (mask & (1u << r)) st[q++] = v[r];
+            __syncthreads();
+            int64_t *out = static_cast<int64_t *>(a.pout[c]);
+            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
     }
 }
 
@@ -215,7 +247,7 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
     a.n = n;
     a.ticket = reinterpret_cast<uint32_t *>(words);
     a.status = words + 1;
-    const unsigned grid = unsigned(ntiles > 0 ? ntiles : 1);
+    const unsigned grid = persistent_grid(ntiles, 4);
     TQP_LAUNCH("filter", k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
     return check_launch("tqp_filter");
 }

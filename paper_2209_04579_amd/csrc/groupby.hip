@@ -18,8 +18,8 @@
 
 namespace tqp {
 
-constexpr int kGbNT = 256;
-constexpr int kGbIPT = 16;
+constexpr int kGbNT = 512;
+constexpr int kGbIPT = 8;
 constexpr int kGbTile = kGbNT * kGbIPT;
 constexpr int kMaxAgg = 4;
 constexpr int kMaxVals = 8;
@@ -46,43 +46,66 @@ __device__ __forceinline__ int64_t agg_term(const AggArgs &a, int g, int64_t row
     return int64_t(uint64_t(vx) * uint64_t(vy));
 }
 
-// Look-back over kNV int64 values.  flags[t]: 0 not ready, 1 aggregate,
-// 2 inclusive; the values sit in aggv / incv rows of kNV.  The value stores
-// are ordered before the flag by a release store, and read after an acquire
-// load of the flag, all at agent scope so every XCD sees the same data.
-__device__ __forceinline__ void lookback_multi(uint32_t *flags, int64_t *aggv, int64_t *incv,
-                                               int64_t tile, int nv, const int64_t (&agg)[kNV],
-                                               int64_t (&excl)[kNV]) {
+// Look-back over kNV int64 values.  Each tile owns 2 * kNV status words; word
+// 2k holds the low 32 bits of value k and word 2k+1 the high 32 bits, each
+// tagged in its top bits with 1 (tile aggregate) or 2 (inclusive prefix); 0
+// means not written yet.  Every word is a single relaxed agent-scope atomic,
+// so no fence orders one against another: a reader accepts a tile's record
+// only when all the words it needs carry the same non-zero tag, and otherwise
+// reads again.  An aggregate, once written, never changes until the same
+// words are rewritten as the inclusive prefix.
+__device__ __forceinline__ uint64_t tag_word(uint64_t tag, uint32_t half) {
+    return (tag << 62) | half;
+}
+
+__device__ __forceinline__ void publish_multi(uint64_t *rec, uint64_t tag, int nv,
+                                              const int64_t (&v)[kNV]) {
+    for (int k = 0; k < nv; k++) {
+        st_relaxed(&rec[2 * k], tag_word(tag, uint32_t(uint64_t(v[k]))));
+        st_relaxed(&rec[2 * k + 1], tag_word(tag, uint32_t(uint64_t(v[k]) >> 32)));
+    }
+}
+
+__device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile, int nv,
+                                               const int64_t (&agg)[kNV], int64_t (&excl)[kNV]) {
 #pragma unroll
     for (int k = 0; k < kNV; k++) excl[k] = 0;
     if (tile == 0) {
-        if (lane_id() == 0) {
-            for (int k = 0; k < nv; k++) st_relaxed(&incv[k], agg[k]);
-            st_release(&flags[0], 2u);
-        }
+        if (lane_id() == 0) publish_multi(status, 2, nv, agg);
         return;
     }
-    if (lane_id() == 0) {
-        for (int k = 0; k < nv; k++) st_relaxed(&aggv[tile * kNV + k], agg[k]);
-        st_release(&flags[tile], 1u);
-    }
+    if (lane_id() == 0) publish_multi(status + tile * 2 * kNV, 1, nv, agg);
     int64_t base = tile - 1;
     while (true) {
         const int64_t idx = base - lane_id();
-        uint32_t f = 2;
+        uint64_t tag = 2;
         int64_t v[kNV];
 #pragma unroll
         for (int k = 0; k < kNV; k++) v[k] = 0;
         if (idx >= 0) {
-            f = ld_acquire(&flags[idx]);
-            while (f == 0) {
+            const uint64_t *rec = status + idx * 2 * kNV;
+            while (true) {
+                // all words are read independently (no early exit), then checked
+                uint64_t w[2 * kNV];
+#pragma unroll
+                for (int k = 0; k < 2 * kNV; k++) w[k] = k < 2 * nv ? ld_relaxed(&rec[k]) : 0;
+                const uint64_t first = w[0] >> 62;
+                bool ok = first != 0;
+#pragma unroll
+                for (int k = 0; k < kNV; k++) {
+                    if (k < nv) {
+                        ok = ok && (w[2 * k] >> 62) == first && (w[2 * k + 1] >> 62) == first;
+                        v[k] = int64_t((w[2 * k + 1] << 32) | (w[2 * k] & 0xffffffffu));
+                    }
+                }
+                if (ok) {
+                    tag = first;
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
-                f = ld_acquire(&flags[idx]);
             }
-            const int64_t *src = (f == 2 ? incv : aggv) + idx * kNV;
-            for (int k = 0; k < nv; k++) v[k] = ld_relaxed(&src[k]);
         }
-        const uint64_t inc = ballot(f == 2);
+        const uint64_t inc = ballot(tag == 2);
         const int stop = inc ? (__ffsll(static_cast<long long>(inc)) - 1) : (kWave - 1);
 #pragma unroll
         for (int k = 0; k < kNV; k++) {
@@ -93,93 +116,169 @@ __device__ __forceinline__ void lookback_multi(uint32_t *flags, int64_t *aggv, i
         base -= kWave;
     }
     if (lane_id() == 0) {
-        for (int k = 0; k < nv; k++) st_relaxed(&incv[tile * kNV + k], excl[k] + agg[k]);
-        st_release(&flags[tile], 2u);
+        int64_t incl[kNV];
+#pragma unroll
+        for (int k = 0; k < kNV; k++) incl[k] = int64_t(uint64_t(excl[k]) + uint64_t(agg[k]));
+        publish_multi(status + tile * 2 * kNV, 2, nv, incl);
     }
 }
 
-template <class K>
+// Reads the value column of N rows (row ids in rows[]) with the dtype branch
+// outside the row loop, so the N loads issue back to back.
+template <int N>
+__device__ __forceinline__ void load_vals(const void *col, int dt, int64_t len,
+                                          const int32_t (&rows)[N], uint32_t valid,
+                                          int64_t (&out)[N]) {
+    if (dt == TQP_INT8) {
+        const int8_t *p = static_cast<const int8_t *>(col);
+#pragma unroll
+        for (int r = 0; r < N; r++)
+            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
+    } else if (dt == TQP_INT32) {
+        const int32_t *p = static_cast<const int32_t *>(col);
+#pragma unroll
+        for (int r = 0; r < N; r++)
+            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
+    } else {
+        const int64_t *p = static_cast<const int64_t *>(col);
+#pragma unroll
+        for (int r = 0; r < N; r++)
+            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
+    }
+}
+
+// One single-pass scan over sorted keys for NAGG aggregates: head count and
+// running sums carried across tiles by look-back; run ends write the running
+// sums, run heads write the key.  Every value is loaded once, into registers.
+template <class K, int NAGG>
 __global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, int64_t n,
                                                    const int64_t *d_n, AggArgs a,
                                                    K *__restrict__ out_key, int64_t key_cap,
-                                                   int64_t *__restrict__ ends /* [kMaxAgg][n] */,
+                                                   int64_t *__restrict__ ends /* [NAGG][n] */,
                                                    int64_t ends_stride, int64_t *d_ngroups,
-                                                   uint32_t *ticket, uint32_t *flags,
-                                                   int64_t *aggv, int64_t *incv) {
+                                                   uint32_t *ticket, uint64_t *status) {
     __shared__ int64_t s_tile;
     __shared__ int64_t s_scan[kGbNT / kWave];
     __shared__ int64_t s_excl[kNV];
     const int64_t cnt = count_of(d_n, n);
     const int64_t ntiles = ceil_div(cnt, kGbTile);
+    const bool kvec = reinterpret_cast<uintptr_t>(keys) % 16 == 0;
+    const bool rvec = a.val_rows && reinterpret_cast<uintptr_t>(a.val_rows) % 16 == 0;
+    for (;;) {
     const int64_t tile = take_tile(ticket, &s_tile);
     if (tile >= ntiles) {
         if (tile == 0 && threadIdx.x == 0) *d_ngroups = 0;
-        return;
+        break;
     }
-    const int nagg = a.nagg;
     const int64_t row0 = tile * kGbTile + int64_t(threadIdx.x) * kGbIPT;
-    K v[16];
+    constexpr int R = kGbIPT;
+    const bool full = row0 + R <= cnt;
+    K v[R];
+    if (kvec && full) {
+        constexpr int kPer = 16 / sizeof(K);
+        const int4 *q = reinterpret_cast<const int4 *>(keys + row0);
 #pragma unroll
-    for (int r = 0; r < 16; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+        for (int j = 0; j < R / kPer; j++) {
+            int4 x = q[j];
+            const K *e = reinterpret_cast<const K *>(&x);
+#pragma unroll
+            for (int t = 0; t < kPer; t++) v[j * kPer + t] = e[t];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+    }
+    int32_t rows[R];
+    if (rvec && full) {
+        const int4 *q = reinterpret_cast<const int4 *>(a.val_rows + row0);
+#pragma unroll
+        for (int j = 0; j < R / 4; j++) {
+            int4 x = q[j];
+            rows[4 * j + 0] = x.x;
+            rows[4 * j + 1] = x.y;
+            rows[4 * j + 2] = x.z;
+            rows[4 * j + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            rows[r] = row0 + r < cnt ? (a.val_rows ? a.val_rows[row0 + r] : int32_t(row0 + r)) : 0;
+    }
     const K before = row0 > 0 && row0 <= cnt ? keys[row0 - 1] : K(0);
-    const K after = row0 + 16 < cnt ? keys[row0 + 16] : K(0);
-    uint32_t head = 0, end = 0;
+    const K after = row0 + R < cnt ? keys[row0 + R] : K(0);
+    uint32_t head = 0, end = 0, valid = 0;
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
+    for (int r = 0; r < R; r++) {
         const int64_t i = row0 + r;
         if (i < cnt) {
+            valid |= 1u << r;
             const K prv = r == 0 ? before : v[r - 1];
-            const K nxt = r == 15 ? after : v[r + 1];
+            const K nxt = r == R - 1 ? after : v[r + 1];
             if (i == 0 || v[r] != prv) head |= 1u << r;
             if (i == cnt - 1 || v[r] != nxt) end |= 1u << r;
         }
     }
-    int64_t agg[kNV], excl[kNV], tot[kNV];
-    agg[0] = __popc(head);
+    // per-row aggregate terms, loaded once
+    int64_t term[NAGG][R];
 #pragma unroll
-    for (int g = 0; g < kMaxAgg; g++) agg[g + 1] = 0;
+    for (int g = 0; g < NAGG; g++) {
+        if (a.op[g] == TQP_AGG_COUNT) {
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int64_t i = row0 + r;
-        if (i < cnt) {
-            const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
+            for (int r = 0; r < R; r++) term[g][r] = (valid >> r) & 1;
+        } else {
+            const int x = a.ia[g];
+            load_vals<R>(a.val[x], a.vdt[x], a.vlen[x], rows, valid, term[g]);
+            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+                int64_t other[R];
+                const int y = a.ib[g];
+                load_vals<R>(a.val[y], a.vdt[y], a.vlen[y], rows, valid, other);
 #pragma unroll
-            for (int g = 0; g < kMaxAgg; g++)
-                if (g < nagg) agg[g + 1] += agg_term(a, g, row);
+                for (int r = 0; r < R; r++)
+                    term[g][r] = int64_t(uint64_t(term[g][r]) * uint64_t(other[r]));
+            }
         }
     }
+    int64_t agg[kNV], excl[kNV], tot[kNV];
 #pragma unroll
-    for (int k = 0; k < kNV; k++) excl[k] = block_excl_scan<kGbNT>(agg[k], &tot[k], s_scan);
+    for (int k = 0; k < kNV; k++) agg[k] = 0;
+    agg[0] = __popc(head);
+#pragma unroll
+    for (int g = 0; g < NAGG; g++) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int r = 0; r < R; r++) s += uint64_t(term[g][r]);
+        agg[g + 1] = int64_t(s);
+    }
+#pragma unroll
+    for (int k = 0; k <= NAGG; k++) excl[k] = block_excl_scan<kGbNT>(agg[k], &tot[k], s_scan);
     if (wave_id() == 0) {
         int64_t pre[kNV];
-        lookback_multi(flags, aggv, incv, tile, nagg + 1, tot, pre);
+        lookback_multi(status, tile, NAGG + 1, tot, pre);
         if (lane_id() == 0)
-            for (int k = 0; k < kNV; k++) s_excl[k] = pre[k];
+            for (int k = 0; k <= NAGG; k++) s_excl[k] = pre[k];
     }
     __syncthreads();
     if (tile == ntiles - 1 && threadIdx.x == 0) *d_ngroups = s_excl[0] + tot[0];
     int64_t hc = s_excl[0] + excl[0];
-    int64_t run[kMaxAgg];
+    uint64_t run[NAGG];
 #pragma unroll
-    for (int g = 0; g < kMaxAgg; g++) run[g] = s_excl[g + 1] + excl[g + 1];
+    for (int g = 0; g < NAGG; g++) run[g] = uint64_t(s_excl[g + 1]) + uint64_t(excl[g + 1]);
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int64_t i = row0 + r;
-        if (i < cnt) {
+    for (int r = 0; r < R; r++) {
+        if ((valid >> r) & 1) {
             if (head & (1u << r)) {
                 if (hc < key_cap) out_key[hc] = v[r];
                 hc++;
             }
-            const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
 #pragma unroll
-            for (int g = 0; g < kMaxAgg; g++)
-                if (g < nagg) run[g] += agg_term(a, g, row);
+            for (int g = 0; g < NAGG; g++) run[g] += uint64_t(term[g][r]);
             if (end & (1u << r)) {
 #pragma unroll
-                for (int g = 0; g < kMaxAgg; g++)
-                    if (g < nagg) ends[g * ends_stride + (hc - 1)] = run[g];
+                for (int g = 0; g < NAGG; g++) ends[g * ends_stride + (hc - 1)] = int64_t(run[g]);
             }
         }
+    }
+    __syncthreads();
     }
 }
 
@@ -231,6 +330,66 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, 
     }
 }
 
+// Domains of at most kTinySpan keys: every thread keeps all the groups'
+// accumulators in registers (selecting, not indexing, the group), so no two
+// lanes ever contend for one counter; waves then reduce with shuffles.
+constexpr int kTinySpan = 8;
+
+template <class K>
+__global__ __launch_bounds__(kGbNT) void k_gb_tiny(const K *__restrict__ keys, int64_t n,
+                                                   const int64_t *d_n, int64_t key_lo, int span,
+                                                   AggArgs a, unsigned long long *__restrict__ gacc) {
+    __shared__ int64_t s_red[kGbNT / kWave][kTinySpan][kMaxAgg + 1];
+    const int nagg = a.nagg;
+    int64_t acc[kTinySpan][kMaxAgg];
+    int64_t cnt_b[kTinySpan];
+#pragma unroll
+    for (int b = 0; b < kTinySpan; b++) {
+        cnt_b[b] = 0;
+#pragma unroll
+        for (int g = 0; g < kMaxAgg; g++) acc[b][g] = 0;
+    }
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t stride = int64_t(gridDim.x) * kGbNT;
+    for (int64_t i = blockIdx.x * int64_t(kGbNT) + threadIdx.x; i < cnt; i += stride) {
+        const uint64_t b = uint64_t(int64_t(keys[i])) - uint64_t(key_lo);
+        if (b >= uint64_t(span)) continue;
+        const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
+        int64_t t[kMaxAgg];
+#pragma unroll
+        for (int g = 0; g < kMaxAgg; g++) t[g] = g < nagg ? agg_term(a, g, row) : 0;
+#pragma unroll
+        for (int bb = 0; bb < kTinySpan; bb++) {
+            const bool hit = uint64_t(bb) == b;
+            cnt_b[bb] += hit ? 1 : 0;
+#pragma unroll
+            for (int g = 0; g < kMaxAgg; g++) acc[bb][g] += hit ? t[g] : 0;
+        }
+    }
+    const int w = wave_id();
+#pragma unroll
+    for (int bb = 0; bb < kTinySpan; bb++) {
+#pragma unroll
+        for (int g = 0; g < kMaxAgg; g++) {
+            const int64_t s = wave_sum(acc[bb][g]);
+            if (lane_id() == 0) s_red[w][bb][g] = s;
+        }
+        const int64_t c = wave_sum(cnt_b[bb]);
+        if (lane_id() == 0) s_red[w][bb][kMaxAgg] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTinySpan * (kMaxAgg + 1)) {
+        const int bb = threadIdx.x / (kMaxAgg + 1), g = threadIdx.x % (kMaxAgg + 1);
+        int64_t s = 0;
+#pragma unroll
+        for (int ww = 0; ww < kGbNT / kWave; ww++) s += s_red[ww][bb][g];
+        if (bb < span && (g < nagg || g == kMaxAgg) && s != 0) {
+            const int slot = g == kMaxAgg ? nagg : g;   // count goes last
+            atomicAdd(&gacc[slot * span + bb], (unsigned long long)s);
+        }
+    }
+}
+
 template <class K>
 __global__ __launch_bounds__(1024) void k_gb_dense_emit(const unsigned long long *__restrict__ gacc,
                                                         int64_t key_lo, int64_t span, int nagg,
@@ -264,9 +423,9 @@ struct GbLayout {
     void *sort_ws;
     size_t sort_ws_bytes;
     int64_t *ends;
-    uint32_t *words;          // ticket + flags
+    uint64_t *words;          // ticket word, then 2 * kNV status words per tile
+    int64_t nwords;
     int64_t ntiles;
-    int64_t *aggv, *incv;
     unsigned long long *gacc;
     size_t bytes;
 };
@@ -295,9 +454,8 @@ static GbLayout gb_layout(void *ws, int64_t n, int dtype, int nagg, uint32_t fla
     }
     L.ends = c.take<int64_t>(size_t(kMaxAgg) * nn);
     L.ntiles = ceil_div(nn, kGbTile);
-    L.words = c.take<uint32_t>(size_t(2 + L.ntiles));
-    L.aggv = c.take<int64_t>(size_t(L.ntiles) * kNV);
-    L.incv = c.take<int64_t>(size_t(L.ntiles) * kNV);
+    L.nwords = 1 + L.ntiles * 2 * kNV;
+    L.words = c.take<uint64_t>(size_t(L.nwords));
     L.bytes = c.bytes();
     return L;
 }
@@ -315,7 +473,14 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
     if (dense_ok(flags, key_span, nagg)) {
         rc = fill_u64(L.gacc, 0, int64_t(nagg + 1) * key_span, s);
         if (rc) return rc;
-        if (n > 0) {
+        if (n > 0 && key_span <= kTinySpan) {
+            int64_t g = ceil_div(n, int64_t(kGbNT) * 32);
+            if (g > 2048) g = 2048;
+            TQP_LAUNCH("gb_tiny", k_gb_tiny<K>, dim3(unsigned(g)), dim3(kGbNT), 0, s,
+                       static_cast<const K *>(key->data), n, d_n, key_lo, int(key_span), args,
+                       L.gacc);
+            if ((rc = check_launch("group-by tiny"))) return rc;
+        } else if (n > 0) {
             int64_t g = ceil_div(n, int64_t(kGbNT) * 64);
             if (g > 2048) g = 2048;
             const size_t lds = size_t(nagg + 1) * key_span * 8;
@@ -346,12 +511,30 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
         k = static_cast<const K *>(L.skey);
         a.val_rows = L.srows;
     }
-    rc = fill_u32(L.words, 0, 2 + L.ntiles, s);
+    rc = fill_u64(L.words, 0, L.nwords, s);
     if (rc) return rc;
-    const unsigned grid = unsigned(L.ntiles);
-    TQP_LAUNCH("gb_scan", k_gb_scan<K>, dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a,
-                       static_cast<K *>(out_key->data), out_key->len, L.ends,
-                       n > 0 ? n : int64_t(1), d_ngroups, L.words, L.words + 2, L.aggv, L.incv);
+    const unsigned grid = persistent_grid(L.ntiles, 2);
+    K *ok = static_cast<K *>(out_key->data);
+    const int64_t es = n > 0 ? n : int64_t(1);
+    uint32_t *tk = reinterpret_cast<uint32_t *>(L.words);
+    switch (nagg) {
+    case 1:
+        TQP_LAUNCH("gb_scan", (k_gb_scan<K, 1>), dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a, ok,
+                   out_key->len, L.ends, es, d_ngroups, tk, L.words + 1);
+        break;
+    case 2:
+        TQP_LAUNCH("gb_scan", (k_gb_scan<K, 2>), dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a, ok,
+                   out_key->len, L.ends, es, d_ngroups, tk, L.words + 1);
+        break;
+    case 3:
+        TQP_LAUNCH("gb_scan", (k_gb_scan<K, 3>), dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a, ok,
+                   out_key->len, L.ends, es, d_ngroups, tk, L.words + 1);
+        break;
+    default:
+        TQP_LAUNCH("gb_scan", (k_gb_scan<K, 4>), dim3(grid), dim3(kGbNT), 0, s, k, n, d_n, a, ok,
+                   out_key->len, L.ends, es, d_ngroups, tk, L.words + 1);
+        break;
+    }
     if ((rc = check_launch("group-by scan"))) return rc;
     int64_t g = ceil_div(out_key->len > 0 ? out_key->len : 1, 256);
     if (g > 4096) g = 4096;

@@ -7,10 +7,12 @@
 //     (key, lstart, lcnt, rstart, rcnt).  Two decoupled look-backs in the same
 //     kernel give each range its slot and its first output pair (the running
 //     sum of lcnt * rcnt), so the pair total is known on the device.
-//  3. Expand: output positions are split evenly over threads, whatever the
-//     key skew; each thread finds its range by binary search over the pair
-//     offsets, then walks (i, j) within the range in row-major order, which is
-//     the canonical (key, i, j) order.
+//     It also records, for every tile of output pairs, the range holding the
+//     tile's first pair.
+//  3. Expand: output pairs are split into equal tiles, whatever the key skew;
+//     a tile stages the pair offsets of its (at most tile-size) ranges in LDS,
+//     each pair finds its range there and takes (i, j) = row-major position
+//     within the range, which is the canonical (key, i, j) order.
 #include "tqp_internal.hpp"
 
 namespace tqp {
@@ -19,8 +21,12 @@ constexpr int kJoinNT = 256;
 constexpr int kJoinIPT = 16;
 constexpr int kJoinTile = kJoinNT * kJoinIPT;
 constexpr int kExpandPer = 8;
+constexpr int kExpandTile = kJoinNT * kExpandPer;   // output pairs per expand tile
 constexpr int kMatchIPT = 4;
 constexpr int kMatchTile = kJoinNT * kMatchIPT;
+constexpr int kMatchWindow = 4096;      // right keys staged in LDS per match tile
+constexpr int kRleNT = 1024;
+constexpr int kRleTile = kRleNT * kJoinIPT;
 
 template <class K>
 __device__ __forceinline__ void load_keys16(const K *p, int64_t row0, int64_t cnt, K (&v)[16]) {
@@ -51,21 +57,25 @@ __device__ __forceinline__ void load_keys16(const K *p, int64_t row0, int64_t cn
 }
 
 // Run heads of a sorted column -> (unique key, run start), count in *d_nu.
+// Tiles of 1024 threads x 16 keys: the keys are only 4-8 bytes each, so a
+// large tile keeps the per-tile ticket and look-back cost small next to the
+// tile's own traffic.
 template <class K>
-__global__ __launch_bounds__(kJoinNT) void k_rle(const K *__restrict__ keys, int64_t n,
-                                                 const int64_t *d_n, K *__restrict__ ukey,
-                                                 int32_t *__restrict__ ustart, int64_t *d_nu,
-                                                 uint32_t *ticket, uint64_t *status) {
+__global__ __launch_bounds__(kRleNT) void k_rle(const K *__restrict__ keys, int64_t n,
+                                                const int64_t *d_n, K *__restrict__ ukey,
+                                                int32_t *__restrict__ ustart, int64_t *d_nu,
+                                                uint32_t *ticket, uint64_t *status) {
     __shared__ int64_t s_tile, s_prefix;
-    __shared__ int32_t s_scan[kJoinNT / kWave];
+    __shared__ int32_t s_scan[kRleNT / kWave];
     const int64_t cnt = count_of(d_n, n);
-    const int64_t ntiles = ceil_div(cnt, kJoinTile);
+    const int64_t ntiles = ceil_div(cnt, kRleTile);
+    for (;;) {
     const int64_t tile = take_tile(ticket, &s_tile);
     if (tile >= ntiles) {
         if (tile == 0 && threadIdx.x == 0) *d_nu = 0;
-        return;
+        break;
     }
-    const int64_t row0 = tile * kJoinTile + int64_t(threadIdx.x) * kJoinIPT;
+    const int64_t row0 = tile * kRleTile + int64_t(threadIdx.x) * kJoinIPT;
     K v[16];
     if (reinterpret_cast<uintptr_t>(keys) % 16 == 0) {
         load_keys16(keys, row0, cnt, v);
@@ -82,7 +92,7 @@ __global__ __launch_bounds__(kJoinNT) void k_rle(const K *__restrict__ keys, int
         prev = v[r];
     }
     int32_t total;
-    const int32_t excl = block_excl_scan<kJoinNT>(int32_t(__popc(head)), &total, s_scan);
+    const int32_t excl = block_excl_scan<kRleNT>(int32_t(__popc(head)), &total, s_scan);
     if (wave_id() == 0) {
         int64_t pre = lookback_count(status, tile, total);
         if (lane_id() == 0) s_prefix = pre;
@@ -97,6 +107,8 @@ __global__ __launch_bounds__(kJoinNT) void k_rle(const K *__restrict__ keys, int
             ustart[q] = int32_t(row0 + r);
             q++;
         }
+    }
+    __syncthreads();
     }
 }
 
@@ -118,6 +130,8 @@ struct MatchArgs {
     int64_t *d_nranges_ws;
     int64_t *d_nranges_user;
     int64_t *d_count;
+    int64_t *tile_first;     // optional: range holding the first pair of each output tile
+    int64_t ntiles_out;
     uint32_t *ticket;
     uint64_t *status_m;
     uint64_t *status_p;
@@ -126,6 +140,8 @@ struct MatchArgs {
 template <class K>
 __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     __shared__ int64_t s_tile, s_pm, s_pp;
+    __shared__ int64_t s_win[2];
+    __shared__ K s_rkeys[kMatchWindow];
     __shared__ int32_t s_scan32[kJoinNT / kWave];
     __shared__ int64_t s_scan64[kJoinNT / kWave];
     const int64_t nuL = count_of(a.d_nuL, a.nl);
@@ -133,6 +149,9 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     const int64_t nl = count_of(a.d_nl, a.nl);
     const int64_t nr = count_of(a.d_nr, a.nr);
     const int64_t ntiles = ceil_div(nuL, kMatchTile);
+    const K *uL = static_cast<const K *>(a.uL);
+    const K *uR = static_cast<const K *>(a.uR);
+    for (;;) {
     const int64_t tile = take_tile(a.ticket, &s_tile);
     if (tile >= ntiles) {
         if (tile == 0 && threadIdx.x == 0) {
@@ -140,15 +159,39 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
             if (a.d_nranges_user) *a.d_nranges_user = 0;
             *a.d_count = 0;
         }
-        return;
+        break;
     }
-    const K *uL = static_cast<const K *>(a.uL);
-    const K *uR = static_cast<const K *>(a.uR);
+    // The right keys this tile can match lie in [w_lo, w_hi): the lower bound
+    // of the tile's first left key and the upper bound of its last.  Two
+    // threads find them; a window that fits is staged in LDS and searched
+    // there, a larger one is searched in place.
+    const int64_t tile_u0 = tile * kMatchTile;
+    const int64_t tile_u1 = (tile_u0 + kMatchTile < nuL ? tile_u0 + kMatchTile : nuL) - 1;
+    if (threadIdx.x < 2) {
+        const K k = uL[threadIdx.x == 0 ? tile_u0 : tile_u1];
+        int64_t lo = 0, hi = nuR;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (threadIdx.x == 0 ? (uR[mid] < k) : !(k < uR[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        s_win[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t w_lo = s_win[0], w_hi = s_win[1];
+    const bool in_lds = w_hi - w_lo <= kMatchWindow;
+    if (in_lds)
+        for (int64_t i = threadIdx.x; i < w_hi - w_lo; i += kJoinNT)
+            s_rkeys[i] = static_cast<const K *>(a.uR)[w_lo + i];
+    __syncthreads();
+    const K *wkeys = in_lds ? reinterpret_cast<const K *>(s_rkeys) : uR + w_lo;
+    const int64_t wn = w_hi - w_lo;
     const int64_t u0 = tile * kMatchTile + int64_t(threadIdx.x) * kMatchIPT;
     int64_t ls[kMatchIPT], lc[kMatchIPT], rs[kMatchIPT], rc[kMatchIPT];
     K key[kMatchIPT];
     uint32_t hit = 0;
     int64_t pairs = 0;
+    int64_t from = 0;                         // keys ascend: each search starts at the last
 #pragma unroll
     for (int r = 0; r < kMatchIPT; r++) {
         const int64_t u = u0 + r;
@@ -159,13 +202,15 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
             key[r] = k;
             ls[r] = a.sL[u];
             lc[r] = (u + 1 < nuL ? int64_t(a.sL[u + 1]) : nl) - ls[r];
-            int64_t lo = 0, hi = nuR;             // lower_bound of k in uR
+            int64_t lo = from, hi = wn;           // lower_bound of k in the window
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
-                if (uR[mid] < k) lo = mid + 1;
+                if (wkeys[mid] < k) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < nuR && uR[lo] == k) {
+            from = lo;
+            if (lo < wn && wkeys[lo] == k) {
+                lo += w_lo;
                 hit |= 1u << r;
                 rs[r] = a.sR[lo];
                 rc[r] = (lo + 1 < nuR ? int64_t(a.sR[lo + 1]) : nr) - rs[r];
@@ -206,58 +251,76 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
             a.urs[q] = rs[r];
             a.urc[q] = rc[r];
         }
-        o += lc[r] * rc[r];
+        const int64_t p = lc[r] * rc[r];
+        if (a.tile_first) {
+            // this range holds the first pair of every output tile starting in it
+            for (int64_t t = ceil_div(o, kExpandTile); t * kExpandTile < o + p && t < a.ntiles_out; t++)
+                a.tile_first[t] = q;
+        }
+        o += p;
         q++;
+    }
+    __syncthreads();
     }
 }
 
+// Output tile t (kExpandTile pairs) starts in range tile_first[t] and ends at
+// most kExpandTile ranges later; those ranges' first-pair offsets are staged in
+// LDS, and each output finds its range there by binary search.  Consecutive
+// threads write consecutive pairs.
 template <class K>
 __global__ __launch_bounds__(kJoinNT) void k_join_expand(
     const int64_t *__restrict__ rkey, const int64_t *__restrict__ rls,
     const int64_t *__restrict__ rlc, const int64_t *__restrict__ rrs,
-    const int64_t *__restrict__ rrc, const int64_t *__restrict__ off, const int64_t *d_nranges,
-    const int64_t *d_count, int64_t cap, const int32_t *__restrict__ lrows,
-    const int32_t *__restrict__ rrows, int32_t *__restrict__ out_l, int32_t *__restrict__ out_r,
-    K *__restrict__ out_key) {
+    const int64_t *__restrict__ rrc, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ tile_first, const int64_t *d_nranges, const int64_t *d_count,
+    int64_t cap, const int32_t *__restrict__ lrows, const int32_t *__restrict__ rrows,
+    int32_t *__restrict__ out_l, int32_t *__restrict__ out_r, K *__restrict__ out_key) {
+    __shared__ int64_t s_off[kExpandTile + 1];
     const int64_t nranges = *d_nranges;
     const int64_t total = *d_count;
     const int64_t limit = total < cap ? total : cap;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x * kExpandPer;
-    for (int64_t o0 = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) * kExpandPer; o0 < limit;
-         o0 += stride) {
-        int64_t lo = 0, hi = nranges;          // last m with off[m] <= o0
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (off[mid] <= o0) lo = mid;
-            else hi = mid;
-        }
-        int64_t m = lo;
-        int64_t lstart = rls[m], lcnt = rlc[m], rstart = rrs[m], rcnt = rrc[m];
-        K key = K(rkey[m]);
-        const int64_t t = o0 - off[m];
-        int64_t i = t / rcnt;
-        int64_t j = t - i * rcnt;
-        const int64_t oend = o0 + kExpandPer < limit ? o0 + kExpandPer : limit;
-        for (int64_t o = o0; o < oend; o++) {
-            if (i == lcnt) {                    // next range
-                m++;
-                lstart = rls[m];
-                lcnt = rlc[m];
-                rstart = rrs[m];
-                rcnt = rrc[m];
-                key = K(rkey[m]);
-                i = 0;
-                j = 0;
+    const int64_t ntiles = ceil_div(limit, kExpandTile);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t o_begin = t * kExpandTile;
+        const int64_t o_end = o_begin + kExpandTile < limit ? o_begin + kExpandTile : limit;
+        const int64_t m0 = tile_first[t];
+        int64_t m1 = t + 1 < ntiles ? tile_first[t + 1] : nranges - 1;
+        if (m1 > m0 + kExpandTile) m1 = m0 + kExpandTile;
+        const int nm = int(m1 - m0 + 1);
+        for (int i = threadIdx.x; i < nm; i += kJoinNT) s_off[i] = off[m0 + i];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kExpandPer; k++) {
+            const int64_t o = o_begin + k * kJoinNT + threadIdx.x;
+            if (o < o_end) {
+                int lo = 0, hi = nm;               // last local range with offset <= o
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= o) lo = mid;
+                    else hi = mid;
+                }
+                const int64_t m = m0 + lo;
+                const uint64_t tt = uint64_t(o - s_off[lo]);
+                const uint64_t rc = uint64_t(rrc[m]);
+                uint64_t i, j;
+                if (rc == 1) {
+                    i = tt;
+                    j = 0;
+                } else if ((tt >> 32) == 0 && (rc >> 32) == 0) {
+                    i = uint32_t(tt) / uint32_t(rc);
+                    j = tt - i * rc;
+                } else {
+                    i = tt / rc;
+                    j = tt - i * rc;
+                }
+                const int64_t li = rls[m] + int64_t(i), rj = rrs[m] + int64_t(j);
+                if (out_l) out_l[o] = lrows ? lrows[li] : int32_t(li);
+                if (out_r) out_r[o] = rrows ? rrows[rj] : int32_t(rj);
+                if (out_key) out_key[o] = K(rkey[m]);
             }
-            const int64_t li = lstart + i, rj = rstart + j;
-            if (out_l) out_l[o] = lrows ? lrows[li] : int32_t(li);
-            if (out_r) out_r[o] = rrows ? rrows[rj] : int32_t(rj);
-            if (out_key) out_key[o] = key;
-            if (++j == rcnt) {
-                j = 0;
-                i++;
-            }
         }
+        __syncthreads();
     }
 }
 
@@ -270,6 +333,8 @@ struct JoinLayout {
     int32_t *sL, *sR;
     int64_t *rng[5];
     int64_t *off;
+    int64_t *tile_first;     // per output tile of the expand: its first range
+    int64_t ntiles_out;
     int64_t *counters;       // nuL, nuR, nranges
     uint64_t *words;         // tickets + statuses
     int64_t nwords;
@@ -277,7 +342,8 @@ struct JoinLayout {
     size_t bytes;
 };
 
-static JoinLayout join_layout(void *ws, int64_t nl, int64_t nr, int dtype, uint32_t flags) {
+static JoinLayout join_layout(void *ws, int64_t nl, int64_t nr, int dtype, uint32_t flags,
+                              int64_t cap) {
     JoinLayout L = {};
     Carver c(ws);
     const int ks = dtype_size(dtype);
@@ -297,9 +363,11 @@ static JoinLayout join_layout(void *ws, int64_t nl, int64_t nr, int dtype, uint3
     const int64_t nm = (nl < nr ? nl : nr) > 0 ? (nl < nr ? nl : nr) : 1;
     for (int k = 0; k < 5; k++) L.rng[k] = c.take<int64_t>(size_t(nm));
     L.off = c.take<int64_t>(size_t(nm));
+    L.ntiles_out = ceil_div(cap > 0 ? cap : 1, kExpandTile);
+    L.tile_first = c.take<int64_t>(size_t(L.ntiles_out));
     L.counters = c.take<int64_t>(4);
-    const int64_t tl = ceil_div(nl > 0 ? nl : 1, kJoinTile);
-    const int64_t tr = ceil_div(nr > 0 ? nr : 1, kJoinTile);
+    const int64_t tl = ceil_div(nl > 0 ? nl : 1, kRleTile);
+    const int64_t tr = ceil_div(nr > 0 ? nr : 1, kRleTile);
     const int64_t tm = ceil_div(nl > 0 ? nl : 1, kMatchTile);
     L.nwords = 4 + tl + tr + 2 * tm;
     L.words = c.take<uint64_t>(size_t(L.nwords));
@@ -320,7 +388,8 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
                       int64_t cap, int64_t *d_count, const tqp_ranges *ranges, int64_t range_cap,
                       int64_t *d_nranges, void *ws, hipStream_t s) {
     const int64_t nl = lkey->len, nr = rkey->len;
-    JoinLayout L = join_layout(ws, nl, nr, lkey->dtype, flags);
+    const bool want_pairs = (out_l || out_r || out_pair_key) && cap > 0;
+    JoinLayout L = join_layout(ws, nl, nr, lkey->dtype, flags, want_pairs ? cap : 0);
     const K *lk = static_cast<const K *>(lkey->data);
     const K *rk = static_cast<const K *>(rkey->data);
     int rc;
@@ -345,12 +414,12 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     rc = fill_u64(L.words, 0, L.nwords, s);
     if (rc) return rc;
     uint32_t *tickets = reinterpret_cast<uint32_t *>(L.words);
-    const unsigned gl = unsigned(ceil_div(nl > 0 ? nl : 1, kJoinTile));
-    const unsigned gr = unsigned(ceil_div(nr > 0 ? nr : 1, kJoinTile));
-    TQP_LAUNCH("rle", k_rle<K>, dim3(gl), dim3(kJoinNT), 0, s, lk, nl, d_nl,
+    const unsigned gl = persistent_grid(ceil_div(nl > 0 ? nl : 1, kRleTile), 1);
+    const unsigned gr = persistent_grid(ceil_div(nr > 0 ? nr : 1, kRleTile), 1);
+    TQP_LAUNCH("rle", k_rle<K>, dim3(gl), dim3(kRleNT), 0, s, lk, nl, d_nl,
                        static_cast<K *>(L.uL), L.sL, &L.counters[0], tickets + 0, L.stL);
     if ((rc = check_launch("join rle left"))) return rc;
-    TQP_LAUNCH("rle", k_rle<K>, dim3(gr), dim3(kJoinNT), 0, s, rk, nr, d_nr,
+    TQP_LAUNCH("rle", k_rle<K>, dim3(gr), dim3(kRleNT), 0, s, rk, nr, d_nr,
                        static_cast<K *>(L.uR), L.sR, &L.counters[1], tickets + 2, L.stR);
     if ((rc = check_launch("join rle right"))) return rc;
     MatchArgs a = {};
@@ -381,18 +450,23 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     }
     a.d_nranges_ws = &L.counters[2];
     a.d_count = d_count;
+    if (want_pairs) {
+        a.tile_first = L.tile_first;
+        a.ntiles_out = L.ntiles_out;
+    }
     a.ticket = tickets + 4;
     a.status_m = L.stM;
     a.status_p = L.stP;
-    const unsigned gm = unsigned(ceil_div(nl > 0 ? nl : 1, kMatchTile));
+    const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, kMatchTile), 4);
     TQP_LAUNCH("join_match", k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
     if ((rc = check_launch("join match"))) return rc;
-    if ((out_l || out_r || out_pair_key) && cap > 0) {
-        int64_t g = ceil_div(cap, int64_t(kJoinNT) * kExpandPer);
-        if (g > 65536) g = 65536;
-        TQP_LAUNCH("join_expand", k_join_expand<K>, dim3(unsigned(g)), dim3(kJoinNT), 0, s, L.rng[0],
-                           L.rng[1], L.rng[2], L.rng[3], L.rng[4], L.off, &L.counters[2], d_count,
-                           cap, lrows, rrows, out_l, out_r, static_cast<K *>(out_pair_key));
+    if (want_pairs) {
+        int64_t g = L.ntiles_out;
+        if (g > 16384) g = 16384;
+        TQP_LAUNCH("join_expand", k_join_expand<K>, dim3(unsigned(g)), dim3(kJoinNT), 0, s,
+                   L.rng[0], L.rng[1], L.rng[2], L.rng[3], L.rng[4], L.off, L.tile_first,
+                   &L.counters[2], d_count, cap, lrows, rrows, out_l, out_r,
+                   static_cast<K *>(out_pair_key));
         if ((rc = check_launch("join expand"))) return rc;
     }
     return TQP_OK;
@@ -402,9 +476,10 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
 
 using namespace tqp;
 
-TQP_API size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags) {
-    if (nl < 0 || nr < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64)) return 0;
-    return join_layout(nullptr, nl, nr, dtype, flags).bytes;
+TQP_API size_t tqp_join_workspace_bytes(int64_t nl, int64_t nr, int dtype, uint32_t flags,
+                                        int64_t cap) {
+    if (nl < 0 || nr < 0 || cap < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64)) return 0;
+    return join_layout(nullptr, nl, nr, dtype, flags, cap).bytes;
 }
 
 TQP_API int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
@@ -429,7 +504,8 @@ TQP_API int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d
          (range_cap > 0 && (!ranges->key || !ranges->lstart || !ranges->lcnt || !ranges->rstart ||
                             !ranges->rcnt))))
         return set_error(TQP_EINVAL, "tqp_join: ranges mode needs five arrays and d_nranges");
-    const size_t need = tqp_join_workspace_bytes(nl, nr, lkey->dtype, flags);
+    const bool want_pairs = (out_l || out_r || out_pair_key) && cap > 0;
+    const size_t need = tqp_join_workspace_bytes(nl, nr, lkey->dtype, flags, want_pairs ? cap : 0);
     if (!ws || ws_bytes < need)
         return set_error(TQP_ECAPACITY, "tqp_join: workspace needs %zu bytes", need);
     hipStream_t s = as_stream(stream);

@@ -43,6 +43,18 @@ struct Carver {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Grid of a persistent tile loop: at most `per_cu` workgroups per compute
+// unit, never more than there are tiles.  Every tile id comes from one
+// device-wide ticket counter, whose atomic serializes (about 11 ns per ticket
+// on MI355X), so a grid of idle workgroups is not free: size it to the
+// machine, not to the capacity.
+constexpr int kComputeUnits = 256;
+inline unsigned persistent_grid(int64_t tiles, int per_cu) {
+    int64_t g = int64_t(kComputeUnits) * per_cu;
+    if (tiles < g) g = tiles;
+    return unsigned(g > 0 ? g : 1);
+}
+
 // Per-kernel timing (see profile.hip).  A scope records one event before and
 // one after the launches it encloses, on the launch stream, when enabled.
 bool profile_on();
@@ -78,6 +90,7 @@ int sort_impl(const void *key_in, int dtype, const int32_t *rows_in, int64_t n,
               const int64_t *d_n, int key_bits, int64_t key_min, void *key_out,
               int32_t *rows_out, void *ws, size_t ws_bytes, hipStream_t s);
 size_t sort_ws_bytes(int64_t n, int dtype, int key_bits);
+size_t sort_ws_bytes(int64_t n, int dtype, int key_bits, int pay_bytes);
 // Host-synchronizing derivation of (key_min, key_bits) for a column.
 int derive_key_range(const void *key, int dtype, int64_t n, const int64_t *d_n,
                      void *scratch16, hipStream_t s, int64_t *key_min, int *key_bits);

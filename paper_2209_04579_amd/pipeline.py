@@ -17,7 +17,7 @@ import torch
 
 from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_workspace_bytes,
                groupby_agg_into, groupby_workspace_bytes, join_into, join_workspace_bytes,
-               pack_key_into, sort_into, sort_workspace_bytes, workspace)
+               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, workspace)
 
 
 def key_range(col: torch.Tensor):
@@ -72,21 +72,24 @@ class StarQuery:
         self.pay_out = [torch.empty(max(n, 1), dtype=fact[k].dtype, device=dev) for k in pay]
         self.cnt = _i64(1, dev)
         self.ws_f = workspace(filter_workspace_bytes(n), dev)
-        # sorts
+        # sorts: the fact side carries its payload, the dim side its category
         self.fk_s = torch.empty(max(n, 1), dtype=fact["fk"].dtype, device=dev)
-        self.fk_perm = _i32(n, dev)
+        self.fpay_s = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_out[1:]]
         self.pk_s = torch.empty(max(nd, 1), dtype=dim["pk"].dtype, device=dev)
-        self.pk_perm = _i32(nd, dev)
-        self.ws_s = workspace(max(sort_workspace_bytes(n, fact["fk"].dtype),
-                                  sort_workspace_bytes(nd, dim["pk"].dtype)), dev)
+        self.cat_s = torch.empty(max(nd, 1), dtype=dim["cat"].dtype, device=dev)
+        self.ws_s = workspace(max(sort_workspace_bytes(n, fact["fk"].dtype,
+                                                       pay_bytes_of(self.fpay_s)),
+                                  sort_workspace_bytes(nd, dim["pk"].dtype, 4)), dev)
         # join: pk is unique for these schemas, so pairs <= |filtered fact|;
-        # the pair count is checked after the run.
+        # the pair count is checked after the run.  Pairs are positions in
+        # the sorted sides, so later reads of the sorted payload are sequential.
         self.cap = max(n, 1)
         self.out_l = _i32(self.cap, dev)
         self.out_r = _i32(self.cap, dev)
         self.out_k = torch.empty(self.cap, dtype=fact["fk"].dtype, device=dev)
         self.npairs = _i64(1, dev)
-        self.ws_j = workspace(join_workspace_bytes(n, nd, fact["fk"].dtype, JOIN_SORTED), dev)
+        self.ws_j = workspace(join_workspace_bytes(n, nd, fact["fk"].dtype, JOIN_SORTED,
+                                                   self.cap), dev)
         # group-bys
         self.gkey = _i64(self.cap, dev)
         if mode == "q1":
@@ -116,29 +119,30 @@ class StarQuery:
         # 1. WHERE day < cut, carrying the payload columns
         filter_into([f["day"]], [(0, "<", self.cut)], self.pay_in, self.pay_out, None,
                     self.cnt, self.ws_f)
-        fk_c = self.pay_out[0]
-        # 2. sort both join sides (stable; row ids carried)
-        sort_into(fk_c, None, self.n, self.fk_s, self.fk_perm, self.ws_s, d_n=self.cnt,
-                  key_bits=self.jk_bits, key_min=self.jk_min)
-        sort_into(d["pk"], None, self.nd, self.pk_s, self.pk_perm, self.ws_s,
-                  key_bits=self.jk_bits, key_min=self.jk_min)
-        # 3. merge join of the sorted sides
+        # 2. sort both join sides (stable), payload moving with the keys
+        sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
+                  key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
+                  pay_out=self.fpay_s)
+        sort_into(d["pk"], None, self.nd, self.pk_s, None, self.ws_s, key_bits=self.jk_bits,
+                  key_min=self.jk_min, pay_in=[d["cat"]], pay_out=[self.cat_s])
+        # 3. merge join of the sorted sides -> (left position, right position, key)
         join_into(self.fk_s, self.pk_s, JOIN_SORTED, self.out_l, self.out_r, self.out_k,
-                  self.cap, self.npairs, self.ws_j, lrows=self.fk_perm, rrows=self.pk_perm,
-                  d_nl=self.cnt)
+                  self.cap, self.npairs, self.ws_j, d_nl=self.cnt)
         # 4. group-bys over the joined rows
+        qty_s = self.fpay_s[0]
         if self.mode == "q1":
-            pack_key_into([(d["cat"], self.out_r, 0, 1)], self.cap, self.gkey, d_n=self.npairs)
-            vals = [self.pay_out[1]]
+            pack_key_into([(self.cat_s, self.out_r, 0, 1)], self.cap, self.gkey, d_n=self.npairs)
+            vals = [qty_s]
         else:
-            pack_key_into([(self.pay_out[3], self.out_l, 0, 2), (d["cat"], self.out_r, 2, 1)],
+            price_s, flag_s = self.fpay_s[1], self.fpay_s[2]
+            pack_key_into([(flag_s, self.out_l, 0, 2), (self.cat_s, self.out_r, 2, 1)],
                           self.cap, self.gkey, d_n=self.npairs)
-            vals = [self.pay_out[1], self.pay_out[2]]
+            vals = [qty_s, price_s]
         groupby_agg_into(self.gkey[:self.cap], vals, self.ga_aggs, self.ga_key, self.ga_out,
                          self.ga_ng, self.ws_ga, flags=self.ga_flags, key_lo=self.ga_lo,
                          key_span=self.ga_span, val_rows=self.out_l, d_n=self.npairs)
         if self.mode == "q2":
-            groupby_agg_into(self.out_k[:self.cap], [self.pay_out[1]], [("sum", 0), ("count",)],
+            groupby_agg_into(self.out_k[:self.cap], [qty_s], [("sum", 0), ("count",)],
                              self.gb_key, self.gb_out, self.gb_ng, self.ws_gb, flags=GB_SORTED,
                              val_rows=self.out_l, d_n=self.npairs)
 

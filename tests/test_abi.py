@@ -40,7 +40,9 @@ def test_argument_errors_are_reported_without_a_gpu():
     # null descriptors: rejected before anything touches a device
     assert L.tqp_filter(None, 0, None, 0, None, None, 0, None, None, None, 0, None) == tqp.TQP_EINVAL
     assert b"ncols" in L.tqp_last_error()
-    assert L.tqp_sort(None, None, 0, None, 0, 0, None, None, None, 0, None) == tqp.TQP_EINVAL
+    assert L.tqp_sort(None, None, 0, None, 0, 0, None, None, None, None, 0, None, 0,
+                      None) == tqp.TQP_EINVAL
     assert L.tqp_groupby_workspace_bytes(10, 9, 1, 0, 0) == 0       # bad dtype
     assert L.tqp_filter_workspace_bytes(1 << 20) > 0
-    assert L.tqp_sort_workspace_bytes(1 << 20, 2) > 8 * (1 << 20)
+    assert L.tqp_sort_workspace_bytes(1 << 20, 2, 0) > 8 * (1 << 20)
+    assert L.tqp_sort_workspace_bytes(1 << 20, 2, 17) > L.tqp_sort_workspace_bytes(1 << 20, 2, 0)

@@ -143,6 +143,24 @@ def test_sort_carries_rows_and_explicit_bits(tqp):
     assert np.array_equal(host(r), rows[perm])
 
 
+@pytest.mark.parametrize("n", [1, 4097, 300_007])
+def test_sort_carries_payload_columns(tqp, n):
+    keys = dg.uniform_int(n, 1, n, -500, 500, np.int64)
+    p8 = dg.uniform_int(n, 2, n, -128, 128, np.int8)
+    p32 = dg.uniform_int(n, 3, n, -(2 ** 31), 2 ** 31 - 1, np.int64).astype(np.int32)
+    p64 = dg.raw_u64(n, 4, n).view(np.int64)
+    sk, rows, (q8, q32, q64) = tqp.sort(dev(keys), payload=[dev(p8), dev(p32), dev(p64)])
+    ok, perm = oracle.sort(keys)
+    assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    assert np.array_equal(host(q8), p8[perm])
+    assert np.array_equal(host(q32), p32[perm])
+    assert np.array_equal(host(q64), p64[perm])
+    sk2, none, (q64b,) = tqp.sort(dev(keys), payload=[dev(p64)], want_rows=False,
+                                  key_bits=10, key_min=-500)
+    assert none is None
+    assert np.array_equal(host(sk2), ok) and np.array_equal(host(q64b), p64[perm])
+
+
 def test_sort_large_zipf_is_deterministic(tqp):
     n = 30_000_000
     keys = dev(sort_case(n, np.int32, "zipf", seed=3))
