@@ -108,6 +108,20 @@ void tqp_profile_enable(int on);
 int tqp_profile_collect(char *buf, size_t len);
 void tqp_profile_reset(void);
 
+/* Launch knobs, the control surface of the autotuner (Section 5's batched
+ * execution tunes launch shapes per workload).  Each knob is an integer in a
+ * fixed range with a default; today all are "workgroups per compute unit" of
+ * one persistent kernel's grid: "filter.per_cu", "sort.per_cu", "rle.per_cu",
+ * "match.per_cu", "gbscan.per_cu".  Knobs change launch shapes only, never
+ * results.  They are process-wide and read when a call enqueues its kernels;
+ * setting them concurrently with calls on other threads is a race.
+ *   tqp_tune_set: TQP_EINVAL for an unknown name or a value out of range.
+ *   tqp_tune_get: writes value / lo / hi (each pointer may be NULL).
+ *   tqp_tune_name: name of knob `index` (0-based), NULL past the last one. */
+int tqp_tune_set(const char *name, int value);
+int tqp_tune_get(const char *name, int *value, int *lo, int *hi);
+const char *tqp_tune_name(int index);
+
 /* ------------------------------------------------------------------------
  * tqp_filter -- WHERE with stream compaction (Section 2.3: Q6's filters).
  * Keeps row i of an n-row table when every predicate holds; n = cols[0].len
@@ -134,13 +148,15 @@ int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n,
                const int64_t *d_n, const tqp_col *dst, void *stream);
 
 /* ------------------------------------------------------------------------
- * tqp_pack_key -- out[i] = sum over terms of mul * f(col[row]) (int64, mod
- * 2^64) for i < count: the packed multi-column group key, e.g.
- * flag * 2 + (cat mod 2).  Each term's rows (if given) hold >= count entries.
- * nterms in [1, 4].  Row ids outside the column read as 0.
+ * tqp_pack_key -- out[i] = sum over terms of mul * f(col[row]) (mod 2^64,
+ * then truncated to out's dtype, int32 or int64) for i < count: the packed
+ * multi-column group key, e.g. flag * 2 + (cat mod 2), or an instance prefix
+ * (inst << 20) + fk.  A term whose column has no data (col.data NULL) adds
+ * the constant mul.  Each term's rows (if given) hold >= count entries.
+ * nterms in [1, 4].  Row ids outside the column read as 0.  out->len >= n.
  * ---------------------------------------------------------------------- */
 int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n,
-                 const int64_t *d_n, int64_t *out, void *stream);
+                 const int64_t *d_n, const tqp_col *out, void *stream);
 
 /* ------------------------------------------------------------------------
  * tqp_sort -- stable ascending sort of signed int32/int64 keys (LSD radix),
@@ -230,6 +246,52 @@ int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t flags,
                     const tqp_col *out_key, int64_t *const *out_aggs,
                     int64_t *d_ngroups,
                     void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned CDF partitioner.  A model F maps a key to [0, 1], monotone
+ * non-decreasing: a 1 -> 32 -> 1 FP32 network (ramp units clamp(w x + c, 0, 1),
+ * positive weights) over the key normalised to [0, 1], refined by nleaf
+ * piecewise-linear leaves.  Buckets floor(F * 2^bits) are contiguous key
+ * ranges, so grouping keys by bucket and sorting inside each bucket sorts
+ * them; the model only decides how balanced the buckets are.
+ *
+ * tqp_lcdf_train: samples every sample_stride-th key of ncols (1 or 2)
+ *   int32/int64 device columns, sorts the sample, fits the network by `steps`
+ *   full-batch Adam steps (learning rate lr) on the squared error against the
+ *   sample ranks, then fits the leaves.  `model` is a device buffer of
+ *   tqp_lcdf_model_bytes(nleaf) bytes (nleaf in [1, 65536]).  No host sync.
+ * tqp_lcdf_buckets: out_bucket[i] = bucket of keys[i] for 2^bucket_bits
+ *   buckets (bits in [1, 24]); for inspection and tests.
+ * ---------------------------------------------------------------------- */
+size_t tqp_lcdf_model_bytes(int nleaf);
+size_t tqp_lcdf_train_workspace_bytes(int64_t total_keys, int sample_stride);
+int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, int nleaf, int steps,
+                   float lr, void *model, size_t model_bytes, void *ws, size_t ws_bytes,
+                   void *stream);
+int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
+                     int32_t *out_bucket, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_partition_sort -- the same stable ascending sort as tqp_sort (same
+ * out_key and out_rows bytes), by partitioning into 2^bucket_bits key-range
+ * buckets (bucket_bits in [1, 16]) and sorting each bucket on its own.
+ *   mode TQP_PART_LEARNED: buckets from `model` (trained by tqp_lcdf_train);
+ *   mode TQP_PART_RADIX:   buckets = top bucket_bits of key - key_min over
+ *                          key_bits bits (key_bits 0 = derive on the device).
+ *   in_rows  : optional row ids (NULL = positions); out_rows required.
+ *   h_stats  : optional HOST array of 4: largest bucket, buckets sorted by
+ *              the radix fallback, keys in them, single-valued large buckets.
+ * Buckets of more than 4096 keys with distinct keys fall back to the radix
+ * sort over their own key range.  SYNCHRONIZES the stream once (to read the
+ * fallback list).  Workspace: tqp_partition_sort_workspace_bytes.
+ * ---------------------------------------------------------------------- */
+#define TQP_PART_LEARNED 1u
+#define TQP_PART_RADIX   2u
+size_t tqp_partition_sort_workspace_bytes(int64_t n, int dtype, int bucket_bits);
+int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint32_t mode,
+                       const void *model, int bucket_bits, int key_bits, int64_t key_min,
+                       const tqp_col *out_key, int32_t *out_rows, int64_t *h_stats,
+                       void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

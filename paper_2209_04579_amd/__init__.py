@@ -97,7 +97,7 @@ def lib():
         L.tqp_gather.restype = i32
         L.tqp_gather.argtypes = [P(Col), vp, i64, vp, P(Col), vp]
         L.tqp_pack_key.restype = i32
-        L.tqp_pack_key.argtypes = [P(KeyTerm), i32, i64, vp, vp, vp]
+        L.tqp_pack_key.argtypes = [P(KeyTerm), i32, i64, vp, P(Col), vp]
         L.tqp_sort_workspace_bytes.restype = sz
         L.tqp_sort_workspace_bytes.argtypes = [i64, i32, i32]
         L.tqp_sort.restype = i32
@@ -110,6 +110,13 @@ def lib():
                                P(Ranges), i64, vp, vp, sz, vp]
         L.tqp_groupby_workspace_bytes.restype = sz
         L.tqp_groupby_workspace_bytes.argtypes = [i64, i32, i32, u32, i64]
+        L.tqp_tune_set.restype = i32
+        L.tqp_tune_set.argtypes = [ctypes.c_char_p, i32]
+        L.tqp_tune_get.restype = i32
+        L.tqp_tune_get.argtypes = [ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_int),
+                                   P(ctypes.c_int)]
+        L.tqp_tune_name.restype = ctypes.c_char_p
+        L.tqp_tune_name.argtypes = [i32]
         L.tqp_profile_enable.restype = None
         L.tqp_profile_enable.argtypes = [i32]
         L.tqp_profile_collect.restype = i32
@@ -205,11 +212,15 @@ def gather(src, idx):
 
 
 def pack_key_into(terms, n, out, d_n=None, stream=None):
-    """terms: [(column, rows or None, mod, mul)] -> out[i] = sum mul * f(col[row])."""
+    """terms: [(column or None, rows or None, mod, mul)] -> out[i] = sum mul * f(col[row]).
+
+    A term with column None adds the constant mul.  out is int32 or int64."""
     arr = (KeyTerm * len(terms))()
     for i, (c, rows, mod, mul) in enumerate(terms):
-        arr[i] = KeyTerm(_col(c), _ptr(rows), int(mod), int(mul))
-    _check(lib().tqp_pack_key(arr, len(terms), int(n), _ptr(d_n), _ptr(out), _stream(stream)))
+        col = _col(c) if c is not None else Col(None, 0, 3, 0)
+        arr[i] = KeyTerm(col, _ptr(rows), int(mod), int(mul))
+    _check(lib().tqp_pack_key(arr, len(terms), int(n), _ptr(d_n), ctypes.byref(_col(out)),
+                              _stream(stream)))
 
 
 # ------------------------------------------------------------------- sort ----
@@ -342,6 +353,28 @@ def groupby_agg(key, vals, aggs, flags=0, key_lo=0, key_span=0, val_rows=None, c
     return ok[:g], [o[:g] for o in outs]
 
 
+# ------------------------------------------------------------ tuning knobs ----
+
+def tune_knobs() -> dict:
+    """{knob name: (value, lo, hi)} for every library tuning knob."""
+    L = lib()
+    out = {}
+    i = 0
+    while True:
+        name = L.tqp_tune_name(i)
+        if not name:
+            break
+        v, lo, hi = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.tqp_tune_get(name, ctypes.byref(v), ctypes.byref(lo), ctypes.byref(hi)))
+        out[name.decode()] = (v.value, lo.value, hi.value)
+        i += 1
+    return out
+
+
+def tune_set(name: str, value: int):
+    _check(lib().tqp_tune_set(name.encode(), int(value)))
+
+
 # -------------------------------------------------------------- profiling ----
 
 def profile_enable(on: bool = True):
@@ -364,3 +397,102 @@ def profile_collect() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+# ------------------------------------------------------ learned partitioner ----
+
+PART_LEARNED, PART_RADIX = 1, 2
+
+
+def _bind_lcdf(L):
+    vp, i64, i32, u32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
+                             ctypes.c_size_t)
+    P = ctypes.POINTER
+    L.tqp_lcdf_model_bytes.restype = sz
+    L.tqp_lcdf_model_bytes.argtypes = [i32]
+    L.tqp_lcdf_train_workspace_bytes.restype = sz
+    L.tqp_lcdf_train_workspace_bytes.argtypes = [i64, i32]
+    L.tqp_lcdf_train.restype = i32
+    L.tqp_lcdf_train.argtypes = [P(Col), i32, i32, i32, i32, ctypes.c_float, vp, sz, vp, sz, vp]
+    L.tqp_lcdf_buckets.restype = i32
+    L.tqp_lcdf_buckets.argtypes = [vp, P(Col), i32, vp, vp]
+    L.tqp_partition_sort_workspace_bytes.restype = sz
+    L.tqp_partition_sort_workspace_bytes.argtypes = [i64, i32, i32]
+    L.tqp_partition_sort.restype = i32
+    L.tqp_partition_sort.argtypes = [P(Col), vp, u32, vp, i32, i32, i64, P(Col), vp, vp, vp, sz,
+                                     vp]
+
+
+def lcdf_train(cols, sample_stride=100, nleaf=4096, steps=200, lr=1e-3, stream=None):
+    """Trains the learned CDF on the keys of cols (1 or 2 device columns).
+
+    Returns the model as a device uint8 tensor."""
+    L = lib()
+    if not hasattr(L, "_lcdf_bound"):
+        _bind_lcdf(L)
+        L._lcdf_bound = True
+    dev = cols[0].device
+    model = torch.zeros(L.tqp_lcdf_model_bytes(nleaf), dtype=torch.uint8, device=dev)
+    total = sum(c.numel() for c in cols)
+    ws = workspace(L.tqp_lcdf_train_workspace_bytes(total, sample_stride), dev)
+    _check(L.tqp_lcdf_train(_cols(cols), len(cols), sample_stride, nleaf, steps, float(lr),
+                            model.data_ptr(), model.numel(), ws.data_ptr(), ws.numel(),
+                            _stream(stream)))
+    return model
+
+
+def lcdf_model_info(model) -> dict:
+    """Reads the training summary fields of a model (synchronizes)."""
+    raw = model[:64].cpu().numpy()
+    import numpy as np
+    nleaf, steps = np.frombuffer(raw[16:24].tobytes(), dtype=np.int32)
+    loss_first, loss_last = np.frombuffer(raw[24:32].tobytes(), dtype=np.float32)
+    return {"nleaf": int(nleaf), "steps": int(steps), "loss_first": float(loss_first),
+            "loss_last": float(loss_last)}
+
+
+def lcdf_buckets(model, keys, bucket_bits, stream=None):
+    L = lib()
+    if not hasattr(L, "_lcdf_bound"):
+        _bind_lcdf(L)
+        L._lcdf_bound = True
+    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _check(L.tqp_lcdf_buckets(model.data_ptr(), ctypes.byref(_col(keys)), int(bucket_bits),
+                              _ptr(out), _stream(stream)))
+    return out
+
+
+def partition_sort_into(key, in_rows, mode, model, bucket_bits, out_key, out_rows, ws,
+                        key_bits=0, key_min=0, stream=None):
+    """Stable sort by key-range buckets; returns the host stats dict (synchronizes)."""
+    L = lib()
+    if not hasattr(L, "_lcdf_bound"):
+        _bind_lcdf(L)
+        L._lcdf_bound = True
+    st = (ctypes.c_int64 * 4)()
+    _check(L.tqp_partition_sort(ctypes.byref(_col(key)), _ptr(in_rows), int(mode),
+                                _ptr(model), int(bucket_bits), int(key_bits), int(key_min),
+                                ctypes.byref(_col(out_key)), _ptr(out_rows), st, _ptr(ws),
+                                ws.numel(), _stream(stream)))
+    return {"max_bucket": st[0], "fallback_buckets": st[1], "fallback_keys": st[2],
+            "single_valued_big": st[3]}
+
+
+def partition_sort_workspace_bytes(n, dtype, bucket_bits):
+    L = lib()
+    if not hasattr(L, "_lcdf_bound"):
+        _bind_lcdf(L)
+        L._lcdf_bound = True
+    return L.tqp_partition_sort_workspace_bytes(n, DTYPES[dtype], bucket_bits)
+
+
+def partition_sort(key, mode=PART_LEARNED, model=None, bucket_bits=12, in_rows=None,
+                   key_bits=0, key_min=0):
+    """Returns (sorted keys, row ids, stats)."""
+    n = key.numel()
+    ok = torch.empty_like(key)
+    rows = torch.empty(n, dtype=torch.int32, device=key.device)
+    ws = workspace(partition_sort_workspace_bytes(n, key.dtype, bucket_bits), key.device)
+    st = partition_sort_into(key, in_rows, mode, model, bucket_bits, ok, rows, ws,
+                             key_bits=key_bits, key_min=key_min)
+    return ok, rows, st

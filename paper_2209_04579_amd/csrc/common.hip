@@ -142,6 +142,55 @@ int derive_key_range(const void *key, int dtype, int64_t n, const int64_t *d_n,
 
 }  // namespace tqp
 
+namespace tqp {
+
+struct KnobDef {
+    const char *name;
+    int def, lo, hi;
+};
+static const KnobDef kKnobs[kTuneCount] = {
+    {"filter.per_cu", 4, 1, 8},
+    {"sort.per_cu", 2, 1, 2},
+    {"rle.per_cu", 1, 1, 2},
+    {"match.per_cu", 4, 1, 8},
+    {"gbscan.per_cu", 2, 1, 4},
+};
+static int g_knob[kTuneCount] = {4, 2, 1, 4, 2};
+
+int tune(TuneKnob k) { return g_knob[k]; }
+
+}  // namespace tqp
+
 TQP_API const char *tqp_last_error(void) { return tqp::g_err; }
+
+TQP_API int tqp_tune_set(const char *name, int value) {
+    tqp::clear_error();
+    for (int k = 0; k < tqp::kTuneCount; k++) {
+        if (name && strcmp(name, tqp::kKnobs[k].name) == 0) {
+            if (value < tqp::kKnobs[k].lo || value > tqp::kKnobs[k].hi)
+                return tqp::set_error(TQP_EINVAL, "tqp_tune_set: %s must be in [%d, %d]", name,
+                                      tqp::kKnobs[k].lo, tqp::kKnobs[k].hi);
+            tqp::g_knob[k] = value;
+            return TQP_OK;
+        }
+    }
+    return tqp::set_error(TQP_EINVAL, "tqp_tune_set: unknown knob %s", name ? name : "(null)");
+}
+
+TQP_API int tqp_tune_get(const char *name, int *value, int *lo, int *hi) {
+    for (int k = 0; k < tqp::kTuneCount; k++) {
+        if (name && strcmp(name, tqp::kKnobs[k].name) == 0) {
+            if (value) *value = tqp::g_knob[k];
+            if (lo) *lo = tqp::kKnobs[k].lo;
+            if (hi) *hi = tqp::kKnobs[k].hi;
+            return TQP_OK;
+        }
+    }
+    return tqp::set_error(TQP_EINVAL, "tqp_tune_get: unknown knob %s", name ? name : "(null)");
+}
+
+TQP_API const char *tqp_tune_name(int index) {
+    return index >= 0 && index < tqp::kTuneCount ? tqp::kKnobs[index].name : nullptr;
+}
 
 TQP_API const char *tqp_version(void) { return "tqp-mi355x 0.1 (gfx950)"; }

@@ -247,7 +247,7 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
     a.n = n;
     a.ticket = reinterpret_cast<uint32_t *>(words);
     a.status = words + 1;
-    const unsigned grid = persistent_grid(ntiles, 4);
+    const unsigned grid = persistent_grid(ntiles, tune(kTuneFilterPerCu));
     TQP_LAUNCH("filter", k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
     return check_launch("tqp_filter");
 }

@@ -41,13 +41,18 @@ struct PackArgs {
     int32_t nterms;
 };
 
+template <class O>
 __global__ __launch_bounds__(kGatherNT) void k_pack_key(PackArgs a, int64_t n, const int64_t *d_n,
-                                                        int64_t *__restrict__ out) {
+                                                        O *__restrict__ out) {
     const int64_t cnt = count_of(d_n, n);
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cnt;
          i += int64_t(gridDim.x) * blockDim.x) {
         uint64_t acc = 0;
         for (int t = 0; t < a.nterms; t++) {
+            if (!a.col[t]) {                       // constant term
+                acc += uint64_t(a.mul[t]);
+                continue;
+            }
             const int64_t r = a.rows[t] ? int64_t(a.rows[t][i]) : i;
             int64_t v = (r >= 0 && r < a.len[t]) ? load_any(a.col[t], a.dt[t], r) : 0;
             if (a.mod[t] > 0) {
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(kGatherNT) void k_pack_key(PackArgs a, int64_t n, c
             }
             acc += uint64_t(a.mul[t]) * uint64_t(v);
         }
-        out[i] = int64_t(acc);
+        out[i] = O(int64_t(acc));
     }
 }
 
@@ -105,15 +110,21 @@ TQP_API int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n, const 
 }
 
 TQP_API int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n, const int64_t *d_n,
-                         int64_t *out, void *stream) {
+                         const tqp_col *out, void *stream) {
     clear_error();
     if (!terms || nterms < 1 || nterms > 4)
         return set_error(TQP_EINVAL, "tqp_pack_key: nterms must be in [1, 4]");
-    if (n < 0 || (n > 0 && !out)) return set_error(TQP_EINVAL, "tqp_pack_key: bad output");
+    if (n < 0 || !out || (out->dtype != TQP_INT32 && out->dtype != TQP_INT64) || out->len < n ||
+        (n > 0 && !out->data))
+        return set_error(TQP_EINVAL, "tqp_pack_key: bad output column");
     PackArgs a = {};
     for (int t = 0; t < nterms; t++) {
         const tqp_keyterm &k = terms[t];
-        if (!dtype_ok(k.col.dtype) || (k.col.len > 0 && !k.col.data) || k.mod < 0)
+        if (!k.col.data) {                          // constant term
+            a.mul[t] = k.mul;
+            continue;
+        }
+        if (!dtype_ok(k.col.dtype) || k.mod < 0)
             return set_error(TQP_EINVAL, "tqp_pack_key: term %d is invalid", t);
         if (!k.rows && k.col.len < n)
             return set_error(TQP_EINVAL, "tqp_pack_key: term %d column is shorter than n", t);
@@ -126,7 +137,12 @@ TQP_API int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n, const 
     }
     a.nterms = nterms;
     if (n == 0) return TQP_OK;
-    TQP_LAUNCH("pack_key", k_pack_key, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, as_stream(stream),
-                       a, n, d_n, out);
+    hipStream_t s = as_stream(stream);
+    if (out->dtype == TQP_INT32)
+        TQP_LAUNCH("pack_key", k_pack_key<int32_t>, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, s, a,
+                   n, d_n, static_cast<int32_t *>(out->data));
+    else
+        TQP_LAUNCH("pack_key", k_pack_key<int64_t>, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, s, a,
+                   n, d_n, static_cast<int64_t *>(out->data));
     return check_launch("tqp_pack_key");
 }

@@ -513,7 +513,7 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
     }
     rc = fill_u64(L.words, 0, L.nwords, s);
     if (rc) return rc;
-    const unsigned grid = persistent_grid(L.ntiles, 2);
+    const unsigned grid = persistent_grid(L.ntiles, tune(kTuneGbScanPerCu));
     K *ok = static_cast<K *>(out_key->data);
     const int64_t es = n > 0 ? n : int64_t(1);
     uint32_t *tk = reinterpret_cast<uint32_t *>(L.words);

@@ -414,8 +414,8 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     rc = fill_u64(L.words, 0, L.nwords, s);
     if (rc) return rc;
     uint32_t *tickets = reinterpret_cast<uint32_t *>(L.words);
-    const unsigned gl = persistent_grid(ceil_div(nl > 0 ? nl : 1, kRleTile), 1);
-    const unsigned gr = persistent_grid(ceil_div(nr > 0 ? nr : 1, kRleTile), 1);
+    const unsigned gl = persistent_grid(ceil_div(nl > 0 ? nl : 1, kRleTile), tune(kTuneRlePerCu));
+    const unsigned gr = persistent_grid(ceil_div(nr > 0 ? nr : 1, kRleTile), tune(kTuneRlePerCu));
     TQP_LAUNCH("rle", k_rle<K>, dim3(gl), dim3(kRleNT), 0, s, lk, nl, d_nl,
                        static_cast<K *>(L.uL), L.sL, &L.counters[0], tickets + 0, L.stL);
     if ((rc = check_launch("join rle left"))) return rc;
@@ -457,7 +457,7 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
     a.ticket = tickets + 4;
     a.status_m = L.stM;
     a.status_p = L.stP;
-    const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, kMatchTile), 4);
+    const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, kMatchTile), tune(kTuneMatchPerCu));
     TQP_LAUNCH("join_match", k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
     if ((rc = check_launch("join match"))) return rc;
     if (want_pairs) {

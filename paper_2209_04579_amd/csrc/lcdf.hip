@@ -1,0 +1,735 @@
+// Learned CDF partitioner and the partition sort it drives.
+//
+// Model.  F(key) approximates the CDF of the key distribution:
+//   x    = (key - kmin) / (kmax - kmin), computed in float64, then float32,
+//   root = sum_j v_j * clamp(w_j * x + c_j, 0, 1) + d      (1 -> 32 -> 1 MLP)
+//   leaf = clamp(floor(root * L), 0, L - 1)
+//   F    = clamp(a_leaf * x + b_leaf, lo_leaf, hi_leaf)      (piecewise linear)
+// with w_j, v_j > 0.  Every step is monotone non-decreasing in x, under
+// float rounding too (round-to-nearest is monotone), and the leaves' clamps
+// are ordered (hi_k <= lo_{k+1}), so F is monotone: a bucket
+// floor(F * 2^bits) is a contiguous key range.  That is the one property the
+// partition sort needs; how well F fits only changes the speed.
+//
+// Training (all on the device, no host round trip): a strided 1% sample of
+// the keys is sorted; the root's 32 ramps start on the sample's 32-quantiles
+// and are refined by full-batch Adam on the mean squared error against the
+// sample ranks; each leaf is then a least-squares line through the sample
+// points the root routes to it, clamped to their rank range.
+//
+// Partition sort.  Two stable radix passes on the bucket number group the
+// keys by bucket (input order kept inside a bucket); one workgroup per bucket
+// then sorts its bucket in LDS by (key, position), which is the stable order.
+// A bucket larger than the LDS tile is left as is when all its keys are equal
+// (already in stable order), otherwise it is sorted by the plain radix sort
+// over its own key range.  With bucket = top bits of (key - kmin) the same
+// pipeline is the plain MSD radix partitioner the learned one is judged
+// against.
+#include <math.h>
+#include <vector>
+
+#include "radix.hpp"
+
+namespace tqp {
+
+constexpr int kHidden = 32;
+constexpr int kNParam = 3 * kHidden + 1;     // centre, log-width, log-height per ramp; d
+constexpr int kTrainPoints = 16384;          // root training set (sample points, even ranks)
+constexpr int kGradBlocks = 64;
+constexpr int kLeafMax = 65536;
+constexpr int kBucketCap = 4096;             // keys sorted in LDS by one workgroup
+constexpr int kBucketNT = 256;
+
+struct LcdfModel {
+    int64_t kmin;
+    double inv_span;
+    int32_t nleaf;
+    int32_t steps_done;
+    float loss_first, loss_last;
+    // effective root parameters used by inference
+    float w[kHidden], c[kHidden], v[kHidden], d;
+    // training state: ramp centre, log width, log height, bias; Adam moments
+    float theta[kNParam], m1[kNParam], m2[kNParam];
+    float pad[3];
+    float4 leaf[1];                           // nleaf entries: (a, b, lo, hi)
+};
+
+static size_t model_bytes(int nleaf) {
+    return sizeof(LcdfModel) + sizeof(float4) * size_t(nleaf > 0 ? nleaf - 1 : 0);
+}
+
+__device__ __forceinline__ float lcdf_x(const LcdfModel *m, int64_t key) {
+    const uint64_t off = uint64_t(key) - uint64_t(m->kmin);
+    double x = key < m->kmin ? 0.0 : double(off) * m->inv_span;
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    return float(x);
+}
+
+__device__ __forceinline__ float lcdf_root(const LcdfModel *m, float x) {
+    float y = m->d;
+#pragma unroll
+    for (int j = 0; j < kHidden; j++) {
+        float h = fmaf(m->w[j], x, m->c[j]);
+        h = h < 0.f ? 0.f : (h > 1.f ? 1.f : h);
+        y = fmaf(m->v[j], h, y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
+    float t = root * float(m->nleaf);
+    int k = t <= 0.f ? 0 : (t >= float(m->nleaf) ? m->nleaf - 1 : int(t));
+    return k;
+}
+
+__device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
+    const float x = lcdf_x(m, key);
+    const float4 L = m->leaf[lcdf_leaf(m, lcdf_root(m, x))];
+    float f = fmaf(L.x, x, L.y);
+    return f < L.z ? L.z : (f > L.w ? L.w : f);
+}
+
+// Bucket ordinals for run_radix: learned, or the top bits of key - kmin.
+template <class K> struct LearnedOrd {
+    const LcdfModel *m;
+    float scale;                                // 2^bucket_bits
+    uint32_t top;                               // 2^bucket_bits - 1
+    __device__ __forceinline__ uint64_t operator()(K k) const {
+        const float f = lcdf_eval(m, int64_t(k)) * scale;
+        uint32_t b = f <= 0.f ? 0u : uint32_t(f);
+        return b > top ? top : b;
+    }
+};
+
+template <class K> struct MsdOrd {
+    K key_min;
+    int shift;
+    __device__ __forceinline__ uint64_t operator()(K k) const {
+        using U = typename KeyTraits<K>::U;
+        return uint64_t(U(U(k) - U(key_min))) >> shift;
+    }
+};
+
+// ---- training ------------------------------------------------------------------
+
+__global__ void k_lcdf_sample(const void *c0, int dt0, int64_t n0, const void *c1, int dt1,
+                              int64_t n1, int64_t stride, int64_t *out) {
+    const int64_t m0 = ceil_div(n0, stride), m1 = ceil_div(n1, stride);
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < m0 + m1;
+         t += int64_t(gridDim.x) * blockDim.x)
+        out[t] = t < m0 ? load_any(c0, dt0, t * stride) : load_any(c1, dt1, (t - m0) * stride);
+}
+
+// One workgroup: normalization from the sorted sample, the training points,
+// and the ramps' starting positions on the sample's quantiles.
+__global__ __launch_bounds__(256) void k_lcdf_init(const int64_t *sorted, int64_t m, int nleaf,
+                                                   LcdfModel *mod, float *tx, float *tq, int T) {
+    __shared__ int64_t s_min, s_max;
+    if (threadIdx.x == 0) {
+        s_min = sorted[0];
+        s_max = sorted[m - 1];
+        mod->kmin = s_min;
+        const double span = double(uint64_t(s_max) - uint64_t(s_min));
+        mod->inv_span = span > 0 ? 1.0 / span : 0.0;
+        mod->nleaf = nleaf;
+        mod->steps_done = 0;
+    }
+    __syncthreads();
+    const double inv = s_max > s_min ? 1.0 / double(uint64_t(s_max) - uint64_t(s_min)) : 0.0;
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const int64_t i = int64_t((double(t) + 0.5) * double(m) / double(T));
+        tx[t] = float(double(uint64_t(sorted[i]) - uint64_t(s_min)) * inv);
+        tq[t] = float((double(i) + 0.5) / double(m));
+    }
+    if (threadIdx.x < kHidden) {
+        const int j = threadIdx.x;
+        const int64_t ia = int64_t(double(j) * double(m - 1) / kHidden);
+        const int64_t ib = int64_t(double(j + 1) * double(m - 1) / kHidden);
+        const float xa = float(double(uint64_t(sorted[ia]) - uint64_t(s_min)) * inv);
+        const float xb = float(double(uint64_t(sorted[ib]) - uint64_t(s_min)) * inv);
+        float width = xb - xa;
+        if (width < 1e-9f) width = 1e-9f;
+        mod->theta[j] = 0.5f * (xa + xb);                    // centre
+        mod->theta[kHidden + j] = logf(width);               // log width
+        mod->theta[2 * kHidden + j] = logf(1.0f / kHidden);  // log height
+    }
+    if (threadIdx.x == 0) mod->theta[3 * kHidden] = 0.f;
+    for (int p = threadIdx.x; p < kNParam; p += blockDim.x) {
+        mod->m1[p] = 0.f;
+        mod->m2[p] = 0.f;
+    }
+}
+
+// Partial gradients of the mean squared error over one slice of the
+// training points; part[block][p] (p = kNParam holds the partial loss).
+__global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const float *tx,
+                                                   const float *tq, int T, float *part) {
+    __shared__ float s_th[kNParam];
+    __shared__ float s_red[256 / kWave][kNParam + 1];
+    for (int p = threadIdx.x; p < kNParam; p += blockDim.x) s_th[p] = mod->theta[p];
+    __syncthreads();
+    float g[kNParam + 1];
+#pragma unroll
+    for (int p = 0; p <= kNParam; p++) g[p] = 0.f;
+    const float inv_t = 2.0f / float(T);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        const float x = tx[t];
+        float y = s_th[3 * kHidden];
+        float z[kHidden];
+#pragma unroll
+        for (int j = 0; j < kHidden; j++) {
+            const float w = __expf(-s_th[kHidden + j]);
+            z[j] = (x - s_th[j]) * w + 0.5f;
+            const float h = z[j] < 0.f ? 0.f : (z[j] > 1.f ? 1.f : z[j]);
+            y += __expf(s_th[2 * kHidden + j]) * h;
+        }
+        const float err = y - tq[t];
+        const float e = err * inv_t;
+        g[kNParam] += err * err / float(T);
+        g[3 * kHidden] += e;
+#pragma unroll
+        for (int j = 0; j < kHidden; j++) {
+            const float w = __expf(-s_th[kHidden + j]);
+            const float v = __expf(s_th[2 * kHidden + j]);
+            const bool act = z[j] > 0.f && z[j] < 1.f;
+            const float h = z[j] < 0.f ? 0.f : (z[j] > 1.f ? 1.f : z[j]);
+            if (act) {
+                g[j] += e * v * (-w);
+                g[kHidden + j] += e * v * (-(z[j] - 0.5f));
+            }
+            g[2 * kHidden + j] += e * v * h;
+        }
+    }
+    const int w = wave_id();
+#pragma unroll
+    for (int p = 0; p <= kNParam; p++) {
+        float s = g[p];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o, kWave);
+        if (lane_id() == 0) s_red[w][p] = s;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p <= kNParam; p += blockDim.x) {
+        float s = 0.f;
+        for (int ww = 0; ww < 256 / kWave; ww++) s += s_red[ww][p];
+        part[blockIdx.x * (kNParam + 1) + p] = s;
+    }
+}
+
+// Sums the partial gradients in a fixed order and takes one Adam step.
+__global__ __launch_bounds__(128) void k_lcdf_adam(LcdfModel *mod, const float *part, int nparts,
+                                                   float lr) {
+    const int step = mod->steps_done + 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    for (int p = threadIdx.x; p <= kNParam; p += blockDim.x) {
+        float g = 0.f;
+        for (int b = 0; b < nparts; b++) g += part[b * (kNParam + 1) + p];
+        if (p == kNParam) {
+            if (step == 1) mod->loss_first = g;
+            mod->loss_last = g;
+            continue;
+        }
+        const float m1 = b1 * mod->m1[p] + (1.f - b1) * g;
+        const float m2 = b2 * mod->m2[p] + (1.f - b2) * g * g;
+        mod->m1[p] = m1;
+        mod->m2[p] = m2;
+        const float mh = m1 / (1.f - powf(b1, float(step)));
+        const float vh = m2 / (1.f - powf(b2, float(step)));
+        float th = mod->theta[p] - lr * mh / (sqrtf(vh) + 1e-12f);
+        if (p >= kHidden && p < 2 * kHidden && th < -40.f) th = -40.f;    // width > 0
+        mod->theta[p] = th;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) mod->steps_done = step;
+}
+
+// Effective root parameters: w = 1 / width, c = 0.5 - centre * w, v = height.
+__global__ void k_lcdf_finalize(LcdfModel *mod) {
+    const int j = threadIdx.x;
+    if (j < kHidden) {
+        const float w = expf(-mod->theta[kHidden + j]);
+        mod->w[j] = w;
+        mod->c[j] = 0.5f - mod->theta[j] * w;
+        mod->v[j] = expf(mod->theta[2 * kHidden + j]);
+    }
+    if (j == 0) mod->d = mod->theta[3 * kHidden];
+}
+
+// One workgroup per leaf: the contiguous run of sorted sample points the root
+// routes to it, and the least-squares line through (x, rank) over that run.
+__global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int64_t *sorted,
+                                                       int64_t m) {
+    __shared__ int64_t s_rng[2];
+    __shared__ double s_red[256 / kWave][5];
+    const int leaf = blockIdx.x;
+    if (threadIdx.x < 2) {
+        const int target = leaf + int(threadIdx.x);      // first point with leaf >= target
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (lcdf_leaf(mod, lcdf_root(mod, lcdf_x(mod, sorted[mid]))) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        s_rng[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t a0 = s_rng[0], a1 = s_rng[1];
+    double sx = 0, sq = 0, sxx = 0, sxq = 0, cnt = 0;
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+        const double x = double(lcdf_x(mod, sorted[i]));
+        const double q = (double(i) + 0.5) / double(m);
+        sx += x;
+        sq += q;
+        sxx += x * x;
+        sxq += x * q;
+        cnt += 1;
+    }
+    double vals[5] = {sx, sq, sxx, sxq, cnt};
+    const int w = wave_id();
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        double s = vals[k];
+        for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o, kWave);
+        if (lane_id() == 0) s_red[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[5] = {0, 0, 0, 0, 0};
+        for (int ww = 0; ww < 256 / kWave; ww++)
+            for (int k = 0; k < 5; k++) t[k] += s_red[ww][k];
+        float4 L;
+        if (a1 <= a0) {
+            L = make_float4(0.f, 0.f, -1.f, -1.f);          // empty: filled in later
+        } else {
+            const double n = t[4];
+            const double mx = t[0] / n, mq = t[1] / n;
+            const double vx = t[2] / n - mx * mx;
+            const double cxq = t[3] / n - mx * mq;
+            double a = vx > 1e-30 ? cxq / vx : 0.0;
+            if (a < 0) a = 0;
+            const double b = mq - a * mx;
+            const float lo = float((double(a0) + 0.5) / double(m));
+            const float hi = float((double(a1 - 1) + 0.5) / double(m));
+            L = make_float4(float(a), float(b), lo, hi);
+        }
+        mod->leaf[leaf] = L;
+    }
+}
+
+// Empty leaves take the rank reached by the leaves before them, so the
+// clamp ranges stay ordered; the first leaf's range starts at 0, the last
+// one's ends at 1.
+__global__ void k_lcdf_leaf_fill(LcdfModel *mod) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float prev = 0.f;
+    for (int k = 0; k < mod->nleaf; k++) {
+        float4 L = mod->leaf[k];
+        if (L.z < 0.f) {
+            L = make_float4(0.f, prev, prev, prev);
+        } else {
+            if (k == 0) L.z = 0.f;
+            prev = L.w;
+        }
+        mod->leaf[k] = L;
+    }
+    float4 last = mod->leaf[mod->nleaf - 1];
+    last.w = 1.f;
+    mod->leaf[mod->nleaf - 1] = last;
+}
+
+template <class K>
+__global__ void k_lcdf_buckets(const LcdfModel *mod, const K *keys, int64_t n, int bits,
+                               int32_t *out) {
+    LearnedOrd<K> ord{mod, float(1u << bits), (1u << bits) - 1};
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = int32_t(ord(keys[i]));
+}
+
+// ---- per-bucket finishing sort -------------------------------------------------
+
+struct BucketStats {
+    unsigned long long max_bucket;
+    unsigned long long overflow;        // multi-valued buckets larger than the LDS tile
+    unsigned long long overflow_keys;
+    unsigned long long single_big;      // single-valued buckets larger than the tile
+};
+
+struct Overflow {
+    int64_t start, len, kmin, kmax;
+};
+
+template <class K, class Ord>
+__global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *rows, int64_t n,
+                                                           Ord ord, BucketStats *stats,
+                                                           Overflow *ovf, int64_t ovf_cap) {
+    __shared__ int64_t s_rng[2];
+    __shared__ K s_key[kBucketCap];
+    __shared__ uint16_t s_idx[kBucketCap];
+    __shared__ int32_t s_row[kBucketCap];
+    const uint64_t b = blockIdx.x;
+    if (threadIdx.x < 2) {
+        const uint64_t target = b + threadIdx.x;       // first position with ordinal >= target
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ord(keys[mid]) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        s_rng[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t start = s_rng[0], size = s_rng[1] - s_rng[0];
+    if (size <= 1) return;
+    if (threadIdx.x == 0) atomicMax(&stats->max_bucket, (unsigned long long)size);
+    if (size > kBucketCap) {
+        // Block-wide min and max of the bucket.  When they are equal every key
+        // is, and the bucket (still in input order) is already stably sorted.
+        K lo = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
+        K hi = KeyTraits<K>::kBits == 32 ? K(INT32_MIN) : K(INT64_MIN);
+        for (int64_t i = start + threadIdx.x; i < start + size; i += kBucketNT) {
+            const K x = keys[i];
+            lo = x < lo ? x : lo;
+            hi = x > hi ? x : hi;
+        }
+        s_key[threadIdx.x] = lo;
+        s_key[kBucketNT + threadIdx.x] = hi;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int t = 1; t < kBucketNT; t++) {
+                lo = s_key[t] < lo ? s_key[t] : lo;
+                hi = s_key[kBucketNT + t] > hi ? s_key[kBucketNT + t] : hi;
+            }
+            if (lo == hi) {
+                atomicAdd(&stats->single_big, 1ull);
+            } else {
+                const unsigned long long slot = atomicAdd(&stats->overflow, 1ull);
+                atomicAdd(&stats->overflow_keys, (unsigned long long)size);
+                if (int64_t(slot) < ovf_cap) ovf[slot] = Overflow{start, size, int64_t(lo), int64_t(hi)};
+            }
+        }
+        return;
+    }
+    int P = 1;
+    while (P < size) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kBucketNT) {
+        if (i < size) {
+            s_key[i] = keys[start + i];
+            s_row[i] = rows[start + i];
+            s_idx[i] = uint16_t(i);
+        } else {
+            s_key[i] = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
+            s_idx[i] = 0xffff;
+        }
+    }
+    __syncthreads();
+    // bitonic network on (key, position): ties keep input order
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kBucketNT) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const K ki = s_key[i], kl = s_key[l];
+                    const uint16_t xi = s_idx[i], xl = s_idx[l];
+                    const bool gt = ki > kl || (ki == kl && xi > xl);
+                    const bool up = (i & k) == 0;
+                    if (gt == up) {
+                        s_key[i] = kl;
+                        s_key[l] = ki;
+                        s_idx[i] = xl;
+                        s_idx[l] = xi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < size; i += kBucketNT) {
+        keys[start + i] = s_key[i];
+        rows[start + i] = s_row[s_idx[i]];
+    }
+}
+
+// Keys of the overflow buckets are copied out, sorted over their own range,
+// and copied back.
+template <class K>
+__global__ void k_copy_range(const K *ks, const int32_t *rs, K *kd, int32_t *rd, int64_t len) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < len;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        kd[i] = ks[i];
+        rd[i] = rs[i];
+    }
+}
+
+// ---- host -----------------------------------------------------------------------
+
+struct TrainLayout {
+    int64_t *sample, *sorted;
+    void *rws;
+    size_t rws_bytes;
+    float *tx, *tq, *part;
+    size_t bytes;
+};
+
+static TrainLayout train_layout(void *ws, int64_t m) {
+    TrainLayout L = {};
+    Carver c(ws);
+    const int64_t mm = m > 0 ? m : 1;
+    L.sample = c.take<int64_t>(size_t(mm));
+    L.sorted = c.take<int64_t>(size_t(mm));
+    L.rws_bytes = radix_ws_bytes(mm, 8, 8, 0);
+    L.rws = c.take<char>(L.rws_bytes);
+    L.tx = c.take<float>(kTrainPoints);
+    L.tq = c.take<float>(kTrainPoints);
+    L.part = c.take<float>(size_t(kGradBlocks) * (kNParam + 1));
+    L.bytes = c.bytes();
+    return L;
+}
+
+static int64_t sample_count(const tqp_col *cols, int ncols, int64_t stride) {
+    int64_t m = 0;
+    for (int i = 0; i < ncols; i++) m += ceil_div(cols[i].len, stride);
+    return m;
+}
+
+struct PartLayout {
+    BucketStats *stats;
+    Overflow *ovf;
+    int64_t ovf_cap;
+    void *rws;
+    size_t rws_bytes;
+    void *tmp_k;
+    int32_t *tmp_r;
+    void *fws;
+    size_t fws_bytes;
+    size_t bytes;
+};
+
+static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
+    PartLayout L = {};
+    Carver c(ws);
+    const int64_t nn = n > 0 ? n : 1;
+    L.stats = c.take<BucketStats>(1);
+    L.ovf_cap = (int64_t(1) << bucket_bits);
+    L.ovf = c.take<Overflow>(size_t(L.ovf_cap));
+    L.rws_bytes = radix_ws_bytes(nn, ksize, npass_for(bucket_bits), 0);
+    L.rws = c.take<char>(L.rws_bytes);
+    // fallback: a copy of the largest overflow range and the radix workspace
+    L.tmp_k = c.take<char>(size_t(nn) * ksize);
+    L.tmp_r = c.take<int32_t>(size_t(nn));
+    L.fws_bytes = radix_ws_bytes(nn, ksize, ksize, 0);
+    L.fws = c.take<char>(L.fws_bytes);
+    L.bytes = c.bytes();
+    return L;
+}
+
+template <class K, class Ord>
+static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n, Ord ord,
+                                int bucket_bits, K *out_key, int32_t *out_rows, int64_t *h_stats,
+                                void *ws, hipStream_t s) {
+    PartLayout L = part_layout(ws, n, sizeof(K), bucket_bits);
+    int rc = fill_u64(L.stats, 0, sizeof(BucketStats) / 8, s);
+    if (rc) return rc;
+    SortCols sc = {};
+    sc.rows_in = in_rows;
+    sc.rows_out = out_rows;
+    rc = run_radix<K, Ord>(key, n, nullptr, npass_for(bucket_bits), ord, out_key, sc, L.rws, s);
+    if (rc) return rc;
+    const unsigned nb = 1u << bucket_bits;
+    TQP_LAUNCH("bucket_sort", (k_bucket_sort<K, Ord>), dim3(nb), dim3(kBucketNT), 0, s, out_key,
+               out_rows, n, ord, L.stats, L.ovf, L.ovf_cap);
+    if ((rc = check_launch("bucket sort"))) return rc;
+    BucketStats hs;
+    hipError_t e = hipMemcpyAsync(&hs, L.stats, sizeof hs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(TQP_EHIP, "partition stats: %s", hipGetErrorString(e));
+    const int64_t novf = int64_t(hs.overflow) < L.ovf_cap ? int64_t(hs.overflow) : L.ovf_cap;
+    if (novf > 0) {
+        std::vector<Overflow> list(static_cast<size_t>(novf));
+        e = hipMemcpy(list.data(), L.ovf, sizeof(Overflow) * size_t(novf), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return set_error(TQP_EHIP, "overflow list: %s", hipGetErrorString(e));
+        for (const Overflow &o : list) {
+            const K *kb = out_key + o.start;
+            int32_t *rb = out_rows + o.start;
+            int64_t g = ceil_div(o.len, 256);
+            if (g > 4096) g = 4096;
+            TQP_LAUNCH("copy_range", k_copy_range<K>, dim3(unsigned(g)), dim3(256), 0, s, kb, rb,
+                       static_cast<K *>(L.tmp_k), L.tmp_r, o.len);
+            if ((rc = check_launch("overflow copy"))) return rc;
+            const uint64_t span = uint64_t(o.kmax) - uint64_t(o.kmin);
+            int bits = 0;
+            while (bits < 64 && (span >> bits) != 0) bits++;
+            SortCols fc = {};
+            fc.rows_in = L.tmp_r;
+            fc.rows_out = rb;
+            rc = run_radix<K, KeyOrd<K>>(static_cast<const K *>(L.tmp_k), o.len, nullptr,
+                                         npass_for(bits), KeyOrd<K>{K(o.kmin)},
+                                         const_cast<K *>(kb), fc, L.fws, s);
+            if (rc) return rc;
+        }
+    }
+    if (h_stats) {
+        h_stats[0] = int64_t(hs.max_bucket);
+        h_stats[1] = int64_t(hs.overflow);
+        h_stats[2] = int64_t(hs.overflow_keys);
+        h_stats[3] = int64_t(hs.single_big);
+    }
+    return TQP_OK;
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+TQP_API size_t tqp_lcdf_model_bytes(int nleaf) {
+    if (nleaf < 1 || nleaf > kLeafMax) return 0;
+    return model_bytes(nleaf);
+}
+
+TQP_API size_t tqp_lcdf_train_workspace_bytes(int64_t total_keys, int sample_stride) {
+    if (total_keys < 0 || sample_stride < 1) return 0;
+    return train_layout(nullptr, ceil_div(total_keys, sample_stride) + 2).bytes;
+}
+
+TQP_API int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, int nleaf, int steps,
+                           float lr, void *model, size_t model_size, void *ws, size_t ws_bytes,
+                           void *stream) {
+    clear_error();
+    if (!cols || ncols < 1 || ncols > 2 || sample_stride < 1 || nleaf < 1 || nleaf > kLeafMax ||
+        steps < 0 || !model)
+        return set_error(TQP_EINVAL, "tqp_lcdf_train: bad argument");
+    for (int i = 0; i < ncols; i++)
+        if ((cols[i].dtype != TQP_INT32 && cols[i].dtype != TQP_INT64) || cols[i].len < 0 ||
+            (cols[i].len > 0 && !cols[i].data))
+            return set_error(TQP_EINVAL, "tqp_lcdf_train: column %d is invalid", i);
+    if (model_size < model_bytes(nleaf))
+        return set_error(TQP_ECAPACITY, "tqp_lcdf_train: model needs %zu bytes", model_bytes(nleaf));
+    int64_t total = 0;
+    for (int i = 0; i < ncols; i++) total += cols[i].len;
+    const int64_t m = sample_count(cols, ncols, sample_stride);
+    if (m < 2) return set_error(TQP_EINVAL, "tqp_lcdf_train: fewer than two sample keys");
+    const size_t need = tqp_lcdf_train_workspace_bytes(total, sample_stride);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_lcdf_train: workspace needs %zu bytes", need);
+    hipStream_t s = as_stream(stream);
+    TrainLayout L = train_layout(ws, m);
+    LcdfModel *mod = static_cast<LcdfModel *>(model);
+    int rc;
+    {
+        int64_t g = ceil_div(m, 256);
+        if (g > 4096) g = 4096;
+        TQP_LAUNCH("lcdf_sample", k_lcdf_sample, dim3(unsigned(g)), dim3(256), 0, s, cols[0].data,
+                   cols[0].dtype, cols[0].len, ncols > 1 ? cols[1].data : nullptr,
+                   ncols > 1 ? cols[1].dtype : TQP_INT64, ncols > 1 ? cols[1].len : 0,
+                   int64_t(sample_stride), L.sample);
+        if ((rc = check_launch("lcdf sample"))) return rc;
+    }
+    SortCols none = {};
+    rc = run_radix<int64_t, KeyOrd<int64_t>>(L.sample, m, nullptr, 8, KeyOrd<int64_t>{INT64_MIN},
+                                             L.sorted, none, L.rws, s);
+    if (rc) return rc;
+    const int T = int(m < kTrainPoints ? m : kTrainPoints);
+    TQP_LAUNCH("lcdf_init", k_lcdf_init, dim3(1), dim3(256), 0, s, L.sorted, m, nleaf, mod, L.tx,
+               L.tq, T);
+    if ((rc = check_launch("lcdf init"))) return rc;
+    for (int it = 0; it < steps; it++) {
+        TQP_LAUNCH("lcdf_grad", k_lcdf_grad, dim3(kGradBlocks), dim3(256), 0, s, mod, L.tx, L.tq, T,
+                   L.part);
+        TQP_LAUNCH("lcdf_adam", k_lcdf_adam, dim3(1), dim3(128), 0, s, mod, L.part, kGradBlocks, lr);
+    }
+    if ((rc = check_launch("lcdf train"))) return rc;
+    TQP_LAUNCH("lcdf_finalize", k_lcdf_finalize, dim3(1), dim3(64), 0, s, mod);
+    TQP_LAUNCH("lcdf_leaf_fit", k_lcdf_leaf_fit, dim3(unsigned(nleaf)), dim3(256), 0, s, mod,
+               L.sorted, m);
+    TQP_LAUNCH("lcdf_leaf_fill", k_lcdf_leaf_fill, dim3(1), dim3(64), 0, s, mod);
+    return check_launch("lcdf leaves");
+}
+
+TQP_API int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
+                             int32_t *out_bucket, void *stream) {
+    clear_error();
+    if (!model || !keys || bucket_bits < 1 || bucket_bits > 24 ||
+        (keys->dtype != TQP_INT32 && keys->dtype != TQP_INT64) ||
+        (keys->len > 0 && (!keys->data || !out_bucket)))
+        return set_error(TQP_EINVAL, "tqp_lcdf_buckets: bad argument");
+    if (keys->len == 0) return TQP_OK;
+    int64_t g = ceil_div(keys->len, 256);
+    if (g > 8192) g = 8192;
+    hipStream_t s = as_stream(stream);
+    if (keys->dtype == TQP_INT32)
+        TQP_LAUNCH("lcdf_buckets", k_lcdf_buckets<int32_t>, dim3(unsigned(g)), dim3(256), 0, s,
+                   static_cast<const LcdfModel *>(model), static_cast<const int32_t *>(keys->data),
+                   keys->len, bucket_bits, out_bucket);
+    else
+        TQP_LAUNCH("lcdf_buckets", k_lcdf_buckets<int64_t>, dim3(unsigned(g)), dim3(256), 0, s,
+                   static_cast<const LcdfModel *>(model), static_cast<const int64_t *>(keys->data),
+                   keys->len, bucket_bits, out_bucket);
+    return check_launch("tqp_lcdf_buckets");
+}
+
+TQP_API size_t tqp_partition_sort_workspace_bytes(int64_t n, int dtype, int bucket_bits) {
+    if (n < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64) || bucket_bits < 1 || bucket_bits > 16)
+        return 0;
+    Carver c(nullptr);
+    c.take<int64_t>(2);
+    c.take<char>(part_layout(nullptr, n, dtype_size(dtype), bucket_bits).bytes);
+    return c.bytes();
+}
+
+TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint32_t mode,
+                               const void *model, int bucket_bits, int key_bits, int64_t key_min,
+                               const tqp_col *out_key, int32_t *out_rows, int64_t *h_stats,
+                               void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!key || !out_key || (key->len > 0 && (!key->data || !out_key->data || !out_rows)))
+        return set_error(TQP_EINVAL, "tqp_partition_sort: null argument");
+    if ((key->dtype != TQP_INT32 && key->dtype != TQP_INT64) || out_key->dtype != key->dtype)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: keys must be int32 or int64");
+    if (mode != TQP_PART_LEARNED && mode != TQP_PART_RADIX)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: unknown mode");
+    if (mode == TQP_PART_LEARNED && !model)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: learned mode needs a model");
+    if (bucket_bits < 1 || bucket_bits > 16 || key_bits < 0 || key_bits > 64)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: bucket_bits in [1, 16], key_bits in [0, 64]");
+    const int64_t n = key->len;
+    if (n > (int64_t(1) << 30) - 1 || out_key->len < n)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: n must be in [0, 2^30 - 1], out >= n");
+    const size_t need = tqp_partition_sort_workspace_bytes(n, key->dtype, bucket_bits);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_partition_sort: workspace needs %zu bytes", need);
+    if (n == 0) {
+        if (h_stats) h_stats[0] = h_stats[1] = h_stats[2] = h_stats[3] = 0;
+        return TQP_OK;
+    }
+    hipStream_t s = as_stream(stream);
+    Carver c(ws);
+    void *scratch = c.take<int64_t>(2);
+    void *pws = c.take<char>(part_layout(nullptr, n, dtype_size(key->dtype), bucket_bits).bytes);
+    if (mode == TQP_PART_RADIX && key_bits == 0) {
+        int rc = derive_key_range(key->data, key->dtype, n, nullptr, scratch, s, &key_min, &key_bits);
+        if (rc) return rc;
+    }
+    const int shift = key_bits > bucket_bits ? key_bits - bucket_bits : 0;
+    if (key->dtype == TQP_INT32) {
+        const int32_t *k = static_cast<const int32_t *>(key->data);
+        int32_t *ok = static_cast<int32_t *>(out_key->data);
+        if (mode == TQP_PART_LEARNED)
+            return partition_sort_typed(k, in_rows, n,
+                                        LearnedOrd<int32_t>{static_cast<const LcdfModel *>(model),
+                                                            float(1u << bucket_bits),
+                                                            (1u << bucket_bits) - 1},
+                                        bucket_bits, ok, out_rows, h_stats, pws, s);
+        return partition_sort_typed(k, in_rows, n, MsdOrd<int32_t>{int32_t(key_min), shift},
+                                    bucket_bits, ok, out_rows, h_stats, pws, s);
+    }
+    const int64_t *k = static_cast<const int64_t *>(key->data);
+    int64_t *ok = static_cast<int64_t *>(out_key->data);
+    if (mode == TQP_PART_LEARNED)
+        return partition_sort_typed(k, in_rows, n,
+                                    LearnedOrd<int64_t>{static_cast<const LcdfModel *>(model),
+                                                        float(1u << bucket_bits),
+                                                        (1u << bucket_bits) - 1},
+                                    bucket_bits, ok, out_rows, h_stats, pws, s);
+    return partition_sort_typed(k, in_rows, n, MsdOrd<int64_t>{key_min, shift}, bucket_bits, ok,
+                                out_rows, h_stats, pws, s);
+}

@@ -1,0 +1,413 @@
+#pragma once
+// Stable LSD radix passes over an ordinal of each key, carrying row ids and up
+// to four payload columns.  The ordinal is a functor: the key itself (minus
+// its minimum) for the sort, or a bucket number for a partitioner.
+//
+//
+// Keys are ranked on u = key - key_min (unsigned), which orders signed keys
+// correctly and drops the bits that never vary.  One sweep builds the 256-bin
+// histograms of every 8-bit digit at once; each digit then takes one pass:
+//   * a workgroup takes a 4096-key tile (dynamic tile id),
+//   * ranks its keys stably: each wave walks its items in input order, finds
+//     the lanes holding the same digit with eight ballots, and bumps a per-wave
+//     LDS counter once per distinct digit,
+//   * publishes its 256 digit counts and looks back over earlier tiles (one
+//     thread per digit) for the global start of each digit run,
+//   * then, column by column (keys, row ids, payloads), stages the tile in LDS
+//     in digit order and writes each digit run out with consecutive threads on
+//     consecutive addresses.
+// Carrying the payload through the passes keeps every later read of it
+// sequential, instead of a random gather through a permutation.
+#include "tqp_internal.hpp"
+
+namespace tqp {
+
+constexpr int kSortNT = 512;
+constexpr int kSortIPT = 8;
+constexpr int kSortTile = kSortNT * kSortIPT;
+constexpr int kRadixBits = 8;
+constexpr int kBins = 1 << kRadixBits;
+constexpr int kSortNW = kSortNT / kWave;
+constexpr int kMaxSortPay = 4;
+constexpr int kHistNT = 256;
+constexpr int kHistIPT = 16;
+constexpr int kLookAhead = 4;             // predecessor statuses fetched per round trip
+constexpr uint32_t kSFlagAgg = 1u << 30;
+constexpr uint32_t kSFlagInc = 2u << 30;
+constexpr uint32_t kSValMask = (1u << 30) - 1;
+
+// 256-bin histograms of every digit in one sweep: each thread reads 16
+// consecutive keys with 16-byte loads and counts them into its wave's LDS
+// histograms; the workgroup then adds its totals to the device histogram.
+template <class K, class Ord>
+__global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ keys, int64_t n,
+                                                        const int64_t *d_n, Ord ord, int npass,
+                                                        uint32_t *__restrict__ ghist) {
+    constexpr int kMaxPass = KeyTraits<K>::kBits / kRadixBits;
+    constexpr int NW = kHistNT / kWave;
+    __shared__ uint32_t s_h[NW][kMaxPass][kBins];
+    for (int i = threadIdx.x; i < NW * kMaxPass * kBins; i += kHistNT) (&s_h[0][0][0])[i] = 0;
+    __syncthreads();
+    const int64_t cnt = count_of(d_n, n);
+    const int w = wave_id();
+    const int64_t chunk = int64_t(kHistNT) * kHistIPT;
+    const bool vec = reinterpret_cast<uintptr_t>(keys) % 16 == 0;
+    for (int64_t base = blockIdx.x * chunk; base < cnt; base += int64_t(gridDim.x) * chunk) {
+        const int64_t row0 = base + int64_t(threadIdx.x) * kHistIPT;
+        K v[kHistIPT];
+        if (vec && row0 + kHistIPT <= cnt) {
+            constexpr int kPer = 16 / sizeof(K);
+            const int4 *q = reinterpret_cast<const int4 *>(keys + row0);
+#pragma unroll
+            for (int j = 0; j < kHistIPT / kPer; j++) {
+                int4 x = q[j];
+                const K *e = reinterpret_cast<const K *>(&x);
+#pragma unroll
+                for (int t = 0; t < kPer; t++) v[j * kPer + t] = e[t];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kHistIPT; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+        }
+#pragma unroll
+        for (int r = 0; r < kHistIPT; r++) {
+            if (row0 + r < cnt) {
+                const uint64_t u = ord(v[r]);
+                for (int p = 0; p < npass; p++)
+                    atomicAdd(&s_h[w][p][(u >> (p * kRadixBits)) & (kBins - 1)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < npass * kBins; i += kHistNT) {
+        const int p = i / kBins, d = i % kBins;
+        uint32_t t = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++) t += s_h[ww][p][d];
+        if (t) atomicAdd(&ghist[p * kBins + d], t);
+    }
+}
+
+struct PassCols {
+    const int32_t *rows_in;      // null: row id = position (first pass)
+    int32_t *rows_out;           // null: row ids not produced
+    const void *pin[kMaxSortPay];
+    void *pout[kMaxSortPay];
+    int32_t pdt[kMaxSortPay];
+    int32_t npay;
+};
+
+// Writes one staged column of the tile (in digit order) to its runs.
+template <class T>
+__device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const uint8_t *s_dig,
+                                            const int64_t *s_gbase, int tile_cnt, T *dst) {
+    const T *st = reinterpret_cast<const T *>(s_stage);
+    for (int i = threadIdx.x; i < tile_cnt; i += kSortNT) dst[s_gbase[s_dig[i]] + i] = st[i];
+}
+
+// One LSD pass.  NPAY payload columns (a compile-time count; dtypes at run
+// time) are read into registers together with the keys, so the tile pays one
+// memory latency before ranking rather than one per column afterwards.
+// At least 4 waves per SIMD (<= 128 VGPRs) so two workgroups share a CU.
+template <class K, int NPAY, class Ord>
+__global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
+    const K *__restrict__ keys_in, K *__restrict__ keys_out, PassCols c, int64_t n,
+    const int64_t *d_n, Ord ord, int shift, const uint32_t *__restrict__ ghist,
+    uint32_t *status, uint32_t *ticket) {
+    __shared__ uint32_t s_hist[kSortNW][kBins];
+    __shared__ uint32_t s_local[kBins];      // tile-local start of each digit run
+    __shared__ int64_t s_gbase[kBins];       // global start of the run minus its local start
+    __shared__ uint64_t s_stage[kSortTile];  // one column of the tile, in digit order
+    __shared__ uint8_t s_dig[kSortTile];     // digit of each sorted tile position
+    __shared__ uint32_t s_scan[kSortNW];
+    __shared__ int64_t s_tile;
+
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t ntiles = ceil_div(cnt, kSortTile);
+    const int tid = threadIdx.x;
+    const int w = wave_id();
+    const int lane = lane_id();
+    // Persistent workgroups: each takes tiles in ticket order until none are left.
+    for (;;) {
+    const int64_t tile = take_tile(ticket, &s_tile);
+    if (tile >= ntiles) break;
+    const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
+
+    // Issue every load of the tile first: keys, row ids, payload columns.
+    K key[kSortIPT];
+    uint32_t dig[kSortIPT];
+    int32_t rowv[kSortIPT];
+    uint64_t pay[kSortIPT][NPAY > 0 ? NPAY : 1];
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const int64_t idx = wbase + k * kWave + lane;
+        const bool valid = idx < cnt;
+        key[k] = valid ? keys_in[idx] : K(0);
+        rowv[k] = 0;
+        if (c.rows_out && valid) rowv[k] = c.rows_in ? c.rows_in[idx] : int32_t(idx);
+#pragma unroll
+        for (int p = 0; p < NPAY; p++)
+            pay[k][p] = valid ? uint64_t(load_any(c.pin[p], c.pdt[p], idx)) : 0;
+    }
+    for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_hist[0][0])[i] = 0;
+    uint32_t gtot;
+    const uint32_t gstart = block_excl_scan<kSortNT>(tid < kBins ? ghist[tid] : 0u, &gtot, s_scan);
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const int64_t idx = wbase + k * kWave + lane;
+        dig[k] = idx < cnt ? uint32_t(ord(key[k]) >> shift) & (kBins - 1) : kBins;
+    }
+
+    // Stable rank of each item among the items of this wave with its digit.
+    uint32_t pos[kSortIPT];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const bool valid = dig[k] < kBins;
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; b++) {
+            const bool bit = (dig[k] >> b) & 1;
+            const uint64_t bb = ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint32_t old = 0;
+        if (valid) old = s_hist[w][dig[k]];
+        pos[k] = old + __popcll(peers & lt);
+        if (valid && (peers & lt) == 0) s_hist[w][dig[k]] = old + __popcll(peers);
+    }
+    __syncthreads();
+
+    // Per digit (threads below kBins): offsets across waves and tile total.
+    uint32_t tot = 0;
+    if (tid < kBins) {
+#pragma unroll
+        for (int ww = 0; ww < kSortNW; ww++) {
+            const uint32_t cw = s_hist[ww][tid];
+            s_hist[ww][tid] = tot;
+            tot += cw;
+        }
+    }
+    uint32_t tile_total;
+    const uint32_t local = block_excl_scan<kSortNT>(tot, &tile_total, s_scan);
+    if (tid < kBins) {
+        s_local[tid] = local;
+        // Decoupled look-back for digit tid across earlier tiles.
+        uint32_t *st = status + tile * kBins + tid;
+        int64_t prefix = 0;
+        if (tile == 0) {
+            st_relaxed(st, kSFlagInc | tot);
+        } else {
+            st_relaxed(st, kSFlagAgg | tot);
+            // Walk back kLookAhead tiles per memory round trip: the statuses
+            // of the next kLookAhead predecessors are fetched together, then
+            // consumed in order until an inclusive prefix is met.
+            bool done = false;
+            for (int64_t t = tile - 1; !done; t -= kLookAhead) {
+                uint32_t sv[kLookAhead];
+#pragma unroll
+                for (int j = 0; j < kLookAhead; j++)
+                    sv[j] = t - j >= 0 ? ld_relaxed(status + (t - j) * kBins + tid) : kSFlagInc;
+#pragma unroll
+                for (int j = 0; j < kLookAhead; j++) {
+                    if (done) break;
+                    while ((sv[j] >> 30) == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        sv[j] = ld_relaxed(status + (t - j) * kBins + tid);
+                    }
+                    prefix += sv[j] & kSValMask;
+                    if ((sv[j] >> 30) == 2) done = true;
+                }
+            }
+            st_relaxed(st, kSFlagInc | uint32_t(prefix + tot));
+        }
+        s_gbase[tid] = int64_t(gstart) + prefix - int64_t(local);
+    }
+    __syncthreads();
+
+    // Tile position of each item; stage the keys in digit order.
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        if (dig[k] < kBins) {
+            pos[k] += s_local[dig[k]] + s_hist[w][dig[k]];
+            reinterpret_cast<K *>(s_stage)[pos[k]] = key[k];
+            s_dig[pos[k]] = uint8_t(dig[k]);
+        }
+    }
+    __syncthreads();
+    const int tile_cnt = int(cnt - tile * kSortTile < kSortTile ? cnt - tile * kSortTile : kSortTile);
+    flush_stage<K>(s_stage, s_dig, s_gbase, tile_cnt, keys_out);
+
+    if (c.rows_out) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++)
+            if (dig[k] < kBins) reinterpret_cast<int32_t *>(s_stage)[pos[k]] = rowv[k];
+        __syncthreads();
+        flush_stage<int32_t>(s_stage, s_dig, s_gbase, tile_cnt, c.rows_out);
+    }
+#pragma unroll
+    for (int p = 0; p < NPAY; p++) {
+        const int dt = c.pdt[p];
+        __syncthreads();
+        if (dt == TQP_INT8) {
+#pragma unroll
+            for (int k = 0; k < kSortIPT; k++)
+                if (dig[k] < kBins) reinterpret_cast<int8_t *>(s_stage)[pos[k]] = int8_t(pay[k][p]);
+            __syncthreads();
+            flush_stage<int8_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int8_t *>(c.pout[p]));
+        } else if (dt == TQP_INT32) {
+#pragma unroll
+            for (int k = 0; k < kSortIPT; k++)
+                if (dig[k] < kBins) reinterpret_cast<int32_t *>(s_stage)[pos[k]] = int32_t(pay[k][p]);
+            __syncthreads();
+            flush_stage<int32_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int32_t *>(c.pout[p]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSortIPT; k++)
+                if (dig[k] < kBins) reinterpret_cast<uint64_t *>(s_stage)[pos[k]] = pay[k][p];
+            __syncthreads();
+            flush_stage<int64_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int64_t *>(c.pout[p]));
+        }
+    }
+    __syncthreads();
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(256) void k_copy_sorted(const K *__restrict__ keys_in, K *__restrict__ keys_out,
+                                                     PassCols c, int64_t n, const int64_t *d_n) {
+    const int64_t cnt = count_of(d_n, n);
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cnt;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        keys_out[i] = keys_in[i];
+        if (c.rows_out) c.rows_out[i] = c.rows_in ? c.rows_in[i] : int32_t(i);
+        for (int p = 0; p < c.npay; p++) store_any(c.pout[p], c.pdt[p], i, load_any(c.pin[p], c.pdt[p], i));
+    }
+}
+
+
+// Ordinal of a key for the plain sort: its offset from the smallest key.
+template <class K> struct KeyOrd {
+    K key_min;
+    __device__ __forceinline__ uint64_t operator()(K k) const {
+        using U = typename KeyTraits<K>::U;
+        return uint64_t(U(U(k) - U(key_min)));
+    }
+};
+
+struct SortCols {
+    const int32_t *rows_in;
+    int32_t *rows_out;
+    const void *pin[kMaxSortPay];
+    void *pout[kMaxSortPay];
+    int32_t pdt[kMaxSortPay];
+    int32_t npay;
+};
+
+inline int npass_for(int key_bits) { return (key_bits + kRadixBits - 1) / kRadixBits; }
+
+// Workspace of run_radix: ping-pong buffers (when more than one pass), the
+// digit histograms, tickets and look-back statuses.
+inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) {
+    const int64_t ntiles = n > 0 ? ceil_div(n, kSortTile) : 1;
+    Carver c(nullptr);
+    if (npass > 1) {
+        c.take<char>(size_t(n) * key_size);
+        c.take<int32_t>(size_t(n));
+        for (int b = 0; b < pay_bytes; b++) c.take<char>(size_t(n));
+    }
+    c.take<uint32_t>(size_t(npass) * kBins + npass + size_t(npass) * ntiles * kBins);
+    return c.bytes();
+}
+
+// Runs npass stable passes over the ordinal's 8-bit digits (least significant
+// first) from key_in into key_out (they must not overlap), with the columns of
+// sc moving along.  npass == 0 copies.
+template <class K, class Ord>
+int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int npass, Ord ord, K *key_out,
+              const SortCols &sc, void *ws, hipStream_t s) {
+    const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
+    const unsigned grid_pass = persistent_grid(grid_all, tune(kTuneSortPerCu));
+    PassCols pc = {};
+    pc.rows_in = sc.rows_in;
+    pc.rows_out = sc.rows_out;
+    pc.npay = sc.npay;
+    for (int p = 0; p < sc.npay; p++) {
+        pc.pin[p] = sc.pin[p];
+        pc.pout[p] = sc.pout[p];
+        pc.pdt[p] = sc.pdt[p];
+    }
+    if (npass == 0) {
+        unsigned g = grid_all > 4096 ? 4096 : grid_all;
+        TQP_LAUNCH("copy_sorted", k_copy_sorted<K>, dim3(g), dim3(256), 0, s, key_in, key_out, pc, n, d_n);
+        return check_launch("sort copy");
+    }
+    const int64_t ntiles = n > 0 ? ceil_div(n, kSortTile) : 1;
+    Carver cv(ws);
+    K *tmp_keys = nullptr;
+    int32_t *tmp_rows = nullptr;
+    void *tmp_pay[kMaxSortPay] = {};
+    if (npass > 1) {
+        tmp_keys = reinterpret_cast<K *>(cv.take<char>(size_t(n) * sizeof(K)));
+        tmp_rows = cv.take<int32_t>(size_t(n));
+        for (int p = 0; p < sc.npay; p++) tmp_pay[p] = cv.take<char>(size_t(n) * dtype_size(sc.pdt[p]));
+    }
+    const size_t nwords = size_t(npass) * kBins + npass + size_t(npass) * ntiles * kBins;
+    uint32_t *words = cv.take<uint32_t>(nwords);
+    uint32_t *ghist = words;
+    uint32_t *tickets = words + npass * kBins;
+    uint32_t *status = tickets + npass;
+    int rc = fill_u32(words, 0, int64_t(nwords), s);
+    if (rc) return rc;
+    {
+        int64_t g = ceil_div(n > 0 ? n : 1, int64_t(kHistNT) * kHistIPT);
+        if (g > 2048) g = 2048;
+        TQP_LAUNCH("radix_hist", (k_radix_hist<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0, s,
+                   key_in, n, d_n, ord, npass, ghist);
+        rc = check_launch("radix histogram");
+        if (rc) return rc;
+    }
+    const K *src_k = key_in;
+    PassCols cur = pc;
+    for (int p = 0; p < npass; p++) {
+        const bool to_out = ((npass - 1 - p) % 2) == 0;
+        K *dk = to_out ? key_out : tmp_keys;
+        PassCols x = cur;
+        x.rows_out = sc.rows_out ? (to_out ? sc.rows_out : tmp_rows) : nullptr;
+        for (int q = 0; q < sc.npay; q++) x.pout[q] = to_out ? sc.pout[q] : tmp_pay[q];
+        uint32_t *st = status + size_t(p) * ntiles * kBins;
+        const int shift = p * kRadixBits;
+        const uint32_t *gh = ghist + p * kBins;
+        switch (sc.npay) {
+        case 0:
+            TQP_LAUNCH("onesweep", (k_onesweep<K, 0, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
+                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+            break;
+        case 1:
+            TQP_LAUNCH("onesweep", (k_onesweep<K, 1, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
+                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+            break;
+        case 2:
+            TQP_LAUNCH("onesweep", (k_onesweep<K, 2, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
+                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+            break;
+        case 3:
+            TQP_LAUNCH("onesweep", (k_onesweep<K, 3, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
+                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+            break;
+        default:
+            TQP_LAUNCH("onesweep", (k_onesweep<K, 4, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
+                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+            break;
+        }
+        rc = check_launch("radix pass");
+        if (rc) return rc;
+        src_k = dk;
+        cur.rows_in = x.rows_out;
+        for (int q = 0; q < sc.npay; q++) cur.pin[q] = x.pout[q];
+    }
+    return TQP_OK;
+}
+
+}  // namespace tqp

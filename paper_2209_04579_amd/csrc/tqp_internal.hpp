@@ -49,6 +49,18 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 // on MI355X), so a grid of idle workgroups is not free: size it to the
 // machine, not to the capacity.
 constexpr int kComputeUnits = 256;
+
+// Tuning knobs (set through tqp_tune_set, read at launch time on the host).
+enum TuneKnob {
+    kTuneFilterPerCu = 0,   // workgroups per CU of the filter's persistent grid
+    kTuneSortPerCu,         // ... of each radix pass
+    kTuneRlePerCu,          // ... of run-length encoding
+    kTuneMatchPerCu,        // ... of the join match
+    kTuneGbScanPerCu,       // ... of the sorted group-by scan
+    kTuneCount
+};
+int tune(TuneKnob k);
+
 inline unsigned persistent_grid(int64_t tiles, int per_cu) {
     int64_t g = int64_t(kComputeUnits) * per_cu;
     if (tiles < g) g = tiles;

@@ -17,7 +17,8 @@ import torch
 
 from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_workspace_bytes,
                groupby_agg_into, groupby_workspace_bytes, join_into, join_workspace_bytes,
-               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, workspace)
+               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, tune_set,
+               workspace)
 
 
 def key_range(col: torch.Tensor):
@@ -44,8 +45,13 @@ class StarQuery:
                (b) GROUP BY fk: SUM(qty), COUNT(*)
     """
 
-    def __init__(self, fact: dict, dim: dict, day_cut: int, mode: str = "q1"):
+    def __init__(self, fact: dict, dim: dict, day_cut: int, mode: str = "q1",
+                 tuning: dict | None = None):
         self.mode = mode
+        # library knobs (see tune_knobs()) applied before each run; the
+        # "gb.dense_max" entry is the largest key domain aggregated directly
+        self.tuning = dict(tuning or {})
+        self.dense_max = int(self.tuning.pop("gb.dense_max", 1024))
         self.f = fact
         self.d = dim
         self.cut = int(day_cut)
@@ -100,7 +106,7 @@ class StarQuery:
             self.ga_span = self.flag_span * 2
             self.ga_lo = self.flag_min * 2
             self.ga_aggs = [("sum", 0), ("sum", 1), ("count",)]
-        dense = 0 < self.ga_span <= 1024
+        dense = 0 < self.ga_span <= min(self.dense_max, 1024)
         self.ga_flags = GB_DENSE if dense else 0
         self.ga_key = _i64(max(self.ga_span, 1) if dense else self.cap, dev)
         self.ga_out = [_i64(self.ga_key.numel(), dev) for _ in self.ga_aggs]
@@ -115,6 +121,8 @@ class StarQuery:
                                                            GB_SORTED), dev)
 
     def run(self):
+        for name, value in self.tuning.items():
+            tune_set(name, value)
         f, d = self.f, self.d
         # 1. WHERE day < cut, carrying the payload columns
         filter_into([f["day"]], [(0, "<", self.cut)], self.pay_in, self.pay_out, None,

@@ -1,0 +1,116 @@
+"""GPU parity of the learned CDF partitioner: the partition sort gives the same
+bytes as the radix sort and the oracle's stable sort whatever the model, the
+model is monotone (buckets are key ranges), a degenerate model forces the
+radix fallback and still sorts exactly, and a join over partition-sorted
+sides gives the oracle's ranges."""
+import numpy as np
+import pytest
+
+import oracle
+import tqp_datagen as dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tqp():
+    import paper_2209_04579_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def mix():
+    c = dg.config4(0, n_left=2_000_000, n_right=500_000)
+    return c["left"], c["right"]
+
+
+def test_model_is_monotone_and_trains(tqp, mix):
+    left, right = mix
+    model = tqp.lcdf_train([dev(left), dev(right)], sample_stride=100, nleaf=4096, steps=100)
+    info = tqp.lcdf_model_info(model)
+    assert info["nleaf"] == 4096 and info["steps"] == 100
+    assert info["loss_last"] <= info["loss_first"] * 1.01
+    sk = np.sort(np.concatenate([left, right]))
+    b = host(tqp.lcdf_buckets(model, dev(sk), 16))
+    assert np.all(np.diff(b) >= 0), "bucket numbers must not decrease along sorted keys"
+    assert b.min() >= 0 and b.max() < 65536
+    # extremes of the key domain stay in range
+    ext = np.array([np.iinfo(np.int64).min, -1, 0, np.iinfo(np.int64).max], np.int64)
+    eb = host(tqp.lcdf_buckets(model, dev(ext), 16))
+    assert np.all(np.diff(eb) >= 0) and eb.min() >= 0 and eb.max() < 65536
+
+
+@pytest.mark.parametrize("bits", [8, 12, 16])
+def test_learned_partition_sort_matches_sort_and_oracle(tqp, mix, bits):
+    left, right = mix
+    model = tqp.lcdf_train([dev(left), dev(right)], steps=50)
+    for keys in (left, right):
+        sk, rows, st = tqp.partition_sort(dev(keys), tqp.PART_LEARNED, model, bucket_bits=bits)
+        ok, perm = oracle.sort(keys)
+        assert np.array_equal(host(sk), ok)
+        assert np.array_equal(host(rows), perm)
+        assert st["max_bucket"] >= 1
+
+
+@pytest.mark.parametrize("bits", [4, 12, 16])
+def test_msd_radix_partition_sort_matches(tqp, mix, bits):
+    left, _ = mix
+    sk, rows, st = tqp.partition_sort(dev(left), tqp.PART_RADIX, None, bucket_bits=bits)
+    ok, perm = oracle.sort(left)
+    assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    assert st["fallback_buckets"] >= 1          # clusters and lognormal mass overflow
+
+
+def test_degenerate_model_forces_fallback(tqp):
+    const = np.full(10_000, 77, np.int64)
+    model = tqp.lcdf_train([dev(const)], sample_stride=10, nleaf=16, steps=5)
+    keys = dg.uniform_int(3, 1, 300_000, -10 ** 6, 10 ** 6, np.int64)
+    sk, rows, st = tqp.partition_sort(dev(keys), tqp.PART_LEARNED, model, bucket_bits=12)
+    ok, perm = oracle.sort(keys)
+    assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    assert st["fallback_buckets"] >= 1 and st["fallback_keys"] >= 300_000 // 2
+
+
+@pytest.mark.parametrize("n", [0, 1, 5, 4097, 100_003])
+def test_partition_sort_small_and_int32(tqp, n):
+    keys = dg.uniform_int(n + 1, 1, n, -50, 50, np.int32)
+    src = keys if n >= 2 else np.array([1, 2], np.int32)
+    model = tqp.lcdf_train([dev(src)], sample_stride=1, nleaf=64, steps=10)
+    for mode, mdl in ((tqp.PART_LEARNED, model), (tqp.PART_RADIX, None)):
+        sk, rows, _ = tqp.partition_sort(dev(keys), mode, mdl, bucket_bits=6)
+        ok, perm = oracle.sort(keys)
+        assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+
+
+def test_heavy_duplicates_single_valued_buckets(tqp):
+    # one key holds 60% of the rows: its bucket is single-valued and kept as is
+    keys = dg.uniform_int(5, 1, 400_000, 0, 10 ** 9, np.int64)
+    keys[dg.uniform_float(5, 2, 400_000) < 0.6] = 123_456_789
+    model = tqp.lcdf_train([dev(keys)], steps=20)
+    sk, rows, st = tqp.partition_sort(dev(keys), tqp.PART_LEARNED, model, bucket_bits=12)
+    ok, perm = oracle.sort(keys)
+    assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    assert st["single_valued_big"] >= 1
+
+
+def test_join_ranges_over_partition_sorted_sides(tqp, mix):
+    left, right = mix
+    model = tqp.lcdf_train([dev(left), dev(right)], steps=50)
+    sl, _, _ = tqp.partition_sort(dev(left), tqp.PART_LEARNED, model, bucket_bits=12)
+    sr, _, _ = tqp.partition_sort(dev(right), tqp.PART_LEARNED, model, bucket_bits=12)
+    got = tqp.join_ranges(sl, sr)
+    want = oracle.join_ranges(left, right)
+    for k in ("key", "lstart", "lcnt", "rstart", "rcnt"):
+        assert np.array_equal(host(got[k]), want[k]), k
+    assert got["total"] == want["total"]
