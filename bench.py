@@ -39,7 +39,77 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel events")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-radix partition comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-sequential comparison")
+    ap.add_argument("--learned-left", type=int, default=200_000_000)
+    ap.add_argument("--learned-right", type=int, default=50_000_000)
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--batch-fact-hi", type=int, default=20_000_000)
+    ap.add_argument("--side-reps", type=int, default=5,
+                    help="timed repetitions of each side comparison")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 counter_collection.csv files "
+                         "(--pmc FETCH_SIZE, --pmc WRITE_SIZE of this script) into "
+                         "profiles/<kernel>_star60m_traffic.json")
+    ap.add_argument("--record-command", default="",
+                    help="the rocprofv3 command lines, stored with the traffic figures")
     return ap.parse_args()
+
+
+COPY_BYTES = 1 << 31           # the plain copy this script times (2 GiB read, 2 GiB written)
+
+
+def _counter_means(path: str, counter: str) -> dict:
+    """{kernel name: (dispatches, mean counter value)} from a counter_collection.csv."""
+    import csv
+    acc = {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            d, tot = acc.get(name, (0, 0.0))
+            acc[name] = (d + 1, tot + float(row["Counter_Value"]))
+    return {k: (d, tot / d) for k, (d, tot) in acc.items()}
+
+
+def record_traffic(fetch_csv: str, write_csv: str, command: str):
+    """Counter-measured HBM bytes per launch of each library kernel.
+
+    FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch and scaled by what
+    the same counter reads for the plain 2 GiB copy in the same run (the
+    largest non-library dispatch), so the figure is in the copy's bytes."""
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+
+    def copy_kib(tab):
+        others = {k: v for k, v in tab.items() if "tqp::" not in k}
+        return max(v[1] for v in others.values())
+    f_copy, w_copy = copy_kib(fetch), copy_kib(write)
+    f_scale, w_scale = COPY_BYTES / (f_copy * 1024.0), COPY_BYTES / (w_copy * 1024.0)
+    out = {}
+    for short, src in KERNEL_FILE.items():
+        names = [k for k in fetch if f"tqp::k_{short}<" in k or f"tqp::k_{short}(" in k]
+        if not names:
+            continue
+        fd = sum(fetch[k][0] for k in names)
+        fk = sum(fetch[k][0] * fetch[k][1] for k in names) / fd
+        wn = [k for k in names if k in write]
+        wd = sum(write[k][0] for k in wn)
+        wk = sum(write[k][0] * write[k][1] for k in wn) / wd if wd else 0.0
+        rec = {"kernel": short, "source_sha": source_sha(src), "dispatches": fd,
+               "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
+               "copy_fetch_kib": round(f_copy, 1), "copy_write_kib": round(w_copy, 1),
+               "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+               "bytes_per_launch": int(fk * 1024 * f_scale + wk * 1024 * w_scale),
+               "command": command}
+        path = os.path.join(ROOT, "profiles", f"{short}_star60m_traffic.json")
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        out[short] = rec["bytes_per_launch"]
+    print(json.dumps(out))
 
 
 def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
@@ -83,7 +153,7 @@ def source_sha(kernel_file: str) -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_FILE = {"filter": "filter.hip", "onesweep": "sort.hip", "radix_hist": "sort.hip",
+KERNEL_FILE = {"filter": "filter.hip", "onesweep": "radix.hpp", "radix_hist": "radix.hpp",
                "rle": "join.hip", "join_match": "join.hip", "join_expand": "join.hip",
                "pack_key": "gather.hip", "gb_dense": "groupby.hip", "gb_scan": "groupby.hip",
                "gb_tiny": "groupby.hip",
@@ -102,8 +172,193 @@ def traffic_for(kernel: str):
     return t.get("bytes_per_launch")
 
 
+def _timed(fn, reps, stream):
+    """Median ms of fn() over reps calls on stream (one untimed call first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_learned(args, tqp, stream) -> dict:
+    """Sort-merge join of two int64 key columns drawn from the lognormal /
+    cluster / Zipf mix: learned-CDF partition sort against the plain MSD radix
+    partition sort with the same bucket count, and against the full LSD radix
+    sort; the join ranges are taken over each method's output."""
+    import torch
+    from tqp_datagen import device as dgd
+
+    nl, nr = args.learned_left, args.learned_right
+    t0 = time.time()
+    c = dgd.config4(args.seed, nl, nr, device="cuda")
+    left, right = c["left"], c["right"]
+    torch.cuda.synchronize()
+    print(f"[bench] learned: generated {nl}+{nr} keys in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    # 4096 partitions of the key range, each cut further by the same model
+    # into 2^(bits - 12) LDS-sized buckets (about 1024 keys on average)
+    bits = max(12, min(24, (max(nl, nr) // 1024).bit_length()))
+    lo = min(int(left.min().item()), int(right.min().item()))
+    hi = max(int(left.max().item()), int(right.max().item()))
+    key_bits = (hi - lo).bit_length()
+    reps = args.side_reps
+
+    model_holder = {}
+
+    def train():
+        model_holder["m"] = tqp.lcdf_train([left, right], sample_stride=100, nleaf=4096,
+                                           steps=200)
+    train_ms = _timed(train, reps, stream)
+    model = model_holder["m"]
+    info = tqp.lcdf_model_info(model)
+
+    sides = [left, right]
+    outk = [torch.empty_like(t) for t in sides]
+    outr = [torch.empty(t.numel(), dtype=torch.int32, device=t.device) for t in sides]
+    ws = tqp.workspace(max(tqp.partition_sort_workspace_bytes(t.numel(), t.dtype, bits)
+                           for t in sides), left.device)
+    stats = {}
+
+    def part(mode, mdl, tag):
+        def fn():
+            for i, t in enumerate(sides):
+                stats[(tag, i)] = tqp.partition_sort_into(t, None, mode, mdl, bits, outk[i],
+                                                          outr[i], ws, key_bits=key_bits,
+                                                          key_min=lo)
+        return fn
+
+    out = {"workload": f"sort-merge join of {nl} x {nr} int64 keys (lognormal sigma=2 / "
+                       "64 dense clusters / Zipf s=1.2 mix)",
+           "partitions": 4096, "buckets": 1 << bits, "model": {"hidden": 32, "leaves": 4096, "sample": "1%",
+                                           "adam_steps": info["steps"],
+                                           "loss_first": info["loss_first"],
+                                           "loss_last": info["loss_last"],
+                                           "train_ms": round(train_ms, 3)}}
+    results = {}
+    ideal = (nl + nr) / 2 / (1 << bits)
+
+    def partition_imbalance(tag):
+        # largest of the 4096 partitions over the mean partition, both sides
+        worst = 0.0
+        for t in sides:
+            if tag == "learned":
+                b = tqp.lcdf_buckets(model, t, 12).long()
+            else:
+                b = ((t - lo) >> max(key_bits - 12, 0)).clamp(0, 4095)
+            h = torch.bincount(b, minlength=4096)
+            worst = max(worst, float(h.max()) / (t.numel() / 4096))
+        return round(worst, 2)
+    for tag, mode, mdl in (("learned", tqp.PART_LEARNED, model), ("radix", tqp.PART_RADIX, None)):
+        ms = _timed(part(mode, mdl, tag), reps, stream)
+        jr = _timed(lambda: tqp.join_ranges(outk[0], outk[1]), 1, stream)
+        results[tag] = (outk[0].clone(), outr[0].clone())
+        s0, s1 = stats[(tag, 0)], stats[(tag, 1)]
+        out[tag] = {"sort_ms": round(ms, 3), "join_ranges_ms": round(jr, 3),
+                    "rows_per_s": round((nl + nr) / ((ms + jr) * 1e-3), 1),
+                    "max_bucket_over_ideal": round(max(s0["max_bucket"], s1["max_bucket"])
+                                                   / ideal, 2),
+                    "fallback_buckets": s0["fallback_buckets"] + s1["fallback_buckets"],
+                    "fallback_key_frac": round((s0["fallback_keys"] + s1["fallback_keys"])
+                                               / (nl + nr), 4),
+                    "single_valued_big": s0["single_valued_big"] + s1["single_valued_big"],
+                    "partition_max_over_mean": partition_imbalance(tag)}
+        print(f"[bench] learned: {tag} {out[tag]}", file=sys.stderr, flush=True)
+
+    # the plain LSD radix sort (the pipeline's own sort) on the same keys
+    sws = tqp.workspace(max(tqp.sort_workspace_bytes(t.numel(), t.dtype) for t in sides),
+                        left.device)
+
+    def lsd():
+        for i, t in enumerate(sides):
+            tqp.sort_into(t, None, t.numel(), outk[i], outr[i], sws, key_bits=key_bits,
+                          key_min=lo)
+    ms = _timed(lsd, reps, stream)
+    same = all(torch.equal(results[t][0], outk[0]) and torch.equal(results[t][1], outr[0])
+               for t in results)
+    out["lsd_radix"] = {"sort_ms": round(ms, 3),
+                        "rows_per_s": round((nl + nr) / ((ms + out["radix"]["join_ranges_ms"])
+                                                         * 1e-3), 1)}
+    out["outputs_identical"] = bool(same)
+    out["learned_speedup_vs_radix_partition"] = round(
+        out["radix"]["sort_ms"] / out["learned"]["sort_ms"], 3)
+    del left, right, outk, outr, ws, sws, results
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(args, tqp, stream) -> dict:
+    """256 independent star queries of log-uniform sizes: one batched plan
+    captured in a HIP graph (knobs picked by the autotuner) against the same
+    queries launched one after another."""
+    import numpy as np
+    import torch
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd import autotune
+    from paper_2209_04579_amd.batch import BatchStarQuery, SequentialStarQueries
+
+    t0 = time.time()
+    insts = dgd.config5(args.seed, instances=args.batch_instances,
+                        fact_hi=args.batch_fact_hi, device="cuda")
+    torch.cuda.synchronize()
+    rows = sum(int(i["n_fact"]) for i in insts)
+    print(f"[bench] batch: generated {len(insts)} instances, {rows} fact rows in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    reps = args.side_reps
+
+    seq = SequentialStarQueries(insts, 1278)
+    seq_ms = _timed(seq.run, reps, stream)
+    want = seq.results()
+    del seq
+    torch.cuda.empty_cache()
+
+    b = BatchStarQuery(insts, 1278)
+    eager_ms = _timed(b.run, reps, stream)
+    defaults = {k: v[0] for k, v in tqp.tune_knobs().items()}
+
+    def plan_for(t):
+        b.q.tuning = dict(t)
+        return b
+    best, best_ms, timings = autotune.tune(plan_for, reps=3, rounds=1, include_dense=False)
+    b.q.tuning = dict(best)
+    b.capture()
+    graph_ms = _timed(b.run, reps, stream)
+    got = b.results()
+    same = all(all(np.array_equal(g[k], w[k]) for k in ("key", "sum_qty", "count"))
+               for g, w in zip(got, want))
+    for k, v in defaults.items():
+        tqp.tune_set(k, v)
+    out = {"workload": f"{len(insts)} star queries (filter day<1278, join fk=pk, group by cat), "
+                       f"fact sizes log-uniform in [10k, {args.batch_fact_hi}], dim = fact/20, "
+                       "Zipf s in [0, 1.5], 25-1e5 groups",
+           "fact_rows": rows,
+           "sequential_ms": round(seq_ms, 3),
+           "batched_eager_ms": round(eager_ms, 3),
+           "batched_graph_ms": round(graph_ms, 3),
+           "graph_rows_per_s": round(rows / (graph_ms * 1e-3), 1),
+           "sequential_rows_per_s": round(rows / (seq_ms * 1e-3), 1),
+           "speedup_vs_sequential": round(seq_ms / graph_ms, 3),
+           "tuned": best, "tuning_trials": len(timings),
+           "results_match_sequential": bool(same)}
+    print(f"[bench] batch: {out}", file=sys.stderr, flush=True)
+    del b, insts
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic, args.record_command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
@@ -207,6 +462,12 @@ def main():
                "sample": f"the whole workload ({args.n_fact} fact rows), one run, "
                          "single-threaded C oracle (hash join + hash group-by)"}
 
+    # side comparisons on their own workloads (outside the headline's timed region)
+    del q, fact, dim
+    torch.cuda.empty_cache()
+    learned = None if args.no_learned else bench_learned(args, tqp, stream)
+    batch = None if args.no_batch else bench_batch(args, tqp, stream)
+
     out = {
         "metric": METRIC,
         "value": round(args.n_fact / (ms * 1e-3), 1),
@@ -232,6 +493,8 @@ def main():
         "stream_copy_GBps": round(copy_gbs, 1),
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "learned_vs_radix": learned,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

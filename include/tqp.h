@@ -108,8 +108,8 @@ void tqp_profile_enable(int on);
 int tqp_profile_collect(char *buf, size_t len);
 void tqp_profile_reset(void);
 
-/* Launch knobs, the control surface of the autotuner (Section 5's batched
- * execution tunes launch shapes per workload).  Each knob is an integer in a
+/* Launch knobs, the control surface of the autotuner (an extension of this
+ * library; the paper tunes nothing at this level).  Each knob is an integer in a
  * fixed range with a default; today all are "workgroups per compute unit" of
  * one persistent kernel's grid: "filter.per_cu", "sort.per_cu", "rle.per_cu",
  * "match.per_cu", "gbscan.per_cu".  Knobs change launch shapes only, never
@@ -257,9 +257,12 @@ int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t flags,
  *
  * tqp_lcdf_train: samples every sample_stride-th key of ncols (1 or 2)
  *   int32/int64 device columns, sorts the sample, fits the network by `steps`
- *   full-batch Adam steps (learning rate lr) on the squared error against the
- *   sample ranks, then fits the leaves.  `model` is a device buffer of
- *   tqp_lcdf_model_bytes(nleaf) bytes (nleaf in [1, 65536]).  No host sync.
+ *   full-batch Adam steps (learning rate lr, e.g. 1e-2) on the squared error
+ *   against the sample ranks, keeps the parameters with the lowest loss seen,
+ *   then fits the leaves.  `model` is a device buffer of
+ *   tqp_lcdf_model_bytes(nleaf) bytes (nleaf in [1, 65536]); its first 36
+ *   bytes are int64 kmin, float64 1/span, int32 nleaf, int32 steps, float32
+ *   loss at the first step, at the last step, and the lowest.  No host sync.
  * tqp_lcdf_buckets: out_bucket[i] = bucket of keys[i] for 2^bucket_bits
  *   buckets (bits in [1, 24]); for inspection and tests.
  * ---------------------------------------------------------------------- */
@@ -274,7 +277,8 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
 /* ------------------------------------------------------------------------
  * tqp_partition_sort -- the same stable ascending sort as tqp_sort (same
  * out_key and out_rows bytes), by partitioning into 2^bucket_bits key-range
- * buckets (bucket_bits in [1, 16]) and sorting each bucket on its own.
+ * buckets (bucket_bits in [1, 24]; about n / 1024 buckets keeps them in LDS)
+ * and sorting each bucket on its own.
  *   mode TQP_PART_LEARNED: buckets from `model` (trained by tqp_lcdf_train);
  *   mode TQP_PART_RADIX:   buckets = top bucket_bits of key - key_min over
  *                          key_bits bits (key_bits 0 = derive on the device).
@@ -282,8 +286,10 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
  *   h_stats  : optional HOST array of 4: largest bucket, buckets sorted by
  *              the radix fallback, keys in them, single-valued large buckets.
  * Buckets of more than 4096 keys with distinct keys fall back to the radix
- * sort over their own key range.  SYNCHRONIZES the stream once (to read the
- * fallback list).  Workspace: tqp_partition_sort_workspace_bytes.
+ * sort over their own key range; if more than 65536 buckets overflow, the
+ * whole input is sorted by the radix sort instead.  SYNCHRONIZES the stream
+ * once (to read the fallback list).  Workspace:
+ * tqp_partition_sort_workspace_bytes.
  * ---------------------------------------------------------------------- */
 #define TQP_PART_LEARNED 1u
 #define TQP_PART_RADIX   2u

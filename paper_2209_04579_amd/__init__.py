@@ -423,7 +423,7 @@ def _bind_lcdf(L):
                                      vp]
 
 
-def lcdf_train(cols, sample_stride=100, nleaf=4096, steps=200, lr=1e-3, stream=None):
+def lcdf_train(cols, sample_stride=100, nleaf=4096, steps=200, lr=1e-2, stream=None):
     """Trains the learned CDF on the keys of cols (1 or 2 device columns).
 
     Returns the model as a device uint8 tensor."""
@@ -446,9 +446,9 @@ def lcdf_model_info(model) -> dict:
     raw = model[:64].cpu().numpy()
     import numpy as np
     nleaf, steps = np.frombuffer(raw[16:24].tobytes(), dtype=np.int32)
-    loss_first, loss_last = np.frombuffer(raw[24:32].tobytes(), dtype=np.float32)
+    loss_first, loss_last, loss_best = np.frombuffer(raw[24:36].tobytes(), dtype=np.float32)
     return {"nleaf": int(nleaf), "steps": int(steps), "loss_first": float(loss_first),
-            "loss_last": float(loss_last)}
+            "loss_last": float(loss_last), "loss_best": float(loss_best)}
 
 
 def lcdf_buckets(model, keys, bucket_bits, stream=None):

@@ -15,7 +15,11 @@
 // the keys is sorted; the root's 32 ramps start on the sample's 32-quantiles
 // and are refined by full-batch Adam on the mean squared error against the
 // sample ranks; each leaf is then a least-squares line through the sample
-// points the root routes to it, clamped to their rank range.
+// points the root routes to it, clamped to their rank range.  Each ramp's
+// centre is trained in units of its starting width (ramps on a dense part of
+// the distribution can be 1e-9 wide in normalised key space, and Adam moves
+// every parameter by about the learning rate at first), and the parameters
+// with the lowest loss seen are the ones kept.
 //
 // Partition sort.  Two stable radix passes on the bucket number group the
 // keys by bucket (input order kept inside a bucket); one workgroup per bucket
@@ -33,24 +37,26 @@
 namespace tqp {
 
 constexpr int kHidden = 32;
-constexpr int kNParam = 3 * kHidden + 1;     // centre, log-width, log-height per ramp; d
+constexpr int kNParam = 3 * kHidden + 1;     // centre offset, log-width, log-height per ramp; d
 constexpr int kTrainPoints = 16384;          // root training set (sample points, even ranks)
 constexpr int kGradBlocks = 64;
 constexpr int kLeafMax = 65536;
 constexpr int kBucketCap = 4096;             // keys sorted in LDS by one workgroup
 constexpr int kBucketNT = 256;
+constexpr int64_t kOvfCap = 65536;           // overflow buckets re-sorted one by one
 
 struct LcdfModel {
     int64_t kmin;
     double inv_span;
     int32_t nleaf;
     int32_t steps_done;
-    float loss_first, loss_last;
+    float loss_first, loss_last, loss_best, pad0;
     // effective root parameters used by inference
     float w[kHidden], c[kHidden], v[kHidden], d;
-    // training state: ramp centre, log width, log height, bias; Adam moments
-    float theta[kNParam], m1[kNParam], m2[kNParam];
-    float pad[3];
+    // training state: ramp centre offset u (centre = c0 + s0 * u), log width,
+    // log height, bias; Adam moments; the best parameters seen and their loss
+    float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
+    float c0[kHidden], s0[kHidden];
     float4 leaf[1];                           // nleaf entries: (a, b, lo, hi)
 };
 
@@ -149,11 +155,16 @@ __global__ __launch_bounds__(256) void k_lcdf_init(const int64_t *sorted, int64_
         const float xb = float(double(uint64_t(sorted[ib]) - uint64_t(s_min)) * inv);
         float width = xb - xa;
         if (width < 1e-9f) width = 1e-9f;
-        mod->theta[j] = 0.5f * (xa + xb);                    // centre
+        mod->c0[j] = 0.5f * (xa + xb);                       // starting centre
+        mod->s0[j] = width;                                  // centre unit
+        mod->theta[j] = 0.f;                                 // centre offset
         mod->theta[kHidden + j] = logf(width);               // log width
         mod->theta[2 * kHidden + j] = logf(1.0f / kHidden);  // log height
     }
-    if (threadIdx.x == 0) mod->theta[3 * kHidden] = 0.f;
+    if (threadIdx.x == 0) {
+        mod->theta[3 * kHidden] = 0.f;
+        mod->loss_best = INFINITY;
+    }
     for (int p = threadIdx.x; p < kNParam; p += blockDim.x) {
         mod->m1[p] = 0.f;
         mod->m2[p] = 0.f;
@@ -167,6 +178,9 @@ __global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const f
     __shared__ float s_th[kNParam];
     __shared__ float s_red[256 / kWave][kNParam + 1];
     for (int p = threadIdx.x; p < kNParam; p += blockDim.x) s_th[p] = mod->theta[p];
+    // the centres themselves in the first kHidden slots
+    if (threadIdx.x < kHidden)
+        s_th[threadIdx.x] = mod->c0[threadIdx.x] + mod->s0[threadIdx.x] * mod->theta[threadIdx.x];
     __syncthreads();
     float g[kNParam + 1];
 #pragma unroll
@@ -194,7 +208,7 @@ __global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const f
             const bool act = z[j] > 0.f && z[j] < 1.f;
             const float h = z[j] < 0.f ? 0.f : (z[j] > 1.f ? 1.f : z[j]);
             if (act) {
-                g[j] += e * v * (-w);
+                g[j] += e * v * (-w) * mod->s0[j];           // d/du = s0 * d/dcentre
                 g[kHidden + j] += e * v * (-(z[j] - 0.5f));
             }
             g[2 * kHidden + j] += e * v * h;
@@ -216,17 +230,30 @@ __global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const f
     }
 }
 
-// Sums the partial gradients in a fixed order and takes one Adam step.
+// Sums the partial gradients in a fixed order, records the parameters if
+// their loss is the lowest so far, and takes one Adam step.
 __global__ __launch_bounds__(128) void k_lcdf_adam(LcdfModel *mod, const float *part, int nparts,
                                                    float lr) {
+    __shared__ float s_loss;
+    __shared__ int s_better;
     const int step = mod->steps_done + 1;
     const float b1 = 0.9f, b2 = 0.999f;
+    if (threadIdx.x == 0) {
+        float l = 0.f;
+        for (int b = 0; b < nparts; b++) l += part[b * (kNParam + 1) + kNParam];
+        s_loss = l;
+        s_better = l < mod->loss_best;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < kNParam; p += blockDim.x)
+        if (s_better) mod->best[p] = mod->theta[p];
     for (int p = threadIdx.x; p <= kNParam; p += blockDim.x) {
         float g = 0.f;
         for (int b = 0; b < nparts; b++) g += part[b * (kNParam + 1) + p];
         if (p == kNParam) {
-            if (step == 1) mod->loss_first = g;
-            mod->loss_last = g;
+            if (step == 1) mod->loss_first = s_loss;
+            mod->loss_last = s_loss;
+            if (s_better) mod->loss_best = s_loss;
             continue;
         }
         const float m1 = b1 * mod->m1[p] + (1.f - b1) * g;
@@ -243,16 +270,20 @@ __global__ __launch_bounds__(128) void k_lcdf_adam(LcdfModel *mod, const float *
     if (threadIdx.x == 0) mod->steps_done = step;
 }
 
-// Effective root parameters: w = 1 / width, c = 0.5 - centre * w, v = height.
+// Effective root parameters from the best parameters seen (the starting ones
+// when no step was taken): w = 1 / width, c = 0.5 - centre * w, v = height.
 __global__ void k_lcdf_finalize(LcdfModel *mod) {
     const int j = threadIdx.x;
+    const bool trained = mod->loss_best < INFINITY;
+    const float *th = trained ? mod->best : mod->theta;
     if (j < kHidden) {
-        const float w = expf(-mod->theta[kHidden + j]);
+        const float w = expf(-th[kHidden + j]);
+        const float centre = mod->c0[j] + mod->s0[j] * th[j];
         mod->w[j] = w;
-        mod->c[j] = 0.5f - mod->theta[j] * w;
-        mod->v[j] = expf(mod->theta[2 * kHidden + j]);
+        mod->c[j] = 0.5f - centre * w;
+        mod->v[j] = expf(th[2 * kHidden + j]);
     }
-    if (j == 0) mod->d = mod->theta[3 * kHidden];
+    if (j == 0) mod->d = th[3 * kHidden];
 }
 
 // One workgroup per leaf: the contiguous run of sorted sample points the root
@@ -510,7 +541,7 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     Carver c(ws);
     const int64_t nn = n > 0 ? n : 1;
     L.stats = c.take<BucketStats>(1);
-    L.ovf_cap = (int64_t(1) << bucket_bits);
+    L.ovf_cap = (int64_t(1) << bucket_bits) < kOvfCap ? (int64_t(1) << bucket_bits) : kOvfCap;
     L.ovf = c.take<Overflow>(size_t(L.ovf_cap));
     L.rws_bytes = radix_ws_bytes(nn, ksize, npass_for(bucket_bits), 0);
     L.rws = c.take<char>(L.rws_bytes);
@@ -543,7 +574,18 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     hipError_t e = hipMemcpyAsync(&hs, L.stats, sizeof hs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(TQP_EHIP, "partition stats: %s", hipGetErrorString(e));
-    const int64_t novf = int64_t(hs.overflow) < L.ovf_cap ? int64_t(hs.overflow) : L.ovf_cap;
+    if (int64_t(hs.overflow) > L.ovf_cap) {
+        // More overflowing buckets than the list holds: the model is useless
+        // for these keys, so sort the whole input by the plain radix sort.
+        SortCols fc = {};
+        fc.rows_in = in_rows;
+        fc.rows_out = out_rows;
+        rc = run_radix<K, KeyOrd<K>>(key, n, nullptr, int(sizeof(K)),
+                                     KeyOrd<K>{sizeof(K) == 4 ? K(INT32_MIN) : K(INT64_MIN)},
+                                     out_key, fc, L.fws, s);
+        if (rc) return rc;
+    }
+    const int64_t novf = int64_t(hs.overflow) <= L.ovf_cap ? int64_t(hs.overflow) : 0;
     if (novf > 0) {
         std::vector<Overflow> list(static_cast<size_t>(novf));
         e = hipMemcpy(list.data(), L.ovf, sizeof(Overflow) * size_t(novf), hipMemcpyDeviceToHost);
@@ -668,7 +710,7 @@ TQP_API int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_
 }
 
 TQP_API size_t tqp_partition_sort_workspace_bytes(int64_t n, int dtype, int bucket_bits) {
-    if (n < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64) || bucket_bits < 1 || bucket_bits > 16)
+    if (n < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64) || bucket_bits < 1 || bucket_bits > 24)
         return 0;
     Carver c(nullptr);
     c.take<int64_t>(2);
@@ -689,8 +731,8 @@ TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint3
         return set_error(TQP_EINVAL, "tqp_partition_sort: unknown mode");
     if (mode == TQP_PART_LEARNED && !model)
         return set_error(TQP_EINVAL, "tqp_partition_sort: learned mode needs a model");
-    if (bucket_bits < 1 || bucket_bits > 16 || key_bits < 0 || key_bits > 64)
-        return set_error(TQP_EINVAL, "tqp_partition_sort: bucket_bits in [1, 16], key_bits in [0, 64]");
+    if (bucket_bits < 1 || bucket_bits > 24 || key_bits < 0 || key_bits > 64)
+        return set_error(TQP_EINVAL, "tqp_partition_sort: bucket_bits in [1, 24], key_bits in [0, 64]");
     const int64_t n = key->len;
     if (n > (int64_t(1) << 30) - 1 || out_key->len < n)
         return set_error(TQP_EINVAL, "tqp_partition_sort: n must be in [0, 2^30 - 1], out >= n");

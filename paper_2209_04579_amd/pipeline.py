@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_workspace_bytes,
-               groupby_agg_into, groupby_workspace_bytes, join_into, join_workspace_bytes,
+               gather_into, groupby_agg_into, groupby_workspace_bytes, join_into, join_workspace_bytes,
                pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, tune_set,
                workspace)
 
@@ -174,3 +174,133 @@ class StarQuery:
                        b_qty=self.gb_out[0][:gb].cpu().numpy(),
                        b_count=self.gb_out[1][:gb].cpu().numpy())
         return out
+
+
+class StarQuery3:
+    """Star join over three filtered dimensions:
+
+        WHERE d1.attr < cut AND d2.attr < cut AND d3.attr < cut
+        JOIN fact.fk3 = d3.pk, fact.fk2 = d2.pk, fact.fk1 = d1.pk
+        GROUP BY d1.cat * 5 + d2.cat: SUM(qty * price), COUNT(*)
+
+    Sort-merge joins in the order fk3 -> fk2 -> fk1 (narrowest key first), so
+    the one sort over all fact rows is a single radix pass and the later
+    sorts run on the shrinking survivor sets.  Each join's left row ids come
+    out as fact row ids (the sort carries them), so only the next join key is
+    gathered per step; qty and price are read once, by the group-by, for the
+    final survivors.  Dimension keys are unique (primary keys), so every
+    join's pair count is at most its left side.
+    """
+
+    def __init__(self, fact: dict, d1: dict, d2: dict, d3: dict, attr_cut: int):
+        self.f, self.d1, self.d2, self.d3 = fact, d1, d2, d3
+        self.cut = int(attr_cut)
+        dev = fact["fk1"].device
+        n = fact["fk1"].numel()
+        self.n = n
+        self.nd = [d1["pk"].numel(), d2["pk"].numel(), d3["pk"].numel()]
+        dims = (d1, d2, d3)
+        # catalog statistics: a join key range covering both sides of each join
+        self.jk = []
+        for fk, d in zip(("fk1", "fk2", "fk3"), dims):
+            flo, fbits = key_range(fact[fk])
+            plo, pbits = key_range(d["pk"])
+            lo = min(flo, plo)
+            hi = max(flo + (1 << fbits) - 1, plo + (1 << pbits) - 1)
+            self.jk.append((lo, int(hi - lo).bit_length()))
+        self.cat_lo = [key_range(d1["cat"])[0], key_range(d2["cat"])[0]]
+        c1_hi = int(d1["cat"].max().item()) if self.nd[0] else 0
+        c2_hi = int(d2["cat"].max().item()) if self.nd[1] else 0
+        if self.nd[0] and self.nd[1] and (self.cat_lo[0] < 0 or self.cat_lo[1] < 0 or c2_hi >= 5):
+            raise ValueError("expects d1.cat >= 0 and d2.cat in [0, 5)")
+        self.g_span = max(c1_hi * 5 + c2_hi + 1, 1)
+        self.g_dense = self.g_span <= 1024
+
+        # filtered, pk-sorted dimensions (category carried)
+        self.dcnt = [_i64(1, dev) for _ in range(3)]
+        self.dpk = [_i32(m, dev) for m in self.nd]
+        self.dcat = [_i32(self.nd[0], dev), _i32(self.nd[1], dev)]
+        self.dpk_s = [_i32(m, dev) for m in self.nd]
+        self.dcat_s = [_i32(self.nd[0], dev), _i32(self.nd[1], dev)]
+        self.ws_f = workspace(filter_workspace_bytes(max(self.nd + [1])), dev)
+        pay = 4
+        ws_sort = max(sort_workspace_bytes(max(m, 1), torch.int32, pay) for m in self.nd)
+        # fact side: one sort over all rows (row ids out), then survivors only
+        self.fk_s = _i32(n, dev)
+        self.rows_s = _i32(n, dev)
+        ws_sort = max(ws_sort, sort_workspace_bytes(max(n, 1), torch.int32, pay))
+        self.ws_s = workspace(ws_sort, dev)
+        self.cnt = [_i64(1, dev) for _ in range(3)]        # pairs after each join
+        self.r = [_i32(n, dev) for _ in range(3)]          # fact row ids after each join
+        self.rpos = _i32(n, dev)                           # dim positions of the last join
+        self.jpos = _i32(n, dev)
+        self.key_g = _i32(n, dev)                          # gathered next join key
+        self.c2 = _i32(n, dev)                             # d2.cat per survivor
+        self.c2_s = _i32(n, dev)
+        ws_j = max(join_workspace_bytes(n, max(m, 1), torch.int32, JOIN_SORTED, max(n, 1))
+                   for m in self.nd)
+        self.ws_j = workspace(ws_j, dev)
+        self.gkey = _i64(n, dev)
+        self.aggs = [("sum_product", 0, 1), ("count",)]
+        gflags = GB_DENSE if self.g_dense else 0
+        self.g_flags = gflags
+        self.g_key = _i64(self.g_span if self.g_dense else n, dev)
+        self.g_out = [_i64(self.g_key.numel(), dev) for _ in self.aggs]
+        self.g_ng = _i64(1, dev)
+        self.ws_g = workspace(groupby_workspace_bytes(max(n, 1), torch.int64, 2, gflags,
+                                                      self.g_span), dev)
+
+    def run(self):
+        f = self.f
+        dims = (self.d1, self.d2, self.d3)
+        # 1. filter each dimension, sort it by pk carrying its category
+        for i, d in enumerate(dims):
+            pay_in = [d["pk"]] + ([d["cat"]] if i < 2 else [])
+            pay_out = [self.dpk[i]] + ([self.dcat[i]] if i < 2 else [])
+            filter_into([d["attr"]], [(0, "<", self.cut)], pay_in, pay_out, None, self.dcnt[i],
+                        self.ws_f)
+            lo, bits = self.jk[i]
+            sort_into(self.dpk[i], None, self.nd[i], self.dpk_s[i], None, self.ws_s,
+                      d_n=self.dcnt[i], key_bits=bits, key_min=lo,
+                      pay_in=pay_out[1:], pay_out=[self.dcat_s[i]] if i < 2 else [])
+        n = self.n
+        # 2. fk3: sort all fact rows (row ids out), merge with d3 -> fact rows r0
+        lo, bits = self.jk[2]
+        sort_into(f["fk3"], None, n, self.fk_s, self.rows_s, self.ws_s, key_bits=bits,
+                  key_min=lo)
+        join_into(self.fk_s, self.dpk_s[2], JOIN_SORTED, self.r[0], None, None, n, self.cnt[0],
+                  self.ws_j, lrows=self.rows_s, d_nr=self.dcnt[2])
+        # 3. fk2 of the survivors: sort carrying their row ids, merge with d2
+        gather_into(f["fk2"], self.r[0], n, self.key_g, d_n=self.cnt[0])
+        lo, bits = self.jk[1]
+        sort_into(self.key_g, self.r[0], n, self.fk_s, self.rows_s, self.ws_s, d_n=self.cnt[0],
+                  key_bits=bits, key_min=lo)
+        join_into(self.fk_s, self.dpk_s[1], JOIN_SORTED, self.r[1], self.rpos, None, n,
+                  self.cnt[1], self.ws_j, lrows=self.rows_s, d_nl=self.cnt[0],
+                  d_nr=self.dcnt[1])
+        gather_into(self.dcat_s[1], self.rpos, n, self.c2, d_n=self.cnt[1])
+        # 4. fk1 of the survivors: sort carrying row ids and d2.cat, merge with d1
+        gather_into(f["fk1"], self.r[1], n, self.key_g, d_n=self.cnt[1])
+        lo, bits = self.jk[0]
+        sort_into(self.key_g, self.r[1], n, self.fk_s, self.rows_s, self.ws_s, d_n=self.cnt[1],
+                  key_bits=bits, key_min=lo, pay_in=[self.c2], pay_out=[self.c2_s])
+        join_into(self.fk_s, self.dpk_s[0], JOIN_SORTED, self.jpos, self.rpos, None, n,
+                  self.cnt[2], self.ws_j, d_nl=self.cnt[1], d_nr=self.dcnt[0])
+        gather_into(self.rows_s, self.jpos, n, self.r[2], d_n=self.cnt[2])
+        # 5. GROUP BY d1.cat * 5 + d2.cat: SUM(qty * price), COUNT(*)
+        pack_key_into([(self.dcat_s[0], self.rpos, 0, 5), (self.c2_s, self.jpos, 0, 1)], n,
+                      self.gkey, d_n=self.cnt[2])
+        groupby_agg_into(self.gkey[:n], [f["qty"], f["price"]], self.aggs, self.g_key,
+                         self.g_out, self.g_ng, self.ws_g, flags=self.g_flags, key_lo=0,
+                         key_span=self.g_span, val_rows=self.r[2], d_n=self.cnt[2])
+
+    def result(self) -> dict:
+        torch.cuda.synchronize()
+        pairs = [int(c.item()) for c in self.cnt]
+        if max(pairs) > self.n:
+            raise RuntimeError(f"join produced {max(pairs)} pairs, more than the {self.n} planned")
+        g = int(self.g_ng.item())
+        return {"dims_kept": [int(c.item()) for c in self.dcnt], "pairs": pairs,
+                "key": self.g_key[:g].cpu().numpy().astype(np.int64),
+                "sum_qp": self.g_out[0][:g].cpu().numpy(),
+                "count": self.g_out[1][:g].cpu().numpy()}

@@ -36,3 +36,14 @@ def test_config5_instance_matches_host():
                     assert np.mean(a[t][k] == b[t][k].numpy()) > 0.9999
                 else:
                     assert np.array_equal(a[t][k], b[t][k].numpy()), (t, k)
+
+
+def test_config3_matches_host():
+    h = dg.config3(2, n_fact=30_000, dims=(5000, 700, 25))
+    d = dd.config3(2, n_fact=30_000, dims=(5000, 700, 25), device="cpu")
+    assert h["attr_cut"] == d["attr_cut"]
+    for t in ("fact", "d1", "d2", "d3"):
+        assert set(h[t]) == set(d[t])
+        for k in h[t]:
+            assert h[t][k].dtype == d[t][k].numpy().dtype, (t, k)
+            assert np.array_equal(h[t][k], d[t][k].numpy()), (t, k)

@@ -95,3 +95,22 @@ def test_tuning_changes_nothing_but_time():
     finally:
         for k, v in defaults.items():
             tune_set(k, v)
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_size_matches_oracle():
+    """256 instances at full size (633M fact rows, drawn on the GPU), captured
+    in a graph, every instance against the oracle on host copies."""
+    from paper_2209_04579_amd.batch import BatchStarQuery
+    from tqp_datagen import device as dgd
+    dev = dgd.config5(0, device="cuda")
+    b = BatchStarQuery([{"fact": i["fact"], "dim": i["dim"]} for i in dev], 1278)
+    b.capture()
+    b.run()
+    got = b.results()
+    del b
+    torch.cuda.empty_cache()
+    insts = [{"fact": {k: v.cpu().numpy() for k, v in i["fact"].items()},
+              "dim": {k: v.cpu().numpy() for k, v in i["dim"].items()},
+              "day_cut": 1278} for i in dev]
+    check_against_oracle(insts, got)

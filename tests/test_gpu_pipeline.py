@@ -74,3 +74,62 @@ def test_q2_full_size():
     got = check_q2(dg.config2(0))
     assert got["rows_filtered"] > 29_000_000
     assert got["pairs"] == got["rows_filtered"]
+
+
+def run_q3(cfg, dev_cfg=None):
+    from paper_2209_04579_amd.pipeline import StarQuery3
+    d = dev_cfg or {t: to_dev(cfg[t]) for t in ("fact", "d1", "d2", "d3")}
+    q = StarQuery3(d["fact"], d["d1"], d["d2"], d["d3"], cfg["attr_cut"])
+    q.run()
+    return q, q.result()
+
+
+def check_q3(cfg, dev_cfg=None):
+    q, got = run_q3(cfg, dev_cfg)
+    want = oracle.q3(cfg)
+    assert not want["overflow"]
+    for k in ("key", "sum_qp", "count"):
+        assert np.array_equal(got[k], want[k]), k
+    # COUNT conserves the last join's pairs
+    assert int(got["count"].sum()) == got["pairs"][2]
+    return q, got
+
+
+def test_q3_reduced_size():
+    cfg = dg.config3(0, n_fact=3_000_000, dims=(100_000, 10_000, 25))
+    _, got = check_q3(cfg)
+    assert got["pairs"][0] > 0 and got["pairs"][2] > 0
+
+
+def test_q3_degenerate():
+    # one-row dims, and dims whose filter keeps nothing
+    c = dg.config3(1, n_fact=20_000, dims=(1, 1, 1))
+    check_q3(c)
+    c = dg.config3(2, n_fact=50_000, dims=(3000, 500, 25))
+    c["attr_cut"] = 0
+    _, got = check_q3(c)
+    assert got["pairs"] == [0, 0, 0] and len(got["key"]) == 0
+    c = dg.config3(3, n_fact=7, dims=(50, 20, 25))
+    check_q3(c)
+
+
+def test_q3_replay_is_identical():
+    cfg = dg.config3(4, n_fact=1_000_000, dims=(50_000, 5_000, 25))
+    q, first = check_q3(cfg)
+    for _ in range(2):
+        q.run()
+        again = q.result()
+        for k in ("key", "sum_qp", "count"):
+            assert np.array_equal(again[k], first[k])
+
+
+def test_q3_full_size():
+    """The 600M-row three-dimension star at full size: tables drawn on the GPU
+    (bit-identical to the host generator), the oracle run on host copies."""
+    from tqp_datagen import device as dgd
+    dcfg = dgd.config3(0, device="cuda")
+    cfg = {t: {k: v.cpu().numpy() for k, v in dcfg[t].items()} for t in ("fact", "d1", "d2", "d3")}
+    cfg["attr_cut"] = dcfg["attr_cut"]
+    _, got = check_q3(cfg, dcfg)
+    assert len(got["key"]) == 125
+    assert 100_000_000 < got["pairs"][0] < 140_000_000

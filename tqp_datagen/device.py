@@ -123,3 +123,25 @@ def config5(seed=0, instances=256, fact_lo=10_000, fact_hi=20_000_000, device="c
                "cat": uniform_int(sk, 5, nd, 0, p["groups"], device, torch.int32)}
         out.append({"fact": fact, "dim": dim, "day_cut": 1278, **p})
     return out
+
+
+def config3(seed=0, n_fact=600_000_000, dims=(1_000_000, 100_000, 25), device="cuda"):
+    """Three-dimension star (every draw is an integer draw, so the tables are
+    bit-identical to the host generator's)."""
+    n1, n2, n3 = dims
+    fact = {
+        "fk1": uniform_int(seed, 1, n_fact, 0, n1, device, torch.int32),
+        "fk2": uniform_int(seed, 2, n_fact, 0, n2, device, torch.int32),
+        "fk3": uniform_int(seed, 3, n_fact, 0, n3, device, torch.int32),
+        "qty": uniform_int(seed, 4, n_fact, 1, 5001, device),
+        "price": uniform_int(seed, 5, n_fact, 100, 10_000_001, device),
+    }
+    d1 = {"pk": permutation(seed, 6, n1, device).to(torch.int32),
+          "cat": uniform_int(seed, 7, n1, 0, 25, device, torch.int32),
+          "attr": uniform_int(seed, 8, n1, 0, 100, device, torch.int32)}
+    d2 = {"pk": permutation(seed, 9, n2, device).to(torch.int32),
+          "cat": uniform_int(seed, 10, n2, 0, 5, device, torch.int32),
+          "attr": uniform_int(seed, 11, n2, 0, 100, device, torch.int32)}
+    pk3 = torch.arange(n3, dtype=torch.int32, device=device)
+    d3 = {"pk": pk3, "attr": 4 * pk3}
+    return {"fact": fact, "d1": d1, "d2": d2, "d3": d3, "attr_cut": 20}
