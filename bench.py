@@ -62,7 +62,7 @@ COPY_BYTES = 1 << 31           # the plain copy this script times (2 GiB read, 2
 
 
 def _counter_means(path: str, counter: str) -> dict:
-    """{kernel name: (dispatches, mean counter value)} from a counter_collection.csv."""
+    """{kernel name: (dispatches, mean, max counter value)} from a counter_collection.csv."""
     import csv
     acc = {}
     with open(path, newline="") as fh:
@@ -70,9 +70,10 @@ def _counter_means(path: str, counter: str) -> dict:
             if row.get("Counter_Name") != counter:
                 continue
             name = row["Kernel_Name"]
-            d, tot = acc.get(name, (0, 0.0))
-            acc[name] = (d + 1, tot + float(row["Counter_Value"]))
-    return {k: (d, tot / d) for k, (d, tot) in acc.items()}
+            v = float(row["Counter_Value"])
+            d, tot, mx = acc.get(name, (0, 0.0, 0.0))
+            acc[name] = (d + 1, tot + v, max(mx, v))
+    return {k: (d, tot / d, mx) for k, (d, tot, mx) in acc.items()}
 
 
 def record_traffic(fetch_csv: str, write_csv: str, command: str):
@@ -80,13 +81,13 @@ def record_traffic(fetch_csv: str, write_csv: str, command: str):
 
     FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch and scaled by what
     the same counter reads for the plain 2 GiB copy in the same run (the
-    largest non-library dispatch), so the figure is in the copy's bytes."""
+    largest single non-library dispatch), so the figure is in the copy's
+    bytes."""
     fetch = _counter_means(fetch_csv, "FETCH_SIZE")
     write = _counter_means(write_csv, "WRITE_SIZE")
 
     def copy_kib(tab):
-        others = {k: v for k, v in tab.items() if "tqp::" not in k}
-        return max(v[1] for v in others.values())
+        return max(v[2] for k, v in tab.items() if "tqp::" not in k)
     f_copy, w_copy = copy_kib(fetch), copy_kib(write)
     f_scale, w_scale = COPY_BYTES / (f_copy * 1024.0), COPY_BYTES / (w_copy * 1024.0)
     out = {}
@@ -135,9 +136,11 @@ def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
     if name == "join_expand":
         return pairs * (4 + 4 + 4) + ul * 6 * 8
     if name == "pack_key":
-        return pairs * (4 + 4 + 1 + 4 + 8)
+        # reads both position columns, flag and cat; writes the int32 key
+        return pairs * (4 + 4 + 1 + 4 + 4)
     if name in ("gb_dense", "gb_tiny"):
-        return pairs * (8 + 4 + 8 + 8)
+        # int32 key, row id, qty and price per pair
+        return pairs * (4 + 4 + 8 + 8)
     if name == "gb_scan":
         return pairs * (4 + 4 + 8) + gb * (4 + 16)
     if name == "gb_diff":
@@ -259,6 +262,14 @@ def bench_learned(args, tqp, stream) -> dict:
         return round(worst, 2)
     for tag, mode, mdl in (("learned", tqp.PART_LEARNED, model), ("radix", tqp.PART_RADIX, None)):
         ms = _timed(part(mode, mdl, tag), reps, stream)
+        # one more run with per-kernel events, for the breakdown
+        tqp.profile_reset()
+        tqp.profile_enable(True)
+        part(mode, mdl, tag)()
+        torch.cuda.synchronize()
+        tqp.profile_enable(False)
+        kern = {k: round(v[1], 3) for k, v in tqp.profile_collect().items()}
+        tqp.profile_reset()
         jr = _timed(lambda: tqp.join_ranges(outk[0], outk[1]), 1, stream)
         results[tag] = (outk[0].clone(), outr[0].clone())
         s0, s1 = stats[(tag, 0)], stats[(tag, 1)]
@@ -270,7 +281,8 @@ def bench_learned(args, tqp, stream) -> dict:
                     "fallback_key_frac": round((s0["fallback_keys"] + s1["fallback_keys"])
                                                / (nl + nr), 4),
                     "single_valued_big": s0["single_valued_big"] + s1["single_valued_big"],
-                    "partition_max_over_mean": partition_imbalance(tag)}
+                    "partition_max_over_mean": partition_imbalance(tag),
+                    "kernel_ms": kern}
         print(f"[bench] learned: {tag} {out[tag]}", file=sys.stderr, flush=True)
 
     # the plain LSD radix sort (the pipeline's own sort) on the same keys
@@ -327,7 +339,8 @@ def bench_batch(args, tqp, stream) -> dict:
     def plan_for(t):
         b.q.tuning = dict(t)
         return b
-    best, best_ms, timings = autotune.tune(plan_for, reps=3, rounds=1, include_dense=False)
+    best, best_ms, timings = autotune.tune(plan_for, reps=3, rounds=1, include_dense=False,
+                                           log=lambda m: print(m, file=sys.stderr, flush=True))
     b.q.tuning = dict(best)
     b.capture()
     graph_ms = _timed(b.run, reps, stream)

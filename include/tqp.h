@@ -110,10 +110,11 @@ void tqp_profile_reset(void);
 
 /* Launch knobs, the control surface of the autotuner (an extension of this
  * library; the paper tunes nothing at this level).  Each knob is an integer in a
- * fixed range with a default; today all are "workgroups per compute unit" of
- * one persistent kernel's grid: "filter.per_cu", "sort.per_cu", "rle.per_cu",
- * "match.per_cu", "gbscan.per_cu".  Knobs change launch shapes only, never
- * results.  They are process-wide and read when a call enqueues its kernels;
+ * fixed range with a default: "filter.per_cu", "sort.per_cu", "rle.per_cu",
+ * "match.per_cu", "gbscan.per_cu" are workgroups per compute unit of one
+ * persistent kernel's grid; "part.ovf_cap" is how many overflowing buckets
+ * tqp_partition_sort re-sorts before it sorts the whole input instead.
+ * Knobs change how the work is done, never results.  They are process-wide and read when a call enqueues its kernels;
  * setting them concurrently with calls on other threads is a race.
  *   tqp_tune_set: TQP_EINVAL for an unknown name or a value out of range.
  *   tqp_tune_get: writes value / lo / hi (each pointer may be NULL).
@@ -286,8 +287,9 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
  *   h_stats  : optional HOST array of 4: largest bucket, buckets sorted by
  *              the radix fallback, keys in them, single-valued large buckets.
  * Buckets of more than 4096 keys with distinct keys fall back to the radix
- * sort over their own key range; if more than 65536 buckets overflow, the
- * whole input is sorted by the radix sort instead.  SYNCHRONIZES the stream
+ * sort over their own key range (all of them gathered into one sort); if
+ * more than 65536 buckets (the "part.ovf_cap" knob) overflow, the whole input
+ * is sorted by the radix sort instead.  SYNCHRONIZES the stream
  * once (to read the fallback list).  Workspace:
  * tqp_partition_sort_workspace_bytes.
  * ---------------------------------------------------------------------- */

@@ -71,8 +71,9 @@ def tune(make_plan, reps: int = 5, rounds: int = 2, include_dense: bool = True,
          log=None) -> tuple[dict, float, dict]:
     """Coordinate descent over the knobs.
 
-    make_plan(tuning) -> plan.  Returns (best tuning, best ms, all timings)."""
-    knobs = {k: v for k, v in tune_knobs().items()}
+    make_plan(tuning) -> plan.  Returns (best tuning, best ms, all timings).
+    Only the launch-shape knobs (".per_cu") are swept."""
+    knobs = {k: v for k, v in tune_knobs().items() if k.endswith(".per_cu")}
     best = {k: v[0] for k, v in knobs.items()}
     if include_dense:
         best["gb.dense_max"] = 1024

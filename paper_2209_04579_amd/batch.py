@@ -1,11 +1,14 @@
 """Many independent star queries of uneven sizes as one batched execution.
 
 Layout.  The instances' tables are stored as one columnar arena: instance k's
-fact rows follow instance k-1's, and every key carries its instance number in
-its high bits (fk' = k << FB | fk, pk' = k << FB | pk, cat' = k << CB | cat).
+fact rows follow instance k-1's, every join key carries its instance number in
+its high bits (fk' = k << FB | fk, pk' = k << FB | pk), and every category is
+offset past the categories of the instances before it (cat' = G_0 + ... +
+G_{k-1} + cat, G_j = instance j's category count from catalog statistics).
 Keys of different instances never compare equal, and keys of instance k sort
 before those of k+1, so one filter -> sort -> merge join -> group-by over the
-arena computes every instance's result at once, in instance order.  Each
+arena computes every instance's result at once, in instance order; the dense
+category offsets keep the group key's range, and so its sort, small.  Each
 operator is then a single persistent launch over all instances -- small
 instances no longer pay a dozen launches each, and large ones no longer run
 alone -- and the whole query is captured in one HIP graph and replayed with a
@@ -47,10 +50,10 @@ class BatchStarQuery:
                 raise ValueError("batched keys and categories must be non-negative")
             return int(t.max().item())
         max_key = max(max(cmax(i["fact"]["fk"]), cmax(i["dim"]["pk"])) for i in instances)
-        max_cat = max(cmax(i["dim"]["cat"]) for i in instances)
+        ncat = [cmax(i["dim"]["cat"]) + 1 for i in instances]
         self.fb = _bits(max_key)                       # bits of a join key
-        self.cb = _bits(max_cat)                       # bits of a category
-        if self.fb + _bits(self.k - 1) > 31 or self.cb + _bits(self.k - 1) > 31:
+        self.cat_off = np.concatenate([[0], np.cumsum(ncat)]).astype(np.int64)
+        if self.fb + _bits(self.k - 1) > 31 or int(self.cat_off[-1]) >= (1 << 31):
             raise ValueError("instance-prefixed keys do not fit int32")
         nf = [int(i["fact"]["fk"].numel()) for i in instances]
         nd = [int(i["dim"]["pk"].numel()) for i in instances]
@@ -74,8 +77,8 @@ class BatchStarQuery:
             if d1 > d0:
                 pack_key_into([(inst["dim"]["pk"], None, 0, 1), (None, None, 0, k << self.fb)],
                               d1 - d0, dim["pk"][d0:d1])
-                pack_key_into([(inst["dim"]["cat"], None, 0, 1), (None, None, 0, k << self.cb)],
-                              d1 - d0, dim["cat"][d0:d1])
+                pack_key_into([(inst["dim"]["cat"], None, 0, 1),
+                               (None, None, 0, int(self.cat_off[k]))], d1 - d0, dim["cat"][d0:d1])
         self.fact, self.dim = fact, dim
         self.q = StarQuery(fact, dim, day_cut, mode="q1", tuning=tuning)
         self.graph = None
@@ -102,13 +105,12 @@ class BatchStarQuery:
     def results(self) -> list:
         """Per-instance {key, sum_qty, count} (host arrays), instance order."""
         r = self.q.result()
-        inst = r["key"] >> self.cb
-        cat = r["key"] & ((1 << self.cb) - 1)
         out = []
-        bounds = np.searchsorted(inst, np.arange(self.k + 1))
+        bounds = np.searchsorted(r["key"], self.cat_off)
         for k in range(self.k):
             a, b = bounds[k], bounds[k + 1]
-            out.append({"key": cat[a:b], "sum_qty": r["sum_qty"][a:b], "count": r["count"][a:b]})
+            out.append({"key": r["key"][a:b] - self.cat_off[k], "sum_qty": r["sum_qty"][a:b],
+                        "count": r["count"][a:b]})
         return out
 
 

@@ -41,27 +41,56 @@ struct PackArgs {
     int32_t nterms;
 };
 
+// Each thread builds kPackR keys per step, term by term, issuing the row-id
+// loads of all of them and then all their value loads, so the dependent
+// gathers overlap.  A power-of-two modulus is a mask (v mod 2^k in [0, 2^k)
+// is v & (2^k - 1) in two's complement).
+constexpr int kPackR = 4;
+
 template <class O>
 __global__ __launch_bounds__(kGatherNT) void k_pack_key(PackArgs a, int64_t n, const int64_t *d_n,
                                                         O *__restrict__ out) {
+    constexpr int R = kPackR;
     const int64_t cnt = count_of(d_n, n);
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cnt;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        uint64_t acc = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * R;
+    for (int64_t base = blockIdx.x * int64_t(blockDim.x) * R; base < cnt; base += stride) {
+        int64_t idx[R];
+        uint64_t acc[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            idx[r] = base + int64_t(r) * blockDim.x + threadIdx.x;
+            acc[r] = 0;
+        }
         for (int t = 0; t < a.nterms; t++) {
             if (!a.col[t]) {                       // constant term
-                acc += uint64_t(a.mul[t]);
+#pragma unroll
+                for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]);
                 continue;
             }
-            const int64_t r = a.rows[t] ? int64_t(a.rows[t][i]) : i;
-            int64_t v = (r >= 0 && r < a.len[t]) ? load_any(a.col[t], a.dt[t], r) : 0;
-            if (a.mod[t] > 0) {
-                v %= a.mod[t];
-                if (v < 0) v += a.mod[t];
+            int64_t row[R], v[R];
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                row[r] = idx[r] < cnt ? (a.rows[t] ? int64_t(a.rows[t][idx[r]]) : idx[r]) : -1;
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                v[r] = (row[r] >= 0 && row[r] < a.len[t]) ? load_any(a.col[t], a.dt[t], row[r]) : 0;
+            const int64_t m = a.mod[t];
+            if (m > 0 && (m & (m - 1)) == 0) {
+#pragma unroll
+                for (int r = 0; r < R; r++) v[r] &= m - 1;
+            } else if (m > 0) {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    v[r] %= m;
+                    if (v[r] < 0) v[r] += m;
+                }
             }
-            acc += uint64_t(a.mul[t]) * uint64_t(v);
+#pragma unroll
+            for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]) * uint64_t(v[r]);
         }
-        out[i] = O(int64_t(acc));
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (idx[r] < cnt) out[idx[r]] = O(int64_t(acc[r]));
     }
 }
 
@@ -139,10 +168,10 @@ TQP_API int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n, const 
     if (n == 0) return TQP_OK;
     hipStream_t s = as_stream(stream);
     if (out->dtype == TQP_INT32)
-        TQP_LAUNCH("pack_key", k_pack_key<int32_t>, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, s, a,
+        TQP_LAUNCH("pack_key", k_pack_key<int32_t>, dim3(grid_for(n, 4 * kPackR)), dim3(kGatherNT), 0, s, a,
                    n, d_n, static_cast<int32_t *>(out->data));
     else
-        TQP_LAUNCH("pack_key", k_pack_key<int64_t>, dim3(grid_for(n, 4)), dim3(kGatherNT), 0, s, a,
+        TQP_LAUNCH("pack_key", k_pack_key<int64_t>, dim3(grid_for(n, 4 * kPackR)), dim3(kGatherNT), 0, s, a,
                    n, d_n, static_cast<int64_t *>(out->data));
     return check_launch("tqp_pack_key");
 }

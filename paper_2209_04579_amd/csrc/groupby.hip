@@ -303,6 +303,8 @@ __global__ __launch_bounds__(256) void k_gb_diff(const int64_t *__restrict__ end
 
 // ---- dense key domain ------------------------------------------------------
 
+constexpr int kDenseR = 4;                  // rows per thread per step (loads issued together)
+
 template <class K>
 __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, int64_t n,
                                                     const int64_t *d_n, int64_t key_lo,
@@ -314,14 +316,45 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, 
     for (int64_t i = threadIdx.x; i < cells; i += kGbNT) s_acc[i] = 0;
     __syncthreads();
     const int64_t cnt = count_of(d_n, n);
-    const int64_t stride = int64_t(gridDim.x) * kGbNT;
-    for (int64_t i = blockIdx.x * int64_t(kGbNT) + threadIdx.x; i < cnt; i += stride) {
-        const uint64_t b = uint64_t(int64_t(keys[i])) - uint64_t(key_lo);
-        if (b >= uint64_t(span)) continue;
-        const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
-        for (int g = 0; g < nagg; g++)
-            atomicAdd(&s_acc[g * span + b], (unsigned long long)agg_term(a, g, row));
-        atomicAdd(&s_acc[nagg * span + b], 1ull);
+    constexpr int R = kDenseR;
+    const int64_t stride = int64_t(gridDim.x) * kGbNT * R;
+    for (int64_t base = blockIdx.x * int64_t(kGbNT) * R; base < cnt; base += stride) {
+        uint32_t ok = 0;
+        uint64_t b[R];
+        int32_t row[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + r * kGbNT + threadIdx.x;
+            const bool in = i < cnt;
+            b[r] = in ? uint64_t(int64_t(keys[i])) - uint64_t(key_lo) : uint64_t(span);
+            row[r] = !in ? 0 : (a.val_rows ? a.val_rows[i] : int32_t(i));
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (b[r] < uint64_t(span)) {
+                ok |= 1u << r;
+                atomicAdd(&s_acc[nagg * span + b[r]], 1ull);
+            }
+        }
+        for (int g = 0; g < nagg; g++) {
+            if (a.op[g] == TQP_AGG_COUNT) {
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if ((ok >> r) & 1) atomicAdd(&s_acc[g * span + b[r]], 1ull);
+                continue;
+            }
+            int64_t v[R];
+            load_vals<R>(a.val[a.ia[g]], a.vdt[a.ia[g]], a.vlen[a.ia[g]], row, ok, v);
+            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+                int64_t vy[R];
+                load_vals<R>(a.val[a.ib[g]], a.vdt[a.ib[g]], a.vlen[a.ib[g]], row, ok, vy);
+#pragma unroll
+                for (int r = 0; r < R; r++) v[r] = int64_t(uint64_t(v[r]) * uint64_t(vy[r]));
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if ((ok >> r) & 1) atomicAdd(&s_acc[g * span + b[r]], (unsigned long long)v[r]);
+        }
     }
     __syncthreads();
     for (int64_t c = threadIdx.x; c < span; c += kGbNT) {
@@ -332,61 +365,89 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, 
 
 // Domains of at most kTinySpan keys: every thread keeps all the groups'
 // accumulators in registers (selecting, not indexing, the group), so no two
-// lanes ever contend for one counter; waves then reduce with shuffles.
+// lanes ever contend for one counter; waves then reduce with shuffles.  Each
+// thread takes kTinyR rows per step and issues all their loads (keys, row ids,
+// then values) before using any, so a wave has kTinyR dependent gathers in
+// flight instead of one.
 constexpr int kTinySpan = 8;
+constexpr int kTinyR = 4;
 
-template <class K>
+template <class K, int NAGG>
 __global__ __launch_bounds__(kGbNT) void k_gb_tiny(const K *__restrict__ keys, int64_t n,
                                                    const int64_t *d_n, int64_t key_lo, int span,
                                                    AggArgs a, unsigned long long *__restrict__ gacc) {
-    __shared__ int64_t s_red[kGbNT / kWave][kTinySpan][kMaxAgg + 1];
-    const int nagg = a.nagg;
-    int64_t acc[kTinySpan][kMaxAgg];
+    constexpr int R = kTinyR;
+    __shared__ int64_t s_red[kGbNT / kWave][kTinySpan][NAGG + 1];
+    int64_t acc[kTinySpan][NAGG];
     int64_t cnt_b[kTinySpan];
 #pragma unroll
     for (int b = 0; b < kTinySpan; b++) {
         cnt_b[b] = 0;
 #pragma unroll
-        for (int g = 0; g < kMaxAgg; g++) acc[b][g] = 0;
+        for (int g = 0; g < NAGG; g++) acc[b][g] = 0;
     }
     const int64_t cnt = count_of(d_n, n);
-    const int64_t stride = int64_t(gridDim.x) * kGbNT;
-    for (int64_t i = blockIdx.x * int64_t(kGbNT) + threadIdx.x; i < cnt; i += stride) {
-        const uint64_t b = uint64_t(int64_t(keys[i])) - uint64_t(key_lo);
-        if (b >= uint64_t(span)) continue;
-        const int64_t row = a.val_rows ? int64_t(a.val_rows[i]) : i;
-        int64_t t[kMaxAgg];
+    const int64_t stride = int64_t(gridDim.x) * kGbNT * R;
+    for (int64_t base = blockIdx.x * int64_t(kGbNT) * R; base < cnt; base += stride) {
+        uint32_t ok = 0;
+        uint64_t b[R];
+        int32_t row[R];
 #pragma unroll
-        for (int g = 0; g < kMaxAgg; g++) t[g] = g < nagg ? agg_term(a, g, row) : 0;
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + r * kGbNT + threadIdx.x;
+            const bool in = i < cnt;
+            b[r] = in ? uint64_t(int64_t(keys[i])) - uint64_t(key_lo) : uint64_t(span);
+            row[r] = !in ? 0 : (a.val_rows ? a.val_rows[i] : int32_t(i));
+        }
 #pragma unroll
-        for (int bb = 0; bb < kTinySpan; bb++) {
-            const bool hit = uint64_t(bb) == b;
-            cnt_b[bb] += hit ? 1 : 0;
+        for (int r = 0; r < R; r++) ok |= (b[r] < uint64_t(span) ? 1u : 0u) << r;
+        int64_t t[NAGG][R];
 #pragma unroll
-            for (int g = 0; g < kMaxAgg; g++) acc[bb][g] += hit ? t[g] : 0;
+        for (int g = 0; g < NAGG; g++) {
+            if (a.op[g] == TQP_AGG_COUNT) {
+#pragma unroll
+                for (int r = 0; r < R; r++) t[g][r] = 1;
+                continue;
+            }
+            const int x = a.ia[g];
+            load_vals<R>(a.val[x], a.vdt[x], a.vlen[x], row, ok, t[g]);
+            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+                const int y = a.ib[g];
+                int64_t vy[R];
+                load_vals<R>(a.val[y], a.vdt[y], a.vlen[y], row, ok, vy);
+#pragma unroll
+                for (int r = 0; r < R; r++) t[g][r] = int64_t(uint64_t(t[g][r]) * uint64_t(vy[r]));
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+#pragma unroll
+            for (int bb = 0; bb < kTinySpan; bb++) {
+                const bool hit = ((ok >> r) & 1) && uint64_t(bb) == b[r];
+                cnt_b[bb] += hit ? 1 : 0;
+#pragma unroll
+                for (int g = 0; g < NAGG; g++) acc[bb][g] += hit ? t[g][r] : 0;
+            }
         }
     }
     const int w = wave_id();
 #pragma unroll
     for (int bb = 0; bb < kTinySpan; bb++) {
 #pragma unroll
-        for (int g = 0; g < kMaxAgg; g++) {
-            const int64_t s = wave_sum(acc[bb][g]);
-            if (lane_id() == 0) s_red[w][bb][g] = s;
+        for (int g = 0; g < NAGG; g++) {
+            const int64_t sv = wave_sum(acc[bb][g]);
+            if (lane_id() == 0) s_red[w][bb][g] = sv;
         }
         const int64_t c = wave_sum(cnt_b[bb]);
-        if (lane_id() == 0) s_red[w][bb][kMaxAgg] = c;
+        if (lane_id() == 0) s_red[w][bb][NAGG] = c;
     }
     __syncthreads();
-    if (threadIdx.x < kTinySpan * (kMaxAgg + 1)) {
-        const int bb = threadIdx.x / (kMaxAgg + 1), g = threadIdx.x % (kMaxAgg + 1);
-        int64_t s = 0;
+    if (threadIdx.x < kTinySpan * (NAGG + 1)) {
+        const int bb = threadIdx.x / (NAGG + 1), g = threadIdx.x % (NAGG + 1);
+        int64_t sv = 0;
 #pragma unroll
-        for (int ww = 0; ww < kGbNT / kWave; ww++) s += s_red[ww][bb][g];
-        if (bb < span && (g < nagg || g == kMaxAgg) && s != 0) {
-            const int slot = g == kMaxAgg ? nagg : g;   // count goes last
-            atomicAdd(&gacc[slot * span + bb], (unsigned long long)s);
-        }
+        for (int ww = 0; ww < kGbNT / kWave; ww++) sv += s_red[ww][bb][g];
+        if (bb < span && sv != 0) atomicAdd(&gacc[g * span + bb], (unsigned long long)sv);
     }
 }
 
@@ -474,11 +535,27 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
         rc = fill_u64(L.gacc, 0, int64_t(nagg + 1) * key_span, s);
         if (rc) return rc;
         if (n > 0 && key_span <= kTinySpan) {
-            int64_t g = ceil_div(n, int64_t(kGbNT) * 32);
+            int64_t g = ceil_div(n, int64_t(kGbNT) * kTinyR * 8);
             if (g > 2048) g = 2048;
-            TQP_LAUNCH("gb_tiny", k_gb_tiny<K>, dim3(unsigned(g)), dim3(kGbNT), 0, s,
-                       static_cast<const K *>(key->data), n, d_n, key_lo, int(key_span), args,
-                       L.gacc);
+            const K *kp = static_cast<const K *>(key->data);
+            switch (nagg) {
+            case 1:
+                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 1>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
+                           n, d_n, key_lo, int(key_span), args, L.gacc);
+                break;
+            case 2:
+                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 2>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
+                           n, d_n, key_lo, int(key_span), args, L.gacc);
+                break;
+            case 3:
+                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 3>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
+                           n, d_n, key_lo, int(key_span), args, L.gacc);
+                break;
+            default:
+                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 4>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
+                           n, d_n, key_lo, int(key_span), args, L.gacc);
+                break;
+            }
             if ((rc = check_launch("group-by tiny"))) return rc;
         } else if (n > 0) {
             int64_t g = ceil_div(n, int64_t(kGbNT) * 64);

@@ -4,7 +4,15 @@
 //   x    = (key - kmin) / (kmax - kmin), computed in float64, then float32,
 //   root = sum_j v_j * clamp(w_j * x + c_j, 0, 1) + d      (1 -> 32 -> 1 MLP)
 //   leaf = clamp(floor(root * L), 0, L - 1)
-//   F    = clamp(a_leaf * x + b_leaf, lo_leaf, hi_leaf)      (piecewise linear)
+//   F    = the leaf's piecewise-linear spline through kKnots knots (key, rank)
+//          taken at evenly spaced points of the leaf's sorted sample, over the
+//          key itself in float64 (not over x: a float32 x cannot tell apart
+//          keys closer than 2^-24 of the key span, and a dense cluster of a
+//          million keys can sit inside such a gap)
+// and, where a leaf holds a heavy key h (one that fills a run of the sorted
+// sample), F jumps exactly at h: keys below h are held at or under the rank
+// where h's copies start, keys above at or over the rank where they end, and
+// h itself sits in the middle, so its copies get a bucket of their own.
 // with w_j, v_j > 0.  Every step is monotone non-decreasing in x, under
 // float rounding too (round-to-nearest is monotone), and the leaves' clamps
 // are ordered (hi_k <= lo_{k+1}), so F is monotone: a bucket
@@ -14,8 +22,9 @@
 // Training (all on the device, no host round trip): a strided 1% sample of
 // the keys is sorted; the root's 32 ramps start on the sample's 32-quantiles
 // and are refined by full-batch Adam on the mean squared error against the
-// sample ranks; each leaf is then a least-squares line through the sample
-// points the root routes to it, clamped to their rank range.  Each ramp's
+// sample ranks; each leaf then takes its knots from the sample points the
+// root routes to it, plus its most repeated sample key when that repeats at
+// least kHeavyMin times.  Each ramp's
 // centre is trained in units of its starting width (ramps on a dense part of
 // the distribution can be 1e-9 wide in normalised key space, and Adam moves
 // every parameter by about the learning rate at first), and the parameters
@@ -30,6 +39,7 @@
 // pipeline is the plain MSD radix partitioner the learned one is judged
 // against.
 #include <math.h>
+#include <algorithm>
 #include <vector>
 
 #include "radix.hpp"
@@ -37,12 +47,14 @@
 namespace tqp {
 
 constexpr int kHidden = 32;
+constexpr int kKnots = 8;                    // spline knots per leaf
 constexpr int kNParam = 3 * kHidden + 1;     // centre offset, log-width, log-height per ramp; d
 constexpr int kTrainPoints = 16384;          // root training set (sample points, even ranks)
 constexpr int kGradBlocks = 64;
 constexpr int kLeafMax = 65536;
 constexpr int kBucketCap = 4096;             // keys sorted in LDS by one workgroup
 constexpr int kBucketNT = 256;
+constexpr int kHeavyMin = 4;                 // sample copies that make a key heavy
 constexpr int64_t kOvfCap = 65536;           // overflow buckets re-sorted one by one
 
 struct LcdfModel {
@@ -57,11 +69,21 @@ struct LcdfModel {
     // log height, bias; Adam moments; the best parameters seen and their loss
     float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
     float c0[kHidden], s0[kHidden];
-    float4 leaf[1];                           // nleaf entries: (a, b, lo, hi)
+    struct Leaf {
+        double kx[kKnots];                    // knot keys, ascending (as float64)
+        double slope[kKnots - 1];             // rank per key unit on each segment
+        float kr[kKnots];                     // knot ranks, ascending
+        float lo, hi;                         // the leaf's rank range
+        int64_t hkey;                         // heavy key, when hlo <= hhi
+        float hlo, hhi;                       // ranks where its copies start / end
+        int32_t nk;                           // knots in use (0: constant lo)
+        int32_t pad;
+    } leaf[1];                                // nleaf entries
 };
+using Leaf = LcdfModel::Leaf;
 
 static size_t model_bytes(int nleaf) {
-    return sizeof(LcdfModel) + sizeof(float4) * size_t(nleaf > 0 ? nleaf - 1 : 0);
+    return sizeof(LcdfModel) + sizeof(Leaf) * size_t(nleaf > 0 ? nleaf - 1 : 0);
 }
 
 __device__ __forceinline__ float lcdf_x(const LcdfModel *m, int64_t key) {
@@ -88,11 +110,38 @@ __device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
     return k;
 }
 
+// F of one key.  The spline segment is the last knot at or below the key;
+// each segment's value is clamped to its two knot ranks, so F is monotone
+// across segments even with rounding.
 __device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
     const float x = lcdf_x(m, key);
-    const float4 L = m->leaf[lcdf_leaf(m, lcdf_root(m, x))];
-    float f = fmaf(L.x, x, L.y);
-    return f < L.z ? L.z : (f > L.w ? L.w : f);
+    const Leaf &L = m->leaf[lcdf_leaf(m, lcdf_root(m, x))];
+    float f = L.lo;
+    const int nk = L.nk;
+    if (nk > 0) {
+        const double kd = double(key);
+        if (kd <= L.kx[0]) {
+            f = L.kr[0];
+        } else if (kd >= L.kx[nk - 1]) {
+            f = L.kr[nk - 1];
+        } else {
+            int j = 0;
+#pragma unroll
+            for (int t = 1; t < kKnots - 1; t++)
+                if (t < nk - 1 && L.kx[t] <= kd) j = t;
+            const double r = double(L.kr[j]) + L.slope[j] * (kd - L.kx[j]);
+            float g = float(r);
+            g = g < L.kr[j] ? L.kr[j] : g;
+            f = g > L.kr[j + 1] ? L.kr[j + 1] : g;
+        }
+    }
+    f = f < L.lo ? L.lo : (f > L.hi ? L.hi : f);
+    if (L.hlo <= L.hhi) {
+        if (key == L.hkey) f = 0.5f * (L.hlo + L.hhi);
+        else if (key < L.hkey) f = f < L.hlo ? f : L.hlo;
+        else f = f > L.hhi ? f : L.hhi;
+    }
+    return f;
 }
 
 // Bucket ordinals for run_radix: learned, or the top bits of key - kmin.
@@ -287,11 +336,12 @@ __global__ void k_lcdf_finalize(LcdfModel *mod) {
 }
 
 // One workgroup per leaf: the contiguous run of sorted sample points the root
-// routes to it, and the least-squares line through (x, rank) over that run.
+// routes to it, the spline knots at evenly spaced points of that run, and the
+// longest run of one key inside it.
 __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int64_t *sorted,
                                                        int64_t m) {
     __shared__ int64_t s_rng[2];
-    __shared__ double s_red[256 / kWave][5];
+    __shared__ int64_t s_run[256 / kWave][2];
     const int leaf = blockIdx.x;
     if (threadIdx.x < 2) {
         const int target = leaf + int(threadIdx.x);      // first point with leaf >= target
@@ -305,67 +355,92 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
     }
     __syncthreads();
     const int64_t a0 = s_rng[0], a1 = s_rng[1];
-    double sx = 0, sq = 0, sxx = 0, sxq = 0, cnt = 0;
+    // longest run of equal keys: each run start finds its end by binary search
+    int64_t best_len = 0, best_start = 0;
     for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
-        const double x = double(lcdf_x(mod, sorted[i]));
-        const double q = (double(i) + 0.5) / double(m);
-        sx += x;
-        sq += q;
-        sxx += x * x;
-        sxq += x * q;
-        cnt += 1;
+        const int64_t v = sorted[i];
+        if (i > a0 && sorted[i - 1] == v) continue;
+        int64_t lo = i + 1, hi = a1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted[mid] == v) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo - i > best_len) {
+            best_len = lo - i;
+            best_start = i;
+        }
     }
-    double vals[5] = {sx, sq, sxx, sxq, cnt};
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t ol = __shfl_xor(best_len, o, kWave);
+        const int64_t os = __shfl_xor(best_start, o, kWave);
+        if (ol > best_len || (ol == best_len && os < best_start)) {
+            best_len = ol;
+            best_start = os;
+        }
+    }
     const int w = wave_id();
-#pragma unroll
-    for (int k = 0; k < 5; k++) {
-        double s = vals[k];
-        for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o, kWave);
-        if (lane_id() == 0) s_red[w][k] = s;
+    if (lane_id() == 0) {
+        s_run[w][0] = best_len;
+        s_run[w][1] = best_start;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t[5] = {0, 0, 0, 0, 0};
-        for (int ww = 0; ww < 256 / kWave; ww++)
-            for (int k = 0; k < 5; k++) t[k] += s_red[ww][k];
-        float4 L;
-        if (a1 <= a0) {
-            L = make_float4(0.f, 0.f, -1.f, -1.f);          // empty: filled in later
-        } else {
-            const double n = t[4];
-            const double mx = t[0] / n, mq = t[1] / n;
-            const double vx = t[2] / n - mx * mx;
-            const double cxq = t[3] / n - mx * mq;
-            double a = vx > 1e-30 ? cxq / vx : 0.0;
-            if (a < 0) a = 0;
-            const double b = mq - a * mx;
-            const float lo = float((double(a0) + 0.5) / double(m));
-            const float hi = float((double(a1 - 1) + 0.5) / double(m));
-            L = make_float4(float(a), float(b), lo, hi);
+    if (threadIdx.x != 0) return;
+    Leaf &L = mod->leaf[leaf];
+    L.hkey = 0;
+    L.hlo = 1.f;
+    L.hhi = 0.f;
+    L.pad = 0;
+    if (a1 <= a0) {                                   // empty: filled in later
+        L.nk = 0;
+        L.lo = L.hi = -1.f;
+        return;
+    }
+    const int64_t cnt = a1 - a0;
+    const int nk = cnt < kKnots ? int(cnt) : kKnots;
+    for (int j = 0; j < nk; j++) {
+        const int64_t p = nk > 1 ? a0 + (cnt - 1) * j / (nk - 1) : a0;
+        L.kx[j] = double(sorted[p]);
+        L.kr[j] = float((double(p) + 0.5) / double(m));
+    }
+    for (int j = 0; j + 1 < nk; j++) {
+        const double dx = L.kx[j + 1] - L.kx[j];
+        L.slope[j] = dx > 0 ? (double(L.kr[j + 1]) - double(L.kr[j])) / dx : 0.0;
+    }
+    L.nk = nk;
+    L.lo = L.kr[0];
+    L.hi = L.kr[nk - 1];
+    int64_t rl = 0, rs = 0;
+    for (int ww = 0; ww < 256 / kWave; ww++)
+        if (s_run[ww][0] > rl || (s_run[ww][0] == rl && s_run[ww][1] < rs)) {
+            rl = s_run[ww][0];
+            rs = s_run[ww][1];
         }
-        mod->leaf[leaf] = L;
+    if (rl >= kHeavyMin) {
+        const float hlo = float(double(rs) / double(m));
+        const float hhi = float(double(rs + rl) / double(m));
+        L.hkey = sorted[rs];
+        L.hlo = hlo < L.lo ? L.lo : (hlo > L.hi ? L.hi : hlo);
+        L.hhi = hhi < L.lo ? L.lo : (hhi > L.hi ? L.hi : hhi);
     }
 }
 
 // Empty leaves take the rank reached by the leaves before them, so the
-// clamp ranges stay ordered; the first leaf's range starts at 0, the last
+// rank ranges stay ordered; the first leaf's range starts at 0, the last
 // one's ends at 1.
 __global__ void k_lcdf_leaf_fill(LcdfModel *mod) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float prev = 0.f;
     for (int k = 0; k < mod->nleaf; k++) {
-        float4 L = mod->leaf[k];
-        if (L.z < 0.f) {
-            L = make_float4(0.f, prev, prev, prev);
+        Leaf &L = mod->leaf[k];
+        if (L.nk == 0) {
+            L.lo = L.hi = prev;
         } else {
-            if (k == 0) L.z = 0.f;
-            prev = L.w;
+            if (k == 0) L.lo = 0.f;
+            prev = L.hi;
         }
-        mod->leaf[k] = L;
     }
-    float4 last = mod->leaf[mod->nleaf - 1];
-    last.w = 1.f;
-    mod->leaf[mod->nleaf - 1] = last;
+    mod->leaf[mod->nleaf - 1].hi = 1.f;
 }
 
 template <class K>
@@ -388,6 +463,7 @@ struct BucketStats {
 
 struct Overflow {
     int64_t start, len, kmin, kmax;
+    int64_t off;                        // position in the gathered overflow keys
 };
 
 template <class K, class Ord>
@@ -481,14 +557,40 @@ __global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *row
     }
 }
 
-// Keys of the overflow buckets are copied out, sorted over their own range,
-// and copied back.
+// The overflow buckets (sorted by start, off = prefix sum of len) are
+// gathered into one contiguous run, sorted together, and scattered back.
+// Buckets are disjoint key ranges in key order, so sorting their
+// concatenation sorts each of them in place.  Element t of the run belongs to
+// the last bucket whose off <= t.
+__device__ __forceinline__ int64_t ovf_src(const Overflow *list, int nlist, int64_t t) {
+    int lo = 0, hi = nlist - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (list[mid].off <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return list[lo].start + (t - list[lo].off);
+}
+
 template <class K>
-__global__ void k_copy_range(const K *ks, const int32_t *rs, K *kd, int32_t *rd, int64_t len) {
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < len;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        kd[i] = ks[i];
-        rd[i] = rs[i];
+__global__ void k_ovf_gather(const K *keys, const int32_t *rows, const Overflow *list, int nlist,
+                             int64_t total, K *kd, int32_t *rd) {
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t src = ovf_src(list, nlist, t);
+        kd[t] = keys[src];
+        rd[t] = rows[src];
+    }
+}
+
+template <class K>
+__global__ void k_ovf_scatter(const K *ks, const int32_t *rs, const Overflow *list, int nlist,
+                              int64_t total, K *keys, int32_t *rows) {
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t dst = ovf_src(list, nlist, t);
+        keys[dst] = ks[t];
+        rows[dst] = rs[t];
     }
 }
 
@@ -529,8 +631,8 @@ struct PartLayout {
     int64_t ovf_cap;
     void *rws;
     size_t rws_bytes;
-    void *tmp_k;
-    int32_t *tmp_r;
+    void *tmp_k, *tmp2_k;
+    int32_t *tmp_r, *tmp2_r;
     void *fws;
     size_t fws_bytes;
     size_t bytes;
@@ -545,9 +647,11 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     L.ovf = c.take<Overflow>(size_t(L.ovf_cap));
     L.rws_bytes = radix_ws_bytes(nn, ksize, npass_for(bucket_bits), 0);
     L.rws = c.take<char>(L.rws_bytes);
-    // fallback: a copy of the largest overflow range and the radix workspace
+    // fallback: the gathered overflow keys, their sorted copy, the radix workspace
     L.tmp_k = c.take<char>(size_t(nn) * ksize);
     L.tmp_r = c.take<int32_t>(size_t(nn));
+    L.tmp2_k = c.take<char>(size_t(nn) * ksize);
+    L.tmp2_r = c.take<int32_t>(size_t(nn));
     L.fws_bytes = radix_ws_bytes(nn, ksize, ksize, 0);
     L.fws = c.take<char>(L.fws_bytes);
     L.bytes = c.bytes();
@@ -564,7 +668,7 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     SortCols sc = {};
     sc.rows_in = in_rows;
     sc.rows_out = out_rows;
-    rc = run_radix<K, Ord>(key, n, nullptr, npass_for(bucket_bits), ord, out_key, sc, L.rws, s);
+    rc = run_radix<K, Ord>(key, n, nullptr, bucket_bits, ord, out_key, sc, L.rws, s);
     if (rc) return rc;
     const unsigned nb = 1u << bucket_bits;
     TQP_LAUNCH("bucket_sort", (k_bucket_sort<K, Ord>), dim3(nb), dim3(kBucketNT), 0, s, out_key,
@@ -574,41 +678,56 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     hipError_t e = hipMemcpyAsync(&hs, L.stats, sizeof hs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(TQP_EHIP, "partition stats: %s", hipGetErrorString(e));
-    if (int64_t(hs.overflow) > L.ovf_cap) {
+    const int64_t cap = tune(kTunePartOvfCap) < L.ovf_cap ? tune(kTunePartOvfCap) : L.ovf_cap;
+    if (int64_t(hs.overflow) > cap) {
         // More overflowing buckets than the list holds: the model is useless
         // for these keys, so sort the whole input by the plain radix sort.
         SortCols fc = {};
         fc.rows_in = in_rows;
         fc.rows_out = out_rows;
-        rc = run_radix<K, KeyOrd<K>>(key, n, nullptr, int(sizeof(K)),
+        rc = run_radix<K, KeyOrd<K>>(key, n, nullptr, int(8 * sizeof(K)),
                                      KeyOrd<K>{sizeof(K) == 4 ? K(INT32_MIN) : K(INT64_MIN)},
                                      out_key, fc, L.fws, s);
         if (rc) return rc;
     }
-    const int64_t novf = int64_t(hs.overflow) <= L.ovf_cap ? int64_t(hs.overflow) : 0;
+    const int64_t novf = int64_t(hs.overflow) <= cap ? int64_t(hs.overflow) : 0;
     if (novf > 0) {
         std::vector<Overflow> list(static_cast<size_t>(novf));
-        e = hipMemcpy(list.data(), L.ovf, sizeof(Overflow) * size_t(novf), hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(list.data(), L.ovf, sizeof(Overflow) * size_t(novf),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return set_error(TQP_EHIP, "overflow list: %s", hipGetErrorString(e));
-        for (const Overflow &o : list) {
-            const K *kb = out_key + o.start;
-            int32_t *rb = out_rows + o.start;
-            int64_t g = ceil_div(o.len, 256);
-            if (g > 4096) g = 4096;
-            TQP_LAUNCH("copy_range", k_copy_range<K>, dim3(unsigned(g)), dim3(256), 0, s, kb, rb,
-                       static_cast<K *>(L.tmp_k), L.tmp_r, o.len);
-            if ((rc = check_launch("overflow copy"))) return rc;
-            const uint64_t span = uint64_t(o.kmax) - uint64_t(o.kmin);
-            int bits = 0;
-            while (bits < 64 && (span >> bits) != 0) bits++;
-            SortCols fc = {};
-            fc.rows_in = L.tmp_r;
-            fc.rows_out = rb;
-            rc = run_radix<K, KeyOrd<K>>(static_cast<const K *>(L.tmp_k), o.len, nullptr,
-                                         npass_for(bits), KeyOrd<K>{K(o.kmin)},
-                                         const_cast<K *>(kb), fc, L.fws, s);
-            if (rc) return rc;
+        std::sort(list.begin(), list.end(),
+                  [](const Overflow &a, const Overflow &b) { return a.start < b.start; });
+        int64_t total = 0, kmin = list[0].kmin, kmax = list[0].kmax;
+        for (Overflow &o : list) {
+            o.off = total;
+            total += o.len;
+            kmin = o.kmin < kmin ? o.kmin : kmin;
+            kmax = o.kmax > kmax ? o.kmax : kmax;
         }
+        e = hipMemcpyAsync(L.ovf, list.data(), sizeof(Overflow) * size_t(novf),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);     // list is host memory
+        if (e != hipSuccess) return set_error(TQP_EHIP, "overflow list: %s", hipGetErrorString(e));
+        int64_t g = ceil_div(total, 256);
+        if (g > 8192) g = 8192;
+        K *tk = static_cast<K *>(L.tmp_k), *tk2 = static_cast<K *>(L.tmp2_k);
+        TQP_LAUNCH("ovf_gather", k_ovf_gather<K>, dim3(unsigned(g)), dim3(256), 0, s, out_key,
+                   out_rows, L.ovf, int(novf), total, tk, L.tmp_r);
+        if ((rc = check_launch("overflow gather"))) return rc;
+        const uint64_t span = uint64_t(kmax) - uint64_t(kmin);
+        int bits = 0;
+        while (bits < 64 && (span >> bits) != 0) bits++;
+        SortCols fc = {};
+        fc.rows_in = L.tmp_r;
+        fc.rows_out = L.tmp2_r;
+        rc = run_radix<K, KeyOrd<K>>(tk, total, nullptr, bits, KeyOrd<K>{K(kmin)}, tk2, fc,
+                                     L.fws, s);
+        if (rc) return rc;
+        TQP_LAUNCH("ovf_scatter", k_ovf_scatter<K>, dim3(unsigned(g)), dim3(256), 0, s, tk2,
+                   L.tmp2_r, L.ovf, int(novf), total, out_key, out_rows);
+        if ((rc = check_launch("overflow scatter"))) return rc;
     }
     if (h_stats) {
         h_stats[0] = int64_t(hs.max_bucket);
@@ -650,6 +769,8 @@ TQP_API int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, in
     for (int i = 0; i < ncols; i++) total += cols[i].len;
     const int64_t m = sample_count(cols, ncols, sample_stride);
     if (m < 2) return set_error(TQP_EINVAL, "tqp_lcdf_train: fewer than two sample keys");
+    if (m > (int64_t(1) << 30) - 1)
+        return set_error(TQP_EINVAL, "tqp_lcdf_train: more than 2^30 - 1 sample keys");
     const size_t need = tqp_lcdf_train_workspace_bytes(total, sample_stride);
     if (!ws || ws_bytes < need)
         return set_error(TQP_ECAPACITY, "tqp_lcdf_train: workspace needs %zu bytes", need);
@@ -667,7 +788,7 @@ TQP_API int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, in
         if ((rc = check_launch("lcdf sample"))) return rc;
     }
     SortCols none = {};
-    rc = run_radix<int64_t, KeyOrd<int64_t>>(L.sample, m, nullptr, 8, KeyOrd<int64_t>{INT64_MIN},
+    rc = run_radix<int64_t, KeyOrd<int64_t>>(L.sample, m, nullptr, 64, KeyOrd<int64_t>{INT64_MIN},
                                              L.sorted, none, L.rws, s);
     if (rc) return rc;
     const int T = int(m < kTrainPoints ? m : kTrainPoints);

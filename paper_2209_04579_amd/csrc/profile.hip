@@ -47,12 +47,12 @@ ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s) {
     std::lock_guard<std::mutex> g(g_mu);
     a_ = take_event();
     b_ = take_event();
-    if (a_) hipEventRecord(a_, s_);
+    if (a_) (void)hipEventRecord(a_, s_);
 }
 
 ProfScope::~ProfScope() {
     if (!a_ || !b_) return;
-    hipEventRecord(b_, s_);
+    (void)hipEventRecord(b_, s_);
     std::lock_guard<std::mutex> g(g_mu);
     g_pending.push_back({name_, a_, b_});
 }
@@ -69,7 +69,7 @@ TQP_API void tqp_profile_enable(int on) {
 TQP_API void tqp_profile_reset(void) {
     std::lock_guard<std::mutex> g(g_mu);
     for (auto &p : g_pending) {
-        hipEventSynchronize(p.b);
+        (void)hipEventSynchronize(p.b);
         g_pool.push_back(p.a);
         g_pool.push_back(p.b);
     }

@@ -3,15 +3,17 @@
 // to four payload columns.  The ordinal is a functor: the key itself (minus
 // its minimum) for the sort, or a bucket number for a partitioner.
 //
-//
 // Keys are ranked on u = key - key_min (unsigned), which orders signed keys
-// correctly and drops the bits that never vary.  One sweep builds the 256-bin
-// histograms of every 8-bit digit at once; each digit then takes one pass:
+// correctly and drops the bits that never vary.  The b significant bits are
+// cut into ceil(b / 8) digits of equal width (at most 8 bits: 21 bits take
+// three 7-bit digits, not 8 + 8 + 5), so each pass has as few bins, and as
+// long runs per bin, as its pass count allows.  One sweep builds the
+// histograms of every digit at once; each digit then takes one pass:
 //   * a workgroup takes a 4096-key tile (dynamic tile id),
 //   * ranks its keys stably: each wave walks its items in input order, finds
-//     the lanes holding the same digit with eight ballots, and bumps a per-wave
-//     LDS counter once per distinct digit,
-//   * publishes its 256 digit counts and looks back over earlier tiles (one
+//     the lanes holding the same digit with one ballot per digit bit, and
+//     bumps a per-wave LDS counter once per distinct digit,
+//   * publishes its digit counts and looks back over earlier tiles (one
 //     thread per digit) for the global start of each digit run,
 //   * then, column by column (keys, row ids, payloads), stages the tile in LDS
 //     in digit order and writes each digit run out with consecutive threads on
@@ -42,7 +44,8 @@ constexpr uint32_t kSValMask = (1u << 30) - 1;
 template <class K, class Ord>
 __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ keys, int64_t n,
                                                         const int64_t *d_n, Ord ord, int npass,
-                                                        uint32_t *__restrict__ ghist) {
+                                                        int dbits, uint32_t *__restrict__ ghist) {
+    const uint32_t dmask = (1u << dbits) - 1;
     constexpr int kMaxPass = KeyTraits<K>::kBits / kRadixBits;
     constexpr int NW = kHistNT / kWave;
     __shared__ uint32_t s_h[NW][kMaxPass][kBins];
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
             if (row0 + r < cnt) {
                 const uint64_t u = ord(v[r]);
                 for (int p = 0; p < npass; p++)
-                    atomicAdd(&s_h[w][p][(u >> (p * kRadixBits)) & (kBins - 1)], 1u);
+                    atomicAdd(&s_h[w][p][(u >> (p * dbits)) & dmask], 1u);
             }
         }
     }
@@ -97,12 +100,17 @@ struct PassCols {
     int32_t npay;
 };
 
-// Writes one staged column of the tile (in digit order) to its runs.
+// Writes one staged column of the tile (in digit order) to its runs: thread
+// t writes tile positions t, t + kSortNT, ... to the global positions in
+// pos[] (computed once per tile; -1 past the tile's end).  Row counts are
+// below 2^30, so positions fit int32.
 template <class T>
-__device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const uint8_t *s_dig,
-                                            const int64_t *s_gbase, int tile_cnt, T *dst) {
+__device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const int32_t (&pos)[kSortIPT],
+                                            T *dst) {
     const T *st = reinterpret_cast<const T *>(s_stage);
-    for (int i = threadIdx.x; i < tile_cnt; i += kSortNT) dst[s_gbase[s_dig[i]] + i] = st[i];
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++)
+        if (pos[k] >= 0) dst[pos[k]] = st[threadIdx.x + k * kSortNT];
 }
 
 // One LSD pass.  NPAY payload columns (a compile-time count; dtypes at run
@@ -112,8 +120,9 @@ __device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const uint8
 template <class K, int NPAY, class Ord>
 __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, PassCols c, int64_t n,
-    const int64_t *d_n, Ord ord, int shift, const uint32_t *__restrict__ ghist,
+    const int64_t *d_n, Ord ord, int shift, int dbits, const uint32_t *__restrict__ ghist,
     uint32_t *status, uint32_t *ticket) {
+    const uint32_t nbins = 1u << dbits;
     __shared__ uint32_t s_hist[kSortNW][kBins];
     __shared__ uint32_t s_local[kBins];      // tile-local start of each digit run
     __shared__ int64_t s_gbase[kBins];       // global start of the run minus its local start
@@ -135,7 +144,6 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
 
     // Issue every load of the tile first: keys, row ids, payload columns.
     K key[kSortIPT];
-    uint32_t dig[kSortIPT];
     int32_t rowv[kSortIPT];
     uint64_t pay[kSortIPT][NPAY > 0 ? NPAY : 1];
 #pragma unroll
@@ -152,29 +160,33 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_hist[0][0])[i] = 0;
     uint32_t gtot;
     const uint32_t gstart = block_excl_scan<kSortNT>(tid < kBins ? ghist[tid] : 0u, &gtot, s_scan);
+    // pd[k] = digit << 16 | position (digit kBins marks a missing item; a
+    // position is below the tile size, 4096).
+    uint32_t pd[kSortIPT];
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
         const int64_t idx = wbase + k * kWave + lane;
-        dig[k] = idx < cnt ? uint32_t(ord(key[k]) >> shift) & (kBins - 1) : kBins;
+        pd[k] = (idx < cnt ? uint32_t(ord(key[k]) >> shift) & (nbins - 1) : kBins) << 16;
     }
 
     // Stable rank of each item among the items of this wave with its digit.
-    uint32_t pos[kSortIPT];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
-        const bool valid = dig[k] < kBins;
+        const uint32_t d = pd[k] >> 16;
+        const bool valid = d < kBins;
         uint64_t peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; b++) {
-            const bool bit = (dig[k] >> b) & 1;
+            if (b >= dbits) break;                   // higher digit bits are all zero
+            const bool bit = (d >> b) & 1;
             const uint64_t bb = ballot(bit);
             peers &= bit ? bb : ~bb;
         }
         uint32_t old = 0;
-        if (valid) old = s_hist[w][dig[k]];
-        pos[k] = old + __popcll(peers & lt);
-        if (valid && (peers & lt) == 0) s_hist[w][dig[k]] = old + __popcll(peers);
+        if (valid) old = s_hist[w][d];
+        pd[k] |= old + __popcll(peers & lt);
+        if (valid && (peers & lt) == 0) s_hist[w][d] = old + __popcll(peers);
     }
     __syncthreads();
 
@@ -190,7 +202,7 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
     uint32_t tile_total;
     const uint32_t local = block_excl_scan<kSortNT>(tot, &tile_total, s_scan);
-    if (tid < kBins) {
+    if (tid < int(nbins)) {
         s_local[tid] = local;
         // Decoupled look-back for digit tid across earlier tiles.
         uint32_t *st = status + tile * kBins + tid;
@@ -228,23 +240,31 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     // Tile position of each item; stage the keys in digit order.
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
-        if (dig[k] < kBins) {
-            pos[k] += s_local[dig[k]] + s_hist[w][dig[k]];
-            reinterpret_cast<K *>(s_stage)[pos[k]] = key[k];
-            s_dig[pos[k]] = uint8_t(dig[k]);
+        const uint32_t d = pd[k] >> 16;
+        if (d < kBins) {
+            const uint32_t p = (pd[k] & 0xffffu) + s_local[d] + s_hist[w][d];
+            pd[k] = (d << 16) | p;
+            reinterpret_cast<K *>(s_stage)[p] = key[k];
+            s_dig[p] = uint8_t(d);
         }
     }
     __syncthreads();
     const int tile_cnt = int(cnt - tile * kSortTile < kSortTile ? cnt - tile * kSortTile : kSortTile);
-    flush_stage<K>(s_stage, s_dig, s_gbase, tile_cnt, keys_out);
+    int32_t gpos[kSortIPT];
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const int i = tid + k * kSortNT;
+        gpos[k] = i < tile_cnt ? int32_t(s_gbase[s_dig[i]] + i) : -1;
+    }
+    flush_stage<K>(s_stage, gpos, keys_out);
 
     if (c.rows_out) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSortIPT; k++)
-            if (dig[k] < kBins) reinterpret_cast<int32_t *>(s_stage)[pos[k]] = rowv[k];
+            if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = rowv[k];
         __syncthreads();
-        flush_stage<int32_t>(s_stage, s_dig, s_gbase, tile_cnt, c.rows_out);
+        flush_stage<int32_t>(s_stage, gpos, c.rows_out);
     }
 #pragma unroll
     for (int p = 0; p < NPAY; p++) {
@@ -253,21 +273,21 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
         if (dt == TQP_INT8) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if (dig[k] < kBins) reinterpret_cast<int8_t *>(s_stage)[pos[k]] = int8_t(pay[k][p]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(pay[k][p]);
             __syncthreads();
-            flush_stage<int8_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int8_t *>(c.pout[p]));
+            flush_stage<int8_t>(s_stage, gpos, static_cast<int8_t *>(c.pout[p]));
         } else if (dt == TQP_INT32) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if (dig[k] < kBins) reinterpret_cast<int32_t *>(s_stage)[pos[k]] = int32_t(pay[k][p]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(pay[k][p]);
             __syncthreads();
-            flush_stage<int32_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int32_t *>(c.pout[p]));
+            flush_stage<int32_t>(s_stage, gpos, static_cast<int32_t *>(c.pout[p]));
         } else {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if (dig[k] < kBins) reinterpret_cast<uint64_t *>(s_stage)[pos[k]] = pay[k][p];
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = pay[k][p];
             __syncthreads();
-            flush_stage<int64_t>(s_stage, s_dig, s_gbase, tile_cnt, static_cast<int64_t *>(c.pout[p]));
+            flush_stage<int64_t>(s_stage, gpos, static_cast<int64_t *>(c.pout[p]));
         }
     }
     __syncthreads();
@@ -306,6 +326,11 @@ struct SortCols {
 };
 
 inline int npass_for(int key_bits) { return (key_bits + kRadixBits - 1) / kRadixBits; }
+// Equal digit widths: the fewest bits per digit that keep npass_for's count.
+inline int digit_bits_for(int key_bits) {
+    const int np = npass_for(key_bits);
+    return np ? (key_bits + np - 1) / np : 0;
+}
 
 // Workspace of run_radix: ping-pong buffers (when more than one pass), the
 // digit histograms, tickets and look-back statuses.
@@ -321,12 +346,15 @@ inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) 
     return c.bytes();
 }
 
-// Runs npass stable passes over the ordinal's 8-bit digits (least significant
-// first) from key_in into key_out (they must not overlap), with the columns of
-// sc moving along.  npass == 0 copies.
+// Sorts by the low `bits` bits of the ordinal: npass_for(bits) stable passes
+// over equal-width digits (least significant first) from key_in into key_out
+// (they must not overlap), with the columns of sc moving along.  bits == 0
+// copies.
 template <class K, class Ord>
-int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int npass, Ord ord, K *key_out,
+int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord, K *key_out,
               const SortCols &sc, void *ws, hipStream_t s) {
+    const int npass = npass_for(bits);
+    const int dbits = digit_bits_for(bits);
     const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
     const unsigned grid_pass = persistent_grid(grid_all, tune(kTuneSortPerCu));
     PassCols pc = {};
@@ -364,7 +392,7 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int npass, Ord ord
         int64_t g = ceil_div(n > 0 ? n : 1, int64_t(kHistNT) * kHistIPT);
         if (g > 2048) g = 2048;
         TQP_LAUNCH("radix_hist", (k_radix_hist<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0, s,
-                   key_in, n, d_n, ord, npass, ghist);
+                   key_in, n, d_n, ord, npass, dbits, ghist);
         rc = check_launch("radix histogram");
         if (rc) return rc;
     }
@@ -377,28 +405,28 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int npass, Ord ord
         x.rows_out = sc.rows_out ? (to_out ? sc.rows_out : tmp_rows) : nullptr;
         for (int q = 0; q < sc.npay; q++) x.pout[q] = to_out ? sc.pout[q] : tmp_pay[q];
         uint32_t *st = status + size_t(p) * ntiles * kBins;
-        const int shift = p * kRadixBits;
+        const int shift = p * dbits;
         const uint32_t *gh = ghist + p * kBins;
         switch (sc.npay) {
         case 0:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 0, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
             break;
         case 1:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 1, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
             break;
         case 2:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 2, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
             break;
         case 3:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 3, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
             break;
         default:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 4, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
             break;
         }
         rc = check_launch("radix pass");

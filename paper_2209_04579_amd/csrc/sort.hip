@@ -30,12 +30,11 @@ static int sort_cols_impl(const void *key_in, int dtype, int64_t n, const int64_
     Carver cv(ws);
     cv.take<int64_t>(2);
     void *rws = cv.take<char>(radix_ws_bytes(n, dtype_size(dtype), npass_for(key_bits), pay_bytes));
-    const int npass = npass_for(key_bits);
     if (dtype == TQP_INT32)
-        return run_radix<int32_t>(static_cast<const int32_t *>(key_in), n, d_n, npass,
+        return run_radix<int32_t>(static_cast<const int32_t *>(key_in), n, d_n, key_bits,
                                   KeyOrd<int32_t>{int32_t(key_min)},
                                   static_cast<int32_t *>(key_out), sc, rws, s);
-    return run_radix<int64_t>(static_cast<const int64_t *>(key_in), n, d_n, npass,
+    return run_radix<int64_t>(static_cast<const int64_t *>(key_in), n, d_n, key_bits,
                               KeyOrd<int64_t>{key_min}, static_cast<int64_t *>(key_out), sc, rws, s);
 }
 

@@ -57,6 +57,8 @@ enum TuneKnob {
     kTuneRlePerCu,          // ... of run-length encoding
     kTuneMatchPerCu,        // ... of the join match
     kTuneGbScanPerCu,       // ... of the sorted group-by scan
+    kTunePartOvfCap,        // overflowing buckets a partition sort re-sorts before it
+                            // sorts the whole input instead
     kTuneCount
 };
 int tune(TuneKnob k);

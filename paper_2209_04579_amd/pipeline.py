@@ -96,8 +96,7 @@ class StarQuery:
         self.npairs = _i64(1, dev)
         self.ws_j = workspace(join_workspace_bytes(n, nd, fact["fk"].dtype, JOIN_SORTED,
                                                    self.cap), dev)
-        # group-bys
-        self.gkey = _i64(self.cap, dev)
+        # group-bys; the packed key is int32 when its catalog range fits
         if mode == "q1":
             self.ga_span = self.cat_span
             self.ga_lo = self.cat_min
@@ -106,12 +105,16 @@ class StarQuery:
             self.ga_span = self.flag_span * 2
             self.ga_lo = self.flag_min * 2
             self.ga_aggs = [("sum", 0), ("sum", 1), ("count",)]
+        fits32 = -(1 << 31) <= self.ga_lo and self.ga_lo + self.ga_span <= (1 << 31)
+        kdt = torch.int32 if fits32 else torch.int64
+        self.gkey = torch.empty(self.cap, dtype=kdt, device=dev)
         dense = 0 < self.ga_span <= min(self.dense_max, 1024)
         self.ga_flags = GB_DENSE if dense else 0
-        self.ga_key = _i64(max(self.ga_span, 1) if dense else self.cap, dev)
+        self.ga_key = torch.empty(max(self.ga_span, 1) if dense else self.cap, dtype=kdt,
+                                  device=dev)
         self.ga_out = [_i64(self.ga_key.numel(), dev) for _ in self.ga_aggs]
         self.ga_ng = _i64(1, dev)
-        self.ws_ga = workspace(groupby_workspace_bytes(self.cap, torch.int64, len(self.ga_aggs),
+        self.ws_ga = workspace(groupby_workspace_bytes(self.cap, kdt, len(self.ga_aggs),
                                                        self.ga_flags, self.ga_span), dev)
         if mode == "q2":
             self.gb_key = torch.empty(self.cap, dtype=fact["fk"].dtype, device=dev)

@@ -154,3 +154,36 @@ def test_full_size_learned_join_matches_oracle(tqp):
     for k in ("key", "lstart", "lcnt", "rstart", "rcnt"):
         assert np.array_equal(host(got[k]), want[k]), k
     assert got["total"] == want["total"]
+
+
+def test_heavy_keys_get_buckets_of_their_own(tqp, mix):
+    """Zipf heavy hitters fill whole buckets; the model's jumps at heavy keys
+    keep them out of multi-valued buckets, so little goes to the fallback,
+    unlike the MSD radix partition of the same keys."""
+    left, right = mix
+    n = left.size
+    bits = max(1, (n // 1024).bit_length())
+    model = tqp.lcdf_train([dev(left), dev(right)], sample_stride=100, nleaf=4096, steps=200)
+    sk, rows, st = tqp.partition_sort(dev(left), tqp.PART_LEARNED, model, bucket_bits=bits)
+    ok, perm = oracle.sort(left)
+    assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    assert st["single_valued_big"] >= 1
+    sk2, rows2, st2 = tqp.partition_sort(dev(left), tqp.PART_RADIX, None, bucket_bits=bits)
+    assert np.array_equal(host(sk2), ok) and np.array_equal(host(rows2), perm)
+    assert st["fallback_keys"] < 0.05 * n
+    assert st["fallback_keys"] < st2["fallback_keys"]
+
+
+def test_overflow_cap_sorts_whole_input(tqp, mix):
+    """With the overflow cap at 1 and several overflowing buckets, the whole
+    input goes through the plain radix sort; the result is the same."""
+    left, _ = mix
+    old = tqp.tune_knobs()["part.ovf_cap"][0]
+    try:
+        tqp.tune_set("part.ovf_cap", 1)
+        sk, rows, st = tqp.partition_sort(dev(left), tqp.PART_RADIX, None, bucket_bits=8)
+        assert st["fallback_buckets"] >= 2
+        ok, perm = oracle.sort(left)
+        assert np.array_equal(host(sk), ok) and np.array_equal(host(rows), perm)
+    finally:
+        tqp.tune_set("part.ovf_cap", old)
