@@ -208,8 +208,9 @@ def bench_learned(args, tqp, stream) -> dict:
     print(f"[bench] learned: generated {nl}+{nr} keys in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     # 4096 partitions of the key range, each cut further by the same model
-    # into 2^(bits - 12) LDS-sized buckets (about 1024 keys on average)
-    bits = max(12, min(24, (max(nl, nr) // 1024).bit_length()))
+    # into 2^(bits - 12) buckets of about 8 keys on average (at most 24 bits:
+    # the model's float32 rank), sorted in registers or LDS after grouping
+    bits = max(12, min(24, (max(nl, nr) // 8).bit_length()))
     lo = min(int(left.min().item()), int(right.min().item()))
     hi = max(int(left.max().item()), int(right.max().item()))
     key_bits = (hi - lo).bit_length()

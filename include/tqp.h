@@ -278,15 +278,15 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
 /* ------------------------------------------------------------------------
  * tqp_partition_sort -- the same stable ascending sort as tqp_sort (same
  * out_key and out_rows bytes), by partitioning into 2^bucket_bits key-range
- * buckets (bucket_bits in [1, 24]; about n / 1024 buckets keeps them in LDS)
- * and sorting each bucket on its own.
+ * buckets (bucket_bits in [1, 24]; about n / 8 buckets keeps most of them
+ * small enough to sort in registers) and sorting each bucket on its own.
  *   mode TQP_PART_LEARNED: buckets from `model` (trained by tqp_lcdf_train);
  *   mode TQP_PART_RADIX:   buckets = top bucket_bits of key - key_min over
  *                          key_bits bits (key_bits 0 = derive on the device).
  *   in_rows  : optional row ids (NULL = positions); out_rows required.
  *   h_stats  : optional HOST array of 4: largest bucket, buckets sorted by
  *              the radix fallback, keys in them, single-valued large buckets.
- * Buckets of more than 4096 keys with distinct keys fall back to the radix
+ * Buckets of more than 8192 keys with distinct keys fall back to the radix
  * sort over their own key range (all of them gathered into one sort); if
  * more than 65536 buckets (the "part.ovf_cap" knob) overflow, the whole input
  * is sorted by the radix sort instead.  SYNCHRONIZES the stream

@@ -112,6 +112,22 @@ __global__ __launch_bounds__(kRleNT) void k_rle(const K *__restrict__ keys, int6
     }
 }
 
+// Run heads of a sorted int32 column for other operators (the partition
+// sort): ukey / ustart receive each run's value and first position, *d_nu
+// the run count.  words: rle_words(n) zeroed-here uint64 words (ticket and
+// look-back statuses).
+size_t rle_words(int64_t n) { return size_t(1 + ceil_div(n > 0 ? n : 1, kRleTile)); }
+
+int rle_i32(const int32_t *keys, int64_t n, int32_t *ukey, int32_t *ustart, int64_t *d_nu,
+            uint64_t *words, hipStream_t s) {
+    int rc = fill_u64(words, 0, int64_t(rle_words(n)), s);
+    if (rc) return rc;
+    const unsigned g = persistent_grid(ceil_div(n > 0 ? n : 1, kRleTile), tune(kTuneRlePerCu));
+    TQP_LAUNCH("rle", k_rle<int32_t>, dim3(g), dim3(kRleNT), 0, s, keys, n, nullptr, ukey, ustart,
+               d_nu, reinterpret_cast<uint32_t *>(words), words + 1);
+    return check_launch("run-length encoding");
+}
+
 struct MatchArgs {
     const void *uL;
     const int32_t *sL;

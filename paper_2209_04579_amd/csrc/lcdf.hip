@@ -6,9 +6,10 @@
 //   leaf = clamp(floor(root * L), 0, L - 1)
 //   F    = the leaf's piecewise-linear spline through kKnots knots (key, rank)
 //          taken at evenly spaced points of the leaf's sorted sample, over the
-//          key itself in float64 (not over x: a float32 x cannot tell apart
-//          keys closer than 2^-24 of the key span, and a dense cluster of a
-//          million keys can sit inside such a gap)
+//          key itself: the segment is found by int64 compares and the offset
+//          into it is the exact int64 difference (not x: a float32 x cannot
+//          tell apart keys closer than 2^-24 of the key span, and a dense
+//          cluster of a million keys can sit inside such a gap)
 // and, where a leaf holds a heavy key h (one that fills a run of the sorted
 // sample), F jumps exactly at h: keys below h are held at or under the rank
 // where h's copies start, keys above at or over the rank where they end, and
@@ -38,6 +39,7 @@
 // over its own key range.  With bucket = top bits of (key - kmin) the same
 // pipeline is the plain MSD radix partitioner the learned one is judged
 // against.
+#include <limits.h>
 #include <math.h>
 #include <algorithm>
 #include <vector>
@@ -52,7 +54,7 @@ constexpr int kNParam = 3 * kHidden + 1;     // centre offset, log-width, log-he
 constexpr int kTrainPoints = 16384;          // root training set (sample points, even ranks)
 constexpr int kGradBlocks = 64;
 constexpr int kLeafMax = 65536;
-constexpr int kBucketCap = 4096;             // keys sorted in LDS by one workgroup
+constexpr int kBucketCap = 8192;             // keys sorted in LDS by one workgroup
 constexpr int kBucketNT = 256;
 constexpr int kHeavyMin = 4;                 // sample copies that make a key heavy
 constexpr int64_t kOvfCap = 65536;           // overflow buckets re-sorted one by one
@@ -70,8 +72,8 @@ struct LcdfModel {
     float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
     float c0[kHidden], s0[kHidden];
     struct Leaf {
-        double kx[kKnots];                    // knot keys, ascending (as float64)
-        double slope[kKnots - 1];             // rank per key unit on each segment
+        int64_t kx[kKnots];                   // knot keys, ascending
+        float slope[kKnots - 1];              // rank per key unit on each segment
         float kr[kKnots];                     // knot ranks, ascending
         float lo, hi;                         // the leaf's rank range
         int64_t hkey;                         // heavy key, when hlo <= hhi
@@ -110,27 +112,28 @@ __device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
     return k;
 }
 
-// F of one key.  The spline segment is the last knot at or below the key;
-// each segment's value is clamped to its two knot ranks, so F is monotone
-// across segments even with rounding.
-__device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
-    const float x = lcdf_x(m, key);
-    const Leaf &L = m->leaf[lcdf_leaf(m, lcdf_root(m, x))];
+// F of one key in its leaf.  The spline segment is the last knot at or below
+// the key; each segment's value is clamped to its two knot ranks, so F is
+// monotone across segments even with rounding.
+__device__ __forceinline__ int lcdf_leaf_of(const LcdfModel *m, int64_t key) {
+    return lcdf_leaf(m, lcdf_root(m, lcdf_x(m, key)));
+}
+
+__device__ __forceinline__ float lcdf_leaf_eval(const Leaf &L, int64_t key) {
     float f = L.lo;
     const int nk = L.nk;
     if (nk > 0) {
-        const double kd = double(key);
-        if (kd <= L.kx[0]) {
+        if (key <= L.kx[0]) {
             f = L.kr[0];
-        } else if (kd >= L.kx[nk - 1]) {
+        } else if (key >= L.kx[nk - 1]) {
             f = L.kr[nk - 1];
         } else {
             int j = 0;
 #pragma unroll
             for (int t = 1; t < kKnots - 1; t++)
-                if (t < nk - 1 && L.kx[t] <= kd) j = t;
-            const double r = double(L.kr[j]) + L.slope[j] * (kd - L.kx[j]);
-            float g = float(r);
+                if (t < nk - 1 && L.kx[t] <= key) j = t;
+            const float d = float(uint64_t(key) - uint64_t(L.kx[j]));   // in [0, 2^64)
+            float g = fmaf(L.slope[j], d, L.kr[j]);
             g = g < L.kr[j] ? L.kr[j] : g;
             f = g > L.kr[j + 1] ? L.kr[j + 1] : g;
         }
@@ -142,6 +145,10 @@ __device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
         else f = f > L.hhi ? f : L.hhi;
     }
     return f;
+}
+
+__device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
+    return lcdf_leaf_eval(m->leaf[lcdf_leaf_of(m, key)], key);
 }
 
 // Bucket ordinals for run_radix: learned, or the top bits of key - kmin.
@@ -159,9 +166,11 @@ template <class K> struct LearnedOrd {
 template <class K> struct MsdOrd {
     K key_min;
     int shift;
+    uint32_t top;                               // 2^bucket_bits - 1
     __device__ __forceinline__ uint64_t operator()(K k) const {
         using U = typename KeyTraits<K>::U;
-        return uint64_t(U(U(k) - U(key_min))) >> shift;
+        const uint64_t b = uint64_t(U(U(k) - U(key_min))) >> shift;
+        return b > top ? top : b;               // keys outside the stated range
     }
 };
 
@@ -400,12 +409,12 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
     const int nk = cnt < kKnots ? int(cnt) : kKnots;
     for (int j = 0; j < nk; j++) {
         const int64_t p = nk > 1 ? a0 + (cnt - 1) * j / (nk - 1) : a0;
-        L.kx[j] = double(sorted[p]);
+        L.kx[j] = sorted[p];
         L.kr[j] = float((double(p) + 0.5) / double(m));
     }
     for (int j = 0; j + 1 < nk; j++) {
-        const double dx = L.kx[j + 1] - L.kx[j];
-        L.slope[j] = dx > 0 ? (double(L.kr[j + 1]) - double(L.kr[j])) / dx : 0.0;
+        const double dx = double(uint64_t(L.kx[j + 1]) - uint64_t(L.kx[j]));
+        L.slope[j] = dx > 0 ? float((double(L.kr[j + 1]) - double(L.kr[j])) / dx) : 0.f;
     }
     L.nk = nk;
     L.lo = L.kr[0];
@@ -456,73 +465,199 @@ __global__ void k_lcdf_buckets(const LcdfModel *mod, const K *keys, int64_t n, i
 
 struct BucketStats {
     unsigned long long max_bucket;
-    unsigned long long overflow;        // multi-valued buckets larger than the LDS tile
-    unsigned long long overflow_keys;
-    unsigned long long single_big;      // single-valued buckets larger than the tile
+    unsigned long long nbig;            // buckets larger than the LDS tile
+    unsigned long long nmed;            // buckets sorted by a workgroup in LDS
+    unsigned long long nwave;           // buckets sorted by one wave
 };
+
+constexpr int kSmallRun = 16;           // buckets up to this size sort in registers
 
 struct Overflow {
     int64_t start, len, kmin, kmax;
     int64_t off;                        // position in the gathered overflow keys
 };
 
+// Bucket number of every key, evaluated once (int32, in [0, nb)).
 template <class K, class Ord>
-__global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *rows, int64_t n,
-                                                           Ord ord, BucketStats *stats,
-                                                           Overflow *ovf, int64_t ovf_cap) {
-    __shared__ int64_t s_rng[2];
+__global__ __launch_bounds__(256) void k_bucket_ids(const K *__restrict__ keys, int64_t n, Ord ord,
+                                                    int32_t *__restrict__ ids) {
+    constexpr int R = 4;                // keys per thread per step, loads issued together
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * R;
+    for (int64_t base = blockIdx.x * int64_t(blockDim.x) * R + threadIdx.x; base < n;
+         base += stride) {
+        K k[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + int64_t(r) * blockDim.x;
+            k[r] = i < n ? keys[i] : K(0);
+        }
+        uint32_t b[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) b[r] = uint32_t(ord(k[r]));
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + int64_t(r) * blockDim.x;
+            if (i < n) ids[i] = int32_t(b[r]);
+        }
+    }
+}
+
+// The buckets that occur are the runs of the grouped bucket numbers: run r
+// starts at rs[r] and ends where run r + 1 starts (the last one at n).
+__device__ __forceinline__ int64_t run_end(const int32_t *rs, int64_t nruns, int64_t r,
+                                           int64_t n) {
+    return r + 1 < nruns ? int64_t(rs[r + 1]) : n;
+}
+
+// One thread per bucket.  Buckets of at most kSmallRun keys are sorted in
+// registers by a bitonic network on (key, position), the stable order;
+// larger ones are listed for one wave (up to kWave keys), a workgroup (up to
+// kBucketCap keys) or the big-bucket path.
+template <class K>
+__global__ __launch_bounds__(256) void k_bucket_small(K *keys, int32_t *rows,
+                                                      const int32_t *__restrict__ rs,
+                                                      const int64_t *__restrict__ d_nruns,
+                                                      int64_t n, BucketStats *stats, int32_t *med,
+                                                      int32_t *wav, Overflow *big, int64_t big_cap) {
+    const K kMax = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
+    const int64_t nruns = *d_nruns;
+    unsigned long long mx = 0;
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nruns;
+         b += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s0 = rs[b], len = run_end(rs, nruns, b, n) - s0;
+        if (len <= 1) continue;
+        mx = (unsigned long long)len > mx ? (unsigned long long)len : mx;
+        if (len > kSmallRun) {
+            if (len <= kWave) {
+                const unsigned long long slot = atomicAdd(&stats->nwave, 1ull);
+                wav[slot] = int32_t(b);
+            } else if (len <= kBucketCap) {
+                const unsigned long long slot = atomicAdd(&stats->nmed, 1ull);
+                med[slot] = int32_t(b);
+            } else {
+                const unsigned long long slot = atomicAdd(&stats->nbig, 1ull);
+                if (int64_t(slot) < big_cap) big[slot] = Overflow{s0, len, 0, 0, 0};
+            }
+            continue;
+        }
+        K k[kSmallRun];
+        int32_t r[kSmallRun];
+        uint32_t p[kSmallRun];
+#pragma unroll
+        for (int i = 0; i < kSmallRun; i++) {
+            k[i] = i < len ? keys[s0 + i] : kMax;
+            r[i] = i < len ? rows[s0 + i] : 0;
+            p[i] = uint32_t(i);
+        }
+#pragma unroll
+        for (int w = 2; w <= kSmallRun; w <<= 1) {
+#pragma unroll
+            for (int j = w >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = 0; i < kSmallRun; i++) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const bool up = (i & w) == 0;
+                        const bool gt = k[i] > k[l] || (k[i] == k[l] && p[i] > p[l]);
+                        if (gt == up) {
+                            const K tk = k[i];
+                            k[i] = k[l];
+                            k[l] = tk;
+                            const int32_t tr = r[i];
+                            r[i] = r[l];
+                            r[l] = tr;
+                            const uint32_t tp = p[i];
+                            p[i] = p[l];
+                            p[l] = tp;
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kSmallRun; i++)
+            if (i < len) {
+                keys[s0 + i] = k[i];
+                rows[s0 + i] = r[i];
+            }
+    }
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned long long om = __shfl_xor(mx, o, kWave);
+        mx = om > mx ? om : mx;
+    }
+    if (lane_id() == 0 && mx) atomicMax(&stats->max_bucket, mx);
+}
+
+// Buckets of kSmallRun + 1 to kWave keys: one wave each, one key per lane,
+// a bitonic network over the lanes (shuffles) on (key, position).
+template <class K>
+__global__ __launch_bounds__(256) void k_bucket_wave(K *keys, int32_t *rows,
+                                                     const int32_t *__restrict__ rs,
+                                                     const int64_t *__restrict__ d_nruns, int64_t n,
+                                                     const int32_t *__restrict__ wav,
+                                                     const BucketStats *stats) {
+    const K kMax = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
+    const int64_t nw = int64_t(stats->nwave);
+    const int64_t nruns = *d_nruns;
+    const int lane = lane_id();
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / kWave);
+    for (int64_t m = blockIdx.x * int64_t(blockDim.x / kWave) + wave_id(); m < nw; m += waves) {
+        const int64_t b = wav[m];
+        const int64_t s0 = rs[b], len = run_end(rs, nruns, b, n) - s0;
+        const bool in = lane < len;
+        K k = in ? keys[s0 + lane] : kMax;
+        int32_t r = in ? rows[s0 + lane] : 0;
+        int32_t p = lane;                           // padding sorts after every key
+#pragma unroll
+        for (int w = 2; w <= kWave; w <<= 1) {
+#pragma unroll
+            for (int j = w >> 1; j > 0; j >>= 1) {
+                const K ok = __shfl_xor(k, j, kWave);
+                const int32_t orow = __shfl_xor(r, j, kWave);
+                const int32_t op = __shfl_xor(p, j, kWave);
+                const bool lower = (lane & j) == 0;
+                const bool up = (lane & w) == 0;
+                const bool mine_gt = k > ok || (k == ok && p > op);
+                // the lower lane of an ascending pair keeps the smaller element
+                const bool take = (lower == up) ? mine_gt : !mine_gt;
+                if (take) {
+                    k = ok;
+                    r = orow;
+                    p = op;
+                }
+            }
+        }
+        if (in) {
+            keys[s0 + lane] = k;
+            rows[s0 + lane] = r;
+        }
+    }
+}
+
+// Persistent workgroups over the listed buckets (more than kSmallRun and at
+// most kBucketCap keys): each is sorted in LDS by (key, position), which is
+// the stable order; each thread holds the row ids of its output slots in
+// registers, so rows are permuted in place.
+template <class K>
+__global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *rows,
+                                                           const int32_t *__restrict__ rs,
+                                                           const int64_t *__restrict__ d_nruns,
+                                                           int64_t n,
+                                                           const int32_t *__restrict__ med,
+                                                           const BucketStats *stats) {
+    constexpr int kPer = kBucketCap / kBucketNT;
     __shared__ K s_key[kBucketCap];
     __shared__ uint16_t s_idx[kBucketCap];
-    __shared__ int32_t s_row[kBucketCap];
-    const uint64_t b = blockIdx.x;
-    if (threadIdx.x < 2) {
-        const uint64_t target = b + threadIdx.x;       // first position with ordinal >= target
-        int64_t lo = 0, hi = n;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (ord(keys[mid]) < target) lo = mid + 1;
-            else hi = mid;
-        }
-        s_rng[threadIdx.x] = lo;
-    }
-    __syncthreads();
-    const int64_t start = s_rng[0], size = s_rng[1] - s_rng[0];
-    if (size <= 1) return;
-    if (threadIdx.x == 0) atomicMax(&stats->max_bucket, (unsigned long long)size);
-    if (size > kBucketCap) {
-        // Block-wide min and max of the bucket.  When they are equal every key
-        // is, and the bucket (still in input order) is already stably sorted.
-        K lo = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
-        K hi = KeyTraits<K>::kBits == 32 ? K(INT32_MIN) : K(INT64_MIN);
-        for (int64_t i = start + threadIdx.x; i < start + size; i += kBucketNT) {
-            const K x = keys[i];
-            lo = x < lo ? x : lo;
-            hi = x > hi ? x : hi;
-        }
-        s_key[threadIdx.x] = lo;
-        s_key[kBucketNT + threadIdx.x] = hi;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int t = 1; t < kBucketNT; t++) {
-                lo = s_key[t] < lo ? s_key[t] : lo;
-                hi = s_key[kBucketNT + t] > hi ? s_key[kBucketNT + t] : hi;
-            }
-            if (lo == hi) {
-                atomicAdd(&stats->single_big, 1ull);
-            } else {
-                const unsigned long long slot = atomicAdd(&stats->overflow, 1ull);
-                atomicAdd(&stats->overflow_keys, (unsigned long long)size);
-                if (int64_t(slot) < ovf_cap) ovf[slot] = Overflow{start, size, int64_t(lo), int64_t(hi)};
-            }
-        }
-        return;
-    }
+    const int64_t nmed = int64_t(stats->nmed);
+    const int64_t nruns = *d_nruns;
+    for (int64_t m = blockIdx.x; m < nmed; m += gridDim.x) {
+    const int64_t b = med[m];
+    const int64_t s0 = rs[b], size = run_end(rs, nruns, b, n) - s0;
     int P = 1;
     while (P < size) P <<= 1;
     for (int i = threadIdx.x; i < P; i += kBucketNT) {
         if (i < size) {
-            s_key[i] = keys[start + i];
-            s_row[i] = rows[start + i];
+            s_key[i] = keys[s0 + i];
             s_idx[i] = uint16_t(i);
         } else {
             s_key[i] = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
@@ -551,9 +686,59 @@ __global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *row
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < size; i += kBucketNT) {
-        keys[start + i] = s_key[i];
-        rows[start + i] = s_row[s_idx[i]];
+    int32_t rv[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const int i = threadIdx.x + r * kBucketNT;
+        rv[r] = i < size ? rows[s0 + s_idx[i]] : 0;
+    }
+    __syncthreads();                     // every row id is read before any is overwritten
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const int i = threadIdx.x + r * kBucketNT;
+        if (i < size) {
+            keys[s0 + i] = s_key[i];
+            rows[s0 + i] = rv[r];
+        }
+    }
+    __syncthreads();                     // LDS is reused by the next bucket
+    }
+}
+
+// Min and max key of the big buckets, in chunks of at most kChunk keys per
+// workgroup: chunk c covers keys [cs[c].start, cs[c].start + cs[c].len) of big
+// bucket cs[c].kmin (its index); one atomic min and max per chunk.
+constexpr int64_t kChunk = 65536;
+
+template <class K>
+__global__ __launch_bounds__(256) void k_big_minmax(const K *__restrict__ keys,
+                                                    const Overflow *__restrict__ cs,
+                                                    long long *__restrict__ mm) {
+    __shared__ long long s_lo[256 / kWave], s_hi[256 / kWave];
+    const Overflow c = cs[blockIdx.x];
+    long long lo = LLONG_MAX, hi = LLONG_MIN;
+    for (int64_t i = c.start + threadIdx.x; i < c.start + c.len; i += blockDim.x) {
+        const long long x = keys[i];
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    for (int o = 1; o < kWave; o <<= 1) {
+        const long long ol = __shfl_xor(lo, o, kWave), oh = __shfl_xor(hi, o, kWave);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    if (lane_id() == 0) {
+        s_lo[wave_id()] = lo;
+        s_hi[wave_id()] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / kWave; w++) {
+            lo = s_lo[w] < lo ? s_lo[w] : lo;
+            hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        atomicMin(&mm[2 * c.kmin], lo);
+        atomicMax(&mm[2 * c.kmin + 1], hi);
     }
 }
 
@@ -627,8 +812,17 @@ static int64_t sample_count(const tqp_col *cols, int ncols, int64_t stride) {
 
 struct PartLayout {
     BucketStats *stats;
-    Overflow *ovf;
+    Overflow *ovf;                      // big buckets, then the overflow list
     int64_t ovf_cap;
+    Overflow *chunks;                   // min/max chunks of the big buckets
+    int64_t chunk_cap;
+    long long *mm;                      // min, max per big bucket
+    int32_t *ids, *ids_sorted;          // bucket number of every key, before / after grouping
+    int32_t *med;                       // buckets sorted by a workgroup
+    int32_t *wav;                       // buckets sorted by one wave
+    int32_t *ruk, *rus;                 // runs of the grouped bucket numbers: value, start
+    int64_t *d_nruns;
+    uint64_t *rle_ws;
     void *rws;
     size_t rws_bytes;
     void *tmp_k, *tmp2_k;
@@ -645,7 +839,18 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     L.stats = c.take<BucketStats>(1);
     L.ovf_cap = (int64_t(1) << bucket_bits) < kOvfCap ? (int64_t(1) << bucket_bits) : kOvfCap;
     L.ovf = c.take<Overflow>(size_t(L.ovf_cap));
-    L.rws_bytes = radix_ws_bytes(nn, ksize, npass_for(bucket_bits), 0);
+    L.chunk_cap = nn / kChunk + 1 + L.ovf_cap;
+    L.chunks = c.take<Overflow>(size_t(L.chunk_cap));
+    L.mm = c.take<long long>(size_t(2 * L.ovf_cap));
+    L.ids = c.take<int32_t>(size_t(nn));
+    L.ids_sorted = c.take<int32_t>(size_t(nn));
+    L.med = c.take<int32_t>(size_t(nn));
+    L.wav = c.take<int32_t>(size_t(nn));
+    L.ruk = c.take<int32_t>(size_t(nn));
+    L.rus = c.take<int32_t>(size_t(nn));
+    L.d_nruns = c.take<int64_t>(1);
+    L.rle_ws = c.take<uint64_t>(rle_words(nn));
+    L.rws_bytes = radix_ws_bytes(nn, 4, npass_for(bucket_bits), ksize);
     L.rws = c.take<char>(L.rws_bytes);
     // fallback: the gathered overflow keys, their sorted copy, the radix workspace
     L.tmp_k = c.take<char>(size_t(nn) * ksize);
@@ -658,6 +863,19 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     return L;
 }
 
+// Copies host -> device on s and waits, so the host buffer may go away.
+static int upload(void *dst, const void *src, size_t bytes, hipStream_t s, const char *what) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? TQP_OK : set_error(TQP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static int download(void *dst, const void *src, size_t bytes, hipStream_t s, const char *what) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? TQP_OK : set_error(TQP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
 template <class K, class Ord>
 static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n, Ord ord,
                                 int bucket_bits, K *out_key, int32_t *out_rows, int64_t *h_stats,
@@ -665,23 +883,49 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     PartLayout L = part_layout(ws, n, sizeof(K), bucket_bits);
     int rc = fill_u64(L.stats, 0, sizeof(BucketStats) / 8, s);
     if (rc) return rc;
+    // 1. every key's bucket number, once
+    {
+        int64_t g = ceil_div(n, 256);
+        if (g > 16384) g = 16384;
+        TQP_LAUNCH("bucket_ids", (k_bucket_ids<K, Ord>), dim3(unsigned(g)), dim3(256), 0, s, key, n,
+                   ord, L.ids);
+        if ((rc = check_launch("bucket ids"))) return rc;
+    }
+    // 2. group the keys by bucket: stable radix passes over the bucket
+    // number, the key and its row id moving along
     SortCols sc = {};
     sc.rows_in = in_rows;
     sc.rows_out = out_rows;
-    rc = run_radix<K, Ord>(key, n, nullptr, bucket_bits, ord, out_key, sc, L.rws, s);
+    sc.npay = 1;
+    sc.pin[0] = key;
+    sc.pout[0] = out_key;
+    sc.pdt[0] = sizeof(K) == 4 ? TQP_INT32 : TQP_INT64;
+    rc = run_radix<int32_t, KeyOrd<int32_t>>(L.ids, n, nullptr, bucket_bits, KeyOrd<int32_t>{0},
+                                             L.ids_sorted, sc, L.rws, s);
     if (rc) return rc;
-    const unsigned nb = 1u << bucket_bits;
-    TQP_LAUNCH("bucket_sort", (k_bucket_sort<K, Ord>), dim3(nb), dim3(kBucketNT), 0, s, out_key,
-               out_rows, n, ord, L.stats, L.ovf, L.ovf_cap);
+    // 3. the buckets that occur (runs of the grouped bucket numbers), then
+    // each one sorted: short ones in registers, the rest by a workgroup in LDS
+    if ((rc = rle_i32(L.ids_sorted, n, L.ruk, L.rus, L.d_nruns, L.rle_ws, s))) return rc;
+    {
+        int64_t g = ceil_div(n, 256);
+        if (g > 16384) g = 16384;
+        TQP_LAUNCH("bucket_small", k_bucket_small<K>, dim3(unsigned(g)), dim3(256), 0, s, out_key,
+                   out_rows, L.rus, L.d_nruns, n, L.stats, L.med, L.wav, L.ovf, L.ovf_cap);
+        if ((rc = check_launch("bucket small sort"))) return rc;
+    }
+    TQP_LAUNCH("bucket_wave", k_bucket_wave<K>, dim3(unsigned(kComputeUnits * 8)), dim3(256), 0, s,
+               out_key, out_rows, L.rus, L.d_nruns, n, L.wav, L.stats);
+    if ((rc = check_launch("bucket wave sort"))) return rc;
+    TQP_LAUNCH("bucket_sort", k_bucket_sort<K>, dim3(unsigned(kComputeUnits * 2)), dim3(kBucketNT),
+               0, s, out_key, out_rows, L.rus, L.d_nruns, n, L.med, L.stats);
     if ((rc = check_launch("bucket sort"))) return rc;
     BucketStats hs;
-    hipError_t e = hipMemcpyAsync(&hs, L.stats, sizeof hs, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return set_error(TQP_EHIP, "partition stats: %s", hipGetErrorString(e));
+    if ((rc = download(&hs, L.stats, sizeof hs, s, "partition stats"))) return rc;
+    int64_t n_ovf = 0, ovf_keys = 0, single = 0;
     const int64_t cap = tune(kTunePartOvfCap) < L.ovf_cap ? tune(kTunePartOvfCap) : L.ovf_cap;
-    if (int64_t(hs.overflow) > cap) {
-        // More overflowing buckets than the list holds: the model is useless
-        // for these keys, so sort the whole input by the plain radix sort.
+    if (int64_t(hs.nbig) > cap) {
+        // More big buckets than the list holds: the partition is useless for
+        // these keys, so sort the whole input by the plain radix sort.
         SortCols fc = {};
         fc.rows_in = in_rows;
         fc.rows_out = out_rows;
@@ -689,51 +933,84 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
                                      KeyOrd<K>{sizeof(K) == 4 ? K(INT32_MIN) : K(INT64_MIN)},
                                      out_key, fc, L.fws, s);
         if (rc) return rc;
-    }
-    const int64_t novf = int64_t(hs.overflow) <= cap ? int64_t(hs.overflow) : 0;
-    if (novf > 0) {
-        std::vector<Overflow> list(static_cast<size_t>(novf));
-        e = hipMemcpyAsync(list.data(), L.ovf, sizeof(Overflow) * size_t(novf),
-                           hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return set_error(TQP_EHIP, "overflow list: %s", hipGetErrorString(e));
-        std::sort(list.begin(), list.end(),
-                  [](const Overflow &a, const Overflow &b) { return a.start < b.start; });
-        int64_t total = 0, kmin = list[0].kmin, kmax = list[0].kmax;
-        for (Overflow &o : list) {
-            o.off = total;
-            total += o.len;
-            kmin = o.kmin < kmin ? o.kmin : kmin;
-            kmax = o.kmax > kmax ? o.kmax : kmax;
+        n_ovf = int64_t(hs.nbig);
+        ovf_keys = n;
+    } else if (hs.nbig > 0) {
+        // 3. min and max of each big bucket: equal means one key, already in
+        // stable order; the others are re-sorted together
+        const size_t nbig = size_t(hs.nbig);
+        std::vector<Overflow> big(nbig);
+        if ((rc = download(big.data(), L.ovf, sizeof(Overflow) * nbig, s, "big buckets"))) return rc;
+        std::vector<Overflow> chunks;
+        for (size_t j = 0; j < nbig; j++)
+            for (int64_t o = 0; o < big[j].len; o += kChunk)
+                chunks.push_back(Overflow{big[j].start + o,
+                                          big[j].len - o < kChunk ? big[j].len - o : kChunk,
+                                          int64_t(j), 0, 0});
+        if (int64_t(chunks.size()) > L.chunk_cap)
+            return set_error(TQP_EHIP, "partition sort: %zu chunks exceed %lld", chunks.size(),
+                             (long long)L.chunk_cap);
+        std::vector<long long> mm(2 * nbig);
+        for (size_t j = 0; j < nbig; j++) {
+            mm[2 * j] = LLONG_MAX;
+            mm[2 * j + 1] = LLONG_MIN;
         }
-        e = hipMemcpyAsync(L.ovf, list.data(), sizeof(Overflow) * size_t(novf),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);     // list is host memory
-        if (e != hipSuccess) return set_error(TQP_EHIP, "overflow list: %s", hipGetErrorString(e));
-        int64_t g = ceil_div(total, 256);
-        if (g > 8192) g = 8192;
-        K *tk = static_cast<K *>(L.tmp_k), *tk2 = static_cast<K *>(L.tmp2_k);
-        TQP_LAUNCH("ovf_gather", k_ovf_gather<K>, dim3(unsigned(g)), dim3(256), 0, s, out_key,
-                   out_rows, L.ovf, int(novf), total, tk, L.tmp_r);
-        if ((rc = check_launch("overflow gather"))) return rc;
-        const uint64_t span = uint64_t(kmax) - uint64_t(kmin);
-        int bits = 0;
-        while (bits < 64 && (span >> bits) != 0) bits++;
-        SortCols fc = {};
-        fc.rows_in = L.tmp_r;
-        fc.rows_out = L.tmp2_r;
-        rc = run_radix<K, KeyOrd<K>>(tk, total, nullptr, bits, KeyOrd<K>{K(kmin)}, tk2, fc,
-                                     L.fws, s);
-        if (rc) return rc;
-        TQP_LAUNCH("ovf_scatter", k_ovf_scatter<K>, dim3(unsigned(g)), dim3(256), 0, s, tk2,
-                   L.tmp2_r, L.ovf, int(novf), total, out_key, out_rows);
-        if ((rc = check_launch("overflow scatter"))) return rc;
+        if ((rc = upload(L.chunks, chunks.data(), sizeof(Overflow) * chunks.size(), s, "chunks")))
+            return rc;
+        if ((rc = upload(L.mm, mm.data(), sizeof(long long) * mm.size(), s, "min/max"))) return rc;
+        TQP_LAUNCH("big_minmax", k_big_minmax<K>, dim3(unsigned(chunks.size())), dim3(256), 0, s,
+                   out_key, L.chunks, L.mm);
+        if ((rc = check_launch("big bucket min/max"))) return rc;
+        if ((rc = download(mm.data(), L.mm, sizeof(long long) * mm.size(), s, "min/max"))) return rc;
+        std::vector<Overflow> list;
+        for (size_t j = 0; j < nbig; j++) {
+            if (mm[2 * j] == mm[2 * j + 1]) {
+                single++;
+                continue;
+            }
+            list.push_back(Overflow{big[j].start, big[j].len, int64_t(mm[2 * j]),
+                                    int64_t(mm[2 * j + 1]), 0});
+            ovf_keys += big[j].len;
+        }
+        n_ovf = int64_t(list.size());
+        if (!list.empty()) {
+            // 4. gather the overflowing buckets, sort them together, scatter back
+            std::sort(list.begin(), list.end(),
+                      [](const Overflow &a, const Overflow &b) { return a.start < b.start; });
+            int64_t total = 0, kmin = list[0].kmin, kmax = list[0].kmax;
+            for (Overflow &o : list) {
+                o.off = total;
+                total += o.len;
+                kmin = o.kmin < kmin ? o.kmin : kmin;
+                kmax = o.kmax > kmax ? o.kmax : kmax;
+            }
+            if ((rc = upload(L.ovf, list.data(), sizeof(Overflow) * list.size(), s, "overflow list")))
+                return rc;
+            int64_t g = ceil_div(total, 256);
+            if (g > 8192) g = 8192;
+            K *tk = static_cast<K *>(L.tmp_k), *tk2 = static_cast<K *>(L.tmp2_k);
+            TQP_LAUNCH("ovf_gather", k_ovf_gather<K>, dim3(unsigned(g)), dim3(256), 0, s, out_key,
+                       out_rows, L.ovf, int(list.size()), total, tk, L.tmp_r);
+            if ((rc = check_launch("overflow gather"))) return rc;
+            const uint64_t span = uint64_t(kmax) - uint64_t(kmin);
+            int bits = 0;
+            while (bits < 64 && (span >> bits) != 0) bits++;
+            SortCols fc = {};
+            fc.rows_in = L.tmp_r;
+            fc.rows_out = L.tmp2_r;
+            rc = run_radix<K, KeyOrd<K>>(tk, total, nullptr, bits, KeyOrd<K>{K(kmin)}, tk2, fc,
+                                         L.fws, s);
+            if (rc) return rc;
+            TQP_LAUNCH("ovf_scatter", k_ovf_scatter<K>, dim3(unsigned(g)), dim3(256), 0, s, tk2,
+                       L.tmp2_r, L.ovf, int(list.size()), total, out_key, out_rows);
+            if ((rc = check_launch("overflow scatter"))) return rc;
+        }
     }
     if (h_stats) {
         h_stats[0] = int64_t(hs.max_bucket);
-        h_stats[1] = int64_t(hs.overflow);
-        h_stats[2] = int64_t(hs.overflow_keys);
-        h_stats[3] = int64_t(hs.single_big);
+        h_stats[1] = n_ovf;
+        h_stats[2] = ovf_keys;
+        h_stats[3] = single;
     }
     return TQP_OK;
 }
@@ -882,7 +1159,7 @@ TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint3
                                                             float(1u << bucket_bits),
                                                             (1u << bucket_bits) - 1},
                                         bucket_bits, ok, out_rows, h_stats, pws, s);
-        return partition_sort_typed(k, in_rows, n, MsdOrd<int32_t>{int32_t(key_min), shift},
+        return partition_sort_typed(k, in_rows, n, MsdOrd<int32_t>{int32_t(key_min), shift, (1u << bucket_bits) - 1},
                                     bucket_bits, ok, out_rows, h_stats, pws, s);
     }
     const int64_t *k = static_cast<const int64_t *>(key->data);
@@ -893,6 +1170,6 @@ TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint3
                                                         float(1u << bucket_bits),
                                                         (1u << bucket_bits) - 1},
                                     bucket_bits, ok, out_rows, h_stats, pws, s);
-    return partition_sort_typed(k, in_rows, n, MsdOrd<int64_t>{key_min, shift}, bucket_bits, ok,
+    return partition_sort_typed(k, in_rows, n, MsdOrd<int64_t>{key_min, shift, (1u << bucket_bits) - 1}, bucket_bits, ok,
                                 out_rows, h_stats, pws, s);
 }

@@ -34,6 +34,16 @@ constexpr int kMaxSortPay = 4;
 constexpr int kHistNT = 256;
 constexpr int kHistIPT = 16;
 constexpr int kLookAhead = 4;             // predecessor statuses fetched per round trip
+// Tiles are handed out in groups of kTileGroup consecutive tiles per XCD:
+// workgroups are dispatched to the chip's 8 XCDs round robin by index, so
+// workgroup b draws from counter b % kXcds, which owns the groups g with
+// g % kXcds == b % kXcds.  Consecutive tiles write adjacent parts of every
+// digit run, so the cache lines they share are mostly completed in one
+// XCD's L2 instead of being written partially from two.  (Correctness does
+// not depend on the placement; every counter's groups are taken in order by
+// resident workgroups, so the look-back always finds its predecessors.)
+constexpr int kXcds = 8;
+constexpr int kTileGroup = 16;
 constexpr uint32_t kSFlagAgg = 1u << 30;
 constexpr uint32_t kSFlagInc = 2u << 30;
 constexpr uint32_t kSValMask = (1u << 30) - 1;
@@ -136,9 +146,11 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const int tid = threadIdx.x;
     const int w = wave_id();
     const int lane = lane_id();
-    // Persistent workgroups: each takes tiles in ticket order until none are left.
+    // Persistent workgroups: each takes its XCD's tiles in order until none are left.
+    const int xcd = int(blockIdx.x % kXcds);
     for (;;) {
-    const int64_t tile = take_tile(ticket, &s_tile);
+    const int64_t j = take_tile(ticket + xcd, &s_tile);
+    const int64_t tile = ((j / kTileGroup) * kXcds + xcd) * kTileGroup + j % kTileGroup;
     if (tile >= ntiles) break;
     const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
 
@@ -342,7 +354,7 @@ inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) 
         c.take<int32_t>(size_t(n));
         for (int b = 0; b < pay_bytes; b++) c.take<char>(size_t(n));
     }
-    c.take<uint32_t>(size_t(npass) * kBins + npass + size_t(npass) * ntiles * kBins);
+    c.take<uint32_t>(size_t(npass) * kBins + size_t(npass) * kXcds + size_t(npass) * ntiles * kBins);
     return c.bytes();
 }
 
@@ -357,6 +369,10 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     const int dbits = digit_bits_for(bits);
     const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
     const unsigned grid_pass = persistent_grid(grid_all, tune(kTuneSortPerCu));
+    // every tile group's counter needs a workgroup (true for these grids)
+    const int64_t groups = ceil_div(int64_t(grid_all), int64_t(kTileGroup));
+    if (int64_t(grid_pass) < (groups < kXcds ? groups : int64_t(kXcds)))
+        return set_error(TQP_EINVAL, "radix: grid %u too small for its tile groups", grid_pass);
     PassCols pc = {};
     pc.rows_in = sc.rows_in;
     pc.rows_out = sc.rows_out;
@@ -381,11 +397,11 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
         tmp_rows = cv.take<int32_t>(size_t(n));
         for (int p = 0; p < sc.npay; p++) tmp_pay[p] = cv.take<char>(size_t(n) * dtype_size(sc.pdt[p]));
     }
-    const size_t nwords = size_t(npass) * kBins + npass + size_t(npass) * ntiles * kBins;
+    const size_t nwords = size_t(npass) * kBins + size_t(npass) * kXcds + size_t(npass) * ntiles * kBins;
     uint32_t *words = cv.take<uint32_t>(nwords);
     uint32_t *ghist = words;
     uint32_t *tickets = words + npass * kBins;
-    uint32_t *status = tickets + npass;
+    uint32_t *status = tickets + npass * kXcds;
     int rc = fill_u32(words, 0, int64_t(nwords), s);
     if (rc) return rc;
     {
@@ -410,23 +426,23 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
         switch (sc.npay) {
         case 0:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 0, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
             break;
         case 1:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 1, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
             break;
         case 2:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 2, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
             break;
         case 3:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 3, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
             break;
         default:
             TQP_LAUNCH("onesweep", (k_onesweep<K, 4, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p);
+                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
             break;
         }
         rc = check_launch("radix pass");

@@ -92,6 +92,11 @@ class ProfScope {
 // Enqueues a fill of `count` 64-bit words (a kernel, not a memset node, so
 // that captured graphs replay it faithfully).
 int fill_u64(void *dst, uint64_t value, int64_t count, hipStream_t s);
+// Run heads of a sorted int32 column (join.hip): value and first position of
+// each run, run count in *d_nu; words: rle_words(n) uint64 of workspace.
+size_t rle_words(int64_t n);
+int rle_i32(const int32_t *keys, int64_t n, int32_t *ukey, int32_t *ustart, int64_t *d_nu,
+            uint64_t *words, hipStream_t s);
 int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s);
 
 // Device-side min / max of a key column over min(*d_n, n) entries, written to

@@ -52,7 +52,7 @@ def test_model_is_monotone_and_trains(tqp, mix):
     assert np.all(np.diff(eb) >= 0) and eb.min() >= 0 and eb.max() < 65536
 
 
-@pytest.mark.parametrize("bits", [8, 12, 16])
+@pytest.mark.parametrize("bits", [8, 12, 16, 20, 24])
 def test_learned_partition_sort_matches_sort_and_oracle(tqp, mix, bits):
     left, right = mix
     model = tqp.lcdf_train([dev(left), dev(right)], steps=50)
@@ -64,7 +64,7 @@ def test_learned_partition_sort_matches_sort_and_oracle(tqp, mix, bits):
         assert st["max_bucket"] >= 1
 
 
-@pytest.mark.parametrize("bits", [4, 12, 16])
+@pytest.mark.parametrize("bits", [4, 12, 16, 24])
 def test_msd_radix_partition_sort_matches(tqp, mix, bits):
     left, _ = mix
     sk, rows, st = tqp.partition_sort(dev(left), tqp.PART_RADIX, None, bucket_bits=bits)
