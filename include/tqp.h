@@ -113,7 +113,10 @@ void tqp_profile_reset(void);
  * fixed range with a default: "filter.per_cu", "sort.per_cu", "rle.per_cu",
  * "match.per_cu", "gbscan.per_cu" are workgroups per compute unit of one
  * persistent kernel's grid; "part.ovf_cap" is how many overflowing buckets
- * tqp_partition_sort re-sorts before it sorts the whole input instead.
+ * tqp_partition_sort re-sorts before it sorts the whole input instead;
+ * "sort.mode" picks how a radix pass finds where each tile's digit runs go:
+ * 0 = decoupled look-back over earlier tiles, 1 = every tile's digit counts
+ * first, then a scan per digit (one more read of the keys, no waiting).
  * Knobs change how the work is done, never results.  They are process-wide and read when a call enqueues its kernels;
  * setting them concurrently with calls on other threads is a race.
  *   tqp_tune_set: TQP_EINVAL for an unknown name or a value out of range.

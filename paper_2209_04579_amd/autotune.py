@@ -72,8 +72,9 @@ def tune(make_plan, reps: int = 5, rounds: int = 2, include_dense: bool = True,
     """Coordinate descent over the knobs.
 
     make_plan(tuning) -> plan.  Returns (best tuning, best ms, all timings).
-    Only the launch-shape knobs (".per_cu") are swept."""
-    knobs = {k: v for k, v in tune_knobs().items() if k.endswith(".per_cu")}
+    Knobs with at most 16 settings are swept (grid sizes, the radix pass
+    mode), not capacity limits."""
+    knobs = {k: v for k, v in tune_knobs().items() if v[2] - v[1] <= 16}
     best = {k: v[0] for k, v in knobs.items()}
     if include_dense:
         best["gb.dense_max"] = 1024

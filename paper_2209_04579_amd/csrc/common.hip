@@ -155,8 +155,9 @@ static const KnobDef kKnobs[kTuneCount] = {
     {"match.per_cu", 4, 1, 8},
     {"gbscan.per_cu", 2, 1, 4},
     {"part.ovf_cap", 65536, 1, 65536},
+    {"sort.mode", 0, 0, 1},
 };
-static int g_knob[kTuneCount] = {4, 2, 1, 4, 2, 65536};
+static int g_knob[kTuneCount] = {4, 2, 1, 4, 2, 65536, 0};
 
 int tune(TuneKnob k) { return g_knob[k]; }
 

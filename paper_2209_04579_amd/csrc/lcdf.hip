@@ -95,15 +95,29 @@ __device__ __forceinline__ float lcdf_x(const LcdfModel *m, int64_t key) {
     return float(x);
 }
 
+// A ramp clamp(h, 0, 1) is one median-of-three (no NaN reaches it: x is a
+// clamped finite value and the parameters are finite).
+__device__ __forceinline__ float ramp(float h) { return __builtin_amdgcn_fmed3f(h, 0.f, 1.f); }
+
 __device__ __forceinline__ float lcdf_root(const LcdfModel *m, float x) {
     float y = m->d;
 #pragma unroll
-    for (int j = 0; j < kHidden; j++) {
-        float h = fmaf(m->w[j], x, m->c[j]);
-        h = h < 0.f ? 0.f : (h > 1.f ? 1.f : h);
-        y = fmaf(m->v[j], h, y);
-    }
+    for (int j = 0; j < kHidden; j++) y = fmaf(m->v[j], ramp(fmaf(m->w[j], x, m->c[j])), y);
     return y;
+}
+
+// The root at R points, parameter by parameter, so each parameter is loaded
+// once for all R (they are wave-uniform scalar loads) and only a few are live.
+template <int R>
+__device__ __forceinline__ void lcdf_root_n(const LcdfModel *m, const float (&x)[R], float (&y)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; r++) y[r] = m->d;
+#pragma unroll 4
+    for (int j = 0; j < kHidden; j++) {
+        const float w = m->w[j], c = m->c[j], v = m->v[j];
+#pragma unroll
+        for (int r = 0; r < R; r++) y[r] = fmaf(v, ramp(fmaf(w, x[r], c)), y[r]);
+    }
 }
 
 __device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
@@ -156,10 +170,23 @@ template <class K> struct LearnedOrd {
     const LcdfModel *m;
     float scale;                                // 2^bucket_bits
     uint32_t top;                               // 2^bucket_bits - 1
-    __device__ __forceinline__ uint64_t operator()(K k) const {
-        const float f = lcdf_eval(m, int64_t(k)) * scale;
-        uint32_t b = f <= 0.f ? 0u : uint32_t(f);
+    __device__ __forceinline__ uint32_t bucket(float f) const {
+        const float t = f * scale;
+        const uint32_t b = t <= 0.f ? 0u : uint32_t(t);
         return b > top ? top : b;
+    }
+    __device__ __forceinline__ uint64_t operator()(K k) const {
+        return bucket(lcdf_eval(m, int64_t(k)));
+    }
+    // R keys at once: roots together, then the leaves (loads in flight together)
+    template <int R>
+    __device__ __forceinline__ void many(const K (&k)[R], uint32_t (&b)[R]) const {
+        float x[R], y[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) x[r] = lcdf_x(m, int64_t(k[r]));
+        lcdf_root_n<R>(m, x, y);
+#pragma unroll
+        for (int r = 0; r < R; r++) b[r] = bucket(lcdf_leaf_eval(m->leaf[lcdf_leaf(m, y[r])], int64_t(k[r])));
     }
 };
 
@@ -252,8 +279,7 @@ __global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const f
         for (int j = 0; j < kHidden; j++) {
             const float w = __expf(-s_th[kHidden + j]);
             z[j] = (x - s_th[j]) * w + 0.5f;
-            const float h = z[j] < 0.f ? 0.f : (z[j] > 1.f ? 1.f : z[j]);
-            y += __expf(s_th[2 * kHidden + j]) * h;
+            y += __expf(s_th[2 * kHidden + j]) * ramp(z[j]);
         }
         const float err = y - tq[t];
         const float e = err * inv_t;
@@ -477,6 +503,17 @@ struct Overflow {
     int64_t off;                        // position in the gathered overflow keys
 };
 
+// R ordinals at once: the learned model evaluates them together.
+template <int R, class K>
+__device__ __forceinline__ void ord_many(const LearnedOrd<K> &o, const K (&k)[R], uint32_t (&b)[R]) {
+    o.template many<R>(k, b);
+}
+template <int R, class K, class Ord>
+__device__ __forceinline__ void ord_many(const Ord &o, const K (&k)[R], uint32_t (&b)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; r++) b[r] = uint32_t(o(k[r]));
+}
+
 // Bucket number of every key, evaluated once (int32, in [0, nb)).
 template <class K, class Ord>
 __global__ __launch_bounds__(256) void k_bucket_ids(const K *__restrict__ keys, int64_t n, Ord ord,
@@ -492,8 +529,7 @@ __global__ __launch_bounds__(256) void k_bucket_ids(const K *__restrict__ keys, 
             k[r] = i < n ? keys[i] : K(0);
         }
         uint32_t b[R];
-#pragma unroll
-        for (int r = 0; r < R; r++) b[r] = uint32_t(ord(k[r]));
+        ord_many<R>(ord, k, b);
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const int64_t i = base + int64_t(r) * blockDim.x;

@@ -127,11 +127,15 @@ __device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const int32
 // time) are read into registers together with the keys, so the tile pays one
 // memory latency before ranking rather than one per column afterwards.
 // At least 4 waves per SIMD (<= 128 VGPRs) so two workgroups share a CU.
-template <class K, int NPAY, class Ord>
+// LB: the global start of each digit run comes from a decoupled look-back
+// over earlier tiles (persistent workgroups, tiles by ticket); otherwise one
+// workgroup per tile reads it from toff[digit * tstride + tile], the tile
+// offsets k_radix_tilescan computed from every tile's digit counts.
+template <class K, int NPAY, class Ord, bool LB>
 __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, PassCols c, int64_t n,
     const int64_t *d_n, Ord ord, int shift, int dbits, const uint32_t *__restrict__ ghist,
-    uint32_t *status, uint32_t *ticket) {
+    uint32_t *status, uint32_t *ticket, int64_t tstride) {
     const uint32_t nbins = 1u << dbits;
     __shared__ uint32_t s_hist[kSortNW][kBins];
     __shared__ uint32_t s_local[kBins];      // tile-local start of each digit run
@@ -146,11 +150,18 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const int tid = threadIdx.x;
     const int w = wave_id();
     const int lane = lane_id();
-    // Persistent workgroups: each takes its XCD's tiles in order until none are left.
+    // LB: persistent workgroups, each taking its XCD's tiles in order until
+    // none are left.  Otherwise: tile = blockIdx.x, once.
     const int xcd = int(blockIdx.x % kXcds);
-    for (;;) {
-    const int64_t j = take_tile(ticket + xcd, &s_tile);
-    const int64_t tile = ((j / kTileGroup) * kXcds + xcd) * kTileGroup + j % kTileGroup;
+    for (int it = 0;; it++) {
+    int64_t tile;
+    if constexpr (LB) {
+        const int64_t j = take_tile(ticket + xcd, &s_tile);
+        tile = ((j / kTileGroup) * kXcds + xcd) * kTileGroup + j % kTileGroup;
+    } else {
+        if (it > 0) break;
+        tile = blockIdx.x;
+    }
     if (tile >= ntiles) break;
     const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
 
@@ -214,7 +225,12 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
     uint32_t tile_total;
     const uint32_t local = block_excl_scan<kSortNT>(tot, &tile_total, s_scan);
-    if (tid < int(nbins)) {
+    if (!LB) {
+        if (tid < int(nbins)) {
+            s_local[tid] = local;
+            s_gbase[tid] = int64_t(status[int64_t(tid) * tstride + tile]) - int64_t(local);
+        }
+    } else if (tid < int(nbins)) {
         s_local[tid] = local;
         // Decoupled look-back for digit tid across earlier tiles.
         uint32_t *st = status + tile * kBins + tid;
@@ -306,6 +322,70 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
 }
 
+// Digit counts of every tile for one pass (the tiles k_onesweep<..., false>
+// will take): counts[digit * tstride + tile].  Tiles past the actual count
+// write zeros, so the scan may run over the whole capacity.
+template <class K, class Ord>
+__global__ __launch_bounds__(kSortNT) void k_radix_tilecount(const K *__restrict__ keys, int64_t n,
+                                                             const int64_t *d_n, Ord ord, int shift,
+                                                             int dbits, uint32_t *counts,
+                                                             int64_t tstride) {
+    __shared__ uint32_t s_c[kSortNW][kBins];
+    const uint32_t nbins = 1u << dbits;
+    const int64_t cnt = count_of(d_n, n);
+    const int64_t tile = blockIdx.x;
+    const int tid = threadIdx.x, w = wave_id();
+    for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_c[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
+    K key[kSortIPT];
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const int64_t idx = wbase + k * kWave + lane_id();
+        key[k] = idx < cnt ? keys[idx] : K(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) {
+        const int64_t idx = wbase + k * kWave + lane_id();
+        if (idx < cnt) atomicAdd(&s_c[w][uint32_t(ord(key[k]) >> shift) & (nbins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = tid; d < int(nbins); d += kSortNT) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int ww = 0; ww < kSortNW; ww++) t += s_c[ww][d];
+        counts[int64_t(d) * tstride + tile] = t;
+    }
+}
+
+// One workgroup per digit: turns that digit's row of tile counts into the
+// global position of each tile's run, in place: the digit's start (counts
+// of all smaller digits, from the pass histogram) plus the counts of the
+// tiles before it.
+constexpr int kScanNT = 1024;
+static __global__ __launch_bounds__(kScanNT) void k_radix_tilescan(uint32_t *counts, int64_t tstride,
+                                                            const uint32_t *__restrict__ ghist) {
+    __shared__ uint32_t s_scan[kScanNT / kWave];
+    __shared__ uint32_t s_base;
+    const int d = blockIdx.x;
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int e = 0; e < d; e++) b += ghist[e];
+        s_base = b;
+    }
+    __syncthreads();
+    uint32_t carry = s_base;
+    uint32_t *row = counts + int64_t(d) * tstride;
+    for (int64_t t0 = 0; t0 < tstride; t0 += kScanNT) {
+        const int64_t t = t0 + threadIdx.x;
+        const uint32_t v = t < tstride ? row[t] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<kScanNT>(v, &total, s_scan);
+        if (t < tstride) row[t] = carry + ex;
+        carry += total;
+    }
+}
+
 template <class K>
 __global__ __launch_bounds__(256) void k_copy_sorted(const K *__restrict__ keys_in, K *__restrict__ keys_out,
                                                      PassCols c, int64_t n, const int64_t *d_n) {
@@ -358,6 +438,15 @@ inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) 
     return c.bytes();
 }
 
+template <class K, int NPAY, class Ord, bool LB>
+static int launch_pass(unsigned grid, hipStream_t s, const K *src, K *dst, const PassCols &x,
+                       int64_t n, const int64_t *d_n, Ord ord, int shift, int dbits,
+                       const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride) {
+    TQP_LAUNCH("onesweep", (k_onesweep<K, NPAY, Ord, LB>), dim3(grid), dim3(kSortNT), 0, s, src,
+               dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    return TQP_OK;
+}
+
 // Sorts by the low `bits` bits of the ordinal: npass_for(bits) stable passes
 // over equal-width digits (least significant first) from key_in into key_out
 // (they must not overlap), with the columns of sc moving along.  bits == 0
@@ -369,6 +458,7 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     const int dbits = digit_bits_for(bits);
     const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
     const unsigned grid_pass = persistent_grid(grid_all, tune(kTuneSortPerCu));
+    const int mode = tune(kTuneSortMode);
     // every tile group's counter needs a workgroup (true for these grids)
     const int64_t groups = ceil_div(int64_t(grid_all), int64_t(kTileGroup));
     if (int64_t(grid_pass) < (groups < kXcds ? groups : int64_t(kXcds)))
@@ -423,28 +513,32 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
         uint32_t *st = status + size_t(p) * ntiles * kBins;
         const int shift = p * dbits;
         const uint32_t *gh = ghist + p * kBins;
-        switch (sc.npay) {
-        case 0:
-            TQP_LAUNCH("onesweep", (k_onesweep<K, 0, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
-            break;
-        case 1:
-            TQP_LAUNCH("onesweep", (k_onesweep<K, 1, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
-            break;
-        case 2:
-            TQP_LAUNCH("onesweep", (k_onesweep<K, 2, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
-            break;
-        case 3:
-            TQP_LAUNCH("onesweep", (k_onesweep<K, 3, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
-            break;
-        default:
-            TQP_LAUNCH("onesweep", (k_onesweep<K, 4, Ord>), dim3(grid_pass), dim3(kSortNT), 0, s,
-                       src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds);
-            break;
+        if (mode == 0) {
+            switch (sc.npay) {
+            case 0: rc = launch_pass<K, 0, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
+            case 1: rc = launch_pass<K, 1, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
+            case 2: rc = launch_pass<K, 2, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
+            case 3: rc = launch_pass<K, 3, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
+            default: rc = launch_pass<K, 4, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
+            }
+        } else {
+            // tile counts, their scan per digit, then one workgroup per tile
+            uint32_t *tc = status;                    // ntiles * kBins words, reused per pass
+            TQP_LAUNCH("radix_tilecount", (k_radix_tilecount<K, Ord>), dim3(grid_all), dim3(kSortNT), 0, s,
+                       src_k, n, d_n, ord, shift, dbits, tc, ntiles);
+            if ((rc = check_launch("radix tile counts"))) return rc;
+            TQP_LAUNCH("radix_tilescan", k_radix_tilescan, dim3(1u << dbits), dim3(kScanNT), 0, s, tc,
+                       ntiles, gh);
+            if ((rc = check_launch("radix tile scan"))) return rc;
+            switch (sc.npay) {
+            case 0: rc = launch_pass<K, 0, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
+            case 1: rc = launch_pass<K, 1, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
+            case 2: rc = launch_pass<K, 2, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
+            case 3: rc = launch_pass<K, 3, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
+            default: rc = launch_pass<K, 4, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
+            }
         }
+        if (rc) return rc;
         rc = check_launch("radix pass");
         if (rc) return rc;
         src_k = dk;

@@ -59,6 +59,7 @@ enum TuneKnob {
     kTuneGbScanPerCu,       // ... of the sorted group-by scan
     kTunePartOvfCap,        // overflowing buckets a partition sort re-sorts before it
                             // sorts the whole input instead
+    kTuneSortMode,          // radix pass: 0 = decoupled look-back, 1 = tile counts + scan
     kTuneCount
 };
 int tune(TuneKnob k);
