@@ -139,8 +139,9 @@ def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
         # reads both position columns, flag and cat; writes the int32 key
         return pairs * (4 + 4 + 1 + 4 + 4)
     if name in ("gb_dense", "gb_tiny"):
-        # int32 key, row id, qty and price per pair
-        return pairs * (4 + 4 + 8 + 8)
+        # the packed key built in the kernel: both position columns, flag and
+        # cat through them; then qty and price through the fact position
+        return pairs * (4 + 4 + 1 + 4 + 8 + 8)
     if name == "gb_scan":
         return pairs * (4 + 4 + 8) + gb * (4 + 16)
     if name == "gb_diff":

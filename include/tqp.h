@@ -252,6 +252,24 @@ int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t flags,
                     void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_groupby_agg_terms -- the dense GROUP BY of tqp_groupby_agg
+ * (TQP_GB_DENSE) over a packed key that is never written to memory: the key of
+ * row i is the tqp_pack_key value of `terms` (nterms in [1, 4]) at i, for
+ * i < count (d_n, else n), computed as the rows are aggregated.  The caller
+ * guarantees key_lo <= key < key_lo + key_span; (nagg + 1) * key_span must be
+ * at most 6144 (the accumulators live in LDS).  out_key is int32 or int64
+ * (the key range must fit it); outputs as tqp_groupby_agg.  Workspace:
+ * tqp_groupby_terms_workspace_bytes(nagg, key_span).
+ * ---------------------------------------------------------------------- */
+size_t tqp_groupby_terms_workspace_bytes(int nagg, int64_t key_span);
+int tqp_groupby_agg_terms(const tqp_keyterm *terms, int nterms, int64_t n, const int64_t *d_n,
+                          int64_t key_lo, int64_t key_span,
+                          const tqp_col *vals, int nvals, const int32_t *val_rows,
+                          const tqp_agg *aggs, int nagg,
+                          const tqp_col *out_key, int64_t *const *out_aggs,
+                          int64_t *d_ngroups, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned CDF partitioner.  A model F maps a key to [0, 1], monotone
  * non-decreasing: a 1 -> 32 -> 1 FP32 network (ramp units clamp(w x + c, 0, 1),
  * positive weights) over the key normalised to [0, 1], refined by nleaf

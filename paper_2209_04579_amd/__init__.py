@@ -126,6 +126,11 @@ def lib():
         L.tqp_groupby_agg.restype = i32
         L.tqp_groupby_agg.argtypes = [P(Col), vp, u32, i64, i64, P(Col), i32, vp, P(Agg), i32,
                                       P(Col), P(vp), vp, vp, sz, vp]
+        L.tqp_groupby_terms_workspace_bytes.restype = sz
+        L.tqp_groupby_terms_workspace_bytes.argtypes = [i32, i64]
+        L.tqp_groupby_agg_terms.restype = i32
+        L.tqp_groupby_agg_terms.argtypes = [P(KeyTerm), i32, i64, vp, i64, i64, P(Col), i32, vp,
+                                            P(Agg), i32, P(Col), P(vp), vp, vp, sz, vp]
         _lib = L
     return _lib
 
@@ -215,12 +220,8 @@ def pack_key_into(terms, n, out, d_n=None, stream=None):
     """terms: [(column or None, rows or None, mod, mul)] -> out[i] = sum mul * f(col[row]).
 
     A term with column None adds the constant mul.  out is int32 or int64."""
-    arr = (KeyTerm * len(terms))()
-    for i, (c, rows, mod, mul) in enumerate(terms):
-        col = _col(c) if c is not None else Col(None, 0, 3, 0)
-        arr[i] = KeyTerm(col, _ptr(rows), int(mod), int(mul))
-    _check(lib().tqp_pack_key(arr, len(terms), int(n), _ptr(d_n), ctypes.byref(_col(out)),
-                              _stream(stream)))
+    _check(lib().tqp_pack_key(_terms(terms), len(terms), int(n), _ptr(d_n),
+                              ctypes.byref(_col(out)), _stream(stream)))
 
 
 # ------------------------------------------------------------------- sort ----
@@ -336,6 +337,28 @@ def groupby_agg_into(key, vals, aggs, out_key, out_aggs, d_ngroups, ws, flags=0,
                                  int(key_span), _cols(vals), len(vals), _ptr(val_rows),
                                  _aggs(aggs), len(aggs), ctypes.byref(_col(out_key)), outs,
                                  _ptr(d_ngroups), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def _terms(terms):
+    arr = (KeyTerm * len(terms))()
+    for i, (c, rows, mod, mul) in enumerate(terms):
+        col = _col(c) if c is not None else Col(None, 0, 3, 0)
+        arr[i] = KeyTerm(col, _ptr(rows), int(mod), int(mul))
+    return arr
+
+
+def groupby_terms_workspace_bytes(nagg, key_span) -> int:
+    return lib().tqp_groupby_terms_workspace_bytes(int(nagg), int(key_span))
+
+
+def groupby_agg_terms_into(terms, n, vals, aggs, out_key, out_aggs, d_ngroups, ws, key_lo,
+                           key_span, val_rows=None, d_n=None, stream=None):
+    """Dense GROUP BY over the packed key of `terms` (as pack_key_into), not materialised."""
+    outs = (ctypes.c_void_p * len(out_aggs))(*[o.data_ptr() for o in out_aggs])
+    _check(lib().tqp_groupby_agg_terms(_terms(terms), len(terms), int(n), _ptr(d_n), int(key_lo),
+                                       int(key_span), _cols(vals), len(vals), _ptr(val_rows),
+                                       _aggs(aggs), len(aggs), ctypes.byref(_col(out_key)), outs,
+                                       _ptr(d_ngroups), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def groupby_agg(key, vals, aggs, flags=0, key_lo=0, key_span=0, val_rows=None, cap=None):

@@ -31,20 +31,6 @@ __global__ __launch_bounds__(kGatherNT) void k_gather(const T *__restrict__ src,
     }
 }
 
-struct PackArgs {
-    const void *col[4];
-    const int32_t *rows[4];
-    int64_t len[4];
-    int64_t mod[4];
-    int64_t mul[4];
-    int32_t dt[4];
-    int32_t nterms;
-};
-
-// Each thread builds kPackR keys per step, term by term, issuing the row-id
-// loads of all of them and then all their value loads, so the dependent
-// gathers overlap.  A power-of-two modulus is a mask (v mod 2^k in [0, 2^k)
-// is v & (2^k - 1) in two's complement).
 constexpr int kPackR = 4;
 
 template <class O>
@@ -57,37 +43,8 @@ __global__ __launch_bounds__(kGatherNT) void k_pack_key(PackArgs a, int64_t n, c
         int64_t idx[R];
         uint64_t acc[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            idx[r] = base + int64_t(r) * blockDim.x + threadIdx.x;
-            acc[r] = 0;
-        }
-        for (int t = 0; t < a.nterms; t++) {
-            if (!a.col[t]) {                       // constant term
-#pragma unroll
-                for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]);
-                continue;
-            }
-            int64_t row[R], v[R];
-#pragma unroll
-            for (int r = 0; r < R; r++)
-                row[r] = idx[r] < cnt ? (a.rows[t] ? int64_t(a.rows[t][idx[r]]) : idx[r]) : -1;
-#pragma unroll
-            for (int r = 0; r < R; r++)
-                v[r] = (row[r] >= 0 && row[r] < a.len[t]) ? load_any(a.col[t], a.dt[t], row[r]) : 0;
-            const int64_t m = a.mod[t];
-            if (m > 0 && (m & (m - 1)) == 0) {
-#pragma unroll
-                for (int r = 0; r < R; r++) v[r] &= m - 1;
-            } else if (m > 0) {
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    v[r] %= m;
-                    if (v[r] < 0) v[r] += m;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]) * uint64_t(v[r]);
-        }
+        for (int r = 0; r < R; r++) idx[r] = base + int64_t(r) * blockDim.x + threadIdx.x;
+        pack_keys<R>(a, idx, cnt, acc);
 #pragma unroll
         for (int r = 0; r < R; r++)
             if (idx[r] < cnt) out[idx[r]] = O(int64_t(acc[r]));
@@ -98,6 +55,29 @@ static unsigned grid_for(int64_t work, int per_thread) {
     int64_t b = ceil_div(work > 0 ? work : 1, int64_t(kGatherNT) * per_thread);
     if (b > 16384) b = 16384;
     return unsigned(b);
+}
+
+int pack_args(const tqp_keyterm *terms, int nterms, int64_t n, PackArgs *a, const char *who) {
+    *a = PackArgs{};
+    for (int t = 0; t < nterms; t++) {
+        const tqp_keyterm &k = terms[t];
+        if (!k.col.data) {                          // constant term
+            a->mul[t] = k.mul;
+            continue;
+        }
+        if (!dtype_ok(k.col.dtype) || k.mod < 0)
+            return set_error(TQP_EINVAL, "%s: term %d is invalid", who, t);
+        if (!k.rows && k.col.len < n)
+            return set_error(TQP_EINVAL, "%s: term %d column is shorter than n", who, t);
+        a->col[t] = k.col.data;
+        a->rows[t] = k.rows;
+        a->len[t] = k.col.len;
+        a->mod[t] = k.mod;
+        a->mul[t] = k.mul;
+        a->dt[t] = k.col.dtype;
+    }
+    a->nterms = nterms;
+    return TQP_OK;
 }
 
 }  // namespace tqp
@@ -147,24 +127,8 @@ TQP_API int tqp_pack_key(const tqp_keyterm *terms, int nterms, int64_t n, const 
         (n > 0 && !out->data))
         return set_error(TQP_EINVAL, "tqp_pack_key: bad output column");
     PackArgs a = {};
-    for (int t = 0; t < nterms; t++) {
-        const tqp_keyterm &k = terms[t];
-        if (!k.col.data) {                          // constant term
-            a.mul[t] = k.mul;
-            continue;
-        }
-        if (!dtype_ok(k.col.dtype) || k.mod < 0)
-            return set_error(TQP_EINVAL, "tqp_pack_key: term %d is invalid", t);
-        if (!k.rows && k.col.len < n)
-            return set_error(TQP_EINVAL, "tqp_pack_key: term %d column is shorter than n", t);
-        a.col[t] = k.col.data;
-        a.rows[t] = k.rows;
-        a.len[t] = k.col.len;
-        a.mod[t] = k.mod;
-        a.mul[t] = k.mul;
-        a.dt[t] = k.col.dtype;
-    }
-    a.nterms = nterms;
+    const int rc = pack_args(terms, nterms, n, &a, "tqp_pack_key");
+    if (rc) return rc;
     if (n == 0) return TQP_OK;
     hipStream_t s = as_stream(stream);
     if (out->dtype == TQP_INT32)

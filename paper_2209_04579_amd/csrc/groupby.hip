@@ -123,27 +123,48 @@ __device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile, i
     }
 }
 
-// Reads the value column of N rows (row ids in rows[]) with the dtype branch
-// outside the row loop, so the N loads issue back to back.
+// Reads the value column of N rows (row ids in rows[]; 0 where the bit of
+// valid is clear or the row is outside the column).  One dtype test for all
+// N and no predicated loads (such rows read element 0), so the N loads issue
+// back to back and the sign extension waits for all of them at once.
 template <int N>
 __device__ __forceinline__ void load_vals(const void *col, int dt, int64_t len,
                                           const int32_t (&rows)[N], uint32_t valid,
                                           int64_t (&out)[N]) {
-    if (dt == TQP_INT8) {
-        const int8_t *p = static_cast<const int8_t *>(col);
+    if (len <= 0) {
 #pragma unroll
-        for (int r = 0; r < N; r++)
-            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
-    } else if (dt == TQP_INT32) {
-        const int32_t *p = static_cast<const int32_t *>(col);
+        for (int r = 0; r < N; r++) out[r] = 0;
+        return;
+    }
+    bool ok[N];
+    int32_t li[N];
+    uint64_t raw[N];
 #pragma unroll
-        for (int r = 0; r < N; r++)
-            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
+    for (int r = 0; r < N; r++) {
+        ok[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len;
+        li[r] = ok[r] ? rows[r] : 0;
+    }
+    load_raw<N>(col, dt, li, raw);
+#pragma unroll
+    for (int r = 0; r < N; r++) out[r] = ok[r] ? sext_of(raw[r], dt) : 0;
+}
+
+// Value-row ids of positions idx[] (position i itself without val_rows; 0
+// past cnt), all loads issued together; needs cnt >= 1.
+template <int N>
+__device__ __forceinline__ void load_rows(const int32_t *val_rows, const int64_t (&idx)[N], int64_t cnt,
+                                          int32_t (&row)[N]) {
+    if (val_rows) {
+        int64_t li[N];
+        uint64_t rr[N];
+#pragma unroll
+        for (int r = 0; r < N; r++) li[r] = idx[r] < cnt ? idx[r] : 0;
+        load_raw<N>(val_rows, TQP_INT32, li, rr);
+#pragma unroll
+        for (int r = 0; r < N; r++) row[r] = idx[r] < cnt ? int32_t(uint32_t(rr[r])) : 0;
     } else {
-        const int64_t *p = static_cast<const int64_t *>(col);
 #pragma unroll
-        for (int r = 0; r < N; r++)
-            out[r] = ((valid >> r) & 1) && rows[r] >= 0 && rows[r] < len ? p[rows[r]] : 0;
+        for (int r = 0; r < N; r++) row[r] = idx[r] < cnt ? int32_t(idx[r]) : 0;
     }
 }
 
@@ -305,8 +326,32 @@ __global__ __launch_bounds__(256) void k_gb_diff(const int64_t *__restrict__ end
 
 constexpr int kDenseR = 4;                  // rows per thread per step (loads issued together)
 
-template <class K>
-__global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, int64_t n,
+// Where a dense group-by reads its keys: a key column, or a packed key built
+// from other columns on the fly (never written to memory).
+template <class K> struct ColKeys {
+    const K *keys;
+    template <int R>
+    __device__ __forceinline__ void get(const int64_t (&idx)[R], int64_t cnt, int64_t (&v)[R]) const {
+        K k[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) k[r] = keys[idx[r] < cnt ? idx[r] : 0];   // cnt >= 1 here
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] = idx[r] < cnt ? int64_t(k[r]) : 0;
+    }
+};
+struct TermKeys {
+    PackArgs a;
+    template <int R>
+    __device__ __forceinline__ void get(const int64_t (&idx)[R], int64_t cnt, int64_t (&v)[R]) const {
+        uint64_t acc[R];
+        pack_keys<R>(a, idx, cnt, acc);
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] = int64_t(acc[r]);
+    }
+};
+
+template <class KS>
+__global__ __launch_bounds__(kGbNT) void k_gb_dense(KS ks, int64_t n,
                                                     const int64_t *d_n, int64_t key_lo,
                                                     int64_t span, AggArgs a,
                                                     unsigned long long *__restrict__ gacc) {
@@ -322,13 +367,14 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, 
         uint32_t ok = 0;
         uint64_t b[R];
         int32_t row[R];
+        int64_t idx[R], kv[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int64_t i = base + r * kGbNT + threadIdx.x;
-            const bool in = i < cnt;
-            b[r] = in ? uint64_t(int64_t(keys[i])) - uint64_t(key_lo) : uint64_t(span);
-            row[r] = !in ? 0 : (a.val_rows ? a.val_rows[i] : int32_t(i));
-        }
+        for (int r = 0; r < R; r++) idx[r] = base + r * kGbNT + threadIdx.x;
+        load_rows<R>(a.val_rows, idx, cnt, row);
+        ks.template get<R>(idx, cnt, kv);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            b[r] = idx[r] < cnt ? uint64_t(kv[r]) - uint64_t(key_lo) : uint64_t(span);
 #pragma unroll
         for (int r = 0; r < R; r++) {
             if (b[r] < uint64_t(span)) {
@@ -372,8 +418,8 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(const K *__restrict__ keys, 
 constexpr int kTinySpan = 8;
 constexpr int kTinyR = 4;
 
-template <class K, int NAGG>
-__global__ __launch_bounds__(kGbNT) void k_gb_tiny(const K *__restrict__ keys, int64_t n,
+template <class KS, int NAGG>
+__global__ __launch_bounds__(kGbNT) void k_gb_tiny(KS ks, int64_t n,
                                                    const int64_t *d_n, int64_t key_lo, int span,
                                                    AggArgs a, unsigned long long *__restrict__ gacc) {
     constexpr int R = kTinyR;
@@ -392,13 +438,14 @@ __global__ __launch_bounds__(kGbNT) void k_gb_tiny(const K *__restrict__ keys, i
         uint32_t ok = 0;
         uint64_t b[R];
         int32_t row[R];
+        int64_t idx[R], kv[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int64_t i = base + r * kGbNT + threadIdx.x;
-            const bool in = i < cnt;
-            b[r] = in ? uint64_t(int64_t(keys[i])) - uint64_t(key_lo) : uint64_t(span);
-            row[r] = !in ? 0 : (a.val_rows ? a.val_rows[i] : int32_t(i));
-        }
+        for (int r = 0; r < R; r++) idx[r] = base + r * kGbNT + threadIdx.x;
+        load_rows<R>(a.val_rows, idx, cnt, row);
+        ks.template get<R>(idx, cnt, kv);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            b[r] = idx[r] < cnt ? uint64_t(kv[r]) - uint64_t(key_lo) : uint64_t(span);
 #pragma unroll
         for (int r = 0; r < R; r++) ok |= (b[r] < uint64_t(span) ? 1u : 0u) << r;
         int64_t t[NAGG][R];
@@ -521,6 +568,52 @@ static GbLayout gb_layout(void *ws, int64_t n, int dtype, int nagg, uint32_t fla
     return L;
 }
 
+// Dense domains: zero the accumulators, aggregate (registers for at most
+// kTinySpan keys, LDS otherwise), emit the groups that occur.  KS gives the
+// keys (a column, or a packed key built on the fly); OK is the output key type.
+template <class OK, class KS>
+static int dense_groupby(const KS &ks, int64_t n, const int64_t *d_n, int64_t key_lo,
+                         int64_t key_span, const AggArgs &args, unsigned long long *gacc,
+                         OK *out_key, int64_t out_cap, int64_t *const *o, int64_t *d_ngroups,
+                         hipStream_t s) {
+    const int nagg = args.nagg;
+    int rc = fill_u64(gacc, 0, int64_t(nagg + 1) * key_span, s);
+    if (rc) return rc;
+    if (n > 0 && key_span <= kTinySpan) {
+        int64_t g = ceil_div(n, int64_t(kGbNT) * kTinyR * 8);
+        if (g > 2048) g = 2048;
+        switch (nagg) {
+        case 1:
+            TQP_LAUNCH("gb_tiny", (k_gb_tiny<KS, 1>), dim3(unsigned(g)), dim3(kGbNT), 0, s, ks, n,
+                       d_n, key_lo, int(key_span), args, gacc);
+            break;
+        case 2:
+            TQP_LAUNCH("gb_tiny", (k_gb_tiny<KS, 2>), dim3(unsigned(g)), dim3(kGbNT), 0, s, ks, n,
+                       d_n, key_lo, int(key_span), args, gacc);
+            break;
+        case 3:
+            TQP_LAUNCH("gb_tiny", (k_gb_tiny<KS, 3>), dim3(unsigned(g)), dim3(kGbNT), 0, s, ks, n,
+                       d_n, key_lo, int(key_span), args, gacc);
+            break;
+        default:
+            TQP_LAUNCH("gb_tiny", (k_gb_tiny<KS, 4>), dim3(unsigned(g)), dim3(kGbNT), 0, s, ks, n,
+                       d_n, key_lo, int(key_span), args, gacc);
+            break;
+        }
+        if ((rc = check_launch("group-by tiny"))) return rc;
+    } else if (n > 0) {
+        int64_t g = ceil_div(n, int64_t(kGbNT) * 64);
+        if (g > 2048) g = 2048;
+        const size_t lds = size_t(nagg + 1) * key_span * 8;
+        TQP_LAUNCH("gb_dense", k_gb_dense<KS>, dim3(unsigned(g)), dim3(kGbNT), lds, s, ks, n, d_n,
+                   key_lo, key_span, args, gacc);
+        if ((rc = check_launch("group-by dense"))) return rc;
+    }
+    TQP_LAUNCH("gb_dense_emit", k_gb_dense_emit<OK>, dim3(1), dim3(1024), 0, s, gacc, key_lo,
+               key_span, nagg, out_key, out_cap, o[0], o[1], o[2], o[3], d_ngroups);
+    return check_launch("group-by dense emit");
+}
+
 template <class K>
 static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags, int64_t key_lo,
                          int64_t key_span, const AggArgs &args, const tqp_col *out_key,
@@ -531,46 +624,10 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
     int64_t *o[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int g = 0; g < nagg; g++) o[g] = out_aggs[g];
     int rc;
-    if (dense_ok(flags, key_span, nagg)) {
-        rc = fill_u64(L.gacc, 0, int64_t(nagg + 1) * key_span, s);
-        if (rc) return rc;
-        if (n > 0 && key_span <= kTinySpan) {
-            int64_t g = ceil_div(n, int64_t(kGbNT) * kTinyR * 8);
-            if (g > 2048) g = 2048;
-            const K *kp = static_cast<const K *>(key->data);
-            switch (nagg) {
-            case 1:
-                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 1>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
-                           n, d_n, key_lo, int(key_span), args, L.gacc);
-                break;
-            case 2:
-                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 2>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
-                           n, d_n, key_lo, int(key_span), args, L.gacc);
-                break;
-            case 3:
-                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 3>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
-                           n, d_n, key_lo, int(key_span), args, L.gacc);
-                break;
-            default:
-                TQP_LAUNCH("gb_tiny", (k_gb_tiny<K, 4>), dim3(unsigned(g)), dim3(kGbNT), 0, s, kp,
-                           n, d_n, key_lo, int(key_span), args, L.gacc);
-                break;
-            }
-            if ((rc = check_launch("group-by tiny"))) return rc;
-        } else if (n > 0) {
-            int64_t g = ceil_div(n, int64_t(kGbNT) * 64);
-            if (g > 2048) g = 2048;
-            const size_t lds = size_t(nagg + 1) * key_span * 8;
-            TQP_LAUNCH("gb_dense", k_gb_dense<K>, dim3(unsigned(g)), dim3(kGbNT), lds, s,
-                               static_cast<const K *>(key->data), n, d_n, key_lo, key_span, args,
-                               L.gacc);
-            if ((rc = check_launch("group-by dense"))) return rc;
-        }
-        TQP_LAUNCH("gb_dense_emit", k_gb_dense_emit<K>, dim3(1), dim3(1024), 0, s, L.gacc, key_lo, key_span,
-                           nagg, static_cast<K *>(out_key->data), out_key->len, o[0], o[1], o[2],
-                           o[3], d_ngroups);
-        return check_launch("group-by dense emit");
-    }
+    if (dense_ok(flags, key_span, nagg))
+        return dense_groupby<K>(ColKeys<K>{static_cast<const K *>(key->data)}, n, d_n, key_lo,
+                                key_span, args, L.gacc, static_cast<K *>(out_key->data),
+                                out_key->len, o, d_ngroups, s);
     const K *k = static_cast<const K *>(key->data);
     AggArgs a = args;
     if (!(flags & TQP_GB_SORTED)) {
@@ -625,6 +682,39 @@ static int groupby_typed(const tqp_col *key, const int64_t *d_n, uint32_t flags,
 
 using namespace tqp;
 
+// Checks the value columns and aggregates of a group-by call and fills
+// AggArgs; n is the row count value columns must cover without val_rows.
+static int agg_args(const tqp_col *vals, int nvals, const int32_t *val_rows, const tqp_agg *aggs,
+                    int nagg, int64_t n, int64_t out_cap, int64_t *const *out_aggs, AggArgs *a,
+                    const char *who) {
+    *a = AggArgs{};
+    for (int c = 0; c < nvals; c++) {
+        if (!dtype_ok(vals[c].dtype) || (vals[c].len > 0 && !vals[c].data))
+            return set_error(TQP_EINVAL, "%s: value column %d is invalid", who, c);
+        if (!val_rows && vals[c].len < n)
+            return set_error(TQP_EINVAL, "%s: value column %d is shorter than keys", who, c);
+        a->val[c] = vals[c].data;
+        a->vlen[c] = vals[c].len;
+        a->vdt[c] = vals[c].dtype;
+    }
+    for (int g = 0; g < nagg; g++) {
+        const tqp_agg &x = aggs[g];
+        if (x.op < TQP_AGG_SUM || x.op > TQP_AGG_SUM_PRODUCT)
+            return set_error(TQP_EINVAL, "%s: aggregate %d has a bad op", who, g);
+        if (x.op != TQP_AGG_COUNT && (x.a < 0 || x.a >= nvals))
+            return set_error(TQP_EINVAL, "%s: aggregate %d names a missing column", who, g);
+        if (x.op == TQP_AGG_SUM_PRODUCT && (x.b < 0 || x.b >= nvals))
+            return set_error(TQP_EINVAL, "%s: aggregate %d names a missing column", who, g);
+        if (out_cap > 0 && !out_aggs[g]) return set_error(TQP_EINVAL, "%s: output %d is null", who, g);
+        a->op[g] = x.op;
+        a->ia[g] = x.a;
+        a->ib[g] = x.b;
+    }
+    a->nagg = nagg;
+    a->val_rows = val_rows;
+    return TQP_OK;
+}
+
 TQP_API size_t tqp_groupby_workspace_bytes(int64_t n, int dtype, int nagg, uint32_t flags,
                                            int64_t key_span) {
     if (n < 0 || (dtype != TQP_INT32 && dtype != TQP_INT64) || nagg < 1 || nagg > kMaxAgg)
@@ -660,31 +750,9 @@ TQP_API int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t fla
     if ((n > 0 && !key->data) || (out_key->len > 0 && !out_key->data))
         return set_error(TQP_EINVAL, "tqp_groupby_agg: null key data");
     AggArgs a = {};
-    for (int c = 0; c < nvals; c++) {
-        if (!dtype_ok(vals[c].dtype) || (vals[c].len > 0 && !vals[c].data))
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: value column %d is invalid", c);
-        if (!val_rows && vals[c].len < n)
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: value column %d is shorter than keys", c);
-        a.val[c] = vals[c].data;
-        a.vlen[c] = vals[c].len;
-        a.vdt[c] = vals[c].dtype;
-    }
-    for (int g = 0; g < nagg; g++) {
-        const tqp_agg &x = aggs[g];
-        if (x.op < TQP_AGG_SUM || x.op > TQP_AGG_SUM_PRODUCT)
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d has a bad op", g);
-        if (x.op != TQP_AGG_COUNT && (x.a < 0 || x.a >= nvals))
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d names a missing column", g);
-        if (x.op == TQP_AGG_SUM_PRODUCT && (x.b < 0 || x.b >= nvals))
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: aggregate %d names a missing column", g);
-        if (out_key->len > 0 && !out_aggs[g])
-            return set_error(TQP_EINVAL, "tqp_groupby_agg: output %d is null", g);
-        a.op[g] = x.op;
-        a.ia[g] = x.a;
-        a.ib[g] = x.b;
-    }
-    a.nagg = nagg;
-    a.val_rows = val_rows;
+    int rc = agg_args(vals, nvals, val_rows, aggs, nagg, n, out_key->len, out_aggs, &a,
+                      "tqp_groupby_agg");
+    if (rc) return rc;
     const size_t need = tqp_groupby_workspace_bytes(n, key->dtype, nagg, flags, key_span);
     if (!ws || ws_bytes < need)
         return set_error(TQP_ECAPACITY, "tqp_groupby_agg: workspace needs %zu bytes", need);
@@ -694,4 +762,61 @@ TQP_API int tqp_groupby_agg(const tqp_col *key, const int64_t *d_n, uint32_t fla
                                       d_ngroups, ws, s);
     return groupby_typed<int64_t>(key, d_n, flags, key_lo, key_span, a, out_key, out_aggs,
                                   d_ngroups, ws, s);
+}
+
+TQP_API size_t tqp_groupby_terms_workspace_bytes(int nagg, int64_t key_span) {
+    if (nagg < 1 || nagg > kMaxAgg || !dense_ok(TQP_GB_DENSE, key_span, nagg)) return 0;
+    Carver c(nullptr);
+    c.take<unsigned long long>(size_t(nagg + 1) * size_t(key_span));
+    return c.bytes();
+}
+
+TQP_API int tqp_groupby_agg_terms(const tqp_keyterm *terms, int nterms, int64_t n,
+                                  const int64_t *d_n, int64_t key_lo, int64_t key_span,
+                                  const tqp_col *vals, int nvals, const int32_t *val_rows,
+                                  const tqp_agg *aggs, int nagg, const tqp_col *out_key,
+                                  int64_t *const *out_aggs, int64_t *d_ngroups, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    clear_error();
+    if (!terms || !out_key || !aggs || !out_aggs || !d_ngroups)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: null argument");
+    if (nterms < 1 || nterms > 4)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: nterms must be in [1, 4]");
+    if (out_key->dtype != TQP_INT32 && out_key->dtype != TQP_INT64)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: out_key must be int32 or int64");
+    if (out_key->len > 0 && !out_key->data)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: null out_key data");
+    if (nagg < 1 || nagg > kMaxAgg)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: nagg must be in [1, %d]", kMaxAgg);
+    if (nvals < 0 || nvals > kMaxVals || (nvals > 0 && !vals))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: nvals must be in [0, %d]", kMaxVals);
+    if (!dense_ok(TQP_GB_DENSE, key_span, nagg))
+        return set_error(TQP_EINVAL,
+                         "tqp_groupby_agg_terms: need 1 <= key_span and (nagg + 1) * key_span <= 6144");
+    if (out_key->dtype == TQP_INT32 &&
+        (key_lo < INT32_MIN || key_lo + key_span - 1 > INT32_MAX))
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: the key range does not fit int32");
+    if (n < 0 || n > (int64_t(1) << 30) - 1)
+        return set_error(TQP_EINVAL, "tqp_groupby_agg_terms: n must be in [0, 2^30 - 1]");
+    PackArgs p;
+    int rc = pack_args(terms, nterms, n, &p, "tqp_groupby_agg_terms");
+    if (rc) return rc;
+    AggArgs a;
+    rc = agg_args(vals, nvals, val_rows, aggs, nagg, n, out_key->len, out_aggs, &a,
+                  "tqp_groupby_agg_terms");
+    if (rc) return rc;
+    const size_t need = tqp_groupby_terms_workspace_bytes(nagg, key_span);
+    if (!ws || ws_bytes < need)
+        return set_error(TQP_ECAPACITY, "tqp_groupby_agg_terms: workspace needs %zu bytes", need);
+    int64_t *o[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int g = 0; g < nagg; g++) o[g] = out_aggs[g];
+    hipStream_t s = as_stream(stream);
+    unsigned long long *gacc = static_cast<unsigned long long *>(ws);
+    if (out_key->dtype == TQP_INT32)
+        return dense_groupby<int32_t>(TermKeys{p}, n, d_n, key_lo, key_span, a, gacc,
+                                      static_cast<int32_t *>(out_key->data), out_key->len, o,
+                                      d_ngroups, s);
+    return dense_groupby<int64_t>(TermKeys{p}, n, d_n, key_lo, key_span, a, gacc,
+                                  static_cast<int64_t *>(out_key->data), out_key->len, o,
+                                  d_ngroups, s);
 }

@@ -165,21 +165,30 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     if (tile >= ntiles) break;
     const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
 
-    // Issue every load of the tile first: keys, row ids, payload columns.
-    K key[kSortIPT];
-    int32_t rowv[kSortIPT];
-    uint64_t pay[kSortIPT][NPAY > 0 ? NPAY : 1];
+    // Issue every load of the tile before the first wait: keys, row ids,
+    // payload columns.  Positions past the end read the last item instead (a
+    // tile exists only if cnt >= 1); those items are marked missing below.
+    // Positions are below 2^30 (the callers' row limit), so 32 bits hold them.
+    uint32_t lidx[kSortIPT];
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
         const int64_t idx = wbase + k * kWave + lane;
-        const bool valid = idx < cnt;
-        key[k] = valid ? keys_in[idx] : K(0);
-        rowv[k] = 0;
-        if (c.rows_out && valid) rowv[k] = c.rows_in ? c.rows_in[idx] : int32_t(idx);
-#pragma unroll
-        for (int p = 0; p < NPAY; p++)
-            pay[k][p] = valid ? uint64_t(load_any(c.pin[p], c.pdt[p], idx)) : 0;
+        lidx[k] = uint32_t(idx < cnt ? idx : cnt - 1);
     }
+    K key[kSortIPT];
+    int32_t rowv[kSortIPT];
+    uint64_t pay[NPAY > 0 ? NPAY : 1][kSortIPT];
+#pragma unroll
+    for (int k = 0; k < kSortIPT; k++) key[k] = keys_in[lidx[k]];
+    if (c.rows_out && c.rows_in) {
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) rowv[k] = c.rows_in[lidx[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) rowv[k] = int32_t(lidx[k]);
+    }
+#pragma unroll
+    for (int p = 0; p < NPAY; p++) load_raw<kSortIPT>(c.pin[p], c.pdt[p], lidx, pay[p]);
     for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_hist[0][0])[i] = 0;
     uint32_t gtot;
     const uint32_t gstart = block_excl_scan<kSortNT>(tid < kBins ? ghist[tid] : 0u, &gtot, s_scan);
@@ -301,19 +310,19 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
         if (dt == TQP_INT8) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(pay[k][p]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(pay[p][k]);
             __syncthreads();
             flush_stage<int8_t>(s_stage, gpos, static_cast<int8_t *>(c.pout[p]));
         } else if (dt == TQP_INT32) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(pay[k][p]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(pay[p][k]);
             __syncthreads();
             flush_stage<int32_t>(s_stage, gpos, static_cast<int32_t *>(c.pout[p]));
         } else {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = pay[k][p];
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = pay[p][k];
             __syncthreads();
             flush_stage<int64_t>(s_stage, gpos, static_cast<int64_t *>(c.pout[p]));
         }

@@ -279,6 +279,30 @@ __device__ __forceinline__ int64_t load_any(const void *p, int dtype, int64_t i)
     default: return static_cast<const int64_t *>(p)[i];
     }
 }
+// N elements of one column at valid positions idx[], zero-extended to 64
+// bits.  The dtype test is taken once for all N, so the N loads are in flight
+// together (a test per element makes the compiler wait after each load).
+template <int N, class I>
+__device__ __forceinline__ void load_raw(const void *p, int dtype, const I (&idx)[N],
+                                         uint64_t (&out)[N]) {
+    if (dtype == TQP_INT8) {
+        const uint8_t *q = static_cast<const uint8_t *>(p);
+#pragma unroll
+        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
+    } else if (dtype == TQP_INT32) {
+        const uint32_t *q = static_cast<const uint32_t *>(p);
+#pragma unroll
+        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
+    } else {
+        const uint64_t *q = static_cast<const uint64_t *>(p);
+#pragma unroll
+        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
+    }
+}
+// The signed value of a zero-extended element of the given dtype.
+__device__ __forceinline__ int64_t sext_of(uint64_t v, int dtype) {
+    return dtype == TQP_INT8 ? int64_t(int8_t(v)) : dtype == TQP_INT32 ? int64_t(int32_t(v)) : int64_t(v);
+}
 __device__ __forceinline__ void store_any(void *p, int dtype, int64_t i, int64_t v) {
     switch (dtype) {
     case TQP_INT8: static_cast<int8_t *>(p)[i] = static_cast<int8_t>(v); break;
@@ -286,5 +310,84 @@ __device__ __forceinline__ void store_any(void *p, int dtype, int64_t i, int64_t
     default: static_cast<int64_t *>(p)[i] = v; break;
     }
 }
+
+// ---- packed multi-column keys ---------------------------------------------
+// key(i) = sum over terms of mul * f(col[rows ? rows[i] : i]) mod 2^64, with
+// f(v) = v mod m in [0, m) when m > 0, f(v) = v otherwise; a term without a
+// column adds mul; a row outside the column reads 0.
+struct PackArgs {
+    const void *col[4];
+    const int32_t *rows[4];
+    int64_t len[4];
+    int64_t mod[4];
+    int64_t mul[4];
+    int32_t dt[4];
+    int32_t nterms;
+};
+
+// The keys of R positions (positions >= cnt give 0), term by term: each
+// term's R row-id loads go out together, then its R value loads.  Loads are
+// never predicated: a position past cnt reads row 0 and a row outside the
+// column reads element 0 (both exist whenever cnt >= 1, as in every caller's
+// loop), and the result is then replaced.  A power-of-two modulus is a mask
+// (v mod 2^k in [0, 2^k) is v & (2^k - 1) in two's complement).
+template <int R>
+__device__ __forceinline__ void pack_keys(const PackArgs &a, const int64_t (&idx)[R], int64_t cnt,
+                                          uint64_t (&acc)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; r++) acc[r] = 0;
+    for (int t = 0; t < a.nterms; t++) {
+        if (!a.col[t]) {                       // constant term
+#pragma unroll
+            for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]);
+            continue;
+        }
+        int64_t row[R];
+        if (a.rows[t]) {
+            int64_t li[R];
+            uint64_t rr[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) li[r] = idx[r] < cnt ? idx[r] : 0;
+            load_raw<R>(a.rows[t], TQP_INT32, li, rr);
+#pragma unroll
+            for (int r = 0; r < R; r++) row[r] = idx[r] < cnt ? int64_t(int32_t(uint32_t(rr[r]))) : -1;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; r++) row[r] = idx[r] < cnt ? idx[r] : -1;
+        }
+        const int64_t len = a.len[t];
+        const int dt = a.dt[t];
+        int64_t v[R];
+        if (len > 0) {
+            int64_t li[R];
+            uint64_t raw[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) li[r] = row[r] >= 0 && row[r] < len ? row[r] : 0;
+            load_raw<R>(a.col[t], dt, li, raw);
+#pragma unroll
+            for (int r = 0; r < R; r++) v[r] = row[r] >= 0 && row[r] < len ? sext_of(raw[r], dt) : 0;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; r++) v[r] = 0;
+        }
+        const int64_t m = a.mod[t];
+        if (m > 0 && (m & (m - 1)) == 0) {
+#pragma unroll
+            for (int r = 0; r < R; r++) v[r] &= m - 1;
+        } else if (m > 0) {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                v[r] %= m;
+                if (v[r] < 0) v[r] += m;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) acc[r] += uint64_t(a.mul[t]) * uint64_t(v[r]);
+    }
+}
+
+// Fills PackArgs from the C-ABI terms; n is the row count a term without row
+// ids must cover.  Returns TQP_OK or an error (message set).
+int pack_args(const tqp_keyterm *terms, int nterms, int64_t n, PackArgs *a, const char *who);
 
 }  // namespace tqp

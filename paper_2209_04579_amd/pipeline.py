@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_workspace_bytes,
-               gather_into, groupby_agg_into, groupby_workspace_bytes, join_into, join_workspace_bytes,
+               gather_into, groupby_agg_into, groupby_agg_terms_into,
+               groupby_terms_workspace_bytes, groupby_workspace_bytes, join_into, join_workspace_bytes,
                pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, tune_set,
                workspace)
 
@@ -107,15 +108,20 @@ class StarQuery:
             self.ga_aggs = [("sum", 0), ("sum", 1), ("count",)]
         fits32 = -(1 << 31) <= self.ga_lo and self.ga_lo + self.ga_span <= (1 << 31)
         kdt = torch.int32 if fits32 else torch.int64
-        self.gkey = torch.empty(self.cap, dtype=kdt, device=dev)
         dense = 0 < self.ga_span <= min(self.dense_max, 1024)
+        self.gkey = None if dense else torch.empty(self.cap, dtype=kdt, device=dev)
+        self.ga_dense = dense
         self.ga_flags = GB_DENSE if dense else 0
         self.ga_key = torch.empty(max(self.ga_span, 1) if dense else self.cap, dtype=kdt,
                                   device=dev)
         self.ga_out = [_i64(self.ga_key.numel(), dev) for _ in self.ga_aggs]
         self.ga_ng = _i64(1, dev)
-        self.ws_ga = workspace(groupby_workspace_bytes(self.cap, kdt, len(self.ga_aggs),
-                                                       self.ga_flags, self.ga_span), dev)
+        # a dense domain aggregates over the packed key directly (never
+        # written); otherwise the key is packed, then sorted by the group-by
+        self.ws_ga = workspace(
+            groupby_terms_workspace_bytes(len(self.ga_aggs), self.ga_span) if dense else
+            groupby_workspace_bytes(self.cap, kdt, len(self.ga_aggs), self.ga_flags,
+                                    self.ga_span), dev)
         if mode == "q2":
             self.gb_key = torch.empty(self.cap, dtype=fact["fk"].dtype, device=dev)
             self.gb_out = [_i64(self.cap, dev) for _ in range(2)]
@@ -142,16 +148,21 @@ class StarQuery:
         # 4. group-bys over the joined rows
         qty_s = self.fpay_s[0]
         if self.mode == "q1":
-            pack_key_into([(self.cat_s, self.out_r, 0, 1)], self.cap, self.gkey, d_n=self.npairs)
+            terms = [(self.cat_s, self.out_r, 0, 1)]
             vals = [qty_s]
         else:
             price_s, flag_s = self.fpay_s[1], self.fpay_s[2]
-            pack_key_into([(flag_s, self.out_l, 0, 2), (self.cat_s, self.out_r, 2, 1)],
-                          self.cap, self.gkey, d_n=self.npairs)
+            terms = [(flag_s, self.out_l, 0, 2), (self.cat_s, self.out_r, 2, 1)]
             vals = [qty_s, price_s]
-        groupby_agg_into(self.gkey[:self.cap], vals, self.ga_aggs, self.ga_key, self.ga_out,
-                         self.ga_ng, self.ws_ga, flags=self.ga_flags, key_lo=self.ga_lo,
-                         key_span=self.ga_span, val_rows=self.out_l, d_n=self.npairs)
+        if self.ga_dense:
+            groupby_agg_terms_into(terms, self.cap, vals, self.ga_aggs, self.ga_key, self.ga_out,
+                                   self.ga_ng, self.ws_ga, self.ga_lo, self.ga_span,
+                                   val_rows=self.out_l, d_n=self.npairs)
+        else:
+            pack_key_into(terms, self.cap, self.gkey, d_n=self.npairs)
+            groupby_agg_into(self.gkey[:self.cap], vals, self.ga_aggs, self.ga_key, self.ga_out,
+                             self.ga_ng, self.ws_ga, flags=self.ga_flags, key_lo=self.ga_lo,
+                             key_span=self.ga_span, val_rows=self.out_l, d_n=self.npairs)
         if self.mode == "q2":
             groupby_agg_into(self.out_k[:self.cap], [qty_s], [("sum", 0), ("count",)],
                              self.gb_key, self.gb_out, self.gb_ng, self.ws_gb, flags=GB_SORTED,
@@ -243,14 +254,15 @@ class StarQuery3:
         ws_j = max(join_workspace_bytes(n, max(m, 1), torch.int32, JOIN_SORTED, max(n, 1))
                    for m in self.nd)
         self.ws_j = workspace(ws_j, dev)
-        self.gkey = _i64(n, dev)
         self.aggs = [("sum_product", 0, 1), ("count",)]
         gflags = GB_DENSE if self.g_dense else 0
         self.g_flags = gflags
+        self.gkey = None if self.g_dense else _i64(n, dev)
         self.g_key = _i64(self.g_span if self.g_dense else n, dev)
         self.g_out = [_i64(self.g_key.numel(), dev) for _ in self.aggs]
         self.g_ng = _i64(1, dev)
-        self.ws_g = workspace(groupby_workspace_bytes(max(n, 1), torch.int64, 2, gflags,
+        self.ws_g = workspace(groupby_terms_workspace_bytes(2, self.g_span) if self.g_dense else
+                              groupby_workspace_bytes(max(n, 1), torch.int64, 2, gflags,
                                                       self.g_span), dev)
 
     def run(self):
@@ -291,11 +303,16 @@ class StarQuery3:
                   self.cnt[2], self.ws_j, d_nl=self.cnt[1], d_nr=self.dcnt[0])
         gather_into(self.rows_s, self.jpos, n, self.r[2], d_n=self.cnt[2])
         # 5. GROUP BY d1.cat * 5 + d2.cat: SUM(qty * price), COUNT(*)
-        pack_key_into([(self.dcat_s[0], self.rpos, 0, 5), (self.c2_s, self.jpos, 0, 1)], n,
-                      self.gkey, d_n=self.cnt[2])
-        groupby_agg_into(self.gkey[:n], [f["qty"], f["price"]], self.aggs, self.g_key,
-                         self.g_out, self.g_ng, self.ws_g, flags=self.g_flags, key_lo=0,
-                         key_span=self.g_span, val_rows=self.r[2], d_n=self.cnt[2])
+        terms = [(self.dcat_s[0], self.rpos, 0, 5), (self.c2_s, self.jpos, 0, 1)]
+        if self.g_dense:
+            groupby_agg_terms_into(terms, n, [f["qty"], f["price"]], self.aggs, self.g_key,
+                                   self.g_out, self.g_ng, self.ws_g, 0, self.g_span,
+                                   val_rows=self.r[2], d_n=self.cnt[2])
+        else:
+            pack_key_into(terms, n, self.gkey, d_n=self.cnt[2])
+            groupby_agg_into(self.gkey[:n], [f["qty"], f["price"]], self.aggs, self.g_key,
+                             self.g_out, self.g_ng, self.ws_g, flags=self.g_flags, key_lo=0,
+                             key_span=self.g_span, val_rows=self.r[2], d_n=self.cnt[2])
 
     def result(self) -> dict:
         torch.cuda.synchronize()

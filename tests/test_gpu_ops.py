@@ -281,3 +281,71 @@ def test_groupby_wraps_modulo_2_64(tqp):
     uk, (s,) = tqp.groupby_agg(dev(keys), [dev(vals)], [("sum", 0)])
     wk, (w,), ovf = oracle.groupby(keys, [vals], [("sum", 0)])
     assert ovf and np.array_equal(host(s), w)
+
+
+def packed_key_host(terms_np, n):
+    """The packed key on the host: sum of mul * f(col[rows]) (numpy int64)."""
+    key = np.zeros(n, np.int64)
+    for col, rows, mod, mul in terms_np:
+        if col is None:
+            key += mul
+            continue
+        v = (col[rows] if rows is not None else col[:n]).astype(np.int64)
+        if mod > 0:
+            v = np.mod(v, mod)
+        key += mul * v
+    return key
+
+
+@pytest.mark.parametrize("n", [0, 1, 4097, 1_000_003])
+@pytest.mark.parametrize("out_dtype", [np.int32, np.int64])
+def test_groupby_agg_terms_matches_oracle(tqp, n, out_dtype):
+    """Dense group-by over a packed key computed in the kernel: the same groups
+    as the oracle over the key packed on the host."""
+    m = 50_000
+    flag = dg.uniform_int(n + 1, 1, m, 0, 3, np.int8)
+    cat = dg.uniform_int(n + 1, 2, m, -9, 25, np.int32)
+    lrow = dg.uniform_int(n + 1, 3, n, 0, m, np.int32)
+    rrow = dg.uniform_int(n + 1, 4, n, 0, m, np.int32)
+    qty = dg.uniform_int(n + 1, 5, m, 1, 5001, np.int64)
+    price = dg.uniform_int(n + 1, 6, m, 100, 10 ** 7, np.int64)
+    # key = 2 * flag + (cat mod 4) + 10, in [10, 20)
+    terms_np = [(flag, lrow, 0, 2), (cat, rrow, 4, 1), (None, None, 0, 10)]
+    terms = [(dev(flag), dev(lrow), 0, 2), (dev(cat), dev(rrow), 4, 1), (None, None, 0, 10)]
+    aggs = [("sum", 0), ("sum_product", 0, 1), ("count",)]
+    span, lo = 10, 10
+    out_key = torch.empty(span, dtype=torch.int32 if out_dtype == np.int32 else torch.int64,
+                          device="cuda")
+    outs = [torch.empty(span, dtype=torch.int64, device="cuda") for _ in aggs]
+    ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = tqp.workspace(tqp.groupby_terms_workspace_bytes(len(aggs), span))
+    tqp.groupby_agg_terms_into(terms, n, [dev(qty), dev(price)], aggs, out_key, outs, ng, ws,
+                               lo, span, val_rows=dev(lrow))
+    g = int(ng.item())
+    key = packed_key_host(terms_np, n)
+    wk, wa, _ = oracle.groupby(key, [qty[lrow], price[lrow]], aggs)
+    assert np.array_equal(host(out_key[:g]).astype(np.int64), wk)
+    for o, w in zip(outs, wa):
+        assert np.array_equal(host(o[:g]), w)
+
+
+def test_groupby_agg_terms_device_count_and_limits(tqp):
+    n = 200_000
+    cat = dg.uniform_int(3, 1, n, 0, 6, np.int32)
+    qty = dg.uniform_int(3, 2, n, 1, 5001, np.int64)
+    d_n = torch.tensor([123_457], dtype=torch.int64, device="cuda")
+    out_key = torch.empty(6, dtype=torch.int64, device="cuda")
+    outs = [torch.empty(6, dtype=torch.int64, device="cuda") for _ in range(2)]
+    ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = tqp.workspace(tqp.groupby_terms_workspace_bytes(2, 6))
+    tqp.groupby_agg_terms_into([(dev(cat), None, 0, 1)], n, [dev(qty)], [("sum", 0), ("count",)],
+                               out_key, outs, ng, ws, 0, 6, d_n=d_n)
+    g = int(ng.item())
+    wk, wa, _ = oracle.groupby(cat[:123_457].astype(np.int64), [qty[:123_457]],
+                               [("sum", 0), ("count",)])
+    assert np.array_equal(host(out_key[:g]), wk)
+    for o, w in zip(outs, wa):
+        assert np.array_equal(host(o[:g]), w)
+    with pytest.raises(tqp.TqpError):          # accumulators beyond the LDS budget
+        tqp.groupby_agg_terms_into([(dev(cat), None, 0, 1)], n, [dev(qty)],
+                                   [("sum", 0), ("count",)], out_key, outs, ng, ws, 0, 4000)
