@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--batch-fact-hi", type=int, default=20_000_000)
     ap.add_argument("--side-reps", type=int, default=5,
                     help="timed repetitions of each side comparison")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the small-star and three-dimension-star throughput lines")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 counter_collection.csv files "
                          "(--pmc FETCH_SIZE, --pmc WRITE_SIZE of this script) into "
@@ -309,6 +311,46 @@ def bench_learned(args, tqp, stream) -> dict:
     return out
 
 
+def bench_configs(args, tqp, stream) -> dict:
+    """Throughput of the other two star queries: the small one (1M fact rows,
+    launch-bound) and the three-dimension star (600M fact rows, drawn on the
+    GPU).  Their results are checked against the oracle by the test suite
+    (full-size cases included), not here."""
+    import torch
+    import tqp_datagen as dg
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import StarQuery, StarQuery3
+
+    out = {}
+    c1 = dg.config1(args.seed)
+    q = StarQuery({k: torch.from_numpy(v).cuda() for k, v in c1["fact"].items()},
+                  {k: torch.from_numpy(v).cuda() for k, v in c1["dim"].items()}, c1["day_cut"])
+    ms = _timed(q.run, 20, stream)
+    got = q.result()
+    out["small_star"] = {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat",
+                         "ms": round(ms, 4), "rows_per_s": round(1_000_000 / (ms * 1e-3), 1),
+                         "groups": int(len(got["key"]))}
+    del q
+    t0 = time.time()
+    c3 = dgd.config3(args.seed, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[bench] star3: generated 600M fact rows in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    q3 = StarQuery3(c3["fact"], c3["d1"], c3["d2"], c3["d3"], c3["attr_cut"])
+    ms = _timed(q3.run, max(args.side_reps, 1), stream)
+    got = q3.result()
+    n3 = int(c3["fact"]["fk1"].numel())
+    out["star3"] = {"workload": "fact 600M rows, three dims (1M, 100k, 25) filtered to ~20%; "
+                                "joins fk3, fk2, fk1; group by d1.cat*5+d2.cat: "
+                                "SUM(qty*price), COUNT",
+                    "ms": round(ms, 3), "rows_per_s": round(n3 / (ms * 1e-3), 1),
+                    "pairs": got["pairs"], "groups": int(len(got["key"]))}
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    del q3, c3
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(args, tqp, stream) -> dict:
     """256 independent star queries of log-uniform sizes: one batched plan
     captured in a HIP graph (knobs picked by the autotuner) against the same
@@ -493,6 +535,7 @@ def main():
     # side comparisons on their own workloads (outside the headline's timed region)
     del q, fact, dim
     torch.cuda.empty_cache()
+    configs = None if args.no_configs else bench_configs(args, tqp, stream)
     learned = None if args.no_learned else bench_learned(args, tqp, stream)
     batch = None if args.no_batch else bench_batch(args, tqp, stream)
 
@@ -521,6 +564,7 @@ def main():
         "stream_copy_GBps": round(copy_gbs, 1),
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "other_configs": configs,
         "learned_vs_radix": learned,
         "batch": batch,
         # the paper reports ratios only, on other hardware and on TPC-H SF1

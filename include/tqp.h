@@ -48,7 +48,9 @@ extern "C" {
 /* Column element types.  Money is int64 fixed-point cents, so sums are exact. */
 typedef enum { TQP_INT8 = 1, TQP_INT32 = 2, TQP_INT64 = 3 } tqp_dtype;
 
-/* A non-owning 1-D device column: `len` elements of `dtype` at `data`. */
+/* A non-owning 1-D device column: `len` elements of `dtype` at `data`, which
+ * is aligned to the element size (entry points that read columns of run-time
+ * dtype check this and return TQP_EINVAL otherwise). */
 typedef struct {
     void    *data;
     int64_t  len;

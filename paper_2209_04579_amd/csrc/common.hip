@@ -36,6 +36,10 @@ int dtype_size(int dtype) {
 }
 
 bool dtype_ok(int dtype) { return dtype_size(dtype) != 0; }
+bool col_aligned(const void *p, int dtype) {
+    const int sz = dtype_size(dtype);
+    return sz != 0 && reinterpret_cast<uintptr_t>(p) % uintptr_t(sz) == 0;
+}
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;

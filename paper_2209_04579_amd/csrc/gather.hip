@@ -65,8 +65,9 @@ int pack_args(const tqp_keyterm *terms, int nterms, int64_t n, PackArgs *a, cons
             a->mul[t] = k.mul;
             continue;
         }
-        if (!dtype_ok(k.col.dtype) || k.mod < 0)
-            return set_error(TQP_EINVAL, "%s: term %d is invalid", who, t);
+        if (!dtype_ok(k.col.dtype) || k.mod < 0 || !col_aligned(k.col.data, k.col.dtype) ||
+            (k.rows && !col_aligned(k.rows, TQP_INT32)))
+            return set_error(TQP_EINVAL, "%s: term %d is invalid or unaligned", who, t);
         if (!k.rows && k.col.len < n)
             return set_error(TQP_EINVAL, "%s: term %d column is shorter than n", who, t);
         a->col[t] = k.col.data;

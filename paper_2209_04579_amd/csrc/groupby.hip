@@ -159,7 +159,8 @@ __device__ __forceinline__ void load_rows(const int32_t *val_rows, const int64_t
         uint64_t rr[N];
 #pragma unroll
         for (int r = 0; r < N; r++) li[r] = idx[r] < cnt ? idx[r] : 0;
-        load_raw<N>(val_rows, TQP_INT32, li, rr);
+#pragma unroll
+        for (int r = 0; r < N; r++) rr[r] = uint32_t(val_rows[li[r]]);
 #pragma unroll
         for (int r = 0; r < N; r++) row[r] = idx[r] < cnt ? int32_t(uint32_t(rr[r])) : 0;
     } else {
@@ -689,8 +690,9 @@ static int agg_args(const tqp_col *vals, int nvals, const int32_t *val_rows, con
                     const char *who) {
     *a = AggArgs{};
     for (int c = 0; c < nvals; c++) {
-        if (!dtype_ok(vals[c].dtype) || (vals[c].len > 0 && !vals[c].data))
-            return set_error(TQP_EINVAL, "%s: value column %d is invalid", who, c);
+        if (!dtype_ok(vals[c].dtype) || (vals[c].len > 0 && !vals[c].data) ||
+            !col_aligned(vals[c].data, vals[c].dtype))
+            return set_error(TQP_EINVAL, "%s: value column %d is invalid or unaligned", who, c);
         if (!val_rows && vals[c].len < n)
             return set_error(TQP_EINVAL, "%s: value column %d is shorter than keys", who, c);
         a->val[c] = vals[c].data;
@@ -710,6 +712,8 @@ static int agg_args(const tqp_col *vals, int nvals, const int32_t *val_rows, con
         a->ia[g] = x.a;
         a->ib[g] = x.b;
     }
+    if (val_rows && !col_aligned(val_rows, TQP_INT32))
+        return set_error(TQP_EINVAL, "%s: val_rows must be 4-byte aligned", who);
     a->nagg = nagg;
     a->val_rows = val_rows;
     return TQP_OK;

@@ -31,6 +31,7 @@ constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kSortNW = kSortNT / kWave;
 constexpr int kMaxSortPay = 4;
+constexpr int kMaxPassCols = kMaxSortPay + 1;   // payload columns + row ids
 constexpr int kHistNT = 256;
 constexpr int kHistIPT = 16;
 constexpr int kLookAhead = 4;             // predecessor statuses fetched per round trip
@@ -82,12 +83,23 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
 #pragma unroll
             for (int r = 0; r < kHistIPT; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
         }
+        // Skewed keys put many lanes of a wave on one counter, and LDS
+        // atomics on one address serialize: the lanes sharing the first
+        // valid lane's digit are counted by one ballot and one add.
 #pragma unroll
         for (int r = 0; r < kHistIPT; r++) {
-            if (row0 + r < cnt) {
-                const uint64_t u = ord(v[r]);
-                for (int p = 0; p < npass; p++)
-                    atomicAdd(&s_h[w][p][(u >> (p * dbits)) & dmask], 1u);
+            const bool valid = row0 + r < cnt;
+            const uint64_t vm = ballot(valid);
+            if (vm == 0) continue;
+            const int first = __builtin_ctzll(vm);
+            const uint64_t u = ord(v[r]);
+            for (int p = 0; p < npass; p++) {
+                const uint32_t d = uint32_t(u >> (p * dbits)) & dmask;
+                const uint32_t f = uint32_t(__builtin_amdgcn_readlane(int(d), first));
+                const bool same = valid && d == f;
+                const uint64_t sm = ballot(same);
+                if (lane_id() == first) atomicAdd(&s_h[w][p][f], uint32_t(__popcll(sm)));
+                else if (valid && !same) atomicAdd(&s_h[w][p][d], 1u);
             }
         }
     }
@@ -101,14 +113,37 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
     }
 }
 
+// The columns a pass moves with its keys: the payload columns, then the row
+// ids when they are produced.  A null source is the item's position (the row
+// ids of a first pass).
 struct PassCols {
-    const int32_t *rows_in;      // null: row id = position (first pass)
-    int32_t *rows_out;           // null: row ids not produced
-    const void *pin[kMaxSortPay];
-    void *pout[kMaxSortPay];
-    int32_t pdt[kMaxSortPay];
-    int32_t npay;
+    const void *pin[kMaxPassCols];
+    void *pout[kMaxPassCols];
+    int32_t pdt[kMaxPassCols];
+    int32_t ncols;
 };
+
+// Column p of the items at positions lidx[]: the aligned 8-byte words that
+// hold them (word_of; from_word extracts the elements when they are staged,
+// so nothing waits for these loads before then).  A null source (the items'
+// positions, filled in at staging) reads the words of `alt` instead, so the
+// same loads are issued on every path and the compiler's wait counts stay
+// exact.
+// The row-id column (ROWID) is int32 by construction and read with 4-byte
+// loads.
+template <bool ROWID>
+__device__ __forceinline__ void load_col(const PassCols &c, int p, const void *alt,
+                                         const uint32_t (&lidx)[kSortIPT], uint64_t (&out)[kSortIPT]) {
+    const void *src = c.pin[p] ? c.pin[p] : alt;
+    if constexpr (ROWID) {
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) out[k] = static_cast<const uint32_t *>(src)[lidx[k]];
+    } else {
+        const int lg = c.pin[p] ? dtype_lg(c.pdt[p]) : 0;
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) out[k] = word_of(src, lg, lidx[k]);
+    }
+}
 
 // Writes one staged column of the tile (in digit order) to its runs: thread
 // t writes tile positions t, t + kSortNT, ... to the global positions in
@@ -124,14 +159,16 @@ __device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const int32
 }
 
 // One LSD pass.  NPAY payload columns (a compile-time count; dtypes at run
-// time) are read into registers together with the keys, so the tile pays one
-// memory latency before ranking rather than one per column afterwards.
+// time) and, with ROWS, the int32 row ids after them move with the keys: the
+// first column is read into registers together with the keys, so its latency
+// overlaps the ranking and look-back, and each later one while its
+// predecessor is written.
 // At least 4 waves per SIMD (<= 128 VGPRs) so two workgroups share a CU.
 // LB: the global start of each digit run comes from a decoupled look-back
 // over earlier tiles (persistent workgroups, tiles by ticket); otherwise one
 // workgroup per tile reads it from toff[digit * tstride + tile], the tile
 // offsets k_radix_tilescan computed from every tile's digit counts.
-template <class K, int NPAY, class Ord, bool LB>
+template <class K, int NPAY, class Ord, bool LB, bool ROWS>
 __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, PassCols c, int64_t n,
     const int64_t *d_n, Ord ord, int shift, int dbits, const uint32_t *__restrict__ ghist,
@@ -153,6 +190,12 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     // LB: persistent workgroups, each taking its XCD's tiles in order until
     // none are left.  Otherwise: tile = blockIdx.x, once.
     const int xcd = int(blockIdx.x % kXcds);
+    // LB: the global start of every digit (the same for all tiles)
+    uint32_t gstart = 0;
+    if constexpr (LB) {
+        uint32_t gtot;
+        gstart = block_excl_scan<kSortNT>(tid < kBins ? ghist[tid] : 0u, &gtot, s_scan);
+    }
     for (int it = 0;; it++) {
     int64_t tile;
     if constexpr (LB) {
@@ -165,9 +208,9 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     if (tile >= ntiles) break;
     const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
 
-    // Issue every load of the tile before the first wait: keys, row ids,
-    // payload columns.  Positions past the end read the last item instead (a
-    // tile exists only if cnt >= 1); those items are marked missing below.
+    // Issue the tile's loads before the first wait: keys and the first moved
+    // column.  Positions past the end read the last item instead (a tile
+    // exists only if cnt >= 1); those items are marked missing below.
     // Positions are below 2^30 (the callers' row limit), so 32 bits hold them.
     uint32_t lidx[kSortIPT];
 #pragma unroll
@@ -176,22 +219,13 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
         lidx[k] = uint32_t(idx < cnt ? idx : cnt - 1);
     }
     K key[kSortIPT];
-    int32_t rowv[kSortIPT];
-    uint64_t pay[NPAY > 0 ? NPAY : 1][kSortIPT];
+    uint64_t cur[kSortIPT];       // the column being moved (column 0 first)
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) key[k] = keys_in[lidx[k]];
-    if (c.rows_out && c.rows_in) {
-#pragma unroll
-        for (int k = 0; k < kSortIPT; k++) rowv[k] = c.rows_in[lidx[k]];
-    } else {
-#pragma unroll
-        for (int k = 0; k < kSortIPT; k++) rowv[k] = int32_t(lidx[k]);
-    }
-#pragma unroll
-    for (int p = 0; p < NPAY; p++) load_raw<kSortIPT>(c.pin[p], c.pdt[p], lidx, pay[p]);
+    constexpr int NC = NPAY + (ROWS ? 1 : 0);   // moved columns, row ids last
+    if (NC > 0) load_col<NPAY == 0>(c, 0, keys_in, lidx, cur);
     for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_hist[0][0])[i] = 0;
-    uint32_t gtot;
-    const uint32_t gstart = block_excl_scan<kSortNT>(tid < kBins ? ghist[tid] : 0u, &gtot, s_scan);
+    __syncthreads();
     // pd[k] = digit << 16 | position (digit kBins marks a missing item; a
     // position is below the tile size, 4096).
     uint32_t pd[kSortIPT];
@@ -295,36 +329,46 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
     flush_stage<K>(s_stage, gpos, keys_out);
 
-    if (c.rows_out) {
-        __syncthreads();
+    // Moved columns one after another: column p + 1 is loaded while column p
+    // is staged and written, so at most two are held in registers.
 #pragma unroll
-        for (int k = 0; k < kSortIPT; k++)
-            if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = rowv[k];
-        __syncthreads();
-        flush_stage<int32_t>(s_stage, gpos, c.rows_out);
-    }
-#pragma unroll
-    for (int p = 0; p < NPAY; p++) {
+    for (int p = 0; p < NC; p++) {
+        uint64_t nxt[kSortIPT];
+        if (p + 1 < NC) {               // both tests fold once the loop is unrolled
+            if (p + 1 == NPAY) load_col<true>(c, p + 1, keys_in, lidx, nxt);
+            else load_col<false>(c, p + 1, keys_in, lidx, nxt);
+        }
         const int dt = c.pdt[p];
+        {
+            const void *src = c.pin[p];
+            const int lg = dtype_lg(dt);
+#pragma unroll
+            for (int k = 0; k < kSortIPT; k++)
+                cur[k] = !src ? uint64_t(lidx[k]) : p == NPAY ? cur[k] : from_word(cur[k], src, lg, lidx[k]);
+        }
         __syncthreads();
         if (dt == TQP_INT8) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(pay[p][k]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(cur[k]);
             __syncthreads();
             flush_stage<int8_t>(s_stage, gpos, static_cast<int8_t *>(c.pout[p]));
         } else if (dt == TQP_INT32) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(pay[p][k]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(cur[k]);
             __syncthreads();
             flush_stage<int32_t>(s_stage, gpos, static_cast<int32_t *>(c.pout[p]));
         } else {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = pay[p][k];
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = cur[k];
             __syncthreads();
             flush_stage<int64_t>(s_stage, gpos, static_cast<int64_t *>(c.pout[p]));
+        }
+        if (p + 1 < NC) {
+#pragma unroll
+            for (int k = 0; k < kSortIPT; k++) cur[k] = nxt[k];
         }
     }
     __syncthreads();
@@ -402,8 +446,8 @@ __global__ __launch_bounds__(256) void k_copy_sorted(const K *__restrict__ keys_
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < cnt;
          i += int64_t(gridDim.x) * blockDim.x) {
         keys_out[i] = keys_in[i];
-        if (c.rows_out) c.rows_out[i] = c.rows_in ? c.rows_in[i] : int32_t(i);
-        for (int p = 0; p < c.npay; p++) store_any(c.pout[p], c.pdt[p], i, load_any(c.pin[p], c.pdt[p], i));
+        for (int p = 0; p < c.ncols; p++)
+            store_any(c.pout[p], c.pdt[p], i, c.pin[p] ? load_any(c.pin[p], c.pdt[p], i) : i);
     }
 }
 
@@ -447,13 +491,32 @@ inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) 
     return c.bytes();
 }
 
-template <class K, int NPAY, class Ord, bool LB>
+template <class K, int NPAY, class Ord, bool LB, bool ROWS>
 static int launch_pass(unsigned grid, hipStream_t s, const K *src, K *dst, const PassCols &x,
                        int64_t n, const int64_t *d_n, Ord ord, int shift, int dbits,
                        const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride) {
-    TQP_LAUNCH("onesweep", (k_onesweep<K, NPAY, Ord, LB>), dim3(grid), dim3(kSortNT), 0, s, src,
+    TQP_LAUNCH("onesweep", (k_onesweep<K, NPAY, Ord, LB, ROWS>), dim3(grid), dim3(kSortNT), 0, s, src,
                dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
     return TQP_OK;
+}
+
+// The instantiation for npay payload columns and (rows) row ids: row ids
+// alone take the typed 4-byte path (ROWS); next to payload columns they are
+// one more column of the generic path, which needs fewer registers there.
+template <class K, class Ord, bool LB>
+static int launch_cols(int npay, bool rows, unsigned grid, hipStream_t s, const K *src, K *dst,
+                       const PassCols &x, int64_t n, const int64_t *d_n, Ord ord, int shift,
+                       int dbits, const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride) {
+    if (rows && npay == 0)
+        return launch_pass<K, 0, Ord, LB, true>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    switch (npay + (rows ? 1 : 0)) {
+    case 0: return launch_pass<K, 0, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    case 1: return launch_pass<K, 1, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    case 2: return launch_pass<K, 2, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    case 3: return launch_pass<K, 3, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    case 4: return launch_pass<K, 4, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    default: return launch_pass<K, 5, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    }
 }
 
 // Sorts by the low `bits` bits of the ordinal: npass_for(bits) stable passes
@@ -473,13 +536,17 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     if (int64_t(grid_pass) < (groups < kXcds ? groups : int64_t(kXcds)))
         return set_error(TQP_EINVAL, "radix: grid %u too small for its tile groups", grid_pass);
     PassCols pc = {};
-    pc.rows_in = sc.rows_in;
-    pc.rows_out = sc.rows_out;
-    pc.npay = sc.npay;
     for (int p = 0; p < sc.npay; p++) {
         pc.pin[p] = sc.pin[p];
         pc.pout[p] = sc.pout[p];
         pc.pdt[p] = sc.pdt[p];
+    }
+    pc.ncols = sc.npay;
+    if (sc.rows_out) {
+        pc.pin[pc.ncols] = sc.rows_in;
+        pc.pout[pc.ncols] = sc.rows_out;
+        pc.pdt[pc.ncols] = TQP_INT32;
+        pc.ncols++;
     }
     if (npass == 0) {
         unsigned g = grid_all > 4096 ? 4096 : grid_all;
@@ -490,11 +557,12 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     Carver cv(ws);
     K *tmp_keys = nullptr;
     int32_t *tmp_rows = nullptr;
-    void *tmp_pay[kMaxSortPay] = {};
+    void *tmp_col[kMaxPassCols] = {};
     if (npass > 1) {
         tmp_keys = reinterpret_cast<K *>(cv.take<char>(size_t(n) * sizeof(K)));
         tmp_rows = cv.take<int32_t>(size_t(n));
-        for (int p = 0; p < sc.npay; p++) tmp_pay[p] = cv.take<char>(size_t(n) * dtype_size(sc.pdt[p]));
+        for (int p = 0; p < sc.npay; p++) tmp_col[p] = cv.take<char>(size_t(n) * dtype_size(sc.pdt[p]));
+        if (sc.rows_out) tmp_col[sc.npay] = tmp_rows;
     }
     const size_t nwords = size_t(npass) * kBins + size_t(npass) * kXcds + size_t(npass) * ntiles * kBins;
     uint32_t *words = cv.take<uint32_t>(nwords);
@@ -504,8 +572,10 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     int rc = fill_u32(words, 0, int64_t(nwords), s);
     if (rc) return rc;
     {
+        // a few workgroups per CU: each merges its counters into the device
+        // histogram once, so fewer workgroups mean fewer device atomics
         int64_t g = ceil_div(n > 0 ? n : 1, int64_t(kHistNT) * kHistIPT);
-        if (g > 2048) g = 2048;
+        if (g > int64_t(kComputeUnits) * 4) g = int64_t(kComputeUnits) * 4;
         TQP_LAUNCH("radix_hist", (k_radix_hist<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0, s,
                    key_in, n, d_n, ord, npass, dbits, ghist);
         rc = check_launch("radix histogram");
@@ -517,19 +587,13 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
         const bool to_out = ((npass - 1 - p) % 2) == 0;
         K *dk = to_out ? key_out : tmp_keys;
         PassCols x = cur;
-        x.rows_out = sc.rows_out ? (to_out ? sc.rows_out : tmp_rows) : nullptr;
-        for (int q = 0; q < sc.npay; q++) x.pout[q] = to_out ? sc.pout[q] : tmp_pay[q];
+        for (int q = 0; q < pc.ncols; q++) x.pout[q] = to_out ? pc.pout[q] : tmp_col[q];
         uint32_t *st = status + size_t(p) * ntiles * kBins;
         const int shift = p * dbits;
         const uint32_t *gh = ghist + p * kBins;
         if (mode == 0) {
-            switch (sc.npay) {
-            case 0: rc = launch_pass<K, 0, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
-            case 1: rc = launch_pass<K, 1, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
-            case 2: rc = launch_pass<K, 2, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
-            case 3: rc = launch_pass<K, 3, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
-            default: rc = launch_pass<K, 4, Ord, true>(grid_pass, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0); break;
-            }
+            rc = launch_cols<K, Ord, true>(sc.npay, sc.rows_out != nullptr, grid_pass, s, src_k, dk, x, n,
+                                           d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0);
         } else {
             // tile counts, their scan per digit, then one workgroup per tile
             uint32_t *tc = status;                    // ntiles * kBins words, reused per pass
@@ -539,20 +603,14 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
             TQP_LAUNCH("radix_tilescan", k_radix_tilescan, dim3(1u << dbits), dim3(kScanNT), 0, s, tc,
                        ntiles, gh);
             if ((rc = check_launch("radix tile scan"))) return rc;
-            switch (sc.npay) {
-            case 0: rc = launch_pass<K, 0, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
-            case 1: rc = launch_pass<K, 1, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
-            case 2: rc = launch_pass<K, 2, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
-            case 3: rc = launch_pass<K, 3, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
-            default: rc = launch_pass<K, 4, Ord, false>(grid_all, s, src_k, dk, x, n, d_n, ord, shift, dbits, gh, tc, nullptr, ntiles); break;
-            }
+            rc = launch_cols<K, Ord, false>(sc.npay, sc.rows_out != nullptr, grid_all, s, src_k, dk, x, n,
+                                            d_n, ord, shift, dbits, gh, tc, nullptr, ntiles);
         }
         if (rc) return rc;
         rc = check_launch("radix pass");
         if (rc) return rc;
         src_k = dk;
-        cur.rows_in = x.rows_out;
-        for (int q = 0; q < sc.npay; q++) cur.pin[q] = x.pout[q];
+        for (int q = 0; q < pc.ncols; q++) cur.pin[q] = x.pout[q];
     }
     return TQP_OK;
 }

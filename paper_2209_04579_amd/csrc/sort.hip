@@ -75,6 +75,8 @@ TQP_API int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n, cons
         return set_error(TQP_EINVAL, "tqp_sort: key_bits must be in [0, 64]");
     if (npay < 0 || npay > kMaxSortPay || (npay > 0 && (!pay_in || !pay_out)))
         return set_error(TQP_EINVAL, "tqp_sort: npay must be in [0, %d] with both arrays", kMaxSortPay);
+    if ((in_rows && !col_aligned(in_rows, TQP_INT32)) || (out_rows && !col_aligned(out_rows, TQP_INT32)))
+        return set_error(TQP_EINVAL, "tqp_sort: row id arrays must be 4-byte aligned");
     SortCols sc = {};
     sc.rows_in = in_rows;
     sc.rows_out = out_rows;
@@ -83,8 +85,9 @@ TQP_API int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n, cons
     for (int p = 0; p < npay; p++) {
         if (!dtype_ok(pay_in[p].dtype) || pay_in[p].dtype != pay_out[p].dtype ||
             pay_in[p].len < n || pay_out[p].len < n ||
-            (n > 0 && (!pay_in[p].data || !pay_out[p].data)))
-            return set_error(TQP_EINVAL, "tqp_sort: payload %d has a bad dtype, length or pointer", p);
+            (n > 0 && (!pay_in[p].data || !pay_out[p].data)) ||
+            !col_aligned(pay_in[p].data, pay_in[p].dtype) || !col_aligned(pay_out[p].data, pay_out[p].dtype))
+            return set_error(TQP_EINVAL, "tqp_sort: payload %d has a bad dtype, length or (unaligned) pointer", p);
         sc.pin[p] = pay_in[p].data;
         sc.pout[p] = pay_out[p].data;
         sc.pdt[p] = pay_in[p].dtype;

@@ -24,6 +24,8 @@ void clear_error();
 int check_launch(const char *what);
 int dtype_size(int dtype);
 bool dtype_ok(int dtype);
+// data is aligned to the element size (kernels read whole aligned words)
+bool col_aligned(const void *p, int dtype);
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Carves aligned sub-buffers out of a caller-provided workspace.  With a null
@@ -279,25 +281,41 @@ __device__ __forceinline__ int64_t load_any(const void *p, int dtype, int64_t i)
     default: return static_cast<const int64_t *>(p)[i];
     }
 }
+// log2 of the element size of a column dtype.
+__device__ __forceinline__ int dtype_lg(int dtype) {
+    return dtype == TQP_INT8 ? 0 : dtype == TQP_INT32 ? 2 : 3;
+}
+
+// Element i of a naturally aligned column of 1-, 4- or 8-byte integers,
+// zero-extended: one 8-byte load of the aligned word that holds it
+// (word_of), then a shift and a mask (from_word).  The same instruction
+// serves every dtype, so a kernel reading columns whose dtypes are known only
+// at run time needs no branch and keeps all its loads in flight together.
+// The aligned word lies in the element's own page, so it is always readable;
+// its other bytes are dropped.
+__device__ __forceinline__ uint64_t word_of(const void *p, int lg, int64_t i) {
+    const char *e = static_cast<const char *>(p) + (i << lg);
+    return *reinterpret_cast<const uint64_t *>(e - (reinterpret_cast<uintptr_t>(e) & 7));
+}
+__device__ __forceinline__ uint64_t from_word(uint64_t w, const void *p, int lg, int64_t i) {
+    const uint64_t mis = (reinterpret_cast<uintptr_t>(p) + (uint64_t(i) << lg)) & 7;
+    const uint64_t v = w >> (mis * 8);
+    return lg == 3 ? v : v & ((uint64_t(1) << (8 << lg)) - 1);
+}
+__device__ __forceinline__ uint64_t load_word(const void *p, int lg, int64_t i) {
+    return from_word(word_of(p, lg, i), p, lg, i);
+}
+
 // N elements of one column at valid positions idx[], zero-extended to 64
-// bits.  The dtype test is taken once for all N, so the N loads are in flight
-// together (a test per element makes the compiler wait after each load).
+// bits, all N loads issued before any result is used.
 template <int N, class I>
 __device__ __forceinline__ void load_raw(const void *p, int dtype, const I (&idx)[N],
                                          uint64_t (&out)[N]) {
-    if (dtype == TQP_INT8) {
-        const uint8_t *q = static_cast<const uint8_t *>(p);
+    const int lg = dtype_lg(dtype);
 #pragma unroll
-        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
-    } else if (dtype == TQP_INT32) {
-        const uint32_t *q = static_cast<const uint32_t *>(p);
+    for (int r = 0; r < N; r++) out[r] = word_of(p, lg, int64_t(idx[r]));
 #pragma unroll
-        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
-    } else {
-        const uint64_t *q = static_cast<const uint64_t *>(p);
-#pragma unroll
-        for (int r = 0; r < N; r++) out[r] = q[idx[r]];
-    }
+    for (int r = 0; r < N; r++) out[r] = from_word(out[r], p, lg, int64_t(idx[r]));
 }
 // The signed value of a zero-extended element of the given dtype.
 __device__ __forceinline__ int64_t sext_of(uint64_t v, int dtype) {
@@ -348,7 +366,8 @@ __device__ __forceinline__ void pack_keys(const PackArgs &a, const int64_t (&idx
             uint64_t rr[R];
 #pragma unroll
             for (int r = 0; r < R; r++) li[r] = idx[r] < cnt ? idx[r] : 0;
-            load_raw<R>(a.rows[t], TQP_INT32, li, rr);
+#pragma unroll
+            for (int r = 0; r < R; r++) rr[r] = uint32_t(a.rows[t][li[r]]);
 #pragma unroll
             for (int r = 0; r < R; r++) row[r] = idx[r] < cnt ? int64_t(int32_t(uint32_t(rr[r]))) : -1;
         } else {

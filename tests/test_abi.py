@@ -46,3 +46,27 @@ def test_argument_errors_are_reported_without_a_gpu():
     assert L.tqp_filter_workspace_bytes(1 << 20) > 0
     assert L.tqp_sort_workspace_bytes(1 << 20, 2, 0) > 8 * (1 << 20)
     assert L.tqp_sort_workspace_bytes(1 << 20, 2, 17) > L.tqp_sort_workspace_bytes(1 << 20, 2, 0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
+def test_unaligned_columns_are_rejected_without_a_gpu():
+    """Columns of run-time dtype are read as aligned 8-byte words, so a column
+    not aligned to its element size is an argument error (the fake addresses
+    below are never dereferenced: validation fails first)."""
+    import paper_2209_04579_amd as tqp
+    L = tqp.lib()
+    # dtype codes of the C header: int32 = 2, int64 = 3
+    key = tqp.Col(0x10000, 10, 2, 0)
+    out = tqp.Col(0x20000, 10, 2, 0)
+    pin = (tqp.Col * 1)(tqp.Col(0x30004, 10, 3, 0))
+    pout = (tqp.Col * 1)(tqp.Col(0x40000, 10, 3, 0))
+    rc = L.tqp_sort(ctypes.byref(key), None, 10, None, 8, 0, ctypes.byref(out), None, pin, pout,
+                    1, None, 0, None)
+    assert rc == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
+    rc = L.tqp_sort(ctypes.byref(key), ctypes.c_void_p(0x50002), 10, None, 8, 0,
+                    ctypes.byref(out), ctypes.c_void_p(0x60000), None, None, 0, None, 0, None)
+    assert rc == tqp.TQP_EINVAL and b"aligned" in L.tqp_last_error()
+    term = (tqp.KeyTerm * 1)(tqp.KeyTerm(tqp.Col(0x70002, 10, 2, 0), None, 0, 1))
+    out64 = tqp.Col(0x80000, 10, 3, 0)
+    rc = L.tqp_pack_key(term, 1, 10, None, ctypes.byref(out64), None)
+    assert rc == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
