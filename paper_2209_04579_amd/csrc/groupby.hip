@@ -58,45 +58,47 @@ __device__ __forceinline__ uint64_t tag_word(uint64_t tag, uint32_t half) {
     return (tag << 62) | half;
 }
 
-__device__ __forceinline__ void publish_multi(uint64_t *rec, uint64_t tag, int nv,
-                                              const int64_t (&v)[kNV]) {
-    for (int k = 0; k < nv; k++) {
+template <int NV>
+__device__ __forceinline__ void publish_multi(uint64_t *rec, uint64_t tag, const int64_t (&v)[NV]) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
         st_relaxed(&rec[2 * k], tag_word(tag, uint32_t(uint64_t(v[k]))));
         st_relaxed(&rec[2 * k + 1], tag_word(tag, uint32_t(uint64_t(v[k]) >> 32)));
     }
 }
 
-__device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile, int nv,
-                                               const int64_t (&agg)[kNV], int64_t (&excl)[kNV]) {
+// Look-back over NV values (records of 2 * kNV words per tile; the first
+// 2 * NV are used), one predecessor per lane per round trip.
+template <int NV>
+__device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile,
+                                               const int64_t (&agg)[NV], int64_t (&excl)[NV]) {
 #pragma unroll
-    for (int k = 0; k < kNV; k++) excl[k] = 0;
+    for (int k = 0; k < NV; k++) excl[k] = 0;
     if (tile == 0) {
-        if (lane_id() == 0) publish_multi(status, 2, nv, agg);
+        if (lane_id() == 0) publish_multi<NV>(status, 2, agg);
         return;
     }
-    if (lane_id() == 0) publish_multi(status + tile * 2 * kNV, 1, nv, agg);
+    if (lane_id() == 0) publish_multi<NV>(status + tile * 2 * kNV, 1, agg);
     int64_t base = tile - 1;
     while (true) {
         const int64_t idx = base - lane_id();
         uint64_t tag = 2;
-        int64_t v[kNV];
+        int64_t v[NV];
 #pragma unroll
-        for (int k = 0; k < kNV; k++) v[k] = 0;
+        for (int k = 0; k < NV; k++) v[k] = 0;
         if (idx >= 0) {
             const uint64_t *rec = status + idx * 2 * kNV;
             while (true) {
                 // all words are read independently (no early exit), then checked
-                uint64_t w[2 * kNV];
+                uint64_t w[2 * NV];
 #pragma unroll
-                for (int k = 0; k < 2 * kNV; k++) w[k] = k < 2 * nv ? ld_relaxed(&rec[k]) : 0;
+                for (int k = 0; k < 2 * NV; k++) w[k] = ld_relaxed(&rec[k]);
                 const uint64_t first = w[0] >> 62;
                 bool ok = first != 0;
 #pragma unroll
-                for (int k = 0; k < kNV; k++) {
-                    if (k < nv) {
-                        ok = ok && (w[2 * k] >> 62) == first && (w[2 * k + 1] >> 62) == first;
-                        v[k] = int64_t((w[2 * k + 1] << 32) | (w[2 * k] & 0xffffffffu));
-                    }
+                for (int k = 0; k < NV; k++) {
+                    ok = ok && (w[2 * k] >> 62) == first && (w[2 * k + 1] >> 62) == first;
+                    v[k] = int64_t((w[2 * k + 1] << 32) | (w[2 * k] & 0xffffffffu));
                 }
                 if (ok) {
                     tag = first;
@@ -108,7 +110,7 @@ __device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile, i
         const uint64_t inc = ballot(tag == 2);
         const int stop = inc ? (__ffsll(static_cast<long long>(inc)) - 1) : (kWave - 1);
 #pragma unroll
-        for (int k = 0; k < kNV; k++) {
+        for (int k = 0; k < NV; k++) {
             const int64_t x = lane_id() <= stop ? v[k] : 0;
             excl[k] += wave_sum(x);
         }
@@ -116,10 +118,10 @@ __device__ __forceinline__ void lookback_multi(uint64_t *status, int64_t tile, i
         base -= kWave;
     }
     if (lane_id() == 0) {
-        int64_t incl[kNV];
+        int64_t incl[NV];
 #pragma unroll
-        for (int k = 0; k < kNV; k++) incl[k] = int64_t(uint64_t(excl[k]) + uint64_t(agg[k]));
-        publish_multi(status + tile * 2 * kNV, 2, nv, incl);
+        for (int k = 0; k < NV; k++) incl[k] = int64_t(uint64_t(excl[k]) + uint64_t(agg[k]));
+        publish_multi<NV>(status + tile * 2 * kNV, 2, incl);
     }
 }
 
@@ -169,18 +171,49 @@ __device__ __forceinline__ void load_rows(const int32_t *val_rows, const int64_t
     }
 }
 
+// Exclusive prefix sums of N values per thread across the block, with one
+// pair of barriers for all N.  lds holds (NT / 64) * N entries.
+template <int NT, int N>
+__device__ __forceinline__ void block_excl_scan_n(const int64_t (&v)[N], int64_t (&ex)[N],
+                                                  int64_t (&tot)[N], int64_t *lds) {
+    constexpr int NW = NT / kWave;
+    int64_t inc[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) inc[k] = wave_incl_scan(v[k]);
+    const int w = wave_id();
+    if (lane_id() == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < N; k++) lds[w * N + k] = inc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        int64_t pre = 0, t = 0;
+#pragma unroll
+        for (int i = 0; i < NW; i++) {
+            const int64_t x = lds[i * N + k];
+            if (i < w) pre += x;
+            t += x;
+        }
+        ex[k] = pre + inc[k] - v[k];
+        tot[k] = t;
+    }
+    __syncthreads();
+}
+
 // One single-pass scan over sorted keys for NAGG aggregates: head count and
 // running sums carried across tiles by look-back; run ends write the running
 // sums, run heads write the key.  Every value is loaded once, into registers.
 template <class K, int NAGG>
-__global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, int64_t n,
+__global__ __launch_bounds__(kGbNT, 4) void k_gb_scan(const K *__restrict__ keys, int64_t n,
                                                    const int64_t *d_n, AggArgs a,
                                                    K *__restrict__ out_key, int64_t key_cap,
                                                    int64_t *__restrict__ ends /* [NAGG][n] */,
                                                    int64_t ends_stride, int64_t *d_ngroups,
                                                    uint32_t *ticket, uint64_t *status) {
     __shared__ int64_t s_tile;
-    __shared__ int64_t s_scan[kGbNT / kWave];
+    __shared__ int64_t s_scan[(kGbNT / kWave) * (NAGG + 1)];
+    __shared__ int64_t s_term[NAGG * kGbIPT * kGbNT];   // [NAGG][kGbIPT][kGbNT]
     __shared__ int64_t s_excl[kNV];
     const int64_t cnt = count_of(d_n, n);
     const int64_t ntiles = ceil_div(cnt, kGbTile);
@@ -260,9 +293,14 @@ __global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, i
             }
         }
     }
-    int64_t agg[kNV], excl[kNV], tot[kNV];
+    // the terms wait in LDS (conflict-free: row r of thread t at r * kGbNT + t)
+    // while the block scan and the look-back run, so they hold no registers
 #pragma unroll
-    for (int k = 0; k < kNV; k++) agg[k] = 0;
+    for (int g = 0; g < NAGG; g++) {
+#pragma unroll
+        for (int r = 0; r < R; r++) s_term[(g * R + r) * kGbNT + threadIdx.x] = term[g][r];
+    }
+    int64_t agg[NAGG + 1], excl[NAGG + 1], tot[NAGG + 1];
     agg[0] = __popc(head);
 #pragma unroll
     for (int g = 0; g < NAGG; g++) {
@@ -271,11 +309,10 @@ __global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, i
         for (int r = 0; r < R; r++) s += uint64_t(term[g][r]);
         agg[g + 1] = int64_t(s);
     }
-#pragma unroll
-    for (int k = 0; k <= NAGG; k++) excl[k] = block_excl_scan<kGbNT>(agg[k], &tot[k], s_scan);
+    block_excl_scan_n<kGbNT, NAGG + 1>(agg, excl, tot, s_scan);
     if (wave_id() == 0) {
-        int64_t pre[kNV];
-        lookback_multi(status, tile, NAGG + 1, tot, pre);
+        int64_t pre[NAGG + 1];
+        lookback_multi<NAGG + 1>(status, tile, tot, pre);
         if (lane_id() == 0)
             for (int k = 0; k <= NAGG; k++) s_excl[k] = pre[k];
     }
@@ -293,7 +330,7 @@ __global__ __launch_bounds__(kGbNT) void k_gb_scan(const K *__restrict__ keys, i
                 hc++;
             }
 #pragma unroll
-            for (int g = 0; g < NAGG; g++) run[g] += uint64_t(term[g][r]);
+            for (int g = 0; g < NAGG; g++) run[g] += uint64_t(s_term[(g * R + r) * kGbNT + threadIdx.x]);
             if (end & (1u << r)) {
 #pragma unroll
                 for (int g = 0; g < NAGG; g++) ends[g * ends_stride + (hc - 1)] = int64_t(run[g]);

@@ -375,9 +375,10 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
 }
 
-// Digit counts of every tile for one pass (the tiles k_onesweep<..., false>
-// will take): counts[digit * tstride + tile].  Tiles past the actual count
-// write zeros, so the scan may run over the whole capacity.
+// Digit counts of every occupied tile for one pass (the tiles
+// k_onesweep<..., false> will take): counts[digit * tstride + tile].  Lanes
+// sharing the first valid lane's digit are counted with one ballot (skewed
+// keys otherwise serialize on one LDS address).
 template <class K, class Ord>
 __global__ __launch_bounds__(kSortNT) void k_radix_tilecount(const K *__restrict__ keys, int64_t n,
                                                              const int64_t *d_n, Ord ord, int shift,
@@ -387,20 +388,29 @@ __global__ __launch_bounds__(kSortNT) void k_radix_tilecount(const K *__restrict
     const uint32_t nbins = 1u << dbits;
     const int64_t cnt = count_of(d_n, n);
     const int64_t tile = blockIdx.x;
-    const int tid = threadIdx.x, w = wave_id();
+    if (tile * kSortTile >= cnt) return;
+    const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
     for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_c[0][0])[i] = 0;
-    __syncthreads();
     const int64_t wbase = tile * kSortTile + int64_t(w) * (kWave * kSortIPT);
     K key[kSortIPT];
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
-        const int64_t idx = wbase + k * kWave + lane_id();
-        key[k] = idx < cnt ? keys[idx] : K(0);
+        const int64_t idx = wbase + k * kWave + lane;
+        key[k] = keys[idx < cnt ? idx : cnt - 1];
     }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
-        const int64_t idx = wbase + k * kWave + lane_id();
-        if (idx < cnt) atomicAdd(&s_c[w][uint32_t(ord(key[k]) >> shift) & (nbins - 1)], 1u);
+        const bool valid = wbase + k * kWave + lane < cnt;
+        const uint64_t vm = ballot(valid);
+        if (vm == 0) continue;
+        const int first = __builtin_ctzll(vm);
+        const uint32_t d = uint32_t(ord(key[k]) >> shift) & (nbins - 1);
+        const uint32_t f = uint32_t(__builtin_amdgcn_readlane(int(d), first));
+        const bool same = valid && d == f;
+        const uint64_t sm = ballot(same);
+        if (lane == first) atomicAdd(&s_c[w][f], uint32_t(__popcll(sm)));
+        else if (valid && !same) atomicAdd(&s_c[w][d], 1u);
     }
     __syncthreads();
     for (int d = tid; d < int(nbins); d += kSortNT) {
@@ -411,16 +421,20 @@ __global__ __launch_bounds__(kSortNT) void k_radix_tilecount(const K *__restrict
     }
 }
 
-// One workgroup per digit: turns that digit's row of tile counts into the
-// global position of each tile's run, in place: the digit's start (counts
-// of all smaller digits, from the pass histogram) plus the counts of the
-// tiles before it.
+// One workgroup per digit: turns that digit's row of tile counts (occupied
+// tiles only) into the global position of each tile's run, in place: the
+// digit's start (counts of all smaller digits, from the pass histogram) plus
+// the counts of the tiles before it.  Each thread scans kScanIPT consecutive
+// tiles.
 constexpr int kScanNT = 1024;
+constexpr int kScanIPT = 8;
 static __global__ __launch_bounds__(kScanNT) void k_radix_tilescan(uint32_t *counts, int64_t tstride,
-                                                            const uint32_t *__restrict__ ghist) {
+                                                            const uint32_t *__restrict__ ghist,
+                                                            int64_t n, const int64_t *d_n) {
     __shared__ uint32_t s_scan[kScanNT / kWave];
     __shared__ uint32_t s_base;
     const int d = blockIdx.x;
+    const int64_t ntiles = ceil_div(count_of(d_n, n), kSortTile);
     if (threadIdx.x == 0) {
         uint32_t b = 0;
         for (int e = 0; e < d; e++) b += ghist[e];
@@ -429,12 +443,21 @@ static __global__ __launch_bounds__(kScanNT) void k_radix_tilescan(uint32_t *cou
     __syncthreads();
     uint32_t carry = s_base;
     uint32_t *row = counts + int64_t(d) * tstride;
-    for (int64_t t0 = 0; t0 < tstride; t0 += kScanNT) {
-        const int64_t t = t0 + threadIdx.x;
-        const uint32_t v = t < tstride ? row[t] : 0u;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += int64_t(kScanNT) * kScanIPT) {
+        const int64_t tb = t0 + int64_t(threadIdx.x) * kScanIPT;
+        uint32_t v[kScanIPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanIPT; j++) {
+            v[j] = tb + j < ntiles ? row[tb + j] : 0u;
+            sum += v[j];
+        }
         uint32_t total;
-        const uint32_t ex = block_excl_scan<kScanNT>(v, &total, s_scan);
-        if (t < tstride) row[t] = carry + ex;
+        uint32_t ex = carry + block_excl_scan<kScanNT>(sum, &total, s_scan);
+#pragma unroll
+        for (int j = 0; j < kScanIPT; j++) {
+            if (tb + j < ntiles) row[tb + j] = ex;
+            ex += v[j];
+        }
         carry += total;
     }
 }
@@ -601,7 +624,7 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
                        src_k, n, d_n, ord, shift, dbits, tc, ntiles);
             if ((rc = check_launch("radix tile counts"))) return rc;
             TQP_LAUNCH("radix_tilescan", k_radix_tilescan, dim3(1u << dbits), dim3(kScanNT), 0, s, tc,
-                       ntiles, gh);
+                       ntiles, gh, n, d_n);
             if ((rc = check_launch("radix tile scan"))) return rc;
             rc = launch_cols<K, Ord, false>(sc.npay, sc.rows_out != nullptr, grid_all, s, src_k, dk, x, n,
                                             d_n, ord, shift, dbits, gh, tc, nullptr, ntiles);
