@@ -44,7 +44,7 @@ constexpr int kLookAhead = 4;             // predecessor statuses fetched per ro
 // not depend on the placement; every counter's groups are taken in order by
 // resident workgroups, so the look-back always finds its predecessors.)
 constexpr int kXcds = 8;
-constexpr int kTileGroup = 16;
+constexpr int kTileGroup = 8;
 constexpr uint32_t kSFlagAgg = 1u << 30;
 constexpr uint32_t kSFlagInc = 2u << 30;
 constexpr uint32_t kSValMask = (1u << 30) - 1;
@@ -178,6 +178,7 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     __shared__ uint32_t s_local[kBins];      // tile-local start of each digit run
     __shared__ int64_t s_gbase[kBins];       // global start of the run minus its local start
     __shared__ uint64_t s_stage[kSortTile];  // one column of the tile, in digit order
+    __shared__ uint64_t s_stage2[kSortTile]; // the next column (staging alternates)
     __shared__ uint8_t s_dig[kSortTile];     // digit of each sorted tile position
     __shared__ uint32_t s_scan[kSortNW];
     __shared__ int64_t s_tile;
@@ -330,7 +331,10 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     flush_stage<K>(s_stage, gpos, keys_out);
 
     // Moved columns one after another: column p + 1 is loaded while column p
-    // is staged and written, so at most two are held in registers.
+    // is staged and written, so at most two are held in registers.  Staging
+    // alternates between two buffers, so one barrier per column suffices: the
+    // barrier after staging column p also ends every thread's writes of
+    // column p - 1, whose buffer column p + 1 then reuses.
 #pragma unroll
     for (int p = 0; p < NC; p++) {
         uint64_t nxt[kSortIPT];
@@ -346,25 +350,25 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
             for (int k = 0; k < kSortIPT; k++)
                 cur[k] = !src ? uint64_t(lidx[k]) : p == NPAY ? cur[k] : from_word(cur[k], src, lg, lidx[k]);
         }
-        __syncthreads();
+        uint64_t *buf = (p & 1) ? s_stage : s_stage2;
         if (dt == TQP_INT8) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(s_stage)[pd[k] & 0xffffu] = int8_t(cur[k]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int8_t *>(buf)[pd[k] & 0xffffu] = int8_t(cur[k]);
             __syncthreads();
-            flush_stage<int8_t>(s_stage, gpos, static_cast<int8_t *>(c.pout[p]));
+            flush_stage<int8_t>(buf, gpos, static_cast<int8_t *>(c.pout[p]));
         } else if (dt == TQP_INT32) {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(s_stage)[pd[k] & 0xffffu] = int32_t(cur[k]);
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<int32_t *>(buf)[pd[k] & 0xffffu] = int32_t(cur[k]);
             __syncthreads();
-            flush_stage<int32_t>(s_stage, gpos, static_cast<int32_t *>(c.pout[p]));
+            flush_stage<int32_t>(buf, gpos, static_cast<int32_t *>(c.pout[p]));
         } else {
 #pragma unroll
             for (int k = 0; k < kSortIPT; k++)
-                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(s_stage)[pd[k] & 0xffffu] = cur[k];
+                if ((pd[k] >> 16) < kBins) reinterpret_cast<uint64_t *>(buf)[pd[k] & 0xffffu] = cur[k];
             __syncthreads();
-            flush_stage<int64_t>(s_stage, gpos, static_cast<int64_t *>(c.pout[p]));
+            flush_stage<int64_t>(buf, gpos, static_cast<int64_t *>(c.pout[p]));
         }
         if (p + 1 < NC) {
 #pragma unroll
