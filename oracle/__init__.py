@@ -69,6 +69,11 @@ def lib():
         _lib.orc_q2.argtypes = [i64, vp, vp, vp, vp, vp, i64, i64, vp, vp,
                                 i64, vp, vp, vp, vp, vp,
                                 i64, vp, vp, vp, vp, vp]
+        _lib.orc_filter_sum.restype = None
+        _lib.orc_filter_sum.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, i32, vp, i32, vp, vp,
+                                        vp]
+        _lib.orc_q6.restype = None
+        _lib.orc_q6.argtypes = [i64, vp, vp, vp, vp, i64, i64, i64, i64, i64, vp, vp, vp]
         _lib.orc_q3.restype = i64
         _lib.orc_q3.argtypes = [i64, vp, vp, vp, vp, vp,
                                 i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
@@ -105,6 +110,42 @@ def filter_rows(cols, preds) -> np.ndarray:
     ptrs = _ptr_array(cols)
     cnt = lib().orc_filter(n, ptrs, _p(dts), len(preds), _p(pc), _p(po), _p(pl), _p(out))
     return out[:cnt].copy()
+
+
+def filter_sum(cols, preds, a=None, b=None):
+    """WHERE + aggregate over the kept rows, nothing materialised.
+
+    cols/preds as in filter_rows; a, b: value arrays (or None).  Returns
+    (SUM(a*b) or SUM(a) mod 2**64 as int, COUNT, exact) where exact says the
+    true sum stayed inside int64.
+    """
+    cols = [_c(c) for c in cols]
+    n = len(cols[0]) if cols else (len(a) if a is not None else 0)
+    dts = np.array([DT[c.dtype] for c in cols] or [0], dtype=np.int32)
+    pc = np.array([p[0] for p in preds] or [0], dtype=np.int32)
+    po = np.array([OPS[p[1]] for p in preds] or [0], dtype=np.int32)
+    pl = np.array([int(p[2]) for p in preds] or [0], dtype=np.int64)
+    a = None if a is None else _c(a)
+    b = None if b is None else _c(b)
+    s, c, ex = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0)
+    lib().orc_filter_sum(n, _ptr_array(cols), _p(dts), len(preds), _p(pc), _p(po), _p(pl),
+                         None if a is None else _p(a), 0 if a is None else DT[a.dtype],
+                         None if b is None else _p(b), 0 if b is None else DT[b.dtype],
+                         ctypes.byref(s), ctypes.byref(c), ctypes.byref(ex))
+    return int(s.value), int(c.value), bool(ex.value)
+
+
+def q6(cfg: dict):
+    """Q6-shaped scan: SUM(price * discount), COUNT(*) under the date,
+    discount and quantity conjunction (see orc_q6)."""
+    t = cfg["items"]
+    ship, disc = _c(t["ship"], np.int64), _c(t["discount"], np.int8)
+    qty, price = _c(t["quantity"], np.int32), _c(t["price"], np.int64)
+    s, c, ex = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0)
+    lib().orc_q6(len(ship), _p(ship), _p(disc), _p(qty), _p(price), cfg["ship_lo"],
+                 cfg["ship_hi"], cfg["disc_lo"], cfg["disc_hi"], cfg["qty_cut"],
+                 ctypes.byref(s), ctypes.byref(c), ctypes.byref(ex))
+    return {"sum": int(s.value), "count": int(c.value), "exact": bool(ex.value)}
 
 
 def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:

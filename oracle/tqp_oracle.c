@@ -579,3 +579,63 @@ int64_t orc_q3(int64_t nf, const int32_t *fk1, const int32_t *fk2,
     dimindex_free(&d1); dimindex_free(&d2); dimindex_free(&d3);
     return ng;
 }
+
+/* ------------------------------------------------------------------------
+ * WHERE + aggregate without materialising the kept rows (the shape of TPC-H
+ * Q6, Section 2.3: filters over columns of different types, then one
+ * aggregate): over the rows where every predicate holds,
+ *   *sum   = SUM(a[i] * b[i])  (b NULL: SUM(a[i]); a NULL: 0), mod 2^64,
+ *   *count = COUNT(*).
+ * *exact receives 1 when the exact sum (kept in __int128, the products too)
+ * stays inside int64, 0 otherwise.
+ * ---------------------------------------------------------------------- */
+void orc_filter_sum(int64_t n, const void *const *cols, const int *dtypes,
+                    int npred, const int *pcol, const int *pop,
+                    const int64_t *plit, const void *a, int adt,
+                    const void *b, int bdt, int64_t *sum, int64_t *count,
+                    int *exact)
+{
+    __int128 s = 0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int keep = 1;
+        for (int p = 0; p < npred; p++)
+            if (!holds(value_at(cols[pcol[p]], dtypes[pcol[p]], i), pop[p], plit[p]))
+                keep = 0;
+        if (!keep) continue;
+        cnt++;
+        if (a) {
+            __int128 t = value_at(a, adt, i);
+            if (b) t *= value_at(b, bdt, i);
+            s += t;
+        }
+    }
+    *sum = (int64_t)(uint64_t)(unsigned __int128)s;
+    *count = cnt;
+    *exact = s >= INT64_MIN && s <= INT64_MAX;
+}
+
+/* Q6-shaped query, written directly:
+ *   SELECT SUM(price * discount), COUNT(*) FROM items
+ *   WHERE ship >= ship_lo AND ship < ship_hi
+ *     AND discount >= disc_lo AND discount <= disc_hi AND quantity < qty_cut
+ * ship: int64 epoch nanoseconds; discount: int8 hundredths; quantity: int32;
+ * price: int64 cents.  The sum is exact (asserted by *exact as above). */
+void orc_q6(int64_t n, const int64_t *ship, const int8_t *discount,
+            const int32_t *quantity, const int64_t *price, int64_t ship_lo,
+            int64_t ship_hi, int64_t disc_lo, int64_t disc_hi, int64_t qty_cut,
+            int64_t *sum, int64_t *count, int *exact)
+{
+    __int128 s = 0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (ship[i] < ship_lo || ship[i] >= ship_hi) continue;
+        if (discount[i] < disc_lo || discount[i] > disc_hi) continue;
+        if (!(quantity[i] < qty_cut)) continue;
+        s += (__int128)price[i] * discount[i];
+        cnt++;
+    }
+    *sum = (int64_t)(uint64_t)(unsigned __int128)s;
+    *count = cnt;
+    *exact = s >= INT64_MIN && s <= INT64_MAX;
+}

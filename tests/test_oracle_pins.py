@@ -331,3 +331,79 @@ def test_q3_matches_numpy_statement():
     assert np.array_equal(r["key"], nk)
     assert np.array_equal(r["sum_qp"], sp)
     assert np.array_equal(r["count"], np.bincount(ix).astype(np.int64))
+
+
+# -------------------------------------------- filter + aggregate (Q6 shape) ----
+
+def wrap64(x: int) -> int:
+    return (x + 2 ** 63) % 2 ** 64 - 2 ** 63
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_sum_brute_force(seed):
+    """Python integers over every kept row: the product, the wrap, the count."""
+    n = 257 + 61 * seed
+    cols = rng_cols(seed, n, dom=20)
+    a = dg.uniform_int(seed, 7, n, -2 ** 31, 2 ** 31, np.int64) * 4_000_000_007
+    b = dg.uniform_int(seed, 8, n, -128, 128, np.int8)
+    preds = [((seed + q) % 3, list(OPS)[(seed * 5 + q) % 6], int(cols[(seed + q) % 3][q * 7 % n]))
+             for q in range(1 + seed % 3)]
+    keep = [i for i in range(n) if all(OPS[op](int(cols[c][i]), lit) for c, op, lit in preds)]
+    exact = sum(int(a[i]) * int(b[i]) for i in keep)
+    s, c, ex = oracle.filter_sum(cols, preds, a, b)
+    assert c == len(keep) and s == wrap64(exact) and ex == (I64_MIN <= exact <= I64_MAX)
+    s1, c1, _ = oracle.filter_sum(cols, preds, a)
+    assert c1 == len(keep) and s1 == wrap64(sum(int(a[i]) for i in keep))
+    assert oracle.filter_sum(cols, preds) == (0, len(keep), True)
+
+
+def test_filter_sum_matches_numpy_and_edge_cases():
+    n = 5000
+    cols = rng_cols(11, n, dom=100)
+    a = dg.uniform_int(11, 9, n, 0, 1 << 30, np.int64)
+    b = dg.uniform_int(11, 10, n, -5, 6, np.int32)
+    preds = [(0, ">=", -40), (1, "<", 60), (2, "!=", 3)]
+    m = (cols[0] >= -40) & (cols[1] < 60) & (cols[2] != 3)
+    s, c, ex = oracle.filter_sum(cols, preds, a, b)
+    assert c == int(m.sum()) and s == int(np.sum(a[m] * b[m])) and ex
+    # no predicate keeps every row; an impossible one keeps none
+    assert oracle.filter_sum(cols, [], a, b)[:2] == (int(np.sum(a * b)), n)
+    assert oracle.filter_sum(cols, [(0, ">", 1000)], a, b) == (0, 0, True)
+    e = [np.zeros(0, np.int32)]
+    assert oracle.filter_sum(e, [(0, "<", 5)], np.zeros(0, np.int64)) == (0, 0, True)
+    # the sum leaves int64: wrapped mod 2**64 and flagged
+    big = np.full(4, I64_MAX // 2 + 7, np.int64)
+    s, c, ex = oracle.filter_sum([np.arange(4, dtype=np.int32)], [], big, np.full(4, 3, np.int8))
+    assert c == 4 and not ex and s == wrap64(4 * 3 * (I64_MAX // 2 + 7))
+
+
+@pytest.mark.parametrize("n", [0, 1, 999, 20_000])
+def test_q6_whole_query_equals_generic_filter_sum(n):
+    """The directly written Q6 loop against the generic conjunction (the same
+    five comparisons as predicates) and a numpy statement of the query."""
+    cfg = dg.config_q6(3, n)
+    t = cfg["items"]
+    got = oracle.q6(cfg)
+    preds = [(0, ">=", cfg["ship_lo"]), (0, "<", cfg["ship_hi"]), (1, ">=", cfg["disc_lo"]),
+             (1, "<=", cfg["disc_hi"]), (2, "<", cfg["qty_cut"])]
+    s, c, ex = oracle.filter_sum([t["ship"], t["discount"], t["quantity"]], preds, t["price"],
+                                 t["discount"])
+    assert (got["sum"], got["count"], got["exact"]) == (s, c, ex) and ex
+    m = ((t["ship"] >= cfg["ship_lo"]) & (t["ship"] < cfg["ship_hi"]) & (t["discount"] >= 5)
+         & (t["discount"] <= 7) & (t["quantity"] < 24))
+    assert c == int(m.sum())
+    assert s == int(np.sum(t["price"][m] * t["discount"][m].astype(np.int64)))
+
+
+def test_q6_table_shape():
+    """Timestamps are whole seconds inside the seven-year window; the kept
+    fraction is near the product of the three selectivities."""
+    cfg = dg.config_q6(0, 200_000)
+    t = cfg["items"]
+    ns_day = 86_400 * 10 ** 9
+    assert t["ship"].dtype == np.int64 and (t["ship"] % 10 ** 9 == 0).all()
+    assert t["ship"].min() >= 8035 * ns_day and t["ship"].max() < (8035 + 2557) * ns_day
+    assert t["discount"].min() == 0 and t["discount"].max() == 10
+    frac = oracle.q6(cfg)["count"] / 200_000
+    expect = 365 / 2557 * 3 / 11 * 23 / 50
+    assert abs(frac - expect) < 0.1 * expect

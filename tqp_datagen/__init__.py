@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "splitmix64", "raw_u64", "uniform_int", "uniform_float", "zipf_ranks",
     "permutation", "config1", "config2", "config3", "config4", "config5",
-    "small_table", "DAY_DOMAIN",
+    "small_table", "DAY_DOMAIN", "config_q6", "Q6_BOUNDS",
 ]
 
 DAY_DOMAIN = 2557          # seven years of day numbers, [0, 2557)
@@ -165,6 +165,33 @@ def config3(seed: int = 0, n_fact: int = 600_000_000,
     pk3 = np.arange(n3, dtype=np.int32)
     d3 = {"pk": pk3, "attr": (4 * pk3).astype(np.int32)}
     return {"fact": fact, "d1": d1, "d2": d2, "d3": d3, "attr_cut": 20}
+
+
+# Q6-shaped scan: ship timestamps as int64 epoch nanoseconds (the paper keeps
+# dates as epoch-based integers, Section 2.1) over the same seven years
+# (1992-01-01 is day 8035 after 1970-01-01), discount in hundredths (int8),
+# quantity (int32), price in cents (int64).  The query keeps one year of
+# ship dates, discounts 0.05..0.07 and quantities below 24.
+_NS_PER_DAY = 86_400 * 1_000_000_000
+_DAY0 = 8035
+Q6_BOUNDS = {"ship_lo": 8766 * _NS_PER_DAY,      # 1994-01-01
+             "ship_hi": 9131 * _NS_PER_DAY,      # 1995-01-01
+             "disc_lo": 5, "disc_hi": 7, "qty_cut": 24}
+
+
+def config_q6(seed: int = 0, n: int = 60_000_000) -> dict:
+    """Q6-shaped table (TPC-H lineitem columns at scale factor 10 has 60M
+    rows): SUM(price * discount), COUNT(*) WHERE ship in [1994, 1995) AND
+    discount BETWEEN 5 AND 7 AND quantity < 24."""
+    day = uniform_int(seed, 1, n, 0, DAY_DOMAIN, np.int64)
+    sec = uniform_int(seed, 2, n, 0, 86_400, np.int64)
+    items = {
+        "ship": ((day + _DAY0) * 86_400 + sec) * 1_000_000_000,
+        "discount": uniform_int(seed, 3, n, 0, 11, np.int8),
+        "quantity": uniform_int(seed, 4, n, 1, 51, np.int32),
+        "price": uniform_int(seed, 5, n, 90_000, 10_494_951, np.int64),
+    }
+    return {"items": items, **Q6_BOUNDS}
 
 
 _C4_SCATTER = 0x2545F4914F6CDD1D   # odd multiplier: a bijection modulo 2**62

@@ -16,7 +16,7 @@ import math
 import numpy as np
 import torch
 
-from . import _C4_SCATTER, _MASK62, DAY_DOMAIN, _zipf_cdf, config5_params
+from . import _C4_SCATTER, _DAY0, _MASK62, DAY_DOMAIN, Q6_BOUNDS, _zipf_cdf, config5_params
 
 _G = np.uint64(0x9E3779B97F4A7C15).astype(np.int64).item()
 _M1 = np.uint64(0xBF58476D1CE4E5B9).astype(np.int64).item()
@@ -145,3 +145,16 @@ def config3(seed=0, n_fact=600_000_000, dims=(1_000_000, 100_000, 25), device="c
     pk3 = torch.arange(n3, dtype=torch.int32, device=device)
     d3 = {"pk": pk3, "attr": 4 * pk3}
     return {"fact": fact, "d1": d1, "d2": d2, "d3": d3, "attr_cut": 20}
+
+
+def config_q6(seed=0, n=60_000_000, device="cuda"):
+    """Q6-shaped table, bit-identical to the host generator's."""
+    day = uniform_int(seed, 1, n, 0, DAY_DOMAIN, device)
+    sec = uniform_int(seed, 2, n, 0, 86_400, device)
+    items = {
+        "ship": ((day + _DAY0) * 86_400 + sec) * 1_000_000_000,
+        "discount": uniform_int(seed, 3, n, 0, 11, device, torch.int8),
+        "quantity": uniform_int(seed, 4, n, 1, 51, device, torch.int32),
+        "price": uniform_int(seed, 5, n, 90_000, 10_494_951, device),
+    }
+    return {"items": items, **Q6_BOUNDS}
