@@ -312,10 +312,11 @@ def bench_learned(args, tqp, stream) -> dict:
 
 
 def bench_configs(args, tqp, stream) -> dict:
-    """Throughput of the other two star queries: the small one (1M fact rows,
-    launch-bound) and the three-dimension star (600M fact rows, drawn on the
-    GPU).  Their results are checked against the oracle by the test suite
-    (full-size cases included), not here."""
+    """Throughput of the other workloads: the small star query (1M fact rows,
+    launch-bound), the three-dimension star (600M fact rows, drawn on the
+    GPU) and the Q6-shaped scan (60M rows).  Their results are checked
+    against the oracle by the test suite (full-size cases included), not
+    here."""
     import torch
     import tqp_datagen as dg
     from tqp_datagen import device as dgd
@@ -345,8 +346,25 @@ def bench_configs(args, tqp, stream) -> dict:
                                 "SUM(qty*price), COUNT",
                     "ms": round(ms, 3), "rows_per_s": round(n3 / (ms * 1e-3), 1),
                     "pairs": got["pairs"], "groups": int(len(got["key"]))}
-    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
     del q3, c3
+    torch.cuda.empty_cache()
+    # Q6-shaped scan: 60M rows, five comparisons over int64 / int8 / int32
+    # columns, SUM(price * discount); one fused launch
+    from paper_2209_04579_amd.pipeline import Q6Scan
+    d6 = dgd.config_q6(args.seed, device="cuda")
+    q6 = Q6Scan(d6["items"], d6)
+    ms = _timed(q6.run, 20, stream)
+    got = q6.result()
+    n6 = q6.n
+    scan_bytes = n6 * (8 + 1 + 4 + 8)        # every referenced column read once
+    out["q6_scan"] = {"workload": "60M rows: ship int64 epoch-ns in one year, discount int8 "
+                                  "BETWEEN 5 AND 7, quantity int32 < 24; SUM(price * discount), "
+                                  "COUNT",
+                      "ms": round(ms, 4), "rows_per_s": round(n6 / (ms * 1e-3), 1),
+                      "scan_GBps": round(scan_bytes / (ms * 1e-3) / 1e9, 1),
+                      "count": got["count"]}
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    del q6, d6
     torch.cuda.empty_cache()
     return out
 

@@ -146,6 +146,22 @@ int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
                void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_filter_sum -- WHERE + aggregate without compaction (Section 2.3: TPC-H
+ * Q6 is four filters over columns of different types feeding one SUM).
+ * Over the rows of an n-row table (n = cols[0].len, every cols[c] of len n)
+ * where every predicate holds:
+ *   *d_sum   = SUM(a[i] * b[i])  (b NULL: SUM(a[i]); a NULL: 0), int64 two's
+ *              complement, i.e. exact modulo 2^64;
+ *   *d_count = COUNT(*).
+ * a and b, when given, hold >= n elements.  ncols in [1, 8]; npred in [0, 8]
+ * (none keeps every row).  d_sum and d_count are device int64s, overwritten.
+ * No workspace; nothing is synchronized.
+ * ---------------------------------------------------------------------- */
+int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
+                   const tqp_col *a, const tqp_col *b, int64_t *d_sum, int64_t *d_count,
+                   void *stream);
+
+/* ------------------------------------------------------------------------
  * tqp_gather -- out[i] = src[idx[i]] for i < count (Fig. 3's index_select).
  * src and dst share a dtype; dst->len >= n.  An index outside [0, src->len)
  * yields 0 instead of a read.

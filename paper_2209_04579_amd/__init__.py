@@ -91,6 +91,8 @@ def lib():
         L.tqp_version.restype = ctypes.c_char_p
         L.tqp_filter_workspace_bytes.restype = sz
         L.tqp_filter_workspace_bytes.argtypes = [i64]
+        L.tqp_filter_sum.restype = i32
+        L.tqp_filter_sum.argtypes = [P(Col), i32, P(Pred), i32, P(Col), P(Col), vp, vp, vp]
         L.tqp_filter.restype = i32
         L.tqp_filter.argtypes = [P(Col), i32, P(Pred), i32, P(Col), P(Col), i32, vp, vp,
                                  vp, sz, vp]
@@ -188,6 +190,17 @@ def filter_into(cols, preds, payload_in, payload_out, out_rows, d_count, ws, str
 
 def filter_workspace_bytes(n: int) -> int:
     return lib().tqp_filter_workspace_bytes(n)
+
+
+def filter_sum_into(cols, preds, d_sum, d_count, a=None, b=None, stream=None):
+    """Enqueues WHERE + SUM(a * b) (b None: SUM(a)) and COUNT(*) over the kept
+    rows into the device int64 scalars d_sum and d_count; nothing is
+    compacted.  preds: [(col_index, op, literal)], possibly empty."""
+    pr = (Pred * max(len(preds), 1))(*[Pred(c, OPS[op], int(lit)) for c, op, lit in preds])
+    _check(lib().tqp_filter_sum(_cols(cols), len(cols), pr, len(preds),
+                                None if a is None else ctypes.byref(_col(a)),
+                                None if b is None else ctypes.byref(_col(b)),
+                                _ptr(d_sum), _ptr(d_count), _stream(stream)))
 
 
 def filter(cols, preds, payload=(), want_rows=True):

@@ -72,6 +72,43 @@ __device__ __forceinline__ void load16(const void *p, int dt, int64_t row0, int6
     }
 }
 
+// Loads 8 consecutive elements starting at row0 (sign-extended to int64).
+__device__ __forceinline__ void load8(const void *p, int dt, int64_t row0, int64_t n, bool vec,
+                                      int64_t (&v)[8]) {
+    if (vec && row0 + 8 <= n) {
+        if (dt == TQP_INT8) {
+            int2 x = *reinterpret_cast<const int2 *>(static_cast<const int8_t *>(p) + row0);
+            const int w[2] = {x.x, x.y};
+#pragma unroll
+            for (int r = 0; r < 8; r++)
+                v[r] = static_cast<int8_t>(static_cast<uint32_t>(w[r >> 2]) >> (8 * (r & 3)));
+        } else if (dt == TQP_INT32) {
+            const int4 *q = reinterpret_cast<const int4 *>(static_cast<const int32_t *>(p) + row0);
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                int4 x = q[k];
+                v[4 * k + 0] = x.x;
+                v[4 * k + 1] = x.y;
+                v[4 * k + 2] = x.z;
+                v[4 * k + 3] = x.w;
+            }
+        } else {
+            const longlong2 *q =
+                reinterpret_cast<const longlong2 *>(static_cast<const int64_t *>(p) + row0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                longlong2 x = q[k];
+                v[2 * k + 0] = x.x;
+                v[2 * k + 1] = x.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; r++)
+            v[r] = (row0 + r < n) ? load_any(p, dt, row0 + r) : 0;
+    }
+}
+
 __device__ __forceinline__ bool cmp_holds(int64_t v, int op, int64_t lit) {
     switch (op) {
     case TQP_LT: return v < lit;
@@ -179,6 +216,101 @@ __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
     }
 }
 
+// WHERE + aggregate without compaction: the predicate pass of k_filter (8
+// consecutive rows per thread here, which halves the registers a column
+// takes and doubles the loads in flight), then SUM(a * b) and COUNT over the
+// kept rows.  a and b are read only by threads holding a kept row, so at low
+// selectivity most of their cache lines are never fetched.  Partial sums are reduced per
+// workgroup and added with one device atomic each; int64 addition wraps
+// modulo 2^64, so every order gives the same bytes.
+struct FilterSumArgs {
+    const void *pcol[kMaxPred];
+    int64_t plit[kMaxPred];
+    int32_t pdt[kMaxPred];
+    int32_t pop[kMaxPred];
+    int32_t pcolid[kMaxPred];
+    int32_t npred;
+    int32_t vec;
+    const void *a;        // null: the sum is 0
+    const void *b;        // null: SUM(a)
+    int32_t adt, bdt;
+    int64_t n;
+    unsigned long long *d_sum;
+    unsigned long long *d_count;
+};
+
+__global__ void k_zero2(unsigned long long *p, unsigned long long *q) {
+    if (threadIdx.x == 0) {
+        *p = 0;
+        *q = 0;
+    }
+}
+
+constexpr int kSumIPT = 8;
+constexpr int kSumTile = kFilterNT * kSumIPT;
+
+__global__ __launch_bounds__(kFilterNT) void k_filter_sum(FilterSumArgs f) {
+    __shared__ unsigned long long s_red[2][kFilterNT / kWave];
+    const int64_t n = f.n;
+    const int64_t ntiles = ceil_div(n, kSumTile);
+    const bool vec = f.vec != 0;
+    uint64_t sum = 0, cnt = 0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * kSumTile + int64_t(threadIdx.x) * kSumIPT;
+        uint32_t mask = 0;
+#pragma unroll
+        for (int r = 0; r < kSumIPT; r++)
+            if (row0 + r < n) mask |= 1u << r;
+        int64_t v[kSumIPT];
+        int loaded = -1;
+        for (int p = 0; p < f.npred; p++) {
+            if (f.pcolid[p] != loaded) {
+                load8(f.pcol[p], f.pdt[p], row0, n, vec, v);
+                loaded = f.pcolid[p];
+            }
+            const int op = f.pop[p];
+            const int64_t lit = f.plit[p];
+            uint32_t m = 0;
+#pragma unroll
+            for (int r = 0; r < kSumIPT; r++)
+                if (cmp_holds(v[r], op, lit)) m |= 1u << r;
+            mask &= m;
+        }
+        cnt += __popc(mask);
+        if (mask && f.a) {
+            int64_t x[kSumIPT];
+            load8(f.a, f.adt, row0, n, vec, x);
+            if (f.b) {
+                load8(f.b, f.bdt, row0, n, vec, v);
+#pragma unroll
+                for (int r = 0; r < kSumIPT; r++)
+                    if (mask & (1u << r)) sum += uint64_t(x[r]) * uint64_t(v[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < kSumIPT; r++)
+                    if (mask & (1u << r)) sum += uint64_t(x[r]);
+            }
+        }
+    }
+    const uint64_t ws = uint64_t(wave_sum(int64_t(sum)));
+    const uint64_t wc = uint64_t(wave_sum(int64_t(cnt)));
+    if (lane_id() == 0) {
+        s_red[0][wave_id()] = ws;
+        s_red[1][wave_id()] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long ts = 0, tc = 0;
+#pragma unroll
+        for (int w = 0; w < kFilterNT / kWave; w++) {
+            ts += s_red[0][w];
+            tc += s_red[1][w];
+        }
+        if (ts) atomicAdd(f.d_sum, ts);
+        if (tc) atomicAdd(f.d_count, tc);
+    }
+}
+
 static size_t filter_ws(int64_t n) {
     Carver c(nullptr);
     c.take<uint64_t>(1 + (n > 0 ? ceil_div(n, kFilterTile) : 1));
@@ -250,4 +382,60 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
     const unsigned grid = persistent_grid(ntiles, tune(kTuneFilterPerCu));
     TQP_LAUNCH("filter", k_filter, dim3(grid), dim3(kFilterNT), 0, s, a);
     return check_launch("tqp_filter");
+}
+
+TQP_API int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
+                           const tqp_col *a, const tqp_col *b, int64_t *d_sum, int64_t *d_count,
+                           void *stream) {
+    clear_error();
+    if (!cols || ncols < 1 || ncols > kMaxPred)
+        return set_error(TQP_EINVAL, "tqp_filter_sum: ncols must be in [1, %d]", kMaxPred);
+    if (npred < 0 || npred > kMaxPred || (npred > 0 && !preds))
+        return set_error(TQP_EINVAL, "tqp_filter_sum: npred must be in [0, %d]", kMaxPred);
+    if (!d_sum || !d_count) return set_error(TQP_EINVAL, "tqp_filter_sum: d_sum and d_count are required");
+    if (b && !a) return set_error(TQP_EINVAL, "tqp_filter_sum: b needs a");
+    const int64_t n = cols[0].len;
+    if (n < 0 || n > INT32_MAX) return set_error(TQP_EINVAL, "tqp_filter_sum: bad row count %lld", (long long)n);
+    FilterSumArgs f = {};
+    bool vec = true;
+    for (int c = 0; c < ncols; c++) {
+        if (!dtype_ok(cols[c].dtype) || cols[c].len != n || (n > 0 && !cols[c].data) ||
+            !col_aligned(cols[c].data, cols[c].dtype))
+            return set_error(TQP_EINVAL, "tqp_filter_sum: column %d has a bad dtype, length or pointer", c);
+        vec = vec && (reinterpret_cast<uintptr_t>(cols[c].data) % 16 == 0);
+    }
+    for (int p = 0; p < npred; p++) {
+        if (preds[p].col < 0 || preds[p].col >= ncols || preds[p].op < TQP_LT || preds[p].op > TQP_NE)
+            return set_error(TQP_EINVAL, "tqp_filter_sum: predicate %d is invalid", p);
+        f.pcol[p] = cols[preds[p].col].data;
+        f.pdt[p] = cols[preds[p].col].dtype;
+        f.pcolid[p] = preds[p].col;
+        f.pop[p] = preds[p].op;
+        f.plit[p] = preds[p].literal;
+    }
+    const tqp_col *vals[2] = {a, b};
+    for (int k = 0; k < 2; k++) {
+        const tqp_col *v = vals[k];
+        if (!v) continue;
+        if (!dtype_ok(v->dtype) || v->len < n || (n > 0 && !v->data) || !col_aligned(v->data, v->dtype))
+            return set_error(TQP_EINVAL, "tqp_filter_sum: value column %c has a bad dtype, length or pointer",
+                             k ? 'b' : 'a');
+        vec = vec && (reinterpret_cast<uintptr_t>(v->data) % 16 == 0);
+    }
+    f.npred = npred;
+    f.vec = vec ? 1 : 0;
+    f.a = a ? a->data : nullptr;
+    f.b = b ? b->data : nullptr;
+    f.adt = a ? a->dtype : 0;
+    f.bdt = b ? b->dtype : 0;
+    f.n = n;
+    f.d_sum = reinterpret_cast<unsigned long long *>(d_sum);
+    f.d_count = reinterpret_cast<unsigned long long *>(d_count);
+    hipStream_t s = as_stream(stream);
+    TQP_LAUNCH("filter_sum_init", k_zero2, dim3(1), dim3(64), 0, s, f.d_sum, f.d_count);
+    int rc = check_launch("tqp_filter_sum");
+    if (rc || n == 0) return rc;
+    const unsigned grid = persistent_grid(ceil_div(n, kSumTile), 2 * tune(kTuneFilterPerCu));
+    TQP_LAUNCH("filter_sum", k_filter_sum, dim3(grid), dim3(kFilterNT), 0, s, f);
+    return check_launch("tqp_filter_sum");
 }

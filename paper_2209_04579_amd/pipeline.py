@@ -15,7 +15,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_workspace_bytes,
+from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_sum_into,
+               filter_workspace_bytes,
                gather_into, groupby_agg_into, groupby_agg_terms_into,
                groupby_terms_workspace_bytes, groupby_workspace_bytes, join_into, join_workspace_bytes,
                pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, tune_set,
@@ -324,3 +325,34 @@ class StarQuery3:
                 "key": self.g_key[:g].cpu().numpy().astype(np.int64),
                 "sum_qp": self.g_out[0][:g].cpu().numpy(),
                 "count": self.g_out[1][:g].cpu().numpy()}
+
+
+class Q6Scan:
+    """The Q6-shaped scan (Section 2.3: filters over columns of different
+    types feeding one aggregate):
+
+        SELECT SUM(price * discount), COUNT(*) FROM items
+        WHERE ship >= ship_lo AND ship < ship_hi
+          AND discount >= disc_lo AND discount <= disc_hi AND quantity < qty_cut
+
+    ship is int64 epoch nanoseconds, discount int8 hundredths, quantity int32,
+    price int64 cents.  One fused launch; nothing is compacted.
+    """
+
+    def __init__(self, items: dict, bounds: dict):
+        self.cols = [items["ship"], items["discount"], items["quantity"]]
+        self.price = items["price"]
+        self.n = items["ship"].numel()
+        self.preds = [(0, ">=", bounds["ship_lo"]), (0, "<", bounds["ship_hi"]),
+                      (1, ">=", bounds["disc_lo"]), (1, "<=", bounds["disc_hi"]),
+                      (2, "<", bounds["qty_cut"])]
+        dev = self.price.device
+        self.d_sum = torch.empty(1, dtype=torch.int64, device=dev)
+        self.d_count = torch.empty(1, dtype=torch.int64, device=dev)
+
+    def run(self):
+        filter_sum_into(self.cols, self.preds, self.d_sum, self.d_count, self.price, self.cols[1])
+
+    def result(self) -> dict:
+        torch.cuda.synchronize()
+        return {"sum": int(self.d_sum.item()), "count": int(self.d_count.item())}
