@@ -74,6 +74,11 @@ def lib():
                                         vp]
         _lib.orc_q6.restype = None
         _lib.orc_q6.argtypes = [i64, vp, vp, vp, vp, i64, i64, i64, i64, i64, vp, vp, vp]
+        _lib.orc_str_match.restype = None
+        _lib.orc_str_match.argtypes = [i64, i32, vp, vp, i32, i32, vp]
+        _lib.orc_q14.restype = None
+        _lib.orc_q14.argtypes = [i64, vp, vp, vp, vp, i64, i64, i64, vp, i32, vp, vp, i32,
+                                 vp, vp, vp, vp, vp]
         _lib.orc_q3.restype = i64
         _lib.orc_q3.argtypes = [i64, vp, vp, vp, vp, vp,
                                 i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
@@ -146,6 +151,34 @@ def q6(cfg: dict):
                  cfg["ship_hi"], cfg["disc_lo"], cfg["disc_hi"], cfg["qty_cut"],
                  ctypes.byref(s), ctypes.byref(c), ctypes.byref(ex))
     return {"sum": int(s.value), "count": int(c.value), "exact": bool(ex.value)}
+
+
+def str_match(chars: np.ndarray, pattern: bytes, mode: str = "prefix") -> np.ndarray:
+    """LIKE 'pattern%' (mode "prefix") or = 'pattern' (mode "equal") over an
+    (n, m) uint8 matrix of zero-padded strings; int8 0/1 per row."""
+    chars = _c(chars, np.uint8)
+    n, m = chars.shape
+    pat = np.frombuffer(bytes(pattern), np.uint8).copy() if pattern else np.zeros(1, np.uint8)
+    out = np.empty(max(n, 1), np.int8)
+    lib().orc_str_match(n, m, _p(chars), _p(pat), len(pattern), {"prefix": 0, "equal": 1}[mode],
+                        _p(out))
+    return out[:n].copy()
+
+
+def q14(cfg: dict):
+    """Q14-shaped join: promo and total revenue, row counts (see orc_q14)."""
+    t, p = cfg["items"], cfg["part"]
+    ship, pkey = _c(t["ship"], np.int64), _c(t["partkey"], np.int32)
+    price, disc = _c(t["price"], np.int64), _c(t["discount"], np.int8)
+    pk, types = _c(p["pk"], np.int32), _c(p["type"], np.uint8)
+    pre = np.frombuffer(bytes(cfg["prefix"]), np.uint8).copy()
+    out = [ctypes.c_int64(0) for _ in range(4)]
+    ex = ctypes.c_int(0)
+    lib().orc_q14(len(ship), _p(ship), _p(pkey), _p(price), _p(disc), cfg["ship_lo"],
+                  cfg["ship_hi"], len(pk), _p(pk), types.shape[1], _p(types), _p(pre), len(pre),
+                  *[ctypes.byref(o) for o in out], ctypes.byref(ex))
+    return {"promo_rev": out[0].value, "total_rev": out[1].value, "count": out[2].value,
+            "promo_count": out[3].value, "exact": bool(ex.value)}
 
 
 def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:

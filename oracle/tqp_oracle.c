@@ -639,3 +639,62 @@ void orc_q6(int64_t n, const int64_t *ship, const int8_t *discount,
     *count = cnt;
     *exact = s >= INT64_MIN && s <= INT64_MAX;
 }
+
+/* ------------------------------------------------------------------------
+ * Strings are the paper's (n x m) tensor of UTF-8 bytes, one row per value,
+ * zero-padded to m (Section 2.1).  LIKE 'p%' holds when the row's first plen
+ * bytes are p (mode 0); = 'p' when they are and the rest of the row is
+ * padding (mode 1).  out[i] is 1 or 0.
+ * ---------------------------------------------------------------------- */
+void orc_str_match(int64_t n, int m, const uint8_t *chars, const uint8_t *pat,
+                   int plen, int mode, int8_t *out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        const uint8_t *row = chars + i * (int64_t)m;
+        int ok = plen <= m && memcmp(row, pat, (size_t)plen) == 0;
+        if (ok && mode == 1)
+            for (int j = plen; j < m; j++)
+                if (row[j] != 0) ok = 0;
+        out[i] = (int8_t)ok;
+    }
+}
+
+/* Q14-shaped query, written directly:
+ *   SELECT SUM(CASE WHEN type LIKE 'prefix%' THEN price * (100 - discount)
+ *              ELSE 0 END), SUM(price * (100 - discount)), COUNT(*)
+ *   FROM items JOIN part ON partkey = pk
+ *   WHERE ship >= ship_lo AND ship < ship_hi
+ * Revenue is in cents x hundredths; sums exact in __int128 (*exact says they
+ * fit int64) and wrapped mod 2^64. */
+void orc_q14(int64_t ni, const int64_t *ship, const int32_t *partkey,
+             const int64_t *price, const int8_t *discount, int64_t ship_lo,
+             int64_t ship_hi, int64_t np, const int32_t *pk, int m,
+             const uint8_t *types, const uint8_t *prefix, int plen,
+             int64_t *promo_rev, int64_t *total_rev, int64_t *count,
+             int64_t *promo_count, int *exact)
+{
+    dimindex d;
+    dimindex_build(&d, np, pk);
+    __int128 promo = 0, total = 0;
+    int64_t cnt = 0, pcnt = 0;
+    for (int64_t i = 0; i < ni; i++) {
+        if (ship[i] < ship_lo || ship[i] >= ship_hi) continue;
+        int64_t s = hmap_get(&d.h, partkey[i]);
+        if (s < 0) continue;
+        for (int64_t j = d.head[s]; j != -1; j = d.next[j]) {
+            __int128 rev = (__int128)price[i] * (100 - (int64_t)discount[i]);
+            total += rev;
+            cnt++;
+            if (plen <= m && memcmp(types + j * (int64_t)m, prefix, (size_t)plen) == 0) {
+                promo += rev;
+                pcnt++;
+            }
+        }
+    }
+    dimindex_free(&d);
+    *promo_rev = (int64_t)(uint64_t)(unsigned __int128)promo;
+    *total_rev = (int64_t)(uint64_t)(unsigned __int128)total;
+    *count = cnt;
+    *promo_count = pcnt;
+    *exact = total >= INT64_MIN && total <= INT64_MAX && promo >= INT64_MIN && promo <= INT64_MAX;
+}

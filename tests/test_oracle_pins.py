@@ -407,3 +407,69 @@ def test_q6_table_shape():
     frac = oracle.q6(cfg)["count"] / 200_000
     expect = 365 / 2557 * 3 / 11 * 23 / 50
     assert abs(frac - expect) < 0.1 * expect
+
+
+# ------------------------------------------ strings and the Q14 shape ----
+
+def test_str_match_brute_force():
+    """Python bytes comparisons row by row, patterns of every length."""
+    n, m = 700, 12
+    lens = dg.uniform_int(4, 1, n, 0, m + 1, np.int64)
+    chars = np.zeros((n, m), np.uint8)
+    letters = dg.uniform_int(4, 2, n * m, 65, 69, np.uint8).reshape(n, m)   # 'A'..'D'
+    for i in range(n):
+        chars[i, :lens[i]] = letters[i, :lens[i]]
+    rows = [bytes(chars[i]) for i in range(n)]
+    for pat in [b"", b"A", b"AB", b"ABC", b"DDDD", bytes(chars[3][:lens[3]]), b"A" * m, b"A" * (m + 1)]:
+        pre = oracle.str_match(chars, pat, "prefix")
+        eq = oracle.str_match(chars, pat, "equal")
+        assert pre.tolist() == [int(len(pat) <= m and r[:len(pat)] == pat) for r in rows], pat
+        assert eq.tolist() == [int(len(pat) <= m and r == pat + bytes(m - len(pat))) for r in rows], pat
+    assert oracle.str_match(np.zeros((0, 5), np.uint8), b"A").size == 0
+
+
+def composed_q14(cfg):
+    """Q14 from the operator oracles: filter -> gather -> join -> string match."""
+    t, p = cfg["items"], cfg["part"]
+    rows = oracle.filter_rows([t["ship"]], [(0, ">=", cfg["ship_lo"]), (0, "<", cfg["ship_hi"])])
+    cnt, li, ri = oracle.join(oracle.gather(t["partkey"], rows), p["pk"])
+    flag = oracle.str_match(p["type"], cfg["prefix"])[ri]
+    price = oracle.gather(oracle.gather(t["price"], rows), li).astype(object)
+    disc = oracle.gather(oracle.gather(t["discount"], rows), li).astype(object)
+    rev = price * (100 - disc)
+    return int(sum(rev[flag == 1])), int(sum(rev)), int(cnt), int((flag == 1).sum())
+
+
+@pytest.mark.parametrize("seed,ni,npart", [(0, 30_000, 2_000), (1, 5_000, 37), (2, 0, 10)])
+def test_q14_whole_query_equals_composed_and_numpy(seed, ni, npart):
+    cfg = dg.config_q14(seed, ni, npart)
+    got = oracle.q14(cfg)
+    promo, total, cnt, pcnt = composed_q14(cfg)
+    assert (got["promo_rev"], got["total_rev"], got["count"], got["promo_count"]) == \
+        (promo, total, cnt, pcnt) and got["exact"]
+    # numpy statement: pk is a permutation, so the part row of key k is inv[k]
+    t, p = cfg["items"], cfg["part"]
+    inv = np.empty(npart, np.int64)
+    inv[p["pk"]] = np.arange(npart)
+    m = (t["ship"] >= cfg["ship_lo"]) & (t["ship"] < cfg["ship_hi"])
+    row = inv[t["partkey"][m]]
+    pl = len(cfg["prefix"])
+    promo_row = (p["type"][:, :pl] == np.frombuffer(cfg["prefix"], np.uint8)).all(axis=1)[row]
+    rev = t["price"][m] * (100 - t["discount"][m].astype(np.int64))
+    assert got["total_rev"] == int(rev.sum()) and got["promo_rev"] == int(rev[promo_row].sum())
+
+
+def test_q14_empty_prefix_selects_every_type():
+    cfg = dg.config_q14(3, 20_000, 300)
+    cfg = dict(cfg, prefix=b"")
+    got = oracle.q14(cfg)
+    assert got["promo_rev"] == got["total_rev"] and got["promo_count"] == got["count"] > 0
+
+
+def test_type_vocabulary_shape():
+    table, prefix = dg.type_vocabulary(0)
+    names = {bytes(r).rstrip(b"\0") for r in table}
+    assert table.shape[0] == 150 and len(names) == 150
+    # a sixth of the types start with the prefix word (followed by its space)
+    assert sum(nm.startswith(prefix) for nm in names) == 25
+    assert all(nm.count(b" ") == 2 for nm in names)

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "splitmix64", "raw_u64", "uniform_int", "uniform_float", "zipf_ranks",
     "permutation", "config1", "config2", "config3", "config4", "config5",
-    "small_table", "DAY_DOMAIN", "config_q6", "Q6_BOUNDS",
+    "small_table", "DAY_DOMAIN", "config_q6", "Q6_BOUNDS", "type_vocabulary", "config_q14",
 ]
 
 DAY_DOMAIN = 2557          # seven years of day numbers, [0, 2557)
@@ -192,6 +192,57 @@ def config_q6(seed: int = 0, n: int = 60_000_000) -> dict:
         "price": uniform_int(seed, 5, n, 90_000, 10_494_951, np.int64),
     }
     return {"items": items, **Q6_BOUNDS}
+
+
+# Q14-shaped join with a string predicate.  Strings are the paper's (n x m)
+# tensor of UTF-8 bytes, zero-padded to the longest (Section 2.1).  Part
+# types are three words drawn from three seeded pools of synthetic upper-case
+# words (6 x 5 x 5 = 150 types); the LIKE prefix is the first pool's first
+# word, which no other word of that pool starts with, so a sixth of the types
+# match.
+def _word(seed: int, stream: int, k: int) -> bytes:
+    ln = int(uniform_int(seed, stream, 1, 3, 10, start=k)[0])
+    return bytes(int(c) for c in uniform_int(seed, stream + 1, ln, 65, 91, start=16 * k))
+
+
+def type_vocabulary(seed: int = 0):
+    """(table, prefix): table is (150, m) uint8, zero-padded; prefix bytes."""
+    pools, k = [], 0
+    for stream, size in ((60, 6), (62, 5), (64, 5)):
+        pool = []
+        while len(pool) < size:
+            w = _word(seed, stream, k)
+            k += 1
+            if all(not (w.startswith(x) or x.startswith(w)) for x in pool):
+                pool.append(w)
+        pools.append(pool)
+    names = [a + b" " + b + b" " + c for a in pools[0] for b in pools[1] for c in pools[2]]
+    m = max(len(x) for x in names)
+    table = np.zeros((len(names), m), np.uint8)
+    for i, x in enumerate(names):
+        table[i, :len(x)] = np.frombuffer(x, np.uint8)
+    return table, pools[0][0]
+
+
+def config_q14(seed: int = 0, n_items: int = 60_000_000, n_part: int = 2_000_000) -> dict:
+    """Q14-shaped: items {ship int64 epoch-ns, partkey int32, price int64
+    cents, discount int8 hundredths}; part {pk = a permutation, type as an
+    (n_part, m) byte matrix}.  Query: ship in [1995-09-01, 1995-10-01), JOIN
+    partkey = pk; revenue = price * (100 - discount); the promo share is
+    SUM(revenue of types LIKE prefix%) over SUM(revenue)."""
+    day = uniform_int(seed, 1, n_items, 0, DAY_DOMAIN, np.int64)
+    sec = uniform_int(seed, 2, n_items, 0, 86_400, np.int64)
+    items = {
+        "ship": ((day + _DAY0) * 86_400 + sec) * 1_000_000_000,
+        "partkey": uniform_int(seed, 3, n_items, 0, n_part, np.int32),
+        "price": uniform_int(seed, 4, n_items, 90_000, 10_494_951, np.int64),
+        "discount": uniform_int(seed, 5, n_items, 0, 11, np.int8),
+    }
+    table, prefix = type_vocabulary(seed)
+    tid = uniform_int(seed, 6, n_part, 0, table.shape[0], np.int64)
+    part = {"pk": permutation(seed, 7, n_part).astype(np.int32), "type": table[tid]}
+    return {"items": items, "part": part, "prefix": prefix,
+            "ship_lo": 9374 * _NS_PER_DAY, "ship_hi": 9404 * _NS_PER_DAY}
 
 
 _C4_SCATTER = 0x2545F4914F6CDD1D   # odd multiplier: a bijection modulo 2**62

@@ -16,7 +16,8 @@ import math
 import numpy as np
 import torch
 
-from . import _C4_SCATTER, _DAY0, _MASK62, DAY_DOMAIN, Q6_BOUNDS, _zipf_cdf, config5_params
+from . import (_C4_SCATTER, _DAY0, _MASK62, _NS_PER_DAY, DAY_DOMAIN, Q6_BOUNDS, _zipf_cdf,
+                config5_params, type_vocabulary)
 
 _G = np.uint64(0x9E3779B97F4A7C15).astype(np.int64).item()
 _M1 = np.uint64(0xBF58476D1CE4E5B9).astype(np.int64).item()
@@ -158,3 +159,21 @@ def config_q6(seed=0, n=60_000_000, device="cuda"):
         "price": uniform_int(seed, 5, n, 90_000, 10_494_951, device),
     }
     return {"items": items, **Q6_BOUNDS}
+
+
+def config_q14(seed=0, n_items=60_000_000, n_part=2_000_000, device="cuda"):
+    """Q14-shaped tables, bit-identical to the host generator's."""
+    day = uniform_int(seed, 1, n_items, 0, DAY_DOMAIN, device)
+    sec = uniform_int(seed, 2, n_items, 0, 86_400, device)
+    items = {
+        "ship": ((day + _DAY0) * 86_400 + sec) * 1_000_000_000,
+        "partkey": uniform_int(seed, 3, n_items, 0, n_part, device, torch.int32),
+        "price": uniform_int(seed, 4, n_items, 90_000, 10_494_951, device),
+        "discount": uniform_int(seed, 5, n_items, 0, 11, device, torch.int8),
+    }
+    table, prefix = type_vocabulary(seed)
+    tid = uniform_int(seed, 6, n_part, 0, table.shape[0], device)
+    part = {"pk": permutation(seed, 7, n_part, device).to(torch.int32),
+            "type": torch.from_numpy(table).to(device)[tid].contiguous()}
+    return {"items": items, "part": part, "prefix": prefix,
+            "ship_lo": 9374 * _NS_PER_DAY, "ship_hi": 9404 * _NS_PER_DAY}
