@@ -314,7 +314,8 @@ def bench_learned(args, tqp, stream) -> dict:
 def bench_configs(args, tqp, stream) -> dict:
     """Throughput of the other workloads: the small star query (1M fact rows,
     launch-bound), the three-dimension star (600M fact rows, drawn on the
-    GPU) and the Q6-shaped scan (60M rows).  Their results are checked
+    GPU), the Q6-shaped scan (60M rows) and the Q14-shaped join (60M items,
+    2M parts).  Their results are checked
     against the oracle by the test suite (full-size cases included), not
     here."""
     import torch
@@ -363,8 +364,24 @@ def bench_configs(args, tqp, stream) -> dict:
                       "ms": round(ms, 4), "rows_per_s": round(n6 / (ms * 1e-3), 1),
                       "scan_GBps": round(scan_bytes / (ms * 1e-3) / 1e9, 1),
                       "count": got["count"]}
-    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
     del q6, d6
+    torch.cuda.empty_cache()
+    # Q14-shaped join with a string predicate: 60M items, 2M parts
+    from paper_2209_04579_amd.pipeline import Q14Query
+    d14 = dgd.config_q14(args.seed, device="cuda")
+    q14 = Q14Query(d14["items"], d14["part"], d14["prefix"], d14["ship_lo"], d14["ship_hi"])
+    ms = _timed(q14.run, 20, stream)
+    got = q14.result()
+    n14 = q14.n
+    out["q14_join"] = {"workload": "60M items (one month of int64 epoch-ns ship dates kept), 2M "
+                                   "parts with (n x 24) byte-matrix types; LIKE prefix flag, "
+                                   "join partkey = pk, SUM(CASE promo THEN price*(100-discount)), "
+                                   "SUM(price*(100-discount))",
+                       "ms": round(ms, 4), "rows_per_s": round(n14 / (ms * 1e-3), 1),
+                       "pairs": got["pairs"],
+                       "promo_share": round(got["promo_rev"] / max(got["total_rev"], 1), 4)}
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    del q14, d14
     torch.cuda.empty_cache()
     return out
 

@@ -162,6 +162,22 @@ int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds, int np
                    void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_str_match -- LIKE over a string column.  Section 2.1 stores a string
+ * column as an (n x m) tensor of UTF-8 bytes, one row per value, zero-padded
+ * to m.  out[i] = 1 when row i starts with pattern[0..plen)
+ * (TQP_STR_PREFIX: LIKE 'pattern%') or is exactly the pattern
+ * (TQP_STR_EQUAL: those bytes, then only zero padding), else 0.
+ *   chars  : device, n * m bytes, row-major;
+ *   pattern: host, plen in [0, 64] bytes (copied into the launch);
+ *   out    : device int8, n entries (a flag column for later operators).
+ * m >= 1; a pattern longer than m matches nothing.  Nothing is synchronized.
+ * ---------------------------------------------------------------------- */
+#define TQP_STR_PREFIX 0
+#define TQP_STR_EQUAL  1
+int tqp_str_match(const uint8_t *chars, int64_t n, int32_t m, const uint8_t *pattern,
+                  int32_t plen, int32_t mode, int8_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * tqp_gather -- out[i] = src[idx[i]] for i < count (Fig. 3's index_select).
  * src and dst share a dtype; dst->len >= n.  An index outside [0, src->len)
  * yields 0 instead of a read.

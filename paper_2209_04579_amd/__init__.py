@@ -91,6 +91,8 @@ def lib():
         L.tqp_version.restype = ctypes.c_char_p
         L.tqp_filter_workspace_bytes.restype = sz
         L.tqp_filter_workspace_bytes.argtypes = [i64]
+        L.tqp_str_match.restype = i32
+        L.tqp_str_match.argtypes = [vp, i64, i32, ctypes.c_char_p, i32, i32, vp, vp]
         L.tqp_filter_sum.restype = i32
         L.tqp_filter_sum.argtypes = [P(Col), i32, P(Pred), i32, P(Col), P(Col), vp, vp, vp]
         L.tqp_filter.restype = i32
@@ -201,6 +203,22 @@ def filter_sum_into(cols, preds, d_sum, d_count, a=None, b=None, stream=None):
                                 None if a is None else ctypes.byref(_col(a)),
                                 None if b is None else ctypes.byref(_col(b)),
                                 _ptr(d_sum), _ptr(d_count), _stream(stream)))
+
+
+STR_PREFIX, STR_EQUAL = 0, 1
+
+
+def str_match_into(chars, pattern: bytes, out, mode: str = "prefix", stream=None):
+    """Enqueues LIKE 'pattern%' (mode "prefix") or = 'pattern' ("equal") over
+    the rows of an (n, m) uint8 device matrix; out: int8 device flags (n)."""
+    if chars.dtype != torch.uint8 or chars.dim() != 2 or not chars.is_cuda or not chars.is_contiguous():
+        raise ValueError("strings must be a contiguous (n, m) uint8 device tensor")
+    if out.dtype != torch.int8 or out.numel() < chars.shape[0] or not out.is_cuda:
+        raise ValueError("out must be an int8 device tensor with n entries")
+    pattern = bytes(pattern)
+    _check(lib().tqp_str_match(_ptr(chars), chars.shape[0], chars.shape[1], pattern, len(pattern),
+                               {"prefix": STR_PREFIX, "equal": STR_EQUAL}[mode], _ptr(out),
+                               _stream(stream)))
 
 
 def filter(cols, preds, payload=(), want_rows=True):

@@ -19,8 +19,8 @@ from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_sum_into,
                filter_workspace_bytes,
                gather_into, groupby_agg_into, groupby_agg_terms_into,
                groupby_terms_workspace_bytes, groupby_workspace_bytes, join_into, join_workspace_bytes,
-               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, tune_set,
-               workspace)
+               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, str_match_into,
+               tune_set, workspace)
 
 
 def key_range(col: torch.Tensor):
@@ -356,3 +356,90 @@ class Q6Scan:
     def result(self) -> dict:
         torch.cuda.synchronize()
         return {"sum": int(self.d_sum.item()), "count": int(self.d_count.item())}
+
+
+class Q14Query:
+    """Q14-shaped join with a string predicate (Section 2.3: Q14 joins the
+    items with the parts and aggregates a CASE over a LIKE on a string):
+
+        SELECT SUM(CASE WHEN type LIKE 'prefix%' THEN price * (100 - discount)
+                   ELSE 0 END), SUM(price * (100 - discount)), COUNT(*)
+        FROM items JOIN part ON partkey = pk
+        WHERE ship >= ship_lo AND ship < ship_hi
+
+    Plan: filter the month carrying partkey, price and discount; the LIKE over
+    the part types (an (n, m) byte matrix) gives a 0/1 flag column; sort both
+    join sides (the part side carrying the flag); merge join; group by the
+    flag (two groups) with SUM(price), SUM(price * discount) and COUNT, so a
+    group's revenue is 100 * SUM(price) - SUM(price * discount), exact in
+    int64.
+    """
+
+    AGGS = [("sum", 0), ("sum_product", 0, 1), ("count",)]
+
+    def __init__(self, items: dict, part: dict, prefix: bytes, ship_lo: int, ship_hi: int):
+        self.items, self.part = items, part
+        self.prefix = bytes(prefix)
+        self.preds = [(0, ">=", int(ship_lo)), (0, "<", int(ship_hi))]
+        dev = items["ship"].device
+        n, npart = items["ship"].numel(), part["pk"].numel()
+        self.n, self.npart = n, npart
+        # catalog statistics of the join key (taken once, outside the query)
+        lo = min(int(items["partkey"].min().item()) if n else 0,
+                 int(part["pk"].min().item()) if npart else 0)
+        hi = max(int(items["partkey"].max().item()) if n else 0,
+                 int(part["pk"].max().item()) if npart else 0)
+        self.jk_min, self.jk_bits = lo, int(hi - lo).bit_length()
+        self.pay_in = [items["partkey"], items["price"], items["discount"]]
+        self.pay_out = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_in]
+        self.cnt = _i64(1, dev)
+        self.ws_f = workspace(filter_workspace_bytes(n), dev)
+        self.flag = torch.empty(max(npart, 1), dtype=torch.int8, device=dev)
+        self.fk_s = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.fpay_s = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_out[1:]]
+        self.pk_s = torch.empty(max(npart, 1), dtype=torch.int32, device=dev)
+        self.flag_s = torch.empty(max(npart, 1), dtype=torch.int8, device=dev)
+        self.ws_s = workspace(max(sort_workspace_bytes(n, torch.int32, pay_bytes_of(self.fpay_s)),
+                                  sort_workspace_bytes(npart, torch.int32, 1)), dev)
+        self.cap = max(n, 1)
+        self.out_l = _i32(self.cap, dev)
+        self.out_r = _i32(self.cap, dev)
+        self.out_k = torch.empty(self.cap, dtype=torch.int32, device=dev)
+        self.npairs = _i64(1, dev)
+        self.ws_j = workspace(join_workspace_bytes(n, npart, torch.int32, JOIN_SORTED, self.cap), dev)
+        self.g_key = torch.empty(2, dtype=torch.int32, device=dev)
+        self.g_out = [_i64(2, dev) for _ in self.AGGS]
+        self.g_ng = _i64(1, dev)
+        self.ws_g = workspace(groupby_terms_workspace_bytes(len(self.AGGS), 2), dev)
+
+    def run(self):
+        it, pt = self.items, self.part
+        filter_into([it["ship"]], self.preds, self.pay_in, self.pay_out, None, self.cnt, self.ws_f)
+        str_match_into(pt["type"], self.prefix, self.flag)
+        sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
+                  key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
+                  pay_out=self.fpay_s)
+        sort_into(pt["pk"], None, self.npart, self.pk_s, None, self.ws_s, key_bits=self.jk_bits,
+                  key_min=self.jk_min, pay_in=[self.flag], pay_out=[self.flag_s])
+        join_into(self.fk_s, self.pk_s, JOIN_SORTED, self.out_l, self.out_r, self.out_k,
+                  self.cap, self.npairs, self.ws_j, d_nl=self.cnt)
+        groupby_agg_terms_into([(self.flag_s, self.out_r, 0, 1)], self.cap, self.fpay_s,
+                               self.AGGS, self.g_key, self.g_out, self.g_ng, self.ws_g, 0, 2,
+                               val_rows=self.out_l, d_n=self.npairs)
+
+    def result(self) -> dict:
+        torch.cuda.synchronize()
+        npairs = int(self.npairs.item())
+        if npairs > self.cap:
+            raise RuntimeError(f"join produced {npairs} pairs, more than the {self.cap} planned")
+        g = int(self.g_ng.item())
+        keys = self.g_key[:g].cpu().tolist()
+        sp, spd, cnt = (o[:g].cpu().tolist() for o in self.g_out)
+
+        def wrap(x):
+            return (x + (1 << 63)) % (1 << 64) - (1 << 63)
+        rev = {k: wrap(100 * a - b) for k, a, b in zip(keys, sp, spd)}
+        count = dict(zip(keys, cnt))
+        return {"rows_filtered": int(self.cnt.item()), "pairs": npairs,
+                "promo_rev": rev.get(1, 0), "total_rev": wrap(sum(rev.values())),
+                "count": sum(count.values()), "promo_count": count.get(1, 0)}

@@ -70,3 +70,15 @@ def test_unaligned_columns_are_rejected_without_a_gpu():
     out64 = tqp.Col(0x80000, 10, 3, 0)
     rc = L.tqp_pack_key(term, 1, 10, None, ctypes.byref(out64), None)
     assert rc == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
+def test_string_match_argument_errors_without_a_gpu():
+    import paper_2209_04579_amd as tqp
+    L = tqp.lib()
+    fake = ctypes.c_void_p(0x10000)
+    assert L.tqp_str_match(fake, 10, 8, b"A" * 65, 65, 0, fake, None) == tqp.TQP_EINVAL
+    assert b"pattern length" in L.tqp_last_error()
+    assert L.tqp_str_match(fake, 10, 0, b"A", 1, 0, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_str_match(fake, 10, 8, b"A", 1, 7, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_str_match(None, 0, 8, b"A", 1, 0, None, None) == tqp.TQP_OK   # empty: no launch
