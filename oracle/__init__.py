@@ -35,8 +35,9 @@ def build(force: bool = True) -> str:
     """Compiles the oracle with gcc into ``oracle/libtqp_oracle.so``."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC])
+        # no contraction: every fused multiply-add in the source is an explicit fmaf
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -79,6 +80,10 @@ def lib():
         _lib.orc_q14.restype = None
         _lib.orc_q14.argtypes = [i64, vp, vp, vp, vp, i64, i64, i64, vp, i32, vp, vp, i32,
                                  vp, vp, vp, vp, vp]
+        _lib.orc_mlp_predict.restype = None
+        _lib.orc_mlp_predict.argtypes = [i64, vp, vp, i32, vp, vp, i32, i32, vp]
+        _lib.orc_q_predict.restype = None
+        _lib.orc_q_predict.argtypes = [i64, vp, vp, i64, vp, i32, vp, i32, i32, i32, vp, vp]
         _lib.orc_q3.restype = i64
         _lib.orc_q3.argtypes = [i64, vp, vp, vp, vp, vp,
                                 i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
@@ -179,6 +184,34 @@ def q14(cfg: dict):
                   *[ctypes.byref(o) for o in out], ctypes.byref(ex))
     return {"promo_rev": out[0].value, "total_rev": out[1].value, "count": out[2].value,
             "promo_count": out[3].value, "exact": bool(ex.value)}
+
+
+def mlp_predict(feats, model: np.ndarray, hidden: int, classes: int, rows=None) -> np.ndarray:
+    """Class (int8) of each row under the fp32 one-hidden-layer MLP (see
+    orc_mlp_predict); feats: list of F integer columns; rows: optional row
+    ids (int32) selecting the rows scored."""
+    feats = [_c(f) for f in feats]
+    model = _c(model, np.float32)
+    rows = None if rows is None else _c(rows, np.int32)
+    n = len(rows) if rows is not None else (len(feats[0]) if feats else 0)
+    dts = np.array([DT[f.dtype] for f in feats], np.int32)
+    out = np.empty(max(n, 1), np.int8)
+    lib().orc_mlp_predict(n, _ptr_array(feats), _p(dts), len(feats),
+                          None if rows is None else _p(rows), _p(model), hidden, classes, _p(out))
+    return out[:n].copy()
+
+
+def q_predict(cfg: dict):
+    """Per rating: predicted-positive count and row count (see orc_q_predict)."""
+    t = cfg["reviews"]
+    feats = [_c(t[f"f{k}"], np.int32) for k in range(cfg["nfeat"])]
+    nr = cfg["nratings"]
+    pos, cnt = np.zeros(nr, np.int64), np.zeros(nr, np.int64)
+    lib().orc_q_predict(len(t["rating"]), _p(_c(t["rating"], np.int8)), _p(_c(t["year"], np.int32)),
+                        cfg["year_min"], _ptr_array(feats), len(feats),
+                        _p(_c(cfg["model"], np.float32)), cfg["hidden"], cfg["classes"], nr,
+                        _p(pos), _p(cnt))
+    return {"positive": pos, "count": cnt}
 
 
 def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:

@@ -698,3 +698,68 @@ void orc_q14(int64_t ni, const int64_t *ship, const int32_t *partkey,
     *promo_count = pcnt;
     *exact = total >= INT64_MIN && total <= INT64_MAX && promo >= INT64_MIN && promo <= INT64_MAX;
 }
+
+/* ------------------------------------------------------------------------
+ * PREDICT inside a query (Section 4's prediction query: a model scores each
+ * row and a group-by with a CASE compares predictions with ratings).  The
+ * model is an MLP with one ReLU hidden layer in fp32:
+ *   h[j]  = relu(b1[j] + sum_k W1[j][k] * x[k])     (k ascending)
+ *   z[c]  = b2[c] + sum_j W2[c][j] * h[j]            (j ascending)
+ *   class = the first c with the largest z[c]
+ * Every multiply-add is one fused fmaf, in the order written, and relu(v) is
+ * (v > 0 ? v : 0), so a kernel taking the same steps reaches the same class.
+ * model = [W1 (H x F, row-major), b1 (H), W2 (C x H), b2 (C)].
+ * x[k] is the k-th feature column of row rows[i] (rows NULL: row i),
+ * converted to float.
+ * ---------------------------------------------------------------------- */
+#include <math.h>
+
+static int mlp_class(const float *model, int F, int H, int C, const float *x)
+{
+    const float *w1 = model, *b1 = w1 + H * F, *w2 = b1 + H, *b2 = w2 + C * H;
+    float h[256], best = 0.0f;
+    int arg = 0;
+    for (int j = 0; j < H; j++) {
+        float acc = b1[j];
+        for (int k = 0; k < F; k++) acc = fmaf(w1[j * F + k], x[k], acc);
+        h[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int c = 0; c < C; c++) {
+        float acc = b2[c];
+        for (int j = 0; j < H; j++) acc = fmaf(w2[c * H + j], h[j], acc);
+        if (c == 0 || acc > best) { best = acc; arg = c; }
+    }
+    return arg;
+}
+
+void orc_mlp_predict(int64_t n, const void *const *feats, const int *dtypes, int F,
+                     const int32_t *rows, const float *model, int H, int C, int8_t *out)
+{
+    float x[64];
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t r = rows ? rows[i] : i;
+        for (int k = 0; k < F; k++) x[k] = (float)value_at(feats[k], dtypes[k], r);
+        out[i] = (int8_t)mlp_class(model, F, H, C, x);
+    }
+}
+
+/* The prediction query, written directly over the whole table:
+ *   SELECT rating, SUM(CASE WHEN PREDICT(model, f) = 1 THEN 1 ELSE 0 END), COUNT(*)
+ *   FROM reviews WHERE year >= year_min GROUP BY rating
+ * out_pos[r], out_cnt[r] for ratings r in [0, nr). */
+void orc_q_predict(int64_t n, const int8_t *rating, const int32_t *year, int64_t year_min,
+                   const int32_t *const *feats, int F, const float *model, int H, int C,
+                   int nr, int64_t *out_pos, int64_t *out_cnt)
+{
+    float x[64];
+    for (int r = 0; r < nr; r++) out_pos[r] = out_cnt[r] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(year[i] >= year_min)) continue;
+        for (int k = 0; k < F; k++) x[k] = (float)feats[k][i];
+        const int cls = mlp_class(model, F, H, C, x);
+        const int r = rating[i];
+        if (r < 0 || r >= nr) continue;
+        out_cnt[r]++;
+        if (cls == 1) out_pos[r]++;
+    }
+}

@@ -473,3 +473,69 @@ def test_type_vocabulary_shape():
     # a sixth of the types start with the prefix word (followed by its space)
     assert sum(nm.startswith(prefix) for nm in names) == 25
     assert all(nm.count(b" ") == 2 for nm in names)
+
+
+# --------------------------------------------- PREDICT inside a query ----
+
+def int_mlp_class(model, F, H, C, x):
+    """Exact integer forward pass (every value below is a small integer, so
+    the fp32 fused multiply-adds of the oracle are exact too)."""
+    w1 = model[:H * F].reshape(H, F)
+    b1 = model[H * F:H * F + H]
+    w2 = model[H * F + H:H * F + H + C * H].reshape(C, H)
+    b2 = model[H * F + H + C * H:]
+    h = [max(int(b1[j]) + sum(int(w1[j, k]) * int(x[k]) for k in range(F)), 0) for j in range(H)]
+    z = [int(b2[c]) + sum(int(w2[c, j]) * h[j] for j in range(H)) for c in range(C)]
+    return z.index(max(z))            # the first of the largest
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_mlp_predict_exact_on_integer_models(seed):
+    F, H, C, n = 5, 7, 3, 400
+    model = dg.uniform_int(seed, 30, H * F + H + C * H + C, -4, 5, np.int64).astype(np.float32)
+    feats = [dg.uniform_int(seed, 40 + k, n, -6, 7, np.int32) for k in range(F)]
+    got = oracle.mlp_predict(feats, model, H, C)
+    want = [int_mlp_class(model, F, H, C, [f[i] for f in feats]) for i in range(n)]
+    assert got.tolist() == want
+
+
+def test_mlp_predict_agrees_with_float64_away_from_ties():
+    cfg = dg.config_predict(1, 50_000)
+    t, model, F, H = cfg["reviews"], cfg["model"].astype(np.float64), cfg["nfeat"], cfg["hidden"]
+    X = np.stack([t[f"f{k}"] for k in range(F)], axis=1).astype(np.float64)
+    w1, b1 = model[:H * F].reshape(H, F), model[H * F:H * F + H]
+    w2, b2 = model[H * F + H:H * F + H + 2 * H].reshape(2, H), model[H * F + H + 2 * H:]
+    z = np.maximum(X @ w1.T + b1, 0) @ w2.T + b2
+    got = oracle.mlp_predict([t[f"f{k}"] for k in range(F)], cfg["model"], H, 2)
+    clear = np.abs(z[:, 1] - z[:, 0]) > 1e-3
+    assert clear.mean() > 0.99
+    assert np.array_equal(got[clear], np.argmax(z[clear], axis=1).astype(np.int8))
+
+
+def test_mlp_predict_ties_rows_and_empty():
+    F, H, C = 3, 4, 3
+    zero = np.zeros(H * F + H + C * H + C, np.float32)
+    feats = [np.arange(10, dtype=np.int32)] * F
+    assert oracle.mlp_predict(feats, zero, H, C).tolist() == [0] * 10      # all tied: first
+    m = zero.copy()
+    m[-1] = 1.0                                                            # b2 = (0, 0, 1)
+    assert oracle.mlp_predict(feats, m, H, C).tolist() == [2] * 10
+    cfg = dg.config_predict(2, 3_000)
+    fs = [cfg["reviews"][f"f{k}"] for k in range(cfg["nfeat"])]
+    rows = np.array([5, 0, 2999, 5, 17], np.int32)
+    full = oracle.mlp_predict(fs, cfg["model"], cfg["hidden"], 2)
+    assert np.array_equal(oracle.mlp_predict(fs, cfg["model"], cfg["hidden"], 2, rows), full[rows])
+    assert oracle.mlp_predict(fs, cfg["model"], cfg["hidden"], 2, rows[:0]).size == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 20_000])
+def test_q_predict_equals_composed(n):
+    cfg = dg.config_predict(3, n)
+    t = cfg["reviews"]
+    got = oracle.q_predict(cfg)
+    rows = oracle.filter_rows([t["year"]], [(0, ">=", cfg["year_min"])])
+    cls = oracle.mlp_predict([t[f"f{k}"] for k in range(cfg["nfeat"])], cfg["model"],
+                             cfg["hidden"], cfg["classes"], rows)
+    r = t["rating"][rows].astype(np.int64)
+    assert np.array_equal(got["count"], np.bincount(r, minlength=cfg["nratings"]))
+    assert np.array_equal(got["positive"], np.bincount(r[cls == 1], minlength=cfg["nratings"]))

@@ -22,6 +22,7 @@ __all__ = [
     "splitmix64", "raw_u64", "uniform_int", "uniform_float", "zipf_ranks",
     "permutation", "config1", "config2", "config3", "config4", "config5",
     "small_table", "DAY_DOMAIN", "config_q6", "Q6_BOUNDS", "type_vocabulary", "config_q14",
+    "mlp_model", "config_predict",
 ]
 
 DAY_DOMAIN = 2557          # seven years of day numbers, [0, 2557)
@@ -243,6 +244,35 @@ def config_q14(seed: int = 0, n_items: int = 60_000_000, n_part: int = 2_000_000
     part = {"pk": permutation(seed, 7, n_part).astype(np.int32), "type": table[tid]}
     return {"items": items, "part": part, "prefix": prefix,
             "ship_lo": 9374 * _NS_PER_DAY, "ship_hi": 9404 * _NS_PER_DAY}
+
+
+# Prediction query: reviews with a 1..5 rating, a year and eight small integer
+# features that lean on the rating (feature k = (rating - 3) * 4 slope_k +
+# noise in [-8, 8]), and
+# a small fp32 model (8 -> 16 -> 2) with seeded weights: the paper's trained
+# models and review data are not available, so the scores are synthetic.
+def mlp_model(seed: int, nfeat: int, hidden: int, classes: int) -> np.ndarray:
+    """[W1 (hidden x nfeat), b1, W2 (classes x hidden), b2] as float32, each
+    weight uniform on [-1, 1) / sqrt(fan-in)."""
+    parts = []
+    for k, (rows, fan) in enumerate(((hidden * nfeat, nfeat), (hidden, nfeat),
+                                     (classes * hidden, hidden), (classes, hidden))):
+        u = uniform_float(seed, 80 + k, rows) * 2.0 - 1.0
+        parts.append((u / np.sqrt(fan)).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def config_predict(seed: int = 0, n: int = 20_000_000, nfeat: int = 8, hidden: int = 16) -> dict:
+    """SELECT rating, SUM(CASE WHEN PREDICT(model, f0..f7) = 1 THEN 1 ELSE 0 END),
+    COUNT(*) FROM reviews WHERE year >= 2016 GROUP BY rating."""
+    rating = uniform_int(seed, 1, n, 1, 6, np.int8)
+    reviews = {"rating": rating, "year": uniform_int(seed, 2, n, 2010, 2024, np.int32)}
+    for k in range(nfeat):
+        slope = (k % 4) - 1                       # -1, 0, 1, 2
+        reviews[f"f{k}"] = ((rating.astype(np.int32) - 3) * slope * 4
+                            + uniform_int(seed, 10 + k, n, -8, 9, np.int32)).astype(np.int32)
+    return {"reviews": reviews, "model": mlp_model(seed, nfeat, hidden, 2), "nfeat": nfeat,
+            "hidden": hidden, "classes": 2, "year_min": 2016, "nratings": 6}
 
 
 _C4_SCATTER = 0x2545F4914F6CDD1D   # odd multiplier: a bijection modulo 2**62

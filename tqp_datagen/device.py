@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import (_C4_SCATTER, _DAY0, _MASK62, _NS_PER_DAY, DAY_DOMAIN, Q6_BOUNDS, _zipf_cdf,
-                config5_params, type_vocabulary)
+                config5_params, mlp_model, type_vocabulary)
 
 _G = np.uint64(0x9E3779B97F4A7C15).astype(np.int64).item()
 _M1 = np.uint64(0xBF58476D1CE4E5B9).astype(np.int64).item()
@@ -177,3 +177,16 @@ def config_q14(seed=0, n_items=60_000_000, n_part=2_000_000, device="cuda"):
             "type": torch.from_numpy(table).to(device)[tid].contiguous()}
     return {"items": items, "part": part, "prefix": prefix,
             "ship_lo": 9374 * _NS_PER_DAY, "ship_hi": 9404 * _NS_PER_DAY}
+
+
+def config_predict(seed=0, n=20_000_000, nfeat=8, hidden=16, device="cuda"):
+    """Prediction-query table, bit-identical to the host generator's (the
+    model is drawn on the host)."""
+    rating = uniform_int(seed, 1, n, 1, 6, device, torch.int8)
+    reviews = {"rating": rating, "year": uniform_int(seed, 2, n, 2010, 2024, device, torch.int32)}
+    for k in range(nfeat):
+        slope = (k % 4) - 1
+        reviews[f"f{k}"] = ((rating.to(torch.int32) - 3) * (slope * 4)
+                            + uniform_int(seed, 10 + k, n, -8, 9, device, torch.int32)).to(torch.int32)
+    return {"reviews": reviews, "model": mlp_model(seed, nfeat, hidden, 2), "nfeat": nfeat,
+            "hidden": hidden, "classes": 2, "year_min": 2016, "nratings": 6}
