@@ -314,8 +314,8 @@ def bench_learned(args, tqp, stream) -> dict:
 def bench_configs(args, tqp, stream) -> dict:
     """Throughput of the other workloads: the small star query (1M fact rows,
     launch-bound), the three-dimension star (600M fact rows, drawn on the
-    GPU), the Q6-shaped scan (60M rows) and the Q14-shaped join (60M items,
-    2M parts).  Their results are checked
+    GPU), the Q6-shaped scan (60M rows), the Q14-shaped join (60M items,
+    2M parts) and the prediction query (20M reviews).  Their results are checked
     against the oracle by the test suite (full-size cases included), not
     here."""
     import torch
@@ -380,8 +380,25 @@ def bench_configs(args, tqp, stream) -> dict:
                        "ms": round(ms, 4), "rows_per_s": round(n14 / (ms * 1e-3), 1),
                        "pairs": got["pairs"],
                        "promo_share": round(got["promo_rev"] / max(got["total_rev"], 1), 4)}
-    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
     del q14, d14
+    torch.cuda.empty_cache()
+    # PREDICT inside a query: 20M reviews, 8 features, 8 -> 16 -> 2 fp32 model
+    from paper_2209_04579_amd.pipeline import PredictQuery
+    dp = dgd.config_predict(args.seed, device="cuda")
+    qp = PredictQuery(dp["reviews"], dp["model"], dp["nfeat"], dp["hidden"], dp["classes"],
+                      dp["year_min"], dp["nratings"])
+    ms = _timed(qp.run, 20, stream)
+    got = qp.result()
+    out["predict_query"] = {"workload": "20M reviews: WHERE year >= 2016, PREDICT with an fp32 "
+                                        "8 -> 16 -> 2 MLP over 8 int32 features, GROUP BY rating "
+                                        "with SUM(CASE class = 1) and COUNT",
+                            "ms": round(ms, 4), "rows_per_s": round(qp.n / (ms * 1e-3), 1),
+                            "rows_scored": got["rows_filtered"],
+                            "positive_share_by_rating": [round(float(p) / max(int(c), 1), 3)
+                                                         for p, c in zip(got["positive"][1:],
+                                                                         got["count"][1:])]}
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    del qp, dp
     torch.cuda.empty_cache()
     return out
 

@@ -178,6 +178,29 @@ int tqp_str_match(const uint8_t *chars, int64_t n, int32_t m, const uint8_t *pat
                   int32_t plen, int32_t mode, int8_t *out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_mlp_predict -- PREDICT inside a query (Section 4's prediction query: a
+ * model scores each row, then a group-by with a CASE compares the
+ * predictions with the ratings).  For i < count (*d_n when d_n is given,
+ * else n), with row = rows[i] (rows NULL: row = i) and x[k] =
+ * feats[k][row] converted to float:
+ *   h[j]  = relu(b1[j] + sum_k W1[j][k] x[k])   k ascending
+ *   z[c]  = b2[c] + sum_j W2[c][j] h[j]          j ascending
+ *   out[i] = the first c with the largest z[c]
+ * in fp32, every multiply-add one fused fma in the order shown, relu(v) =
+ * (v > 0 ? v : 0); integer features convert exactly below 2^24.
+ *   feats : nfeat in [1, 16] columns of any integer dtype; a row outside a
+ *           column reads 0;
+ *   model : device fp32 [W1 (hidden x nfeat, row-major), b1 (hidden),
+ *           W2 (classes x hidden), b2 (classes)]; hidden in [1, 64],
+ *           classes in [1, 8];
+ *   out   : device int8, n entries.
+ * Nothing is synchronized.
+ * ---------------------------------------------------------------------- */
+int tqp_mlp_predict(const tqp_col *feats, int nfeat, const int32_t *rows, int64_t n,
+                    const int64_t *d_n, const float *model, int hidden, int classes,
+                    int8_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * tqp_gather -- out[i] = src[idx[i]] for i < count (Fig. 3's index_select).
  * src and dst share a dtype; dst->len >= n.  An index outside [0, src->len)
  * yields 0 instead of a read.

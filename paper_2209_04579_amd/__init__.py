@@ -91,6 +91,8 @@ def lib():
         L.tqp_version.restype = ctypes.c_char_p
         L.tqp_filter_workspace_bytes.restype = sz
         L.tqp_filter_workspace_bytes.argtypes = [i64]
+        L.tqp_mlp_predict.restype = i32
+        L.tqp_mlp_predict.argtypes = [P(Col), i32, vp, i64, vp, vp, i32, i32, vp, vp]
         L.tqp_str_match.restype = i32
         L.tqp_str_match.argtypes = [vp, i64, i32, ctypes.c_char_p, i32, i32, vp, vp]
         L.tqp_filter_sum.restype = i32
@@ -203,6 +205,22 @@ def filter_sum_into(cols, preds, d_sum, d_count, a=None, b=None, stream=None):
                                 None if a is None else ctypes.byref(_col(a)),
                                 None if b is None else ctypes.byref(_col(b)),
                                 _ptr(d_sum), _ptr(d_count), _stream(stream)))
+
+
+def mlp_predict_into(feats, model, hidden: int, classes: int, out, n=None, rows=None, d_n=None,
+                     stream=None):
+    """Enqueues PREDICT: out[i] = class of row rows[i] (or i) under the fp32
+    one-hidden-layer MLP whose packed weights are the device float32 tensor
+    model ([W1, b1, W2, b2])."""
+    if model.dtype != torch.float32 or not model.is_cuda or not model.is_contiguous():
+        raise ValueError("model must be a contiguous float32 device tensor")
+    f = len(feats)
+    if model.numel() != hidden * f + hidden + classes * hidden + classes:
+        raise ValueError("model size does not match nfeat, hidden and classes")
+    if n is None:
+        n = rows.numel() if rows is not None else feats[0].numel()
+    _check(lib().tqp_mlp_predict(_cols(feats), f, _ptr(rows), int(n), _ptr(d_n), _ptr(model),
+                                 int(hidden), int(classes), _ptr(out), _stream(stream)))
 
 
 STR_PREFIX, STR_EQUAL = 0, 1

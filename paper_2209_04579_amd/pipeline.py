@@ -19,6 +19,7 @@ from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_sum_into,
                filter_workspace_bytes,
                gather_into, groupby_agg_into, groupby_agg_terms_into,
                groupby_terms_workspace_bytes, groupby_workspace_bytes, join_into, join_workspace_bytes,
+               mlp_predict_into,
                pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, str_match_into,
                tune_set, workspace)
 
@@ -443,3 +444,56 @@ class Q14Query:
         return {"rows_filtered": int(self.cnt.item()), "pairs": npairs,
                 "promo_rev": rev.get(1, 0), "total_rev": wrap(sum(rev.values())),
                 "count": sum(count.values()), "promo_count": count.get(1, 0)}
+
+
+class PredictQuery:
+    """PREDICT inside a query (Section 4's prediction query):
+
+        SELECT rating, SUM(CASE WHEN PREDICT(model, f0..) = 1 THEN 1 ELSE 0 END), COUNT(*)
+        FROM reviews WHERE year >= year_min GROUP BY rating
+
+    Plan: filter the years carrying the rating and the kept row ids; score
+    the kept rows (features read through the row ids); group by
+    rating * 2 + class, a dense domain, with COUNT.
+    """
+
+    def __init__(self, reviews: dict, model, nfeat: int, hidden: int, classes: int,
+                 year_min: int, nratings: int):
+        dev = reviews["rating"].device
+        n = reviews["rating"].numel()
+        self.n, self.hidden, self.classes, self.nratings = n, hidden, classes, nratings
+        self.year, self.rating = reviews["year"], reviews["rating"]
+        self.feats = [reviews[f"f{k}"] for k in range(nfeat)]
+        self.model = torch.as_tensor(model, dtype=torch.float32).to(dev).contiguous()
+        self.preds = [(0, ">=", int(year_min))]
+        self.rows = _i32(n, dev)
+        self.rating_f = torch.empty(max(n, 1), dtype=torch.int8, device=dev)
+        self.cnt = _i64(1, dev)
+        self.ws_f = workspace(filter_workspace_bytes(n), dev)
+        self.cls = torch.empty(max(n, 1), dtype=torch.int8, device=dev)
+        self.span = nratings * classes
+        self.g_key = torch.empty(self.span, dtype=torch.int32, device=dev)
+        self.g_cnt = [_i64(self.span, dev)]
+        self.g_ng = _i64(1, dev)
+        self.ws_g = workspace(groupby_terms_workspace_bytes(1, self.span), dev)
+
+    def run(self):
+        filter_into([self.year], self.preds, [self.rating], [self.rating_f], self.rows, self.cnt,
+                    self.ws_f)
+        mlp_predict_into(self.feats, self.model, self.hidden, self.classes, self.cls, n=self.n,
+                         rows=self.rows, d_n=self.cnt)
+        groupby_agg_terms_into([(self.rating_f, None, 0, self.classes), (self.cls, None, 0, 1)],
+                               self.n, [], [("count",)], self.g_key, self.g_cnt, self.g_ng,
+                               self.ws_g, 0, self.span, d_n=self.cnt)
+
+    def result(self) -> dict:
+        torch.cuda.synchronize()
+        g = int(self.g_ng.item())
+        pos = np.zeros(self.nratings, np.int64)
+        cnt = np.zeros(self.nratings, np.int64)
+        for k, c in zip(self.g_key[:g].cpu().tolist(), self.g_cnt[0][:g].cpu().tolist()):
+            r, cls = divmod(k, self.classes)
+            cnt[r] += c
+            if cls == 1:
+                pos[r] += c
+        return {"rows_filtered": int(self.cnt.item()), "positive": pos, "count": cnt}

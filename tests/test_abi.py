@@ -82,3 +82,16 @@ def test_string_match_argument_errors_without_a_gpu():
     assert L.tqp_str_match(fake, 10, 0, b"A", 1, 0, fake, None) == tqp.TQP_EINVAL
     assert L.tqp_str_match(fake, 10, 8, b"A", 1, 7, fake, None) == tqp.TQP_EINVAL
     assert L.tqp_str_match(None, 0, 8, b"A", 1, 0, None, None) == tqp.TQP_OK   # empty: no launch
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
+def test_predict_argument_errors_without_a_gpu():
+    import paper_2209_04579_amd as tqp
+    L = tqp.lib()
+    f = (tqp.Col * 1)(tqp.Col(0x10000, 10, 2, 0))
+    fake = ctypes.c_void_p(0x20000)
+    assert L.tqp_mlp_predict(f, 0, None, 10, None, fake, 4, 2, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_mlp_predict(f, 1, None, 10, None, fake, 65, 2, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_mlp_predict(f, 1, None, 10, None, fake, 4, 9, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_mlp_predict(f, 1, None, 11, None, fake, 4, 2, fake, None) == tqp.TQP_EINVAL
+    assert L.tqp_mlp_predict(f, 1, None, 0, None, fake, 4, 2, fake, None) == tqp.TQP_OK
