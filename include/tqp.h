@@ -178,7 +178,7 @@ int tqp_str_match(const uint8_t *chars, int64_t n, int32_t m, const uint8_t *pat
                   int32_t plen, int32_t mode, int8_t *out, void *stream);
 
 /* ------------------------------------------------------------------------
- * tqp_mlp_predict -- PREDICT inside a query (Section 4's prediction query: a
+ * tqp_mlp_predict -- PREDICT inside a query (Section 3.3's prediction query: a
  * model scores each row, then a group-by with a CASE compares the
  * predictions with the ratings).  For i < count (*d_n when d_n is given,
  * else n), with row = rows[i] (rows NULL: row = i) and x[k] =

@@ -700,7 +700,7 @@ void orc_q14(int64_t ni, const int64_t *ship, const int32_t *partkey,
 }
 
 /* ------------------------------------------------------------------------
- * PREDICT inside a query (Section 4's prediction query: a model scores each
+ * PREDICT inside a query (Section 3.3's prediction query: a model scores each
  * row and a group-by with a CASE compares predictions with ratings).  The
  * model is an MLP with one ReLU hidden layer in fp32:
  *   h[j]  = relu(b1[j] + sum_k W1[j][k] * x[k])     (k ascending)

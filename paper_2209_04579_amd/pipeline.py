@@ -447,7 +447,7 @@ class Q14Query:
 
 
 class PredictQuery:
-    """PREDICT inside a query (Section 4's prediction query):
+    """PREDICT inside a query (Section 3.3's prediction query):
 
         SELECT rating, SUM(CASE WHEN PREDICT(model, f0..) = 1 THEN 1 ELSE 0 END), COUNT(*)
         FROM reviews WHERE year >= year_min GROUP BY rating

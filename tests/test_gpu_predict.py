@@ -1,5 +1,5 @@
-"""GPU parity for PREDICT inside a query (tqp_mlp_predict, Section 4's
-prediction query): the class of every row equals the oracle's, which takes
+"""GPU parity for PREDICT inside a query (tqp_mlp_predict, Section 3.3's
+prediction queries): the class of every row equals the oracle's, which takes
 the same fp32 fused multiply-adds in the same order, over models of every
 supported shape, every feature dtype, with and without row ids; then the
 whole prediction query (filter, score, GROUP BY rating with a CASE count)
