@@ -49,7 +49,7 @@ class StarQuery:
     """
 
     def __init__(self, fact: dict, dim: dict, day_cut: int, mode: str = "q1",
-                 tuning: dict | None = None):
+                 tuning: dict | None = None, overlap: bool = True):
         self.mode = mode
         # library knobs (see tune_knobs()) applied before each run; the
         # "gb.dense_max" entry is the largest key domain aggregated directly
@@ -89,6 +89,12 @@ class StarQuery:
         self.ws_s = workspace(max(sort_workspace_bytes(n, fact["fk"].dtype,
                                                        pay_bytes_of(self.fpay_s)),
                                   sort_workspace_bytes(nd, dim["pk"].dtype, 4)), dev)
+        # overlap: the dimension side's sort runs on a second stream (default
+        # priority) beside the fact side's filter and sort, with its own
+        # workspace; the join waits for both
+        self.side = torch.cuda.Stream(device=dev) if overlap else None
+        self.ws_sd = (workspace(sort_workspace_bytes(nd, dim["pk"].dtype, 4), dev) if overlap
+                      else self.ws_s)
         # join: pk is unique for these schemas, so pairs <= |filtered fact|;
         # the pair count is checked after the run.  Pairs are positions in
         # the sorted sides, so later reads of the sorted payload are sequential.
@@ -135,6 +141,15 @@ class StarQuery:
         for name, value in self.tuning.items():
             tune_set(name, value)
         f, d = self.f, self.d
+        main = torch.cuda.current_stream(self.dev)
+
+        def dim_sort():
+            sort_into(d["pk"], None, self.nd, self.pk_s, None, self.ws_sd, key_bits=self.jk_bits,
+                      key_min=self.jk_min, pay_in=[d["cat"]], pay_out=[self.cat_s])
+        if self.side is not None:
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                dim_sort()
         # 1. WHERE day < cut, carrying the payload columns
         filter_into([f["day"]], [(0, "<", self.cut)], self.pay_in, self.pay_out, None,
                     self.cnt, self.ws_f)
@@ -142,8 +157,10 @@ class StarQuery:
         sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
                   key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
                   pay_out=self.fpay_s)
-        sort_into(d["pk"], None, self.nd, self.pk_s, None, self.ws_s, key_bits=self.jk_bits,
-                  key_min=self.jk_min, pay_in=[d["cat"]], pay_out=[self.cat_s])
+        if self.side is not None:
+            main.wait_stream(self.side)
+        else:
+            dim_sort()
         # 3. merge join of the sorted sides -> (left position, right position, key)
         join_into(self.fk_s, self.pk_s, JOIN_SORTED, self.out_l, self.out_r, self.out_k,
                   self.cap, self.npairs, self.ws_j, d_nl=self.cnt)
@@ -400,8 +417,11 @@ class Q14Query:
         self.fpay_s = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_out[1:]]
         self.pk_s = torch.empty(max(npart, 1), dtype=torch.int32, device=dev)
         self.flag_s = torch.empty(max(npart, 1), dtype=torch.int8, device=dev)
-        self.ws_s = workspace(max(sort_workspace_bytes(n, torch.int32, pay_bytes_of(self.fpay_s)),
-                                  sort_workspace_bytes(npart, torch.int32, 1)), dev)
+        self.ws_s = workspace(sort_workspace_bytes(n, torch.int32, pay_bytes_of(self.fpay_s)), dev)
+        # the part side (string match and its sort) runs on a second stream
+        # beside the items' filter and sort; the join waits for both
+        self.side = torch.cuda.Stream(device=dev)
+        self.ws_sp = workspace(sort_workspace_bytes(npart, torch.int32, 1), dev)
         self.cap = max(n, 1)
         self.out_l = _i32(self.cap, dev)
         self.out_r = _i32(self.cap, dev)
@@ -415,13 +435,18 @@ class Q14Query:
 
     def run(self):
         it, pt = self.items, self.part
+        main = torch.cuda.current_stream(self.items["ship"].device)
+        self.side.wait_stream(main)
+        with torch.cuda.stream(self.side):
+            str_match_into(pt["type"], self.prefix, self.flag)
+            sort_into(pt["pk"], None, self.npart, self.pk_s, None, self.ws_sp,
+                      key_bits=self.jk_bits, key_min=self.jk_min, pay_in=[self.flag],
+                      pay_out=[self.flag_s])
         filter_into([it["ship"]], self.preds, self.pay_in, self.pay_out, None, self.cnt, self.ws_f)
-        str_match_into(pt["type"], self.prefix, self.flag)
         sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
                   key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
                   pay_out=self.fpay_s)
-        sort_into(pt["pk"], None, self.npart, self.pk_s, None, self.ws_s, key_bits=self.jk_bits,
-                  key_min=self.jk_min, pay_in=[self.flag], pay_out=[self.flag_s])
+        main.wait_stream(self.side)
         join_into(self.fk_s, self.pk_s, JOIN_SORTED, self.out_l, self.out_r, self.out_k,
                   self.cap, self.npairs, self.ws_j, d_nl=self.cnt)
         groupby_agg_terms_into([(self.flag_s, self.out_r, 0, 1)], self.cap, self.fpay_s,
