@@ -80,8 +80,7 @@ class BatchStarQuery:
                 pack_key_into([(inst["dim"]["cat"], None, 0, 1),
                                (None, None, 0, int(self.cat_off[k]))], d1 - d0, dim["cat"][d0:d1])
         self.fact, self.dim = fact, dim
-        # one stream: the whole plan is captured into a single-stream graph
-        self.q = StarQuery(fact, dim, day_cut, mode="q1", tuning=tuning, overlap=False)
+        self.q = StarQuery(fact, dim, day_cut, mode="q1", tuning=tuning)
         self.graph = None
 
     def run(self):
@@ -119,7 +118,7 @@ class SequentialStarQueries:
     """The same instances as independent queries, launched one after another."""
 
     def __init__(self, instances: list, day_cut: int, tuning: dict | None = None):
-        self.qs = [StarQuery(i["fact"], i["dim"], day_cut, mode="q1", tuning=tuning, overlap=False)
+        self.qs = [StarQuery(i["fact"], i["dim"], day_cut, mode="q1", tuning=tuning)
                    for i in instances]
 
     def run(self):

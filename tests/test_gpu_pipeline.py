@@ -54,9 +54,10 @@ def test_q1_replay_is_identical():
             assert np.array_equal(again[k], first[k])
 
 
-def check_q2(cfg):
+def check_q2(cfg, overlap=False):
     from paper_2209_04579_amd.pipeline import StarQuery
-    q = StarQuery(to_dev(cfg["fact"]), to_dev(cfg["dim"]), cfg["day_cut"], mode="q2")
+    q = StarQuery(to_dev(cfg["fact"]), to_dev(cfg["dim"]), cfg["day_cut"], mode="q2",
+                  overlap=overlap)
     q.run()
     got = q.result()
     want = oracle.q2(cfg["fact"], cfg["dim"], cfg["day_cut"])
@@ -68,6 +69,11 @@ def check_q2(cfg):
 
 def test_q2_reduced_size():
     check_q2(dg.config2(0, n_fact=3_000_000, n_dim=100_000))
+
+
+def test_q2_with_the_dimension_sort_on_a_second_stream():
+    cfg = dg.config2(5, n_fact=3_000_000, n_dim=200_000)
+    assert check_q2(cfg, overlap=True)["pairs"] > 0
 
 
 def test_q2_full_size():
