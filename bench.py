@@ -470,7 +470,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

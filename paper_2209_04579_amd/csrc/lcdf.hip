@@ -37,7 +37,7 @@
 // A bucket larger than the LDS tile is left as is when all its keys are equal
 // (already in stable order), otherwise it is sorted by the plain radix sort
 // over its own key range.  With bucket = top bits of (key - kmin) the same
-// pipeline is the plain MSD radix partitioner the learned one is judged
+// pipeline is the plain MSD radix partitioner the learned one is compared
 // against.
 #include <limits.h>
 #include <math.h>
