@@ -5,9 +5,12 @@
  * (arXiv 2209.04579): tables are columnar, one contiguous (n x 1) device array
  * per numeric column (Section 2.1), and the executor turns input columns into
  * result columns (Section 2.2, "Execution").  The operators are the ones the
- * paper's TPC-H workload exercises (Section 2.3): predicate filters, an
- * equi-join and SUM/COUNT aggregation, here with a group-by (Fig. 4).  The sort
- * is the step a sort-merge join and a sort-based group-by rest on.
+ * paper's TPC-H workload exercises (Section 2.3): predicate filters (also
+ * fused with an aggregate, Q6's shape), an equi-join and SUM/COUNT
+ * aggregation, here with a group-by (Fig. 4); LIKE over string columns, which
+ * Section 2.1 stores as zero-padded (n x m) byte tensors (Q14's CASE); and a
+ * model's prediction inside a query (Section 3.3).  The sort is the step a
+ * sort-merge join and a sort-based group-by rest on.
  *
  * Conventions for every entry point:
  *  - Every pointer to column data, row ids, counts, outputs and workspace is
