@@ -122,8 +122,9 @@ void tqp_profile_reset(void);
  * "sort.mode" picks how a radix pass finds where each tile's digit runs go:
  * 0 = decoupled look-back over earlier tiles, 1 = every tile's digit counts
  * first, then a scan per digit (one more read of the keys, no waiting).
- * Knobs change how the work is done, never results.  They are process-wide and read when a call enqueues its kernels;
- * setting them concurrently with calls on other threads is a race.
+ * Knobs change how the work is done, never results.  They are process-wide
+ * and read when a call enqueues its kernels; setting them concurrently with
+ * calls on other threads is a race.
  *   tqp_tune_set: TQP_EINVAL for an unknown name or a value out of range.
  *   tqp_tune_get: writes value / lo / hi (each pointer may be NULL).
  *   tqp_tune_name: name of knob `index` (0-based), NULL past the last one. */
@@ -205,8 +206,9 @@ int tqp_mlp_predict(const tqp_col *feats, int nfeat, const int32_t *rows, int64_
 
 /* ------------------------------------------------------------------------
  * tqp_gather -- out[i] = src[idx[i]] for i < count (Fig. 3's index_select).
- * src and dst share a dtype; dst->len >= n.  An index outside [0, src->len)
- * yields 0 instead of a read.
+ * src and dst share a dtype; dst->len >= n.  idx is 16-byte aligned (it is
+ * read four ids at a time; TQP_EINVAL otherwise).  An index outside
+ * [0, src->len) yields 0 instead of a read.
  * ---------------------------------------------------------------------- */
 int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n,
                const int64_t *d_n, const tqp_col *dst, void *stream);

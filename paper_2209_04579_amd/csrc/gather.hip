@@ -96,6 +96,8 @@ TQP_API int tqp_gather(const tqp_col *src, const int32_t *idx, int64_t n, const 
                                        (long long)dst->len, (long long)n);
     if (reinterpret_cast<uintptr_t>(idx) % 16 != 0)
         return set_error(TQP_EINVAL, "tqp_gather: idx must be 16-byte aligned");
+    if (!col_aligned(src->data, src->dtype) || !col_aligned(dst->data, dst->dtype))
+        return set_error(TQP_EINVAL, "tqp_gather: src and dst must be aligned to their dtype");
     if (n == 0) return TQP_OK;
     hipStream_t s = as_stream(stream);
     const unsigned g = grid_for(n, 4);

@@ -70,6 +70,10 @@ def test_unaligned_columns_are_rejected_without_a_gpu():
     out64 = tqp.Col(0x80000, 10, 3, 0)
     rc = L.tqp_pack_key(term, 1, 10, None, ctypes.byref(out64), None)
     assert rc == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
+    src = tqp.Col(0x90004, 10, 3, 0)
+    rc = L.tqp_gather(ctypes.byref(src), ctypes.c_void_p(0xA0000), 10, None,
+                      ctypes.byref(out64), None)
+    assert rc == tqp.TQP_EINVAL and b"aligned to their dtype" in L.tqp_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
