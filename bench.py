@@ -125,12 +125,17 @@ def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
     if name == "filter":
         return n * (4 + 4 + 8 + 8 + 1) + kept * (4 + 8 + 8 + 1)
     if name == "radix_hist":
-        return 4.0 * (kept + nd)
+        # fact side (filtered): fk and day of every row, one keep bit written
+        # per row; dim side: pk
+        return n * (4 + 4 + 1 / 8) + 4.0 * nd
     if name == "onesweep":
-        # every pass reads and writes each element once: the fact side moves
-        # fk (4) + qty (8) + price (8) + flag (1), the dim side pk (4) + cat (4)
+        # the fact side moves fk (4) + qty (8) + price (8) + flag (1): its
+        # first pass reads them for every row (at this selectivity every
+        # cache line holds kept rows) plus the keep bits and writes the kept
+        # rows, later passes read and write the kept rows; every dim pass
+        # reads and writes pk (4) + cat (4)
         p = st["passes"]
-        return p * (kept * 2.0 * 21 + nd * 2.0 * 8)
+        return (n * (21 + 1 / 8) + kept * 21) + (p - 1) * kept * 2.0 * 21 + p * nd * 2.0 * 8
     if name == "rle":
         return 4.0 * (kept + nd) + 8.0 * (ul + ur)
     if name == "join_match":

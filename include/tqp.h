@@ -247,6 +247,27 @@ int tqp_sort(const tqp_col *key, const int32_t *in_rows, int64_t n,
              void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_filter_sort -- WHERE, then the stable sort, in one go: the result of
+ * tqp_filter (Section 2.3's predicate filters) carrying the key and payload
+ * columns, then tqp_sort of the kept rows, without the filtered table ever
+ * being written.  The table has n = key->len rows; every cols[c] and
+ * pay_in[c] has len >= n.  Row i is kept when every predicate holds on it
+ * (ncols in [1, 8], npred in [1, 4]).  With k = *d_count kept rows (written
+ * to device memory), for j < k:
+ *   out_key[j]    : the kept keys, ascending; ties keep row order;
+ *   out_rows[j]   : optional (capacity n); the row id (in the table) of j;
+ *   pay_out[c][j] = pay_in[c][out_rows[j]], npay in [0, 4].
+ * key_bits / key_min as for tqp_sort, bounding every key of the table
+ * (0 = derive over all n keys, which SYNCHRONIZES the stream).  Outputs have
+ * capacity n.  Workspace: tqp_sort_workspace_bytes(n, key dtype, pay_bytes).
+ * ---------------------------------------------------------------------- */
+int tqp_filter_sort(const tqp_col *cols, int ncols, const tqp_pred *preds, int npred,
+                    const tqp_col *key, int key_bits, int64_t key_min,
+                    const tqp_col *out_key, int32_t *out_rows,
+                    const tqp_col *pay_in, const tqp_col *pay_out, int npay,
+                    int64_t *d_count, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * tqp_join -- inner equi-join, bag semantics, sort-merge (Section 2.3: Q14).
  *   lkey/rkey : same dtype (int32 or int64).  With TQP_JOIN_SORTED both are
  *               ascending and lrows/rrows (optional; NULL = position) give the

@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "TqpError", "lib", "library_path", "filter", "filter_into", "gather_into", "gather",
-    "pack_key_into", "sort", "sort_into", "join", "join_into", "join_ranges",
+    "pack_key_into", "sort", "sort_into", "filter_sort_into", "join", "join_into", "join_ranges",
     "groupby_agg", "groupby_agg_into", "OPS", "DTYPES",
 ]
 
@@ -109,6 +109,9 @@ def lib():
         L.tqp_sort.restype = i32
         L.tqp_sort.argtypes = [P(Col), vp, i64, vp, i32, i64, P(Col), vp, P(Col), P(Col), i32,
                                vp, sz, vp]
+        L.tqp_filter_sort.restype = i32
+        L.tqp_filter_sort.argtypes = [P(Col), i32, P(Pred), i32, P(Col), i32, i64, P(Col), vp,
+                                      P(Col), P(Col), i32, vp, vp, sz, vp]
         L.tqp_join_workspace_bytes.restype = sz
         L.tqp_join_workspace_bytes.argtypes = [i64, i64, i32, u32, i64]
         L.tqp_join.restype = i32
@@ -289,6 +292,20 @@ def sort_into(key, in_rows, n, out_key, out_rows, ws, d_n=None, key_bits=0, key_
                           int(key_bits), int(key_min), ctypes.byref(_col(out_key)),
                           _ptr(out_rows), _cols(list(pay_in)), _cols(list(pay_out)),
                           len(pay_in), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def filter_sort_into(cols, preds, key, out_key, out_rows, d_count, ws, key_bits=0, key_min=0,
+                     pay_in=(), pay_out=(), stream=None):
+    """Enqueues WHERE then the stable sort by key of the kept rows, in one
+    operator: out_key / out_rows / pay_out hold the kept rows sorted, d_count
+    their number.  preds: [(col_index, op, literal)]; workspace as for the
+    sort of key.numel() rows."""
+    pr = (Pred * len(preds))(*[Pred(c, OPS[op], int(lit)) for c, op, lit in preds])
+    _check(lib().tqp_filter_sort(_cols(cols), len(cols), pr, len(preds),
+                                 ctypes.byref(_col(key)), int(key_bits), int(key_min),
+                                 ctypes.byref(_col(out_key)), _ptr(out_rows),
+                                 _cols(list(pay_in)), _cols(list(pay_out)), len(pay_in),
+                                 _ptr(d_count), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def sort(key, in_rows=None, key_bits=0, key_min=0, payload=(), want_rows=True):

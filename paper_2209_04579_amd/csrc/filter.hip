@@ -109,17 +109,6 @@ __device__ __forceinline__ void load8(const void *p, int dt, int64_t row0, int64
     }
 }
 
-__device__ __forceinline__ bool cmp_holds(int64_t v, int op, int64_t lit) {
-    switch (op) {
-    case TQP_LT: return v < lit;
-    case TQP_LE: return v <= lit;
-    case TQP_GT: return v > lit;
-    case TQP_GE: return v >= lit;
-    case TQP_EQ: return v == lit;
-    default: return v != lit;
-    }
-}
-
 __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
     __shared__ int64_t s_tile;
     __shared__ int64_t s_prefix;

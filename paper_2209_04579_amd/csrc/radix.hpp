@@ -32,6 +32,7 @@ constexpr int kBins = 1 << kRadixBits;
 constexpr int kSortNW = kSortNT / kWave;
 constexpr int kMaxSortPay = 4;
 constexpr int kMaxPassCols = kMaxSortPay + 1;   // payload columns + row ids
+constexpr int kMaxSortPred = 4;            // predicates of a filtered first pass
 constexpr int kHistNT = 256;
 constexpr int kHistIPT = 16;
 constexpr int kLookAhead = 4;             // predecessor statuses fetched per round trip
@@ -49,9 +50,62 @@ constexpr uint32_t kSFlagAgg = 1u << 30;
 constexpr uint32_t kSFlagInc = 2u << 30;
 constexpr uint32_t kSValMask = (1u << 30) - 1;
 
+// The conjunction a filtered sort applies before its first pass: item i is
+// kept when col[q][i] op[q] lit[q] holds for every q < npred.  Columns are
+// naturally aligned, of run-time dtype, read as aligned words.
+struct PassPred {
+    const void *col[kMaxSortPred];
+    int64_t lit[kMaxSortPred];
+    int32_t dt[kMaxSortPred];
+    int32_t op[kMaxSortPred];
+    int32_t npred;
+};
+
+// Bit r of the result: item idx[r] satisfies every predicate (no item past
+// cnt is tested; their bits are 0).  One predicate's N loads go out together.
+template <int N, class I>
+__device__ __forceinline__ uint32_t keep_mask(const PassPred &f, const I (&idx)[N], int64_t cnt) {
+    uint32_t m = 0;
+    I li[N];
+#pragma unroll
+    for (int r = 0; r < N; r++) {
+        m |= (int64_t(idx[r]) < cnt ? 1u : 0u) << r;
+        li[r] = int64_t(idx[r]) < cnt ? idx[r] : I(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxSortPred; q++) {
+        if (q >= f.npred) break;
+        uint64_t raw[N];
+        load_raw<N>(f.col[q], f.dt[q], li, raw);
+#pragma unroll
+        for (int r = 0; r < N; r++)
+            if (!cmp_holds(sext_of(raw[r], f.dt[q]), f.op[q], f.lit[q])) m &= ~(1u << r);
+    }
+    return m;
+}
+
 // 256-bin histograms of every digit in one sweep: each thread reads 16
 // consecutive keys with 16-byte loads and counts them into its wave's LDS
 // histograms; the workgroup then adds its totals to the device histogram.
+// Skewed keys put many lanes of a wave on one counter, and LDS atomics on
+// one address serialize: the lanes sharing the first valid lane's digit are
+// counted by one ballot and one add.
+template <class Ord>
+__device__ __forceinline__ void count_digits(uint32_t (*h)[kBins], bool valid, uint64_t u,
+                                             int npass, int dbits, uint32_t dmask) {
+    const uint64_t vm = ballot(valid);
+    if (vm == 0) return;
+    const int first = __builtin_ctzll(vm);
+    for (int p = 0; p < npass; p++) {
+        const uint32_t d = uint32_t(u >> (p * dbits)) & dmask;
+        const uint32_t f = uint32_t(__builtin_amdgcn_readlane(int(d), first));
+        const bool same = valid && d == f;
+        const uint64_t sm = ballot(same);
+        if (lane_id() == first) atomicAdd(&h[p][f], uint32_t(__popcll(sm)));
+        else if (valid && !same) atomicAdd(&h[p][d], 1u);
+    }
+}
+
 template <class K, class Ord>
 __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ keys, int64_t n,
                                                         const int64_t *d_n, Ord ord, int npass,
@@ -83,25 +137,9 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
 #pragma unroll
             for (int r = 0; r < kHistIPT; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
         }
-        // Skewed keys put many lanes of a wave on one counter, and LDS
-        // atomics on one address serialize: the lanes sharing the first
-        // valid lane's digit are counted by one ballot and one add.
 #pragma unroll
-        for (int r = 0; r < kHistIPT; r++) {
-            const bool valid = row0 + r < cnt;
-            const uint64_t vm = ballot(valid);
-            if (vm == 0) continue;
-            const int first = __builtin_ctzll(vm);
-            const uint64_t u = ord(v[r]);
-            for (int p = 0; p < npass; p++) {
-                const uint32_t d = uint32_t(u >> (p * dbits)) & dmask;
-                const uint32_t f = uint32_t(__builtin_amdgcn_readlane(int(d), first));
-                const bool same = valid && d == f;
-                const uint64_t sm = ballot(same);
-                if (lane_id() == first) atomicAdd(&s_h[w][p][f], uint32_t(__popcll(sm)));
-                else if (valid && !same) atomicAdd(&s_h[w][p][d], 1u);
-            }
-        }
+        for (int r = 0; r < kHistIPT; r++)
+            count_digits<Ord>(s_h[w], row0 + r < cnt, ord(v[r]), npass, dbits, dmask);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < npass * kBins; i += kHistNT) {
@@ -111,6 +149,73 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
         for (int ww = 0; ww < NW; ww++) t += s_h[ww][p][d];
         if (t) atomicAdd(&ghist[p * kBins + d], t);
     }
+}
+
+// The histograms of a filtered sort, over the items the predicates flt keep
+// (n items, no device count).  Each step a wave tests 8 items per lane
+// (item r of lane l: base + r * kHistNT + 64 * wave + l, so each r covers
+// 64 consecutive items, one word of keep_bits), writes the keep bits, and
+// queues its kept keys in LDS; it then counts the queue 64 keys at a time, so
+// rejected items cost no counting.  Also adds the kept count to *d_kept and
+// sets bit i % 64 of keep_bits[i / 64] for each kept item i (every word up to
+// item n - 1 is written).
+constexpr int kHistFIPT = 8;
+template <class K, class Ord>
+__global__ __launch_bounds__(kHistNT) void k_radix_hist_filt(const K *__restrict__ keys, int64_t n,
+                                                             Ord ord, int npass, int dbits,
+                                                             uint32_t *__restrict__ ghist,
+                                                             PassPred flt, int64_t *d_kept,
+                                                             uint64_t *__restrict__ keep_bits) {
+    const uint32_t dmask = (1u << dbits) - 1;
+    constexpr int kMaxPass = KeyTraits<K>::kBits / kRadixBits;
+    constexpr int NW = kHistNT / kWave;
+    __shared__ uint32_t s_h[NW][kMaxPass][kBins];
+    __shared__ K s_q[NW][kWave * kHistFIPT];      // one wave's kept keys of one step
+    for (int i = threadIdx.x; i < NW * kMaxPass * kBins; i += kHistNT) (&s_h[0][0][0])[i] = 0;
+    __syncthreads();
+    const int w = wave_id();
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int64_t chunk = int64_t(kHistNT) * kHistFIPT;
+    uint32_t kept = 0;
+    for (int64_t base = blockIdx.x * chunk; base < n; base += int64_t(gridDim.x) * chunk) {
+        const int64_t w0 = base + int64_t(w) * kWave;
+        int64_t ri[kHistFIPT];
+        K v[kHistFIPT];
+#pragma unroll
+        for (int r = 0; r < kHistFIPT; r++) ri[r] = w0 + int64_t(r) * kHistNT + lane;
+#pragma unroll
+        for (int r = 0; r < kHistFIPT; r++) v[r] = keys[ri[r] < n ? ri[r] : 0];
+        const uint32_t keep = keep_mask<kHistFIPT>(flt, ri, n);
+        kept += __popc(keep);
+        uint32_t qn = 0;                            // the same in every lane
+#pragma unroll
+        for (int r = 0; r < kHistFIPT; r++) {
+            const bool kr = (keep >> r) & 1;
+            const uint64_t m = ballot(kr);
+            if (lane == 0 && w0 + int64_t(r) * kHistNT < n)
+                keep_bits[(w0 + int64_t(r) * kHistNT) >> 6] = m;
+            if (kr) s_q[w][qn + __popcll(m & lt)] = v[r];
+            qn += __popcll(m);
+        }
+        __syncthreads();                            // the queue is written
+        for (uint32_t j0 = 0; j0 < qn; j0 += kWave) {
+            const uint32_t j = j0 + lane;
+            const bool valid = j < qn;
+            const K key = s_q[w][valid ? j : 0];
+            count_digits<Ord>(s_h[w], valid, ord(key), npass, dbits, dmask);
+        }
+        __syncthreads();                            // ... and read before it is reused
+    }
+    for (int i = threadIdx.x; i < npass * kBins; i += kHistNT) {
+        const int p = i / kBins, d = i % kBins;
+        uint32_t t = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++) t += s_h[ww][p][d];
+        if (t) atomicAdd(&ghist[p * kBins + d], t);
+    }
+    const uint64_t wk = wave_sum(uint64_t(kept));
+    if (lane == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long *>(d_kept), (unsigned long long)wk);
 }
 
 // The columns a pass moves with its keys: the payload columns, then the row
@@ -168,11 +273,16 @@ __device__ __forceinline__ void flush_stage(const uint64_t *s_stage, const int32
 // over earlier tiles (persistent workgroups, tiles by ticket); otherwise one
 // workgroup per tile reads it from toff[digit * tstride + tile], the tile
 // offsets k_radix_tilescan computed from every tile's digit counts.
-template <class K, int NPAY, class Ord, bool LB, bool ROWS>
+// FILT (with LB only): items whose bit in keep_bits is clear (bit i % 64 of
+// word i / 64, written by the filtered histogram) are dropped, as items past
+// the end are, so the pass also compacts: its output holds the kept items,
+// sorted by the digit, in their input order within a digit.
+template <class K, int NPAY, class Ord, bool LB, bool ROWS, bool FILT>
 __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, PassCols c, int64_t n,
     const int64_t *d_n, Ord ord, int shift, int dbits, const uint32_t *__restrict__ ghist,
-    uint32_t *status, uint32_t *ticket, int64_t tstride) {
+    uint32_t *status, uint32_t *ticket, int64_t tstride, const uint64_t *__restrict__ keep_bits) {
+    static_assert(LB || !FILT, "a filtered pass takes its offsets from the look-back");
     const uint32_t nbins = 1u << dbits;
     __shared__ uint32_t s_hist[kSortNW][kBins];
     __shared__ uint32_t s_local[kBins];      // tile-local start of each digit run
@@ -181,6 +291,7 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     __shared__ uint64_t s_stage2[kSortTile]; // the next column (staging alternates)
     __shared__ uint8_t s_dig[kSortTile];     // digit of each sorted tile position
     __shared__ uint32_t s_scan[kSortNW];
+    __shared__ uint32_t s_kept;
     __shared__ int64_t s_tile;
 
     const int64_t cnt = count_of(d_n, n);
@@ -223,6 +334,20 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     uint64_t cur[kSortIPT];       // the column being moved (column 0 first)
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) key[k] = keys_in[lidx[k]];
+    uint32_t keep = 0xffffffffu;
+    if constexpr (FILT) {
+        // item k of every lane lies in one 64-item word (wbase is a multiple of 64)
+        const int64_t last = (cnt - 1) >> 6;
+        uint64_t kw[kSortIPT];
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) {
+            const int64_t wi = (wbase + k * kWave) >> 6;
+            kw[k] = keep_bits[wi < last ? wi : last];
+        }
+        keep = 0;
+#pragma unroll
+        for (int k = 0; k < kSortIPT; k++) keep |= uint32_t((kw[k] >> lane) & 1) << k;
+    }
     constexpr int NC = NPAY + (ROWS ? 1 : 0);   // moved columns, row ids last
     if (NC > 0) load_col<NPAY == 0>(c, 0, keys_in, lidx, cur);
     for (int i = tid; i < kSortNW * kBins; i += kSortNT) (&s_hist[0][0])[i] = 0;
@@ -233,7 +358,8 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
         const int64_t idx = wbase + k * kWave + lane;
-        pd[k] = (idx < cnt ? uint32_t(ord(key[k]) >> shift) & (nbins - 1) : kBins) << 16;
+        const bool in = idx < cnt && ((keep >> k) & 1);
+        pd[k] = (in ? uint32_t(ord(key[k]) >> shift) & (nbins - 1) : kBins) << 16;
     }
 
     // Stable rank of each item among the items of this wave with its digit.
@@ -269,6 +395,7 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
     }
     uint32_t tile_total;
     const uint32_t local = block_excl_scan<kSortNT>(tot, &tile_total, s_scan);
+    if (FILT && tid == 0) s_kept = tile_total;
     if (!LB) {
         if (tid < int(nbins)) {
             s_local[tid] = local;
@@ -321,7 +448,10 @@ __global__ __launch_bounds__(kSortNT, 4) void k_onesweep(
         }
     }
     __syncthreads();
-    const int tile_cnt = int(cnt - tile * kSortTile < kSortTile ? cnt - tile * kSortTile : kSortTile);
+    // the tile's items that are not missing (FILT: as counted by the scan,
+    // kept in LDS rather than a register through the look-back)
+    const int tile_cnt = FILT ? int(s_kept)
+                              : int(cnt - tile * kSortTile < kSortTile ? cnt - tile * kSortTile : kSortTile);
     int32_t gpos[kSortIPT];
 #pragma unroll
     for (int k = 0; k < kSortIPT; k++) {
@@ -515,44 +645,55 @@ inline size_t radix_ws_bytes(int64_t n, int key_size, int npass, int pay_bytes) 
         for (int b = 0; b < pay_bytes; b++) c.take<char>(size_t(n));
     }
     c.take<uint32_t>(size_t(npass) * kBins + size_t(npass) * kXcds + size_t(npass) * ntiles * kBins);
+    c.take<uint64_t>(size_t(ceil_div(n > 0 ? n : 1, 64)));     // keep bits of a filtered sort
     return c.bytes();
 }
 
-template <class K, int NPAY, class Ord, bool LB, bool ROWS>
+template <class K, int NPAY, class Ord, bool LB, bool ROWS, bool FILT>
 static int launch_pass(unsigned grid, hipStream_t s, const K *src, K *dst, const PassCols &x,
                        int64_t n, const int64_t *d_n, Ord ord, int shift, int dbits,
-                       const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride) {
-    TQP_LAUNCH("onesweep", (k_onesweep<K, NPAY, Ord, LB, ROWS>), dim3(grid), dim3(kSortNT), 0, s, src,
-               dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+                       const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride,
+                       const uint64_t *keep_bits) {
+    TQP_LAUNCH("onesweep", (k_onesweep<K, NPAY, Ord, LB, ROWS, FILT>), dim3(grid), dim3(kSortNT), 0, s,
+               src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride, keep_bits);
     return TQP_OK;
 }
 
 // The instantiation for npay payload columns and (rows) row ids: row ids
 // alone take the typed 4-byte path (ROWS); next to payload columns they are
 // one more column of the generic path, which needs fewer registers there.
-template <class K, class Ord, bool LB>
+template <class K, class Ord, bool LB, bool FILT = false>
 static int launch_cols(int npay, bool rows, unsigned grid, hipStream_t s, const K *src, K *dst,
                        const PassCols &x, int64_t n, const int64_t *d_n, Ord ord, int shift,
-                       int dbits, const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride) {
-    if (rows && npay == 0)
-        return launch_pass<K, 0, Ord, LB, true>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+                       int dbits, const uint32_t *gh, uint32_t *st, uint32_t *ticket, int64_t tstride,
+                       const uint64_t *keep_bits = nullptr) {
+#define TQP_PASS(NP, R) launch_pass<K, NP, Ord, LB, R, FILT>(grid, s, src, dst, x, n, d_n, ord, shift, \
+                                                             dbits, gh, st, ticket, tstride, keep_bits)
+    if (rows && npay == 0) return TQP_PASS(0, true);
     switch (npay + (rows ? 1 : 0)) {
-    case 0: return launch_pass<K, 0, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
-    case 1: return launch_pass<K, 1, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
-    case 2: return launch_pass<K, 2, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
-    case 3: return launch_pass<K, 3, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
-    case 4: return launch_pass<K, 4, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
-    default: return launch_pass<K, 5, Ord, LB, false>(grid, s, src, dst, x, n, d_n, ord, shift, dbits, gh, st, ticket, tstride);
+    case 0: return TQP_PASS(0, false);
+    case 1: return TQP_PASS(1, false);
+    case 2: return TQP_PASS(2, false);
+    case 3: return TQP_PASS(3, false);
+    case 4: return TQP_PASS(4, false);
+    default: return TQP_PASS(5, false);
     }
+#undef TQP_PASS
 }
 
 // Sorts by the low `bits` bits of the ordinal: npass_for(bits) stable passes
 // over equal-width digits (least significant first) from key_in into key_out
 // (they must not overlap), with the columns of sc moving along.  bits == 0
-// copies.
+// copies.  With pred (then bits >= 1 and d_n null): only the items the
+// predicates keep are sorted -- the histogram counts only them and writes
+// their number to *d_kept, the first pass drops the others (always by
+// look-back), and the later passes run over *d_kept items.
 template <class K, class Ord>
 int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord, K *key_out,
-              const SortCols &sc, void *ws, hipStream_t s) {
+              const SortCols &sc, void *ws, hipStream_t s, const PassPred *pred = nullptr,
+              int64_t *d_kept = nullptr) {
+    if (pred && (bits < 1 || d_n || !d_kept))
+        return set_error(TQP_EINVAL, "radix: a filtered sort needs key bits and a kept counter");
     const int npass = npass_for(bits);
     const int dbits = digit_bits_for(bits);
     const unsigned grid_all = unsigned(ceil_div(n > 0 ? n : 1, kSortTile));
@@ -596,20 +737,30 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     uint32_t *ghist = words;
     uint32_t *tickets = words + npass * kBins;
     uint32_t *status = tickets + npass * kXcds;
+    uint64_t *keep_bits = cv.take<uint64_t>(size_t(ceil_div(n > 0 ? n : 1, 64)));
     int rc = fill_u32(words, 0, int64_t(nwords), s);
     if (rc) return rc;
+    if (pred && (rc = fill_u64(reinterpret_cast<uint64_t *>(d_kept), 0, 1, s))) return rc;
     {
         // a few workgroups per CU: each merges its counters into the device
         // histogram once, so fewer workgroups mean fewer device atomics
         int64_t g = ceil_div(n > 0 ? n : 1, int64_t(kHistNT) * kHistIPT);
         if (g > int64_t(kComputeUnits) * 4) g = int64_t(kComputeUnits) * 4;
-        TQP_LAUNCH("radix_hist", (k_radix_hist<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0, s,
-                   key_in, n, d_n, ord, npass, dbits, ghist);
+        if (pred) {
+            g = ceil_div(n > 0 ? n : 1, int64_t(kHistNT) * kHistFIPT);
+            if (g > int64_t(kComputeUnits) * 4) g = int64_t(kComputeUnits) * 4;
+            TQP_LAUNCH("radix_hist", (k_radix_hist_filt<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0,
+                       s, key_in, n, ord, npass, dbits, ghist, *pred, d_kept, keep_bits);
+        } else {
+            TQP_LAUNCH("radix_hist", (k_radix_hist<K, Ord>), dim3(unsigned(g)), dim3(kHistNT), 0, s,
+                       key_in, n, d_n, ord, npass, dbits, ghist);
+        }
         rc = check_launch("radix histogram");
         if (rc) return rc;
     }
     const K *src_k = key_in;
     PassCols cur = pc;
+    const int64_t *pass_n = pred ? d_kept : d_n;   // item count of the passes after a filtered one
     for (int p = 0; p < npass; p++) {
         const bool to_out = ((npass - 1 - p) % 2) == 0;
         K *dk = to_out ? key_out : tmp_keys;
@@ -618,20 +769,24 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
         uint32_t *st = status + size_t(p) * ntiles * kBins;
         const int shift = p * dbits;
         const uint32_t *gh = ghist + p * kBins;
-        if (mode == 0) {
+        if (pred && p == 0) {
+            rc = launch_cols<K, Ord, true, true>(sc.npay, sc.rows_out != nullptr, grid_pass, s, src_k,
+                                                 dk, x, n, nullptr, ord, shift, dbits, gh, st,
+                                                 tickets, 0, keep_bits);
+        } else if (mode == 0) {
             rc = launch_cols<K, Ord, true>(sc.npay, sc.rows_out != nullptr, grid_pass, s, src_k, dk, x, n,
-                                           d_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0);
+                                           pass_n, ord, shift, dbits, gh, st, tickets + p * kXcds, 0);
         } else {
             // tile counts, their scan per digit, then one workgroup per tile
             uint32_t *tc = status;                    // ntiles * kBins words, reused per pass
             TQP_LAUNCH("radix_tilecount", (k_radix_tilecount<K, Ord>), dim3(grid_all), dim3(kSortNT), 0, s,
-                       src_k, n, d_n, ord, shift, dbits, tc, ntiles);
+                       src_k, n, pass_n, ord, shift, dbits, tc, ntiles);
             if ((rc = check_launch("radix tile counts"))) return rc;
             TQP_LAUNCH("radix_tilescan", k_radix_tilescan, dim3(1u << dbits), dim3(kScanNT), 0, s, tc,
-                       ntiles, gh, n, d_n);
+                       ntiles, gh, n, pass_n);
             if ((rc = check_launch("radix tile scan"))) return rc;
             rc = launch_cols<K, Ord, false>(sc.npay, sc.rows_out != nullptr, grid_all, s, src_k, dk, x, n,
-                                            d_n, ord, shift, dbits, gh, tc, nullptr, ntiles);
+                                            pass_n, ord, shift, dbits, gh, tc, nullptr, ntiles);
         }
         if (rc) return rc;
         rc = check_launch("radix pass");

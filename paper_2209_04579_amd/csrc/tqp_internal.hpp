@@ -329,6 +329,18 @@ __device__ __forceinline__ void store_any(void *p, int dtype, int64_t i, int64_t
     }
 }
 
+// `v op lit` for a tqp_cmp code, compared as mathematical integers.
+__device__ __forceinline__ bool cmp_holds(int64_t v, int op, int64_t lit) {
+    switch (op) {
+    case TQP_LT: return v < lit;
+    case TQP_LE: return v <= lit;
+    case TQP_GT: return v > lit;
+    case TQP_GE: return v >= lit;
+    case TQP_EQ: return v == lit;
+    default: return v != lit;
+    }
+}
+
 // ---- packed multi-column keys ---------------------------------------------
 // key(i) = sum over terms of mul * f(col[rows ? rows[i] : i]) mod 2^64, with
 // f(v) = v mod m in [0, m) when m > 0, f(v) = v otherwise; a term without a

@@ -20,7 +20,8 @@ from . import (GB_DENSE, GB_SORTED, JOIN_SORTED, filter_into, filter_sum_into,
                gather_into, groupby_agg_into, groupby_agg_terms_into,
                groupby_terms_workspace_bytes, groupby_workspace_bytes, join_into, join_workspace_bytes,
                mlp_predict_into,
-               pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes, str_match_into,
+               filter_sort_into, pack_key_into, pay_bytes_of, sort_into, sort_workspace_bytes,
+               str_match_into,
                tune_set, workspace)
 
 
@@ -49,8 +50,12 @@ class StarQuery:
     """
 
     def __init__(self, fact: dict, dim: dict, day_cut: int, mode: str = "q1",
-                 tuning: dict | None = None, overlap: bool = False):
+                 tuning: dict | None = None, overlap: bool = False, fused: bool = True):
         self.mode = mode
+        # fused: WHERE and the fact side's sort are one operator
+        # (filter_sort_into), so the filtered table is never written; else a
+        # filter writes it and the sort reads it back
+        self.fused = fused
         # library knobs (see tune_knobs()) applied before each run; the
         # "gb.dense_max" entry is the largest key domain aggregated directly
         self.tuning = dict(tuning or {})
@@ -78,12 +83,13 @@ class StarQuery:
         pay = ["fk", "qty"] + (["price", "flag"] if mode == "q2" else [])
         self.pay_names = pay
         self.pay_in = [fact[k] for k in pay]
-        self.pay_out = [torch.empty(max(n, 1), dtype=fact[k].dtype, device=dev) for k in pay]
         self.cnt = _i64(1, dev)
-        self.ws_f = workspace(filter_workspace_bytes(n), dev)
+        if not fused:
+            self.pay_out = [torch.empty(max(n, 1), dtype=fact[k].dtype, device=dev) for k in pay]
+            self.ws_f = workspace(filter_workspace_bytes(n), dev)
         # sorts: the fact side carries its payload, the dim side its category
         self.fk_s = torch.empty(max(n, 1), dtype=fact["fk"].dtype, device=dev)
-        self.fpay_s = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_out[1:]]
+        self.fpay_s = [torch.empty(max(n, 1), dtype=t.dtype, device=dev) for t in self.pay_in[1:]]
         self.pk_s = torch.empty(max(nd, 1), dtype=dim["pk"].dtype, device=dev)
         self.cat_s = torch.empty(max(nd, 1), dtype=dim["cat"].dtype, device=dev)
         self.ws_s = workspace(max(sort_workspace_bytes(n, fact["fk"].dtype,
@@ -152,13 +158,18 @@ class StarQuery:
             self.side.wait_stream(main)
             with torch.cuda.stream(self.side):
                 dim_sort()
-        # 1. WHERE day < cut, carrying the payload columns
-        filter_into([f["day"]], [(0, "<", self.cut)], self.pay_in, self.pay_out, None,
-                    self.cnt, self.ws_f)
-        # 2. sort both join sides (stable), payload moving with the keys
-        sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
-                  key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
-                  pay_out=self.fpay_s)
+        # 1. WHERE day < cut, and 2. sort both join sides (stable), payload
+        # moving with the keys
+        if self.fused:
+            filter_sort_into([f["day"]], [(0, "<", self.cut)], f["fk"], self.fk_s, None,
+                             self.cnt, self.ws_s, key_bits=self.jk_bits, key_min=self.jk_min,
+                             pay_in=self.pay_in[1:], pay_out=self.fpay_s)
+        else:
+            filter_into([f["day"]], [(0, "<", self.cut)], self.pay_in, self.pay_out, None,
+                        self.cnt, self.ws_f)
+            sort_into(self.pay_out[0], None, self.n, self.fk_s, None, self.ws_s, d_n=self.cnt,
+                      key_bits=self.jk_bits, key_min=self.jk_min, pay_in=self.pay_out[1:],
+                      pay_out=self.fpay_s)
         if self.side is not None:
             main.wait_stream(self.side)
         else:

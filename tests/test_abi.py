@@ -99,3 +99,33 @@ def test_predict_argument_errors_without_a_gpu():
     assert L.tqp_mlp_predict(f, 1, None, 10, None, fake, 4, 9, fake, None) == tqp.TQP_EINVAL
     assert L.tqp_mlp_predict(f, 1, None, 11, None, fake, 4, 2, fake, None) == tqp.TQP_EINVAL
     assert L.tqp_mlp_predict(f, 1, None, 0, None, fake, 4, 2, fake, None) == tqp.TQP_OK
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
+def test_filter_sort_argument_errors_without_a_gpu():
+    """Rejected before anything is enqueued (the fake addresses are never
+    dereferenced)."""
+    import paper_2209_04579_amd as tqp
+    L = tqp.lib()
+    cols = (tqp.Col * 1)(tqp.Col(0x10000, 10, 2, 0))
+    pred = (tqp.Pred * 5)(*[tqp.Pred(0, 0, 5)] * 5)
+    key = tqp.Col(0x20000, 10, 2, 0)
+    out = tqp.Col(0x30000, 10, 2, 0)
+    cnt, ws = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000)
+    big = 1 << 30
+
+    def call(c=cols, nc=1, p=pred, np_=1, k=key, o=out, c_=cnt, wsb=big):
+        return L.tqp_filter_sort(c, nc, p, np_, ctypes.byref(k), 0, 0, ctypes.byref(o), None,
+                                 None, None, 0, c_, ws, wsb, None)
+    assert call(np_=0) == tqp.TQP_EINVAL and b"npred" in L.tqp_last_error()
+    assert call(np_=5) == tqp.TQP_EINVAL
+    assert call(nc=0) == tqp.TQP_EINVAL and b"ncols" in L.tqp_last_error()
+    assert call(c_=None) == tqp.TQP_EINVAL and b"d_count" in L.tqp_last_error()
+    assert call(o=tqp.Col(0x30000, 10, 3, 0)) == tqp.TQP_EINVAL
+    assert call(o=tqp.Col(0x30000, 9, 2, 0)) == tqp.TQP_ECAPACITY
+    assert call(k=tqp.Col(0x20002, 10, 2, 0)) == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
+    bad_pred = (tqp.Pred * 1)(tqp.Pred(1, 0, 5))
+    assert call(p=bad_pred) == tqp.TQP_EINVAL and b"predicate 0" in L.tqp_last_error()
+    short = (tqp.Col * 1)(tqp.Col(0x10000, 9, 2, 0))
+    assert call(c=short) == tqp.TQP_EINVAL and b"column 0" in L.tqp_last_error()
+    assert call(wsb=16) == tqp.TQP_ECAPACITY and b"workspace" in L.tqp_last_error()

@@ -54,10 +54,10 @@ def test_q1_replay_is_identical():
             assert np.array_equal(again[k], first[k])
 
 
-def check_q2(cfg, overlap=False):
+def check_q2(cfg, overlap=False, fused=True):
     from paper_2209_04579_amd.pipeline import StarQuery
     q = StarQuery(to_dev(cfg["fact"]), to_dev(cfg["dim"]), cfg["day_cut"], mode="q2",
-                  overlap=overlap)
+                  overlap=overlap, fused=fused)
     q.run()
     got = q.result()
     want = oracle.q2(cfg["fact"], cfg["dim"], cfg["day_cut"])
@@ -74,6 +74,13 @@ def test_q2_reduced_size():
 def test_q2_with_the_dimension_sort_on_a_second_stream():
     cfg = dg.config2(5, n_fact=3_000_000, n_dim=200_000)
     assert check_q2(cfg, overlap=True)["pairs"] > 0
+
+
+def test_q2_with_a_separate_filter_and_sort():
+    """The unfused plan (the filter writes the kept rows, the sort reads them)."""
+    cfg = dg.config2(6, n_fact=2_000_000, n_dim=150_000)
+    assert check_q2(cfg, fused=False)["pairs"] > 0
+    assert check_q2(cfg, overlap=True, fused=False)["pairs"] > 0
 
 
 def test_q2_full_size():
