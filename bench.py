@@ -94,7 +94,8 @@ def record_traffic(fetch_csv: str, write_csv: str, command: str):
     f_scale, w_scale = COPY_BYTES / (f_copy * 1024.0), COPY_BYTES / (w_copy * 1024.0)
     out = {}
     for short, src in KERNEL_FILE.items():
-        names = [k for k in fetch if f"tqp::k_{short}<" in k or f"tqp::k_{short}(" in k]
+        names = [k for k in fetch if any(f"tqp::k_{a}<" in k or f"tqp::k_{a}(" in k
+                                         for a in KERNEL_ALIASES.get(short, (short,)))]
         if not names:
             continue
         fd = sum(fetch[k][0] for k in names)
@@ -169,6 +170,11 @@ KERNEL_FILE = {"filter": "filter.hip", "onesweep": "radix.hpp", "radix_hist": "r
                "pack_key": "gather.hip", "gb_dense": "groupby.hip", "gb_scan": "groupby.hip",
                "gb_tiny": "groupby.hip",
                "gb_diff": "groupby.hip"}
+
+
+# kernels timed under one name (the filtered histogram of tqp_filter_sort
+# and the plain one both launch as "radix_hist")
+KERNEL_ALIASES = {"radix_hist": ("radix_hist", "radix_hist_filt")}
 
 
 def traffic_for(kernel: str):
