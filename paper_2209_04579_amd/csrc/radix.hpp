@@ -84,13 +84,10 @@ __device__ __forceinline__ uint32_t keep_mask(const PassPred &f, const I (&idx)[
     return m;
 }
 
-// 256-bin histograms of every digit in one sweep: each thread reads 16
-// consecutive keys with 16-byte loads and counts them into its wave's LDS
-// histograms; the workgroup then adds its totals to the device histogram.
-// Skewed keys put many lanes of a wave on one counter, and LDS atomics on
-// one address serialize: the lanes sharing the first valid lane's digit are
-// counted by one ballot and one add.
-template <class Ord>
+// Counts the ordinal u of every valid lane into the wave's LDS histograms
+// h[pass][digit].  Skewed keys put many lanes of a wave on one counter, and
+// LDS atomics on one address serialize: the lanes sharing the first valid
+// lane's digit are counted by one ballot and one add.
 __device__ __forceinline__ void count_digits(uint32_t (*h)[kBins], bool valid, uint64_t u,
                                              int npass, int dbits, uint32_t dmask) {
     const uint64_t vm = ballot(valid);
@@ -106,6 +103,9 @@ __device__ __forceinline__ void count_digits(uint32_t (*h)[kBins], bool valid, u
     }
 }
 
+// 256-bin histograms of every digit in one sweep: each thread reads 16
+// consecutive keys with 16-byte loads and counts them into its wave's LDS
+// histograms; the workgroup then adds its totals to the device histogram.
 template <class K, class Ord>
 __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ keys, int64_t n,
                                                         const int64_t *d_n, Ord ord, int npass,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist(const K *__restrict__ ke
         }
 #pragma unroll
         for (int r = 0; r < kHistIPT; r++)
-            count_digits<Ord>(s_h[w], row0 + r < cnt, ord(v[r]), npass, dbits, dmask);
+            count_digits(s_h[w], row0 + r < cnt, ord(v[r]), npass, dbits, dmask);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < npass * kBins; i += kHistNT) {
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kHistNT) void k_radix_hist_filt(const K *__restrict
             const uint32_t j = j0 + lane;
             const bool valid = j < qn;
             const K key = s_q[w][valid ? j : 0];
-            count_digits<Ord>(s_h[w], valid, ord(key), npass, dbits, dmask);
+            count_digits(s_h[w], valid, ord(key), npass, dbits, dmask);
         }
         __syncthreads();                            // ... and read before it is reused
     }
