@@ -618,8 +618,10 @@ static int dense_groupby(const KS &ks, int64_t n, const int64_t *d_n, int64_t ke
     int rc = fill_u64(gacc, 0, int64_t(nagg + 1) * key_span, s);
     if (rc) return rc;
     if (n > 0 && key_span <= kTinySpan) {
+        // no more workgroups than are resident at once (4 per CU at this
+        // kernel's register count): measured 4% faster than twice as many
         int64_t g = ceil_div(n, int64_t(kGbNT) * kTinyR * 8);
-        if (g > 2048) g = 2048;
+        if (g > int64_t(kComputeUnits) * 4) g = int64_t(kComputeUnits) * 4;
         switch (nagg) {
         case 1:
             TQP_LAUNCH("gb_tiny", (k_gb_tiny<KS, 1>), dim3(unsigned(g)), dim3(kGbNT), 0, s, ks, n,

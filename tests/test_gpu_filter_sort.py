@@ -136,3 +136,23 @@ def test_filter_sort_with_tile_count_mode(tqp):
     assert k == len(want_k)
     assert np.array_equal(got_k, want_k)
     assert np.array_equal(got_r, want_r)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_filter_sort_four_payload_columns_and_rows(tqp, dtype):
+    """The widest pass: four payload columns and the row ids (five moved
+    columns), keys spanning four 8-bit digits, an equality predicate on an
+    int8 column."""
+    n = 333_337
+    keys = dg.uniform_int(21, 1, n, -(1 << 31), 1 << 31, dtype)
+    flag = dg.uniform_int(21, 2, n, 0, 3, np.int8)
+    cols, preds = [flag], [(0, "==", 1)]
+    payload = [dg.uniform_int(21, 3 + c, n, -100, 100, t)
+               for c, t in enumerate((np.int64, np.int8, np.int32, np.int64))]
+    want_k, want_r, want_p = expected(cols, preds, keys, payload)
+    k, got_k, got_r, got_p = run(tqp, cols, preds, keys, payload)
+    assert k == len(want_k) and 0 < k < n
+    assert np.array_equal(got_k, want_k)
+    assert np.array_equal(got_r, want_r)
+    for g, w in zip(got_p, want_p):
+        assert np.array_equal(g, w)
