@@ -10,7 +10,8 @@
  * aggregation, here with a group-by (Fig. 4); LIKE over string columns, which
  * Section 2.1 stores as zero-padded (n x m) byte tensors (Q14's CASE); and a
  * model's prediction inside a query (Section 3.3).  The sort is the step a
- * sort-merge join and a sort-based group-by rest on.
+ * sort-merge join and a sort-based group-by rest on; tqp_filter_sort fuses a
+ * filter with it, so that the filtered table is never materialised.
  *
  * Conventions for every entry point:
  *  - Every pointer to column data, row ids, counts, outputs and workspace is
