@@ -36,8 +36,10 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         # no contraction: every fused multiply-add in the source is an explicit fmaf
+        # -fopenmp: only the *_mt whole-query functions (the multi-core timing
+        # leg) use threads; everything else is single-threaded
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -84,6 +86,16 @@ def lib():
         _lib.orc_mlp_predict.argtypes = [i64, vp, vp, i32, vp, vp, i32, i32, vp]
         _lib.orc_q_predict.restype = None
         _lib.orc_q_predict.argtypes = [i64, vp, vp, i64, vp, i32, vp, i32, i32, i32, vp, vp]
+        _lib.orc_max_threads.restype = i32
+        _lib.orc_max_threads.argtypes = []
+        _lib.orc_q1_mt.restype = i64
+        _lib.orc_q1_mt.argtypes = [i32] + list(_lib.orc_q1.argtypes)
+        _lib.orc_q2_mt.restype = i32
+        _lib.orc_q2_mt.argtypes = [i32] + list(_lib.orc_q2.argtypes)
+        _lib.orc_q3_mt.restype = i64
+        _lib.orc_q3_mt.argtypes = [i32, i64, vp, vp, vp, vp, vp,
+                                   i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
+                                   i64, i64, vp, vp, vp, vp]
         _lib.orc_q3.restype = i64
         _lib.orc_q3.argtypes = [i64, vp, vp, vp, vp, vp,
                                 i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp,
@@ -293,21 +305,37 @@ def groupby(keys: np.ndarray, vals, aggs):
     return ok[:ng].copy(), [o[:ng].copy() for o in outs], bool(ovf.value)
 
 
-def q1(fact: dict, dim: dict, day_cut: int):
-    """SELECT cat, SUM(qty), COUNT(*) ... WHERE day < day_cut GROUP BY cat."""
+def max_threads() -> int:
+    """Threads the multi-core whole-query functions use by default."""
+    return int(lib().orc_max_threads())
+
+
+def _mt(fn_1, fn_mt, threads):
+    """The single-thread function (threads 0: the parity checker) or its
+    multi-threaded twin bound to a thread count."""
+    if not threads:
+        return fn_1
+    return lambda *a: fn_mt(int(threads), *a)
+
+
+def q1(fact: dict, dim: dict, day_cut: int, threads: int = 0):
+    """SELECT cat, SUM(qty), COUNT(*) ... WHERE day < day_cut GROUP BY cat.
+    threads > 0 runs the multi-threaded twin (same result)."""
     fk, qty, day = _c(fact["fk"], np.int32), _c(fact["qty"], np.int64), _c(fact["day"], np.int32)
     pk, cat = _c(dim["pk"], np.int32), _c(dim["cat"], np.int32)
     cap = max(len(pk), 1)
     k, s, c = (np.empty(cap, np.int64) for _ in range(3))
     ovf = ctypes.c_int(0)
-    ng = lib().orc_q1(len(fk), _p(fk), _p(qty), _p(day), day_cut, len(pk), _p(pk),
+    ng = _mt(lib().orc_q1, lib().orc_q1_mt, threads)(
+        len(fk), _p(fk), _p(qty), _p(day), day_cut, len(pk), _p(pk),
                       _p(cat), cap, _p(k), _p(s), _p(c), ctypes.byref(ovf))
     return {"key": k[:ng].copy(), "sum_qty": s[:ng].copy(), "count": c[:ng].copy(),
             "overflow": bool(ovf.value)}
 
 
-def q2(fact: dict, dim: dict, day_cut: int):
-    """Skewed star query: low-cardinality and per-fk group-bys after the join."""
+def q2(fact: dict, dim: dict, day_cut: int, threads: int = 0):
+    """Skewed star query: low-cardinality and per-fk group-bys after the join.
+    threads > 0 runs the multi-threaded twin (same result)."""
     fk = _c(fact["fk"], np.int32)
     qty = _c(fact["qty"], np.int64)
     price = _c(fact["price"], np.int64)
@@ -320,7 +348,8 @@ def q2(fact: dict, dim: dict, day_cut: int):
     b = [np.empty(capb, np.int64) for _ in range(3)]
     nga, ngb = ctypes.c_int64(0), ctypes.c_int64(0)
     ovf = ctypes.c_int(0)
-    lib().orc_q2(len(fk), _p(fk), _p(qty), _p(price), _p(flag), _p(day), day_cut,
+    _mt(lib().orc_q2, lib().orc_q2_mt, threads)(
+        len(fk), _p(fk), _p(qty), _p(price), _p(flag), _p(day), day_cut,
                  len(pk), _p(pk), _p(cat), capa, *[_p(x) for x in a], ctypes.byref(nga),
                  capb, *[_p(x) for x in b], ctypes.byref(ngb), ctypes.byref(ovf))
     na, nb = nga.value, ngb.value
@@ -330,8 +359,9 @@ def q2(fact: dict, dim: dict, day_cut: int):
             "b_count": b[2][:nb].copy(), "overflow": bool(ovf.value)}
 
 
-def q3(cfg: dict):
-    """Star join over three filtered dims, GROUP BY d1.cat * 5 + d2.cat."""
+def q3(cfg: dict, threads: int = 0):
+    """Star join over three filtered dims, GROUP BY d1.cat * 5 + d2.cat.
+    threads > 0 runs the multi-threaded twin (same result)."""
     f, d1, d2, d3 = cfg["fact"], cfg["d1"], cfg["d2"], cfg["d3"]
     fk1, fk2, fk3 = (_c(f[k], np.int32) for k in ("fk1", "fk2", "fk3"))
     qty, price = _c(f["qty"], np.int64), _c(f["price"], np.int64)
@@ -341,7 +371,8 @@ def q3(cfg: dict):
     cap = 1 << 16
     k, s, c = (np.empty(cap, np.int64) for _ in range(3))
     ovf = ctypes.c_int(0)
-    ng = lib().orc_q3(len(fk1), _p(fk1), _p(fk2), _p(fk3), _p(qty), _p(price),
+    ng = _mt(lib().orc_q3, lib().orc_q3_mt, threads)(
+        len(fk1), _p(fk1), _p(fk2), _p(fk3), _p(qty), _p(price),
                       len(a1[0]), *[_p(x) for x in a1], len(a2[0]), *[_p(x) for x in a2],
                       len(a3[0]), *[_p(x) for x in a3], cfg["attr_cut"], cap,
                       _p(k), _p(s), _p(c), ctypes.byref(ovf))

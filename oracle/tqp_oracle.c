@@ -763,3 +763,151 @@ void orc_q_predict(int64_t n, const int8_t *rating, const int32_t *year, int64_t
         if (cls == 1) out_pos[r]++;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * The same whole queries on several host threads: the CPU-baseline leg
+ * that times the oracle on every core of the host.  Each thread runs the
+ * loop body of orc_q1 / orc_q2 / orc_q3 above over its own contiguous share
+ * of the fact rows into its own group accumulator; the accumulators are then
+ * added group by group (sums of __int128 values, so the merge order changes
+ * nothing) and emitted as before.  The parity checker is the single-thread
+ * function; these are checked against it.
+ * ---------------------------------------------------------------------- */
+#include <omp.h>
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
+static void groups_merge(groups *dst, const groups *src)
+{
+    for (int64_t q = 0; q < src->ng; q++)
+        groups_add(dst, src->key[q], src->s[3 * q], src->s[3 * q + 1], src->s[3 * q + 2]);
+}
+
+int64_t orc_q1_mt(int threads, int64_t nf, const int32_t *fk, const int64_t *qty,
+                  const int32_t *day, int64_t day_cut, int64_t nd,
+                  const int32_t *pk, const int32_t *cat, int64_t cap,
+                  int64_t *o_cat, int64_t *o_sum, int64_t *o_cnt, int *ovf)
+{
+    dimindex d;
+    dimindex_build(&d, nd, pk);
+    groups *gt = (groups *)calloc((size_t)threads, sizeof(groups));
+#pragma omp parallel num_threads(threads)
+    {
+        groups *g = &gt[omp_get_thread_num()];
+        groups_init(g, 64);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nf; i++) {
+            if (!((int64_t)day[i] < day_cut)) continue;
+            int64_t s = hmap_get(&d.h, fk[i]);
+            if (s < 0) continue;
+            for (int64_t j = d.head[s]; j != -1; j = d.next[j])
+                groups_add(g, cat[j], qty[i], 1, 0);
+        }
+    }
+    groups all;
+    groups_init(&all, 64);
+    for (int t = 0; t < threads; t++) {
+        if (gt[t].cap) { groups_merge(&all, &gt[t]); groups_free(&gt[t]); }
+    }
+    free(gt);
+    *ovf = 0;
+    int64_t ng = groups_emit(&all, cap, o_cat, o_sum, o_cnt, NULL, ovf);
+    groups_free(&all); dimindex_free(&d);
+    return ng;
+}
+
+int orc_q2_mt(int threads, int64_t nf, const int32_t *fk, const int64_t *qty,
+              const int64_t *price, const int8_t *flag, const int32_t *day,
+              int64_t day_cut, int64_t nd, const int32_t *pk, const int32_t *cat,
+              int64_t capa, int64_t *a_key, int64_t *a_qty, int64_t *a_price,
+              int64_t *a_cnt, int64_t *nga,
+              int64_t capb, int64_t *b_key, int64_t *b_qty, int64_t *b_cnt,
+              int64_t *ngb, int *ovf)
+{
+    dimindex d;
+    dimindex_build(&d, nd, pk);
+    groups *ga = (groups *)calloc((size_t)threads, sizeof(groups));
+    groups *gb = (groups *)calloc((size_t)threads, sizeof(groups));
+#pragma omp parallel num_threads(threads)
+    {
+        const int t = omp_get_thread_num();
+        groups_init(&ga[t], 64);
+        groups_init(&gb[t], 1 << 16);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nf; i++) {
+            if (!((int64_t)day[i] < day_cut)) continue;
+            int64_t s = hmap_get(&d.h, fk[i]);
+            if (s < 0) continue;
+            for (int64_t j = d.head[s]; j != -1; j = d.next[j]) {
+                int64_t c = cat[j];
+                int64_t cm = ((c % 2) + 2) % 2;
+                groups_add(&ga[t], (int64_t)flag[i] * 2 + cm, qty[i], price[i], 1);
+                groups_add(&gb[t], fk[i], qty[i], 1, 0);
+            }
+        }
+    }
+    groups a, b;
+    groups_init(&a, 64);
+    groups_init(&b, nd > 0 ? nd : 1);
+    for (int t = 0; t < threads; t++) {
+        if (ga[t].cap) { groups_merge(&a, &ga[t]); groups_free(&ga[t]); }
+        if (gb[t].cap) { groups_merge(&b, &gb[t]); groups_free(&gb[t]); }
+    }
+    free(ga); free(gb);
+    *ovf = 0;
+    *nga = groups_emit(&a, capa, a_key, a_qty, a_price, a_cnt, ovf);
+    *ngb = groups_emit(&b, capb, b_key, b_qty, b_cnt, NULL, ovf);
+    groups_free(&a); groups_free(&b); dimindex_free(&d);
+    return 0;
+}
+
+int64_t orc_q3_mt(int threads, int64_t nf, const int32_t *fk1, const int32_t *fk2,
+                  const int32_t *fk3, const int64_t *qty, const int64_t *price,
+                  int64_t n1, const int32_t *pk1, const int32_t *cat1, const int32_t *attr1,
+                  int64_t n2, const int32_t *pk2, const int32_t *cat2, const int32_t *attr2,
+                  int64_t n3, const int32_t *pk3, const int32_t *attr3,
+                  int64_t attr_cut, int64_t cap, int64_t *o_key, int64_t *o_sum,
+                  int64_t *o_cnt, int *ovf)
+{
+    dimindex d1, d2, d3;
+    dimindex_build(&d1, n1, pk1);
+    dimindex_build(&d2, n2, pk2);
+    dimindex_build(&d3, n3, pk3);
+    groups *gt = (groups *)calloc((size_t)threads, sizeof(groups));
+#pragma omp parallel num_threads(threads)
+    {
+        groups *g = &gt[omp_get_thread_num()];
+        groups_init(g, 256);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nf; i++) {
+            int64_t s3 = hmap_get(&d3.h, fk3[i]);
+            if (s3 < 0) continue;
+            for (int64_t j3 = d3.head[s3]; j3 != -1; j3 = d3.next[j3]) {
+                if (!((int64_t)attr3[j3] < attr_cut)) continue;
+                int64_t s2 = hmap_get(&d2.h, fk2[i]);
+                if (s2 < 0) continue;
+                for (int64_t j2 = d2.head[s2]; j2 != -1; j2 = d2.next[j2]) {
+                    if (!((int64_t)attr2[j2] < attr_cut)) continue;
+                    int64_t s1 = hmap_get(&d1.h, fk1[i]);
+                    if (s1 < 0) continue;
+                    for (int64_t j1 = d1.head[s1]; j1 != -1; j1 = d1.next[j1]) {
+                        if (!((int64_t)attr1[j1] < attr_cut)) continue;
+                        groups_add(g, (int64_t)cat1[j1] * 5 + cat2[j2],
+                                   (__int128)qty[i] * (__int128)price[i], 1, 0);
+                    }
+                }
+            }
+        }
+    }
+    groups all;
+    groups_init(&all, 256);
+    for (int t = 0; t < threads; t++) {
+        if (gt[t].cap) { groups_merge(&all, &gt[t]); groups_free(&gt[t]); }
+    }
+    free(gt);
+    *ovf = 0;
+    int64_t ng = groups_emit(&all, cap, o_key, o_sum, o_cnt, NULL, ovf);
+    groups_free(&all);
+    dimindex_free(&d1); dimindex_free(&d2); dimindex_free(&d3);
+    return ng;
+}

@@ -333,6 +333,28 @@ def test_q3_matches_numpy_statement():
     assert np.array_equal(r["count"], np.bincount(ix).astype(np.int64))
 
 
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_multithreaded_whole_queries_equal_the_single_thread_oracle(threads):
+    """The multi-core timing leg (per-thread group accumulators merged at the
+    end) returns the single-thread oracle's bytes, including with duplicate
+    dimension keys, misses and an empty fact table."""
+    c1 = dg.config1(3, n_fact=50_000, n_dim=700)
+    c1["dim"]["pk"][::7] = 5                      # duplicate keys and misses
+    for fact, dim in ((c1["fact"], c1["dim"]),
+                      ({k: v[:0] for k, v in c1["fact"].items()}, c1["dim"])):
+        a = oracle.q1(fact, dim, c1["day_cut"])
+        b = oracle.q1(fact, dim, c1["day_cut"], threads=threads)
+        assert all(np.array_equal(a[k], b[k]) for k in a)
+    c2 = dg.config2(1, n_fact=120_000, n_dim=9_000)
+    a = oracle.q2(c2["fact"], c2["dim"], c2["day_cut"])
+    b = oracle.q2(c2["fact"], c2["dim"], c2["day_cut"], threads=threads)
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+    c3 = dg.config3(2, n_fact=150_000, dims=(4_000, 600, 25))
+    a = oracle.q3(c3)
+    b = oracle.q3(c3, threads=threads)
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+
+
 # -------------------------------------------- filter + aggregate (Q6 shape) ----
 
 def wrap64(x: int) -> int:
