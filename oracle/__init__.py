@@ -53,6 +53,8 @@ def lib():
         i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
         _lib.orc_filter.restype = i64
         _lib.orc_filter.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp]
+        _lib.orc_semijoin.restype = i64
+        _lib.orc_semijoin.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
         _lib.orc_gather.restype = None
         _lib.orc_gather.argtypes = [i64, vp, i32, vp, vp]
         _lib.orc_sort.restype = i32
@@ -224,6 +226,25 @@ def q_predict(cfg: dict):
                         _p(_c(cfg["model"], np.float32)), cfg["hidden"], cfg["classes"], nr,
                         _p(pos), _p(cnt))
     return {"positive": pos, "count": cnt}
+
+
+def semijoin_rows(keys, sets) -> np.ndarray:
+    """Row ids (int32, ascending) of the left table whose key keys[s][i]
+    occurs among sets[s] (the other side's keys) for every s.
+
+    keys: list of equal-length 1-D int8/int32/int64 arrays (the left side's
+    key columns); sets: list of 1-D integer arrays, one per key column.
+    """
+    keys = [_c(k) for k in keys]
+    sets = [_c(t) for t in sets]
+    n = len(keys[0]) if keys else 0
+    dts = np.array([DT[k.dtype] for k in keys] or [0], dtype=np.int32)
+    sdt = np.array([DT[t.dtype] for t in sets] or [0], dtype=np.int32)
+    sn = np.array([len(t) for t in sets] or [0], dtype=np.int64)
+    out = np.empty(max(n, 1), dtype=np.int32)
+    cnt = lib().orc_semijoin(n, len(keys), _ptr_array(keys), _p(dts), _ptr_array(sets), _p(sdt),
+                             _p(sn), _p(out))
+    return out[:cnt].copy()
 
 
 def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:

@@ -206,6 +206,38 @@ static int64_t hmap_put(hmap *h, int64_t key, int64_t slot)
 }
 
 /* ------------------------------------------------------------------------
+ * Semi-join: row i of the left table is kept when, for every set s, its key
+ * keys[s][i] equals at least one of the set_n[s] keys of the other side
+ * (setkeys[s]).  This is the relational definition of L semi-join R on an
+ * equality, taken over several right sides at once (a conjunction).  Returns
+ * the number of kept rows; writes their ids ascending.  Each right side is
+ * put in a hash set first; lookups are exact integer comparisons.
+ * ---------------------------------------------------------------------- */
+int64_t orc_semijoin(int64_t n, int nsets, const void *const *keys, const int *dtypes,
+                     const void *const *setkeys, const int *setdt, const int64_t *set_n,
+                     int32_t *out_rows)
+{
+    hmap *h = (hmap *)malloc((size_t)(nsets > 0 ? nsets : 1) * sizeof(hmap));
+    for (int s = 0; s < nsets; s++) {
+        hmap_init(&h[s], set_n[s]);
+        for (int64_t j = 0; j < set_n[s]; j++)
+            hmap_put(&h[s], value_at(setkeys[s], setdt[s], j), j);
+    }
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int keep = 1;
+        for (int s = 0; s < nsets && keep; s++)
+            if (hmap_get(&h[s], value_at(keys[s], dtypes[s], i)) < 0)
+                keep = 0;
+        if (keep)
+            out_rows[cnt++] = (int32_t)i;
+    }
+    for (int s = 0; s < nsets; s++) hmap_free(&h[s]);
+    free(h);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------
  * Inner equi-join, bag semantics, as a hash join: a chained hash table over R
  * (chains in ascending j), probed by every L row in order.  The pairs are then
  * put in the canonical order (key, i, j).  Returns the pair count; writes the

@@ -51,6 +51,49 @@ def test_filter_brute_force(seed):
         assert got.tolist() == want, preds
 
 
+@pytest.mark.parametrize("seed", range(5))
+def test_semijoin_brute_force(seed):
+    """Semi-join over one to three right sides: a Python set per side and a
+    row loop, on tiny tables with duplicates, misses, negative keys and mixed
+    dtypes."""
+    n = 200 + 41 * seed
+    left = rng_cols(seed, n, dom=30)
+    for trial in range(8):
+        k = 1 + trial % 3
+        cols = [(trial + q) % 3 for q in range(k)]
+        keys = [left[c] for c in cols]
+        sets = []
+        for q in range(k):
+            m = (trial * 5 + q * 11 + seed) % 40
+            dt = (np.int8, np.int32, np.int64)[(trial + q + seed) % 3]
+            sets.append(dg.uniform_int(seed + 100 * trial, 20 + q, m, -30, 30, dt))
+        got = oracle.semijoin_rows(keys, sets)
+        py = [set(int(v) for v in t) for t in sets]
+        want = [i for i in range(n) if all(int(keys[q][i]) in py[q] for q in range(k))]
+        assert got.tolist() == want, (trial, [len(t) for t in sets])
+
+
+def test_semijoin_matches_numpy_isin_and_edge_cases():
+    rng = np.random.default_rng(7)
+    n = 50_000
+    k1 = rng.integers(-(2 ** 40), 2 ** 40, n, dtype=np.int64)
+    k2 = rng.integers(0, 1000, n, dtype=np.int64).astype(np.int32)
+    s1 = np.concatenate([k1[rng.integers(0, n, 3000)], rng.integers(0, 2 ** 40, 500)])
+    s2 = rng.integers(0, 1000, 300).astype(np.int32)
+    want = np.nonzero(np.isin(k1, s1) & np.isin(k2, s2))[0].astype(np.int32)
+    assert np.array_equal(oracle.semijoin_rows([k1, k2], [s1, s2]), want)
+    # an empty right side keeps nothing; the full domain keeps everything
+    assert len(oracle.semijoin_rows([k2], [np.zeros(0, np.int32)])) == 0
+    assert np.array_equal(oracle.semijoin_rows([k2], [np.arange(1000, dtype=np.int32)]),
+                          np.arange(n, dtype=np.int32))
+    # empty left side; int64 extremes compare exactly (no wrap, no truncation)
+    assert len(oracle.semijoin_rows([k1[:0]], [s1])) == 0
+    ext = np.array([I64_MIN, -1, 0, I64_MAX, I32_MAX + 1], np.int64)
+    assert oracle.semijoin_rows([ext], [np.array([I64_MAX, I32_MAX], np.int64)]).tolist() == [3]
+    assert oracle.semijoin_rows([ext], [np.array([I32_MAX], np.int32)]).tolist() == []
+    assert oracle.semijoin_rows([ext], [np.array([-1], np.int8)]).tolist() == [1]
+
+
 def test_filter_literal_outside_column_range():
     c8 = np.array([-128, -1, 0, 1, 127], np.int8)
     # mathematical comparison: nothing in int8 is >= 200, everything is > -1000
