@@ -122,7 +122,10 @@ void tqp_profile_reset(void);
  * tqp_partition_sort re-sorts before it sorts the whole input instead;
  * "sort.mode" picks how a radix pass finds where each tile's digit runs go:
  * 0 = decoupled look-back over earlier tiles, 1 = every tile's digit counts
- * first, then a scan per digit (one more read of the keys, no waiting).
+ * first, then a scan per digit (one more read of the keys, no waiting);
+ * "semijoin.wg" is tqp_semijoin's workgroup size in units of 256 threads
+ * (1, 2 or 4; a larger workgroup takes a larger tile) and "semijoin.per_cu"
+ * its threads per compute unit in the same units.
  * Knobs change how the work is done, never results.  They are process-wide
  * and read when a call enqueues its kernels; setting them concurrently with
  * calls on other threads is a race.
@@ -132,6 +135,17 @@ void tqp_profile_reset(void);
 int tqp_tune_set(const char *name, int value);
 int tqp_tune_get(const char *name, int *value, int *lo, int *hi);
 const char *tqp_tune_name(int index);
+
+/* ------------------------------------------------------------------------
+ * tqp_minmax -- the value range of a column: d_out[0] = min and d_out[1] =
+ * max of the first count keys (count = min(*d_n, key->len) with d_n, else
+ * key->len), as int64; with no keys, d_out = {INT64_MAX, INT64_MIN}.  The
+ * statistics a planner keeps per column (Section 2.2 compiles a query into
+ * an operator plan): they fix a sort's pass count, a dense group-by's domain
+ * and a key set's range.  key: any integer dtype.  d_out: device, 2 int64s.
+ * Nothing is synchronized.
+ * ---------------------------------------------------------------------- */
+int tqp_minmax(const tqp_col *key, const int64_t *d_n, int64_t *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
  * tqp_filter -- WHERE with stream compaction (Section 2.3: Q6's filters).
@@ -300,6 +314,50 @@ int tqp_join(const tqp_col *lkey, const int32_t *lrows, const int64_t *d_nl,
              int64_t *d_count,
              const tqp_ranges *ranges, int64_t range_cap, int64_t *d_nranges,
              void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Semi-join reduction (in front of the joins of a star query, Section 2.3's
+ * join queries).  A fact row can only join (inner) with a dimension when its
+ * foreign key occurs among that dimension's keys, so rows failing the test
+ * for any dimension are dropped before the sort-merge joins; the joins'
+ * result is unchanged.
+ *
+ * A key set is a bitmap over the key range [lo, lo + nbits): bit (k - lo) of
+ * bits (word (k - lo) / 32, bit (k - lo) % 32) is set when key k is in the
+ * set.  bits is device memory of ceil(nbits / 32) uint32 words, owned by the
+ * caller; nbits in [0, TQP_KEYSET_MAX_BITS] (0 = the empty set), and
+ * lo + nbits - 1 <= INT64_MAX.  Both calls return TQP_EINVAL otherwise.
+ *
+ * tqp_keyset_build: clears bits, then sets the bit of each of the first
+ *   count keys (count = min(*d_n, key->len) with d_n, else key->len) that lies
+ *   in the range; keys outside it are ignored.  key: any integer dtype.
+ * tqp_semijoin: keeps row i of an n-row table (n = keys[0].len) when
+ *   keys[s][i] is in sets[s] for every s < nsets (nsets in [1, 4]).  The key
+ *   columns share one dtype (int32 or int64) and length n.
+ *   out_rows   : optional, capacity n; kept row ids, ascending.
+ *   keys_out   : optional array of nsets columns (an entry with data NULL is
+ *                skipped): keys_out[s][k] = keys[s][out_rows[k]], capacity n.
+ *   pay_out[c] : pay_out[c][k] = pay_in[c][out_rows[k]] (npay in [0, 4],
+ *                same dtype, len >= n); only kept rows of pay_in are read.
+ *   d_count    : required; receives the number of kept rows.
+ * Sets are staged in on-chip memory while they fit (up to 36864 words in all
+ * with 1024-thread workgroups, a quarter of that per 256 threads with
+ * smaller ones); the others are read from device memory.  Workspace:
+ * tqp_semijoin_workspace_bytes(n, key dtype).  Nothing is synchronized.
+ * ---------------------------------------------------------------------- */
+#define TQP_KEYSET_MAX_BITS (1ll << 36)
+typedef struct {
+    const uint32_t *bits;
+    int64_t         lo;
+    int64_t         nbits;
+} tqp_keyset;
+int tqp_keyset_build(const tqp_col *key, const int64_t *d_n, int64_t lo, int64_t nbits,
+                     uint32_t *bits, void *stream);
+size_t tqp_semijoin_workspace_bytes(int64_t n, int dtype);
+int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
+                 const tqp_col *keys_out, const tqp_col *pay_in, const tqp_col *pay_out,
+                 int npay, int32_t *out_rows, int64_t *d_count,
+                 void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * tqp_groupby_agg -- GROUP BY key with SUM / COUNT / SUM of products

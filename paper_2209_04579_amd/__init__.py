@@ -22,7 +22,8 @@ import torch
 __all__ = [
     "TqpError", "lib", "library_path", "filter", "filter_into", "gather_into", "gather",
     "pack_key_into", "sort", "sort_into", "filter_sort_into", "join", "join_into", "join_ranges",
-    "groupby_agg", "groupby_agg_into", "OPS", "DTYPES",
+    "groupby_agg", "groupby_agg_into", "keyset_build_into", "semijoin_into", "minmax",
+    "minmax_into", "OPS", "DTYPES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,6 +67,10 @@ class Ranges(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("lstart", ctypes.c_void_p),
                 ("lcnt", ctypes.c_void_p), ("rstart", ctypes.c_void_p),
                 ("rcnt", ctypes.c_void_p)]
+
+
+class KeySet(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("lo", ctypes.c_int64), ("nbits", ctypes.c_int64)]
 
 
 _lib = None
@@ -140,6 +145,15 @@ def lib():
         L.tqp_groupby_agg_terms.restype = i32
         L.tqp_groupby_agg_terms.argtypes = [P(KeyTerm), i32, i64, vp, i64, i64, P(Col), i32, vp,
                                             P(Agg), i32, P(Col), P(vp), vp, vp, sz, vp]
+        L.tqp_minmax.restype = i32
+        L.tqp_minmax.argtypes = [P(Col), vp, vp, vp]
+        L.tqp_keyset_build.restype = i32
+        L.tqp_keyset_build.argtypes = [P(Col), vp, i64, i64, vp, vp]
+        L.tqp_semijoin_workspace_bytes.restype = sz
+        L.tqp_semijoin_workspace_bytes.argtypes = [i64, i32]
+        L.tqp_semijoin.restype = i32
+        L.tqp_semijoin.argtypes = [P(Col), P(KeySet), i32, P(Col), P(Col), P(Col), i32, vp, vp,
+                                   vp, sz, vp]
         _lib = L
     return _lib
 
@@ -253,6 +267,64 @@ def filter(cols, preds, payload=(), want_rows=True):
     filter_into(cols, preds, list(payload), pout, rows, cnt, ws)
     k = int(cnt.item())
     return (rows[:k] if rows is not None else None), [p[:k] for p in pout]
+
+
+# ------------------------------------------------------------ statistics ----
+
+def minmax_into(col, d_out, d_n=None, stream=None):
+    """Enqueues d_out[0] = min, d_out[1] = max of the column (device int64 x 2)."""
+    _check(lib().tqp_minmax(ctypes.byref(_col(col)), _ptr(d_n), _ptr(d_out), _stream(stream)))
+
+
+def minmax(col):
+    """(min, max) of a device column as Python ints, None when it is empty
+    (reads the two values back: one synchronization)."""
+    out = torch.empty(2, dtype=torch.int64, device=col.device)
+    minmax_into(col, out)
+    lo, hi = (int(v) for v in out.cpu().tolist())
+    return None if lo > hi else (lo, hi)
+
+
+# -------------------------------------------------------------- semi-join ----
+
+def keyset_words(nbits: int) -> int:
+    """uint32 words of a key set over nbits keys."""
+    return (int(nbits) + 31) // 32
+
+
+def keyset_build_into(key, lo: int, nbits: int, bits, d_n=None, stream=None):
+    """Enqueues the key set {key[i] : i < count} over [lo, lo + nbits) into the
+    device int32 tensor bits (keyset_words(nbits) words); keys outside the
+    range are ignored."""
+    if nbits > 0 and (bits.dtype != torch.int32 or bits.numel() < keyset_words(nbits)
+                      or not bits.is_cuda):
+        raise ValueError("bits must be an int32 device tensor of keyset_words(nbits) words")
+    _check(lib().tqp_keyset_build(ctypes.byref(_col(key)), _ptr(d_n), int(lo), int(nbits),
+                                  _ptr(bits), _stream(stream)))
+
+
+def semijoin_workspace_bytes(n: int, dtype) -> int:
+    return lib().tqp_semijoin_workspace_bytes(int(n), DTYPES[dtype])
+
+
+def semijoin_into(keys, sets, out_rows, d_count, ws, keys_out=None, payload_in=(),
+                  payload_out=(), stream=None):
+    """Enqueues the semi-join reduction: rows i where keys[s][i] is in sets[s]
+    for every s, compacted in ascending order.  sets: [(bits, lo, nbits)];
+    keys_out: optional list (entries may be None) of compacted key columns."""
+    ns = len(keys)
+    if len(sets) != ns:
+        raise ValueError("one key set per key column")
+    ks = (KeySet * ns)(*[KeySet(_ptr(b) if int(nb) > 0 else None, int(lo), int(nb))
+                         for b, lo, nb in sets])
+    ko = None
+    if keys_out is not None:
+        ko = (Col * ns)()
+        for i, t in enumerate(keys_out):
+            ko[i] = _col(t) if t is not None else Col(None, 0, 0, 0)
+    _check(lib().tqp_semijoin(_cols(keys), ks, ns, ko, _cols(list(payload_in)),
+                              _cols(list(payload_out)), len(payload_in), _ptr(out_rows),
+                              _ptr(d_count), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 # ----------------------------------------------------------------- gather ----

@@ -71,6 +71,30 @@ int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s) {
     return check_launch("fill_u32");
 }
 
+// Clears nsec sections of words: section k starts at p + k * stride and is
+// cleared over its first ceil(count / per) * width words, count =
+// min(*d_n, n).  Lets a call planned for capacity n clear only what its
+// actual count will touch.
+__global__ void k_clear_sections(uint32_t *p, int nsec, int64_t stride, const int64_t *d_n,
+                                 int64_t n, int64_t per, int64_t width) {
+    const int64_t cnt = count_of(d_n, n);
+    int64_t need = ceil_div(cnt > 0 ? cnt : 1, per) * width;
+    if (need > stride) need = stride;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < need * nsec;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[(i / need) * stride + i % need] = 0;
+}
+
+int clear_sections(uint32_t *dst, int nsec, int64_t stride, const int64_t *d_n, int64_t n,
+                   int64_t per, int64_t width, hipStream_t s) {
+    if (nsec <= 0 || stride <= 0) return TQP_OK;
+    int64_t blocks = ceil_div(int64_t(nsec) * stride, 256);
+    if (blocks > 2048) blocks = 2048;
+    TQP_LAUNCH("clear_sections", k_clear_sections, dim3(unsigned(blocks)), dim3(256), 0, s, dst,
+               nsec, stride, d_n, n, per, width);
+    return check_launch("clear_sections");
+}
+
 // Min and max of the first count keys.  out[0], out[1] must hold INT64_MAX
 // and INT64_MIN beforehand.
 template <class K>
@@ -112,7 +136,10 @@ int launch_minmax(const void *key, int dtype, int64_t n, const int64_t *d_n,
     if (n <= 0) return TQP_OK;
     int64_t blocks = ceil_div(n, 256 * 16);
     if (blocks > 2048) blocks = 2048;
-    if (dtype == TQP_INT32)
+    if (dtype == TQP_INT8)
+        TQP_LAUNCH("minmax", k_minmax<int8_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
+                           static_cast<const int8_t *>(key), n, d_n, out);
+    else if (dtype == TQP_INT32)
         TQP_LAUNCH("minmax", k_minmax<int32_t>, dim3(unsigned(blocks)), dim3(256), 0, s,
                            static_cast<const int32_t *>(key), n, d_n, out);
     else
@@ -160,8 +187,10 @@ static const KnobDef kKnobs[kTuneCount] = {
     {"gbscan.per_cu", 2, 1, 4},
     {"part.ovf_cap", 65536, 1, 65536},
     {"sort.mode", 0, 0, 1},
+    {"semijoin.per_cu", 4, 1, 8},
+    {"semijoin.wg", 4, 1, 4},
 };
-static int g_knob[kTuneCount] = {4, 2, 1, 4, 2, 65536, 0};
+static int g_knob[kTuneCount] = {4, 2, 1, 4, 2, 65536, 0, 4, 4};
 
 int tune(TuneKnob k) { return g_knob[k]; }
 
@@ -197,6 +226,16 @@ TQP_API int tqp_tune_get(const char *name, int *value, int *lo, int *hi) {
 
 TQP_API const char *tqp_tune_name(int index) {
     return index >= 0 && index < tqp::kTuneCount ? tqp::kKnobs[index].name : nullptr;
+}
+
+TQP_API int tqp_minmax(const tqp_col *key, const int64_t *d_n, int64_t *d_out, void *stream) {
+    tqp::clear_error();
+    if (!key || !tqp::dtype_ok(key->dtype) || key->len < 0 || (key->len > 0 && !key->data) ||
+        !tqp::col_aligned(key->data, key->dtype))
+        return tqp::set_error(TQP_EINVAL, "tqp_minmax: bad key column");
+    if (!d_out) return tqp::set_error(TQP_EINVAL, "tqp_minmax: d_out is required");
+    return tqp::launch_minmax(key->data, key->dtype, key->len, d_n, d_out,
+                              tqp::as_stream(stream));
 }
 
 TQP_API const char *tqp_version(void) { return "tqp-mi355x 0.1 (gfx950)"; }

@@ -9,7 +9,8 @@ def test_knob_registry_ranges_and_errors():
     from paper_2209_04579_amd import TqpError, tune_knobs, tune_set
     knobs = tune_knobs()
     assert set(knobs) == {"filter.per_cu", "sort.per_cu", "rle.per_cu", "match.per_cu",
-                          "gbscan.per_cu", "part.ovf_cap", "sort.mode"}
+                          "gbscan.per_cu", "part.ovf_cap", "sort.mode", "semijoin.per_cu",
+                          "semijoin.wg"}
     for name, (value, lo, hi) in knobs.items():
         assert 0 <= lo <= value <= hi
     name, (value, lo, hi) = "filter.per_cu", knobs["filter.per_cu"]

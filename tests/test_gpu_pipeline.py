@@ -89,46 +89,72 @@ def test_q2_full_size():
     assert got["pairs"] == got["rows_filtered"]
 
 
-def run_q3(cfg, dev_cfg=None):
+PLANS3 = ["semijoin", "sort"]
+
+
+def run_q3(cfg, dev_cfg=None, plan="semijoin"):
     from paper_2209_04579_amd.pipeline import StarQuery3
     d = dev_cfg or {t: to_dev(cfg[t]) for t in ("fact", "d1", "d2", "d3")}
-    q = StarQuery3(d["fact"], d["d1"], d["d2"], d["d3"], cfg["attr_cut"])
+    q = StarQuery3(d["fact"], d["d1"], d["d2"], d["d3"], cfg["attr_cut"], plan=plan)
     q.run()
     return q, q.result()
 
 
-def check_q3(cfg, dev_cfg=None):
-    q, got = run_q3(cfg, dev_cfg)
-    want = oracle.q3(cfg)
+def check_q3(cfg, dev_cfg=None, plan="semijoin", want=None):
+    q, got = run_q3(cfg, dev_cfg, plan)
+    want = want or oracle.q3(cfg)
     assert not want["overflow"]
     for k in ("key", "sum_qp", "count"):
         assert np.array_equal(got[k], want[k]), k
     # COUNT conserves the last join's pairs
     assert int(got["count"].sum()) == got["pairs"][2]
+    if plan == "semijoin":
+        # pk is unique in every dimension, so every reduced row joins once
+        assert got["pairs"] == [got["reduced"]] * 3
     return q, got
 
 
-def test_q3_reduced_size():
+@pytest.mark.parametrize("plan", PLANS3)
+def test_q3_reduced_size(plan):
     cfg = dg.config3(0, n_fact=3_000_000, dims=(100_000, 10_000, 25))
-    _, got = check_q3(cfg)
+    _, got = check_q3(cfg, plan=plan)
     assert got["pairs"][0] > 0 and got["pairs"][2] > 0
 
 
-def test_q3_degenerate():
+@pytest.mark.parametrize("plan", PLANS3)
+def test_q3_degenerate(plan):
     # one-row dims, and dims whose filter keeps nothing
     c = dg.config3(1, n_fact=20_000, dims=(1, 1, 1))
-    check_q3(c)
+    check_q3(c, plan=plan)
     c = dg.config3(2, n_fact=50_000, dims=(3000, 500, 25))
     c["attr_cut"] = 0
-    _, got = check_q3(c)
+    _, got = check_q3(c, plan=plan)
     assert got["pairs"] == [0, 0, 0] and len(got["key"]) == 0
     c = dg.config3(3, n_fact=7, dims=(50, 20, 25))
-    check_q3(c)
+    check_q3(c, plan=plan)
 
 
-def test_q3_replay_is_identical():
+def test_q3_fact_keys_outside_the_dimensions():
+    # foreign keys below and above every dimension key, and dims whose keys
+    # do not start at 0: the key sets must reject them, not wrap
+    c = dg.config3(5, n_fact=200_003, dims=(5000, 700, 25))
+    for t, off in (("d1", 1000), ("d2", -300), ("d3", 7)):
+        c[t]["pk"] = (c[t]["pk"] + off).astype(np.int32)
+    f = c["fact"]
+    f["fk1"] = (f["fk1"] + 990).astype(np.int32)
+    f["fk2"] = (f["fk2"] - 310).astype(np.int32)
+    f["fk3"] = (f["fk3"] + 5).astype(np.int32)
+    f["fk1"][::101] = np.iinfo(np.int32).min
+    f["fk2"][::103] = np.iinfo(np.int32).max
+    want = oracle.q3(c)
+    for plan in PLANS3:
+        check_q3(c, plan=plan, want=want)
+
+
+@pytest.mark.parametrize("plan", PLANS3)
+def test_q3_replay_is_identical(plan):
     cfg = dg.config3(4, n_fact=1_000_000, dims=(50_000, 5_000, 25))
-    q, first = check_q3(cfg)
+    q, first = check_q3(cfg, plan=plan)
     for _ in range(2):
         q.run()
         again = q.result()
@@ -136,13 +162,19 @@ def test_q3_replay_is_identical():
             assert np.array_equal(again[k], first[k])
 
 
+@pytest.mark.timeout(400)
 def test_q3_full_size():
-    """The 600M-row three-dimension star at full size: tables drawn on the GPU
-    (bit-identical to the host generator), the oracle run on host copies."""
+    """The 600M-row three-dimension star at full size, both plans: tables
+    drawn on the GPU (bit-identical to the host generator), the oracle run on
+    host copies."""
     from tqp_datagen import device as dgd
     dcfg = dgd.config3(0, device="cuda")
     cfg = {t: {k: v.cpu().numpy() for k, v in dcfg[t].items()} for t in ("fact", "d1", "d2", "d3")}
     cfg["attr_cut"] = dcfg["attr_cut"]
-    _, got = check_q3(cfg, dcfg)
-    assert len(got["key"]) == 125
-    assert 100_000_000 < got["pairs"][0] < 140_000_000
+    want = oracle.q3(cfg)
+    for plan in PLANS3:
+        q, got = check_q3(cfg, dcfg, plan=plan, want=want)
+        assert len(got["key"]) == 125
+        del q
+        torch.cuda.empty_cache()
+    assert 4_000_000 < got["pairs"][2] < 5_600_000
