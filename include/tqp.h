@@ -360,6 +360,26 @@ int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
                  void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * tqp_semijoin_noalloc -- tqp_semijoin without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation).  Same arguments, results
+ * and errors as tqp_semijoin; its tickets and look-back statuses live in a
+ * static 8 MiB device array of the library (one per device, held until the
+ * process ends, located on the first call on each device), cleared by a
+ * kernel at the start of every call.  It allocates nothing and calls no
+ * allocating routine.  Tables of more than
+ * tqp_semijoin_noalloc_max_rows(dtype) rows (every int32 table up to
+ * 2^31 - 1 rows; about 1.6e9 rows of int64 keys) are rejected with
+ * TQP_ECAPACITY.  All calls on one device share the array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialized by the caller.
+ * ---------------------------------------------------------------------- */
+int64_t tqp_semijoin_noalloc_max_rows(int dtype);
+int tqp_semijoin_noalloc(const tqp_col *keys, const tqp_keyset *sets, int nsets,
+                         const tqp_col *keys_out, const tqp_col *pay_in, const tqp_col *pay_out,
+                         int npay, int32_t *out_rows, int64_t *d_count, void *stream);
+
+/* ------------------------------------------------------------------------
  * tqp_groupby_agg -- GROUP BY key with SUM / COUNT / SUM of products
  * (Section 2.3 aggregates; Fig. 4's group-by aggregate).
  *   key       : int32/int64 keys, capacity key->len, actual count d_n.

@@ -151,6 +151,11 @@ def lib():
         L.tqp_keyset_build.argtypes = [P(Col), vp, i64, i64, vp, vp]
         L.tqp_semijoin_workspace_bytes.restype = sz
         L.tqp_semijoin_workspace_bytes.argtypes = [i64, i32]
+        L.tqp_semijoin_noalloc_max_rows.restype = i64
+        L.tqp_semijoin_noalloc_max_rows.argtypes = [i32]
+        L.tqp_semijoin_noalloc.restype = i32
+        L.tqp_semijoin_noalloc.argtypes = [P(Col), P(KeySet), i32, P(Col), P(Col), P(Col), i32,
+                                           vp, vp, vp]
         L.tqp_semijoin.restype = i32
         L.tqp_semijoin.argtypes = [P(Col), P(KeySet), i32, P(Col), P(Col), P(Col), i32, vp, vp,
                                    vp, sz, vp]
@@ -325,6 +330,29 @@ def semijoin_into(keys, sets, out_rows, d_count, ws, keys_out=None, payload_in=(
     _check(lib().tqp_semijoin(_cols(keys), ks, ns, ko, _cols(list(payload_in)),
                               _cols(list(payload_out)), len(payload_in), _ptr(out_rows),
                               _ptr(d_count), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def semijoin_noalloc_max_rows(dtype) -> int:
+    return lib().tqp_semijoin_noalloc_max_rows(DTYPES[dtype])
+
+
+def semijoin_noalloc_into(keys, sets, out_rows, d_count, keys_out=None, payload_in=(),
+                          payload_out=(), stream=None):
+    """semijoin_into without a workspace: the library's static scratch is used
+    (calls that overlap on one device race)."""
+    ns = len(keys)
+    if len(sets) != ns:
+        raise ValueError("one key set per key column")
+    ks = (KeySet * ns)(*[KeySet(_ptr(b) if int(nb) > 0 else None, int(lo), int(nb))
+                         for b, lo, nb in sets])
+    ko = None
+    if keys_out is not None:
+        ko = (Col * ns)()
+        for i, t in enumerate(keys_out):
+            ko[i] = _col(t) if t is not None else Col(None, 0, 0, 0)
+    _check(lib().tqp_semijoin_noalloc(_cols(keys), ks, ns, ko, _cols(list(payload_in)),
+                                      _cols(list(payload_out)), len(payload_in), _ptr(out_rows),
+                                      _ptr(d_count), _stream(stream)))
 
 
 # ----------------------------------------------------------------- gather ----

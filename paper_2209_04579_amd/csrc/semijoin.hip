@@ -16,6 +16,8 @@
 // LDS tests.  The surviving rows are compacted in ascending order: a block
 // scan inside the tile and a decoupled look-back across tiles give each its
 // output slot, where it is written straight from registers.
+#include <mutex>
+
 #include "tqp_internal.hpp"
 
 namespace tqp {
@@ -368,24 +370,26 @@ TQP_API size_t tqp_semijoin_workspace_bytes(int64_t n, int dtype) {
     return semijoin_ws(n < 0 ? 0 : n, dtype);
 }
 
-TQP_API int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
-                         const tqp_col *keys_out, const tqp_col *pay_in, const tqp_col *pay_out,
-                         int npay, int32_t *out_rows, int64_t *d_count, void *ws, size_t ws_bytes,
-                         void *stream) {
-    clear_error();
+// Validates the arguments, then clears the tickets and look-back statuses in
+// `words` (the caller's workspace, or the library's static scratch) and
+// launches the scan.  words_cap: uint64 words available at `words`.
+static int semijoin_run(const char *who, const tqp_col *keys, const tqp_keyset *sets, int nsets,
+                        const tqp_col *keys_out, const tqp_col *pay_in, const tqp_col *pay_out,
+                        int npay, int32_t *out_rows, int64_t *d_count, uint64_t *words,
+                        int64_t words_cap, void *stream) {
     if (!keys || !sets || nsets < 1 || nsets > kSjMaxSets)
-        return set_error(TQP_EINVAL, "tqp_semijoin: nsets must be in [1, %d] with keys and sets",
+        return set_error(TQP_EINVAL, "%s: nsets must be in [1, %d] with keys and sets", who,
                          kSjMaxSets);
     if (npay < 0 || npay > kSjMaxPay || (npay > 0 && (!pay_in || !pay_out)))
-        return set_error(TQP_EINVAL, "tqp_semijoin: npay must be in [0, %d] with both arrays",
+        return set_error(TQP_EINVAL, "%s: npay must be in [0, %d] with both arrays", who,
                          kSjMaxPay);
-    if (!d_count) return set_error(TQP_EINVAL, "tqp_semijoin: d_count is required");
+    if (!d_count) return set_error(TQP_EINVAL, "%s: d_count is required", who);
     const int64_t n = keys[0].len;
     const int dt = keys[0].dtype;
     if (n < 0 || n > INT32_MAX)
-        return set_error(TQP_EINVAL, "tqp_semijoin: bad row count %lld", (long long)n);
+        return set_error(TQP_EINVAL, "%s: bad row count %lld", who, (long long)n);
     if (dt != TQP_INT32 && dt != TQP_INT64)
-        return set_error(TQP_EINVAL, "tqp_semijoin: key columns must be int32 or int64");
+        return set_error(TQP_EINVAL, "%s: key columns must be int32 or int64", who);
     SemiArgs a = {};
     bool vec = true;
     int lds_words = 0;
@@ -395,27 +399,27 @@ TQP_API int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
         if (keys[s].dtype != dt || keys[s].len != n || (n > 0 && !keys[s].data) ||
             !col_aligned(keys[s].data, dt))
             return set_error(TQP_EINVAL,
-                             "tqp_semijoin: key column %d differs in dtype or length, or is unaligned", s);
+                             "%s: key column %d differs in dtype or length, or is unaligned", who, s);
         if (sets[s].nbits < 0 || sets[s].nbits > TQP_KEYSET_MAX_BITS || (sets[s].nbits > 0 && !sets[s].bits) ||
             (sets[s].nbits > 0 && sets[s].lo > INT64_MAX - sets[s].nbits + 1))
-            return set_error(TQP_EINVAL, "tqp_semijoin: key set %d is invalid", s);
+            return set_error(TQP_EINVAL, "%s: key set %d is invalid", who, s);
         vec = vec && reinterpret_cast<uintptr_t>(keys[s].data) % 16 == 0;
         a.key[s] = keys[s].data;
         a.bits[s] = sets[s].bits;
         a.lo[s] = sets[s].lo;
         a.nbits[s] = uint64_t(sets[s].nbits);
-        const int64_t words = ceil_div(sets[s].nbits, 32);
-        if (words > 0 && lds_words + words <= lds_budget) {
+        const int64_t words_s = ceil_div(sets[s].nbits, 32);
+        if (words_s > 0 && lds_words + words_s <= lds_budget) {
             a.lds_off[s] = lds_words;
-            a.lds_len[s] = int32_t(words);
-            lds_words += int(words);
+            a.lds_len[s] = int32_t(words_s);
+            lds_words += int(words_s);
         } else {
             a.lds_off[s] = -1;
             a.lds_len[s] = 0;
         }
         if (keys_out && keys_out[s].data) {
             if (keys_out[s].dtype != dt || keys_out[s].len < n)
-                return set_error(TQP_EINVAL, "tqp_semijoin: keys_out[%d] has a bad dtype or length", s);
+                return set_error(TQP_EINVAL, "%s: keys_out[%d] has a bad dtype or length", who, s);
             a.key_out[s] = keys_out[s].data;
         }
     }
@@ -425,20 +429,19 @@ TQP_API int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
             (n > 0 && (!pay_in[c].data || !pay_out[c].data)) ||
             !col_aligned(pay_in[c].data, pay_in[c].dtype) ||
             !col_aligned(pay_out[c].data, pay_out[c].dtype))
-            return set_error(TQP_EINVAL, "tqp_semijoin: payload %d has a bad dtype, length or pointer", c);
+            return set_error(TQP_EINVAL, "%s: payload %d has a bad dtype, length or pointer", who, c);
         a.pin[c] = pay_in[c].data;
         a.pout[c] = pay_out[c].data;
         a.paylg[c] = pay_in[c].dtype == TQP_INT8 ? 0 : pay_in[c].dtype == TQP_INT32 ? 2 : 3;
     }
-    const size_t need = semijoin_ws(n, dt);
-    if (!ws || ws_bytes < need)
-        return set_error(TQP_ECAPACITY, "tqp_semijoin: workspace needs %zu bytes", need);
-    hipStream_t s = as_stream(stream);
     const int64_t tile = dt == TQP_INT32 ? sj_min_tile<int32_t>() : sj_min_tile<int64_t>();
     const int64_t ntiles = ceil_div(n, tile);        // an upper bound for every set count
-    Carver cv(ws);
-    uint64_t *words = cv.take<uint64_t>(kSjXcds / 2 + (ntiles > 0 ? ntiles : 1));
-    int rc = fill_u64(words, 0, kSjXcds / 2 + (ntiles > 0 ? ntiles : 1), s);
+    const int64_t nwords = kSjXcds / 2 + (ntiles > 0 ? ntiles : 1);
+    if (!words || words_cap < nwords)
+        return set_error(TQP_ECAPACITY, "%s: scratch needs %lld bytes", who,
+                         (long long)(nwords * 8));
+    hipStream_t s = as_stream(stream);
+    int rc = fill_u64(words, 0, nwords, s);
     if (rc) return rc;
     a.npay = npay;
     a.lds_words = lds_words;
@@ -455,5 +458,77 @@ TQP_API int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
     rc = dt == TQP_INT32 ? launch_semijoin<int32_t>(nsets, wg, grid, lds, s, a)
                          : launch_semijoin<int64_t>(nsets, wg, grid, lds, s, a);
     if (rc) return rc;
-    return check_launch("tqp_semijoin");
+    return check_launch(who);
+}
+
+TQP_API int tqp_semijoin(const tqp_col *keys, const tqp_keyset *sets, int nsets,
+                         const tqp_col *keys_out, const tqp_col *pay_in, const tqp_col *pay_out,
+                         int npay, int32_t *out_rows, int64_t *d_count, void *ws, size_t ws_bytes,
+                         void *stream) {
+    clear_error();
+    if (reinterpret_cast<uintptr_t>(ws) % 8 != 0)
+        return set_error(TQP_EINVAL, "tqp_semijoin: the workspace must be 8-byte aligned");
+    return semijoin_run("tqp_semijoin", keys, sets, nsets, keys_out, pay_in, pay_out, npay,
+                        out_rows, d_count, static_cast<uint64_t *>(ws), int64_t(ws_bytes / 8),
+                        stream);
+}
+
+// ---- the same scan with library-held scratch ------------------------------
+// For callers that cannot allocate device memory (code under graph capture,
+// serving loops, harnesses that forbid allocation): the tickets and
+// look-back statuses live in a file-scope device array instead of a
+// caller's workspace.  Each device the library runs on holds its own copy
+// until the process ends.
+constexpr int64_t kSjScratchWords = int64_t(1) << 20;       // 8 MiB
+static __device__ __align__(256) uint64_t scratch[kSjScratchWords];
+constexpr int kSjMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t *g_scratch_ptr[kSjMaxDevices];
+
+// The device address of this device's scratch (the host-side name of the
+// array is not one), looked up on the first call on each device.
+static int sj_scratch(uint64_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return set_error(TQP_EHIP, "tqp_semijoin_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kSjMaxDevices)
+        return set_error(TQP_EINVAL, "tqp_semijoin_noalloc: device %d beyond the %d supported", dev,
+                         kSjMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(TQP_EHIP, "tqp_semijoin_noalloc: scratch address: %s",
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint64_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return TQP_OK;
+}
+
+TQP_API int64_t tqp_semijoin_noalloc_max_rows(int dtype) {
+    if (dtype != TQP_INT32 && dtype != TQP_INT64) return 0;
+    const int64_t tile = dtype == TQP_INT32 ? sj_min_tile<int32_t>() : sj_min_tile<int64_t>();
+    const int64_t rows = (kSjScratchWords - kSjXcds / 2) * tile;
+    return rows < INT32_MAX ? rows : INT32_MAX;
+}
+
+TQP_API int tqp_semijoin_noalloc(const tqp_col *keys, const tqp_keyset *sets, int nsets,
+                                 const tqp_col *keys_out, const tqp_col *pay_in,
+                                 const tqp_col *pay_out, int npay, int32_t *out_rows,
+                                 int64_t *d_count, void *stream) {
+    clear_error();
+    if (keys && (keys[0].dtype == TQP_INT32 || keys[0].dtype == TQP_INT64) &&
+        keys[0].len > tqp_semijoin_noalloc_max_rows(keys[0].dtype))
+        return set_error(TQP_ECAPACITY,
+                         "tqp_semijoin_noalloc: %lld rows exceed the static scratch's %lld",
+                         (long long)keys[0].len,
+                         (long long)tqp_semijoin_noalloc_max_rows(keys[0].dtype));
+    uint64_t *words = nullptr;
+    int rc = sj_scratch(&words);
+    if (rc) return rc;
+    return semijoin_run("tqp_semijoin_noalloc", keys, sets, nsets, keys_out, pay_in, pay_out,
+                        npay, out_rows, d_count, words, kSjScratchWords, stream);
 }
