@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark: rows/s of the filter -> sort -> join -> group-by pipeline on the
-skewed star-schema workload, with the dominant kernel's HBM roofline and the
-CPU oracle timed beside it.
+"""Benchmark: rows/s of the filter -> join -> group-by pipeline on the
+three-dimension star schema, with the dominant kernel's HBM roofline and the
+CPU oracle timed beside it on the host's cores.
 
-Workload (one step = one whole query over one batch of resident input):
-  fact 60M rows {fk int32 Zipf s=1 over 2M keys, qty int64 [1,5000] cents,
-  price int64 [100,1e7] cents, flag int8 [0,3), day int32 [0,2557)},
-  dim 2M rows {pk = permutation, cat int32 [0,25)};
-  WHERE day < 1278, JOIN fk = pk,
-  GROUP BY (flag, cat mod 2): SUM(qty), SUM(price), COUNT;  GROUP BY fk: SUM(qty), COUNT.
+Headline workload (one step = one whole query over resident input):
+  fact 600M rows {fk1 int32 U[0,1e6), fk2 int32 U[0,1e5), fk3 int32 U[0,25),
+  qty int64 cents U[1,5000], price int64 cents U[100,1e7]};
+  d1 1M rows {pk, cat U[0,25), attr U[0,100)}, d2 100k rows {pk, cat U[0,5),
+  attr}, d3 25 rows {pk, attr = 4 pk};
+  WHERE d_i.attr < 20 (each dimension keeps ~20%), JOIN fk3 = d3.pk,
+  fk2 = d2.pk, fk1 = d1.pk, GROUP BY d1.cat * 5 + d2.cat: SUM(qty * price),
+  COUNT(*).
+
+The other workloads are side entries, each with its own roofline: the skewed
+60M-row star, the small 1M-row star, the Q6- and Q14-shaped queries, the
+prediction query, the learned-vs-radix partitioned join (200M x 50M int64
+keys) and the batch of 256 star queries.
 
 Prints one JSON line.  Only one GPU is used.
 """
@@ -18,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 METRIC = "rows/s filter→join→group-by, % peak HBM GB/s; learned vs radix partition"
+COPY_BYTES = 1 << 31           # the plain copy this script times (2 GiB read, 2 GiB written)
 
 
 def parse():
@@ -34,33 +43,53 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--n-fact", type=int, default=60_000_000)
-    ap.add_argument("--n-dim", type=int, default=2_000_000)
+    ap.add_argument("--only", choices=("star600m", "star60m"), default=None,
+                    help="run one workload's timed steps only (for counter profiles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000,
+                    help="fact rows of the headline workload the CPU oracle is timed on")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel events")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-radix partition comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-sequential comparison")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the side workloads (60M and 1M stars, Q6, Q14, prediction)")
     ap.add_argument("--learned-left", type=int, default=200_000_000)
     ap.add_argument("--learned-right", type=int, default=50_000_000)
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-fact-hi", type=int, default=20_000_000)
     ap.add_argument("--side-reps", type=int, default=5,
-                    help="timed repetitions of each side comparison")
-    ap.add_argument("--no-configs", action="store_true",
-                    help="skip the small-star and three-dimension-star throughput lines")
+                    help="timed repetitions of each side comparison (median reported)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 counter_collection.csv files "
-                         "(--pmc FETCH_SIZE, --pmc WRITE_SIZE of this script) into "
-                         "profiles/<kernel>_star60m_traffic.json")
+                         "(--pmc FETCH_SIZE, --pmc WRITE_SIZE of this script with --only TAG) "
+                         "into profiles/<kernel>_<TAG>_traffic.json")
+    ap.add_argument("--traffic-tag", choices=("star600m", "star60m"), default="star600m")
     ap.add_argument("--record-command", default="",
                     help="the rocprofv3 command lines, stored with the traffic figures")
     return ap.parse_args()
 
 
-COPY_BYTES = 1 << 31           # the plain copy this script times (2 GiB read, 2 GiB written)
+# ------------------------------------------------------- counter traffic ----
+
+KERNEL_FILE = {"semijoin": "semijoin.hip", "filter": "filter.hip", "onesweep": "radix.hpp",
+               "radix_hist": "radix.hpp", "rle": "join.hip", "join_match": "join.hip",
+               "join_expand": "join.hip", "pack_key": "gather.hip", "gather": "gather.hip",
+               "gb_dense": "groupby.hip", "gb_scan": "groupby.hip", "gb_tiny": "groupby.hip",
+               "gb_diff": "groupby.hip", "keyset_set": "semijoin.hip"}
+# kernels timed under one name (the filtered histogram of tqp_filter_sort
+# and the plain one both launch as "radix_hist")
+KERNEL_ALIASES = {"radix_hist": ("radix_hist", "radix_hist_filt")}
+
+
+def source_sha(kernel_file: str) -> str:
+    h = hashlib.sha256()
+    for f in (kernel_file, "tqp_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2209_04579_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _counter_means(path: str, counter: str) -> dict:
@@ -78,18 +107,20 @@ def _counter_means(path: str, counter: str) -> dict:
     return {k: (d, tot / d, mx) for k, (d, tot, mx) in acc.items()}
 
 
-def record_traffic(fetch_csv: str, write_csv: str, command: str):
+def record_traffic(fetch_csv: str, write_csv: str, tag: str, command: str):
     """Counter-measured HBM bytes per launch of each library kernel.
 
     FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch and scaled by what
     the same counter reads for the plain 2 GiB copy in the same run (the
-    largest single non-library dispatch), so the figure is in the copy's
-    bytes."""
+    largest dispatch of the runtime's buffer-copy kernel), so the figure is
+    in the copy's bytes."""
     fetch = _counter_means(fetch_csv, "FETCH_SIZE")
     write = _counter_means(write_csv, "WRITE_SIZE")
 
     def copy_kib(tab):
-        return max(v[2] for k, v in tab.items() if "tqp::" not in k)
+        # the plain copy is the runtime's buffer-copy kernel (the largest
+        # dispatch of it: the 2 GiB copy)
+        return max(v[2] for k, v in tab.items() if "copyBuffer" in k)
     f_copy, w_copy = copy_kib(fetch), copy_kib(write)
     f_scale, w_scale = COPY_BYTES / (f_copy * 1024.0), COPY_BYTES / (w_copy * 1024.0)
     out = {}
@@ -103,84 +134,23 @@ def record_traffic(fetch_csv: str, write_csv: str, command: str):
         wn = [k for k in names if k in write]
         wd = sum(write[k][0] for k in wn)
         wk = sum(write[k][0] * write[k][1] for k in wn) / wd if wd else 0.0
-        rec = {"kernel": short, "source_sha": source_sha(src), "dispatches": fd,
+        rec = {"kernel": short, "workload": tag, "source_sha": source_sha(src), "dispatches": fd,
                "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
                "copy_fetch_kib": round(f_copy, 1), "copy_write_kib": round(w_copy, 1),
                "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
                "bytes_per_launch": int(fk * 1024 * f_scale + wk * 1024 * w_scale),
                "command": command}
-        path = os.path.join(ROOT, "profiles", f"{short}_star60m_traffic.json")
+        path = os.path.join(ROOT, "profiles", f"{short}_{tag}_traffic.json")
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1)
         out[short] = rec["bytes_per_launch"]
     print(json.dumps(out))
 
 
-def kernel_bytes(name: str, launches: int, st: dict) -> float | None:
-    """Algorithmic HBM bytes of all launches of one kernel in one step.
-
-    Each kernel's bytes are its per-element figure times the elements its
-    launches process (the figures are stated in the design notes)."""
-    n, kept, nd, pairs = st["n"], st["kept"], st["nd"], st["pairs"]
-    ul, ur, gb = st["uniq_l"], st["uniq_r"], st["groups_b"]
-    if name == "filter":
-        return n * (4 + 4 + 8 + 8 + 1) + kept * (4 + 8 + 8 + 1)
-    if name == "radix_hist":
-        # fact side (filtered): fk and day of every row, one keep bit written
-        # per row; dim side: pk
-        return n * (4 + 4 + 1 / 8) + 4.0 * nd
-    if name == "onesweep":
-        # the fact side moves fk (4) + qty (8) + price (8) + flag (1): its
-        # first pass reads them for every row (at this selectivity every
-        # cache line holds kept rows) plus the keep bits and writes the kept
-        # rows, later passes read and write the kept rows; every dim pass
-        # reads and writes pk (4) + cat (4)
-        p = st["passes"]
-        return (n * (21 + 1 / 8) + kept * 21) + (p - 1) * kept * 2.0 * 21 + p * nd * 2.0 * 8
-    if name == "rle":
-        return 4.0 * (kept + nd) + 8.0 * (ul + ur)
-    if name == "join_match":
-        return ul * (4 + 4 + 4 + 4 + 6 * 8)
-    if name == "join_expand":
-        return pairs * (4 + 4 + 4) + ul * 6 * 8
-    if name == "pack_key":
-        # reads both position columns, flag and cat; writes the int32 key
-        return pairs * (4 + 4 + 1 + 4 + 4)
-    if name in ("gb_dense", "gb_tiny"):
-        # the packed key built in the kernel: both position columns, flag and
-        # cat through them; then qty and price through the fact position
-        return pairs * (4 + 4 + 1 + 4 + 8 + 8)
-    if name == "gb_scan":
-        return pairs * (4 + 4 + 8) + gb * (4 + 16)
-    if name == "gb_diff":
-        return gb * 32.0
-    return None
-
-
-def source_sha(kernel_file: str) -> str:
-    h = hashlib.sha256()
-    for f in (kernel_file, "tqp_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2209_04579_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-KERNEL_FILE = {"filter": "filter.hip", "onesweep": "radix.hpp", "radix_hist": "radix.hpp",
-               "rle": "join.hip", "join_match": "join.hip", "join_expand": "join.hip",
-               "pack_key": "gather.hip", "gb_dense": "groupby.hip", "gb_scan": "groupby.hip",
-               "gb_tiny": "groupby.hip",
-               "gb_diff": "groupby.hip"}
-
-
-# kernels timed under one name (the filtered histogram of tqp_filter_sort
-# and the plain one both launch as "radix_hist")
-KERNEL_ALIASES = {"radix_hist": ("radix_hist", "radix_hist_filt")}
-
-
-def traffic_for(kernel: str):
+def traffic_for(kernel: str, tag: str):
     """Counter-measured HBM bytes per launch, if a profile of the current source exists."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_star60m_traffic.json")
-    if not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{tag}_traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_FILE:
         return None
     with open(path) as fh:
         t = json.load(fh)
@@ -188,6 +158,87 @@ def traffic_for(kernel: str):
         return None
     return t.get("bytes_per_launch")
 
+
+# --------------------------------------------------- algorithmic bytes ----
+
+def _passes(bits: int) -> int:
+    """Radix passes of a key of `bits` significant bits (8-bit digits or fewer)."""
+    return (bits + 7) // 8
+
+
+def star3_kernel_bytes(name: str, st: dict) -> float | None:
+    """Algorithmic HBM bytes of all launches of one kernel in one step of the
+    three-dimension star's semi-join plan (the figures are stated in the
+    design notes).  n fact rows; S rows kept by the semi-join; c0, c1, c2
+    rows after the fk3, fk2, fk1 joins; nd / kd dimension rows / kept rows."""
+    n, S = st["n"], st["S"]
+    c0, c1, c2 = st["pairs"]
+    nd, kd = st["nd"], st["kd"]
+    p = st["passes"]                  # (d1, d2, d3, fk3 sort, fk2 sort, fk1 sort)
+    if name == "semijoin":
+        # the three foreign-key columns read once; row id + three keys
+        # written per kept row
+        return 12.0 * n + 16.0 * S
+    if name == "filter":
+        # attr read per dimension row; pk (and cat) read and written per kept row
+        return sum(4.0 * nd[i] + kd[i] * 2 * (4 + 4 * (i < 2)) for i in range(3))
+    if name == "keyset_set":
+        return 4.0 * sum(kd)
+    if name == "radix_hist":
+        return 4.0 * (sum(kd) + S + c0 + c1)
+    if name == "onesweep":
+        dims = sum(p[i] * kd[i] * 2 * (4 + 4 * (i < 2)) for i in range(3))
+        return dims + p[3] * S * 2 * 16 + p[4] * c0 * 2 * 12 + p[5] * c1 * 2 * 12
+    joins = ((S, kd[2], c0), (c0, kd[1], c1), (c1, kd[0], c2))
+    if name == "rle":
+        return sum((l + r) * 4.0 + 2 * min(l, r) * 8.0 for l, r, _ in joins)
+    if name == "join_match":
+        return sum(min(l, r) * 64.0 for l, r, _ in joins)
+    if name == "join_expand":
+        return sum(c * 8.0 + min(l, r) * 48.0 for l, r, c in joins)
+    if name == "gather":
+        return 12.0 * (3 * c0 + 3 * c1 + c2)
+    if name == "gb_dense":
+        return 36.0 * c2
+    return None
+
+
+def star_kernel_bytes(name: str, st: dict) -> float | None:
+    """Algorithmic HBM bytes of all launches of one kernel in one step of the
+    one-dimension star (60M skewed rows or 1M small rows): pay = bytes of the
+    fact payload the sort moves (fk + qty [+ price + flag]), gbv = bytes the
+    low-cardinality group-by reads per joined row."""
+    n, kept, nd, pairs = st["n"], st["kept"], st["nd"], st["pairs"]
+    ul, ur, gb, pay = st["uniq_l"], st["uniq_r"], st["groups_b"], st["pay"]
+    if name == "filter":
+        return n * (4 + pay) + kept * pay
+    if name == "radix_hist":
+        # fact side (filtered): fk and day of every row, one keep bit written
+        # per row; dim side: pk
+        return n * (4 + 4 + 1 / 8) + 4.0 * nd
+    if name == "onesweep":
+        # the first fact pass reads the payload of every row (at this
+        # selectivity every cache line holds kept rows) plus the keep bits and
+        # writes the kept rows; later passes read and write the kept rows;
+        # every dim pass reads and writes pk (4) + cat (4)
+        p = st["passes"]
+        return (n * (pay + 1 / 8) + kept * pay) + (p - 1) * kept * 2.0 * pay + p * nd * 2.0 * 8
+    if name == "rle":
+        return 4.0 * (kept + nd) + 8.0 * (ul + ur)
+    if name == "join_match":
+        return ul * (4 + 4 + 4 + 4 + 6 * 8)
+    if name == "join_expand":
+        return pairs * (4 + 4 + 4) + ul * 6 * 8
+    if name in ("gb_dense", "gb_tiny"):
+        return pairs * st["gbv"]
+    if name == "gb_scan":
+        return pairs * (4 + 4 + 8) + gb * (4 + 16)
+    if name == "gb_diff":
+        return gb * 32.0
+    return None
+
+
+# ---------------------------------------------------------------- timing ----
 
 def _timed(fn, reps, stream):
     """Median ms of fn() over reps calls on stream (one untimed call first)."""
@@ -206,11 +257,359 @@ def _timed(fn, reps, stream):
     return ts[len(ts) // 2]
 
 
+def timed_steps(fn, steps, warmup, stream):
+    """W untimed steps, then K steps between two synchronizations with an
+    event between consecutive steps.  Returns (mean ms over the K steps,
+    median ms of a step)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return ev[0].elapsed_time(ev[-1]) / steps, per[len(per) // 2]
+
+
+def kernel_profile(fn, steps):
+    """{kernel: (launches, total ms)} over `steps` calls of fn with the
+    library's per-launch HIP events (on each launch's stream)."""
+    import torch
+    import paper_2209_04579_amd as tqp
+    tqp.profile_reset()
+    tqp.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    tqp.profile_enable(False)
+    prof = tqp.profile_collect()
+    tqp.profile_reset()
+    return prof
+
+
+def kernel_table(prof, steps, bytes_fn, st):
+    kernels = {}
+    for name, (cnt, tot_ms) in prof.items():
+        per_step = cnt / steps
+        kernels[name] = {"launches_per_step": per_step, "avg_ms": round(tot_ms / cnt, 5),
+                         "ms_per_step": round(tot_ms / steps, 5)}
+        b = bytes_fn(name, st)
+        if b is not None and tot_ms > 0:
+            kernels[name]["algo_bytes_per_step"] = int(b)
+            kernels[name]["algo_GBps"] = round(b / (tot_ms / steps * 1e-3) / 1e9, 1)
+    return kernels
+
+
+def roofline_of(kernels, bytes_fn, st, tag, timed):
+    """The dominant kernel's algorithmic bytes per launch over its average
+    launch time, against the HBM peak."""
+    cands = [k for k in kernels if "algo_bytes_per_step" in kernels[k]]
+    if not cands:
+        return None
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    if dom not in cands:
+        dom = max(cands, key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
+    per_launch = bytes_fn(dom, st) / d["launches_per_step"]
+    achieved = per_launch / (d["avg_ms"] * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, tag) if tag else None,
+            "algo_bytes_per_launch": int(per_launch), "avg_launch_ms": d["avg_ms"],
+            "share_of_step": round(d["ms_per_step"] / sum(k["ms_per_step"]
+                                                          for k in kernels.values()), 3),
+            "timed": timed}
+
+
+def pipeline_of(kernels, ms):
+    b = sum(k.get("algo_bytes_per_step", 0) for k in kernels.values())
+    return {"algo_bytes_per_step": int(b), "GBps": round(b / (ms * 1e-3) / 1e9, 1),
+            "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def stream_copy_gbs(stream):
+    """Plain-copy bandwidth on this run (2 GiB), the scale for the HBM counters."""
+    import torch
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * src.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def host_info() -> dict:
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+# -------------------------------------------------------------- headline ----
+
+def star3_stats(q, res):
+    """Sizes the byte figures need, from a finished run of the star plan."""
+    passes = [_passes(q.jk[0][1]), _passes(q.jk[1][1]), _passes(q.jk[2][1]),
+              _passes(q.jk[2][1]), _passes(q.jk[1][1]), _passes(q.jk[0][1])]
+    return {"n": q.n, "S": res["reduced"], "pairs": res["pairs"], "nd": q.nd,
+            "kd": res["dims_kept"], "passes": passes}
+
+
+def cpu_baseline_star3(args, cfg, q_full_res) -> dict:
+    """The oracle's whole-query function on the first rows of the same fact
+    table (the full dimensions): all host cores (its multi-threaded twin),
+    median of 5 after 2 warm-up runs, and one thread, median of 3; checked
+    against the GPU plan run on the same rows."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2209_04579_amd.pipeline import StarQuery3
+
+    m = min(args.cpu_sample_rows, int(cfg["fact"]["fk1"].numel()))
+    sample = {"fact": {k: v[:m].cpu().numpy() for k, v in cfg["fact"].items()},
+              "attr_cut": cfg["attr_cut"]}
+    for t in ("d1", "d2", "d3"):
+        sample[t] = {k: v.cpu().numpy() for k, v in cfg[t].items()}
+    oracle.lib()
+    threads = oracle.max_threads()
+
+    def run(th, reps, warm):
+        for _ in range(warm):
+            oracle.q3(sample, threads=th)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            want = oracle.q3(sample, threads=th)
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2], want
+    t_mt, want = run(threads, 5, 2)
+    t_1, want1 = run(0, 3, 0)
+    # the GPU plan on the same rows
+    dev_fact = {k: v[:m] for k, v in cfg["fact"].items()}
+    qs = StarQuery3(dev_fact, cfg["d1"], cfg["d2"], cfg["d3"], cfg["attr_cut"])
+    qs.run()
+    got = qs.result()
+    del qs
+    torch.cuda.empty_cache()
+    ok = all(np.array_equal(got[k], want[k]) and np.array_equal(want1[k], want[k])
+             for k in ("key", "sum_qp", "count"))
+    return {"value": round(m / t_mt, 1), "unit": "rows/s", "cores": int(threads),
+            "kind": "oracle", "seconds": round(t_mt, 3), "matches_gpu": bool(ok),
+            "single_thread": {"value": round(m / t_1, 1), "seconds": round(t_1, 3)},
+            **host_info(),
+            "sample": f"the first {m} of the 600M fact rows with the full dimensions "
+                      f"(whole query: three filtered hash joins + hash group-by), the C "
+                      f"oracle's multi-threaded twin on {threads} threads, median of 5 after "
+                      "2 warm-up runs; single_thread: the parity oracle itself, median of 3"}
+
+
+def bench_star3(args, tqp, stream, copy_gbs) -> dict:
+    import torch
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import StarQuery3
+
+    t0 = time.time()
+    cfg = dgd.config3(args.seed, device="cuda")
+    torch.cuda.synchronize()
+    print(f"[bench] star600m: generated 600M fact rows in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    q = StarQuery3(cfg["fact"], cfg["d1"], cfg["d2"], cfg["d3"], cfg["attr_cut"])
+    ms, med = timed_steps(q.run, args.steps, args.warmup, stream)
+    res = q.result()
+    print(f"[bench] star600m: {ms:.3f} ms/step (median {med:.3f}); reduced {res['reduced']}, "
+          f"pairs {res['pairs']}", file=sys.stderr, flush=True)
+    st = star3_stats(q, res)
+    kernels, roofline, pipe = {}, None, None
+    if not args.no_kernel_events:
+        prof = kernel_profile(q.run, args.steps)
+        kernels = kernel_table(prof, args.steps, star3_kernel_bytes, st)
+        roofline = roofline_of(kernels, star3_kernel_bytes, st, "star600m",
+                               f"{args.steps} further steps with per-kernel HIP events")
+        pipe = pipeline_of(kernels, ms)
+    n = q.n
+    del q
+    torch.cuda.empty_cache()
+    cpu = None if (args.no_cpu_baseline or args.only) else cpu_baseline_star3(args, cfg, res)
+    del cfg
+    torch.cuda.empty_cache()
+    return {"ms": ms, "median_ms": med, "n": n, "res": res, "kernels": kernels,
+            "roofline": roofline, "pipeline_hbm": pipe, "cpu_baseline": cpu}
+
+
+# ---------------------------------------------------------- side entries ----
+
+def bench_star60m(args, tqp, stream) -> dict:
+    """The skewed one-dimension star (60M fact rows, Zipf fk), with its roofline."""
+    import torch
+    import tqp_datagen as dg
+    from paper_2209_04579_amd.pipeline import StarQuery
+
+    t0 = time.time()
+    cfg = dg.config2(args.seed)
+    fact = {k: torch.from_numpy(v).cuda() for k, v in cfg["fact"].items()}
+    dim = {k: torch.from_numpy(v).cuda() for k, v in cfg["dim"].items()}
+    print(f"[bench] star60m: generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    q = StarQuery(fact, dim, cfg["day_cut"], mode="q2")
+    ms, med = timed_steps(q.run, args.steps, args.warmup, stream)
+    res = q.result()
+    n, nd = fact["fk"].numel(), dim["pk"].numel()
+    st = {"n": n, "nd": nd, "kept": res["rows_filtered"], "pairs": res["pairs"],
+          "groups_b": len(res["b_key"]), "passes": _passes(q.jk_bits),
+          "uniq_l": len(res["b_key"]), "uniq_r": nd, "pay": 21,
+          "gbv": 4 + 4 + 1 + 4 + 8 + 8}
+    out = {"workload": "skewed star query: fact 60M rows (fk Zipf s=1 over 2M keys), dim 2M; "
+                       "day<1278; join fk=pk; group by (flag, cat mod 2) and by fk",
+           "ms": round(ms, 4), "median_ms": round(med, 4),
+           "rows_per_s": round(n / (ms * 1e-3), 1)}
+    if not args.no_kernel_events:
+        kernels = kernel_table(kernel_profile(q.run, args.steps), args.steps, star_kernel_bytes, st)
+        out["roofline"] = roofline_of(kernels, star_kernel_bytes, st, "star60m",
+                                      f"{args.steps} further steps with per-kernel HIP events")
+        out["pipeline_hbm"] = pipeline_of(kernels, ms)
+        out["kernels"] = kernels
+    del q, fact, dim
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_configs(args, tqp, stream) -> dict:
+    """Throughput of the other query workloads: the small star query (1M fact
+    rows, cache-resident and launch-bound), the Q6-shaped scan (60M rows), the
+    Q14-shaped join (60M items, 2M parts) and the prediction query (20M
+    reviews).  Their results are checked against the oracle by the test suite
+    (full-size cases included), not here."""
+    import torch
+    import tqp_datagen as dg
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import PredictQuery, Q6Scan, Q14Query, StarQuery
+
+    out = {}
+    c1 = dg.config1(args.seed)
+    q = StarQuery({k: torch.from_numpy(v).cuda() for k, v in c1["fact"].items()},
+                  {k: torch.from_numpy(v).cuda() for k, v in c1["dim"].items()}, c1["day_cut"])
+    ms = _timed(q.run, 20, stream)
+    got = q.result()
+    st = {"n": 1_000_000, "nd": 10_000, "kept": got["rows_filtered"], "pairs": got["pairs"],
+          "groups_b": 0, "passes": _passes(q.jk_bits), "uniq_l": 10_000, "uniq_r": 10_000,
+          "pay": 12, "gbv": 4 + 4 + 4 + 8}
+    kernels = kernel_table(kernel_profile(q.run, 20), 20, star_kernel_bytes, st)
+    out["small_star"] = {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat "
+                                     "(16 MB of input: cache-resident, launch-bound)",
+                         "ms": round(ms, 4), "rows_per_s": round(1_000_000 / (ms * 1e-3), 1),
+                         "groups": int(len(got["key"])),
+                         "roofline": roofline_of(kernels, star_kernel_bytes, st, None,
+                                                 "20 steps with per-kernel HIP events"),
+                         "launches_per_step": sum(k["launches_per_step"]
+                                                  for k in kernels.values())}
+    del q
+    # Q6-shaped scan: 60M rows, five comparisons over int64 / int8 / int32
+    # columns, SUM(price * discount); one fused launch
+    d6 = dgd.config_q6(args.seed, device="cuda")
+    q6 = Q6Scan(d6["items"], d6)
+    ms = _timed(q6.run, 20, stream)
+    got = q6.result()
+    n6 = q6.n
+    scan_bytes = n6 * (8 + 1 + 4) + got["count"] * 8
+    kern = kernel_profile(q6.run, 20)
+    fs = kern.get("filter_sum", (20, ms * 20))
+    achieved = scan_bytes / (fs[1] / fs[0] * 1e-3) / 1e9
+    out["q6_scan"] = {"workload": "60M rows: ship int64 epoch-ns in one year, discount int8 "
+                                  "BETWEEN 5 AND 7, quantity int32 < 24; SUM(price * discount), "
+                                  "COUNT",
+                      "ms": round(ms, 4), "rows_per_s": round(n6 / (ms * 1e-3), 1),
+                      "count": got["count"],
+                      "roofline": {"kernel": "filter_sum", "bound": "hbm",
+                                   "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "algo_bytes_per_launch": int(scan_bytes),
+                                   "avg_launch_ms": round(fs[1] / fs[0], 5)}}
+    del q6, d6
+    torch.cuda.empty_cache()
+    # Q14-shaped join with a string predicate: 60M items, 2M parts
+    d14 = dgd.config_q14(args.seed, device="cuda")
+    q14 = Q14Query(d14["items"], d14["part"], d14["prefix"], d14["ship_lo"], d14["ship_hi"])
+    ms = _timed(q14.run, 20, stream)
+    got = q14.result()
+    n14 = q14.n
+    kern = kernel_profile(q14.run, 20)
+    fl = kern.get("filter", (20, ms * 20))
+    # the filter reads ship (8 B) of every row and the payload lines of kept rows
+    fbytes = n14 * 8 + got["rows_filtered"] * (4 + 8 + 1) * 2
+    achieved = fbytes / (fl[1] / fl[0] * 1e-3) / 1e9
+    out["q14_join"] = {"workload": "60M items (one month of int64 epoch-ns ship dates kept), 2M "
+                                   "parts with (n x 24) byte-matrix types; LIKE prefix flag, "
+                                   "join partkey = pk, SUM(CASE promo THEN price*(100-discount)), "
+                                   "SUM(price*(100-discount))",
+                       "ms": round(ms, 4), "rows_per_s": round(n14 / (ms * 1e-3), 1),
+                       "pairs": got["pairs"],
+                       "promo_revenue_ratio": [got["promo_rev"], got["total_rev"]],
+                       "roofline": {"kernel": "filter", "bound": "hbm",
+                                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                    "algo_bytes_per_launch": int(fbytes),
+                                    "avg_launch_ms": round(fl[1] / fl[0], 5)},
+                       "kernel_ms": {k: round(v[1] / 20, 4) for k, v in kern.items()}}
+    del q14, d14
+    torch.cuda.empty_cache()
+    # PREDICT inside a query: 20M reviews, 8 features, 8 -> 16 -> 2 fp32 model
+    dp = dgd.config_predict(args.seed, device="cuda")
+    qp = PredictQuery(dp["reviews"], dp["model"], dp["nfeat"], dp["hidden"], dp["classes"],
+                      dp["year_min"], dp["nratings"])
+    ms = _timed(qp.run, 20, stream)
+    got = qp.result()
+    kern = kernel_profile(qp.run, 20)
+    mp = kern.get("mlp_predict", (20, ms * 20))
+    pbytes = got["rows_filtered"] * (4 + 8 * 4 + 1)
+    achieved = pbytes / (mp[1] / mp[0] * 1e-3) / 1e9
+    out["predict_query"] = {"workload": "20M reviews: WHERE year >= 2016, PREDICT with an fp32 "
+                                        "8 -> 16 -> 2 MLP over 8 int32 features, GROUP BY rating "
+                                        "with SUM(CASE class = 1) and COUNT",
+                            "ms": round(ms, 4), "rows_per_s": round(qp.n / (ms * 1e-3), 1),
+                            "rows_scored": got["rows_filtered"],
+                            "positive_share_by_rating": [round(float(p) / max(int(c), 1), 3)
+                                                         for p, c in zip(got["positive"][1:],
+                                                                         got["count"][1:])],
+                            "roofline": {"kernel": "mlp_predict", "bound": "hbm",
+                                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s",
+                                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                         "algo_bytes_per_launch": int(pbytes),
+                                         "avg_launch_ms": round(mp[1] / mp[0], 5)},
+                            "kernel_ms": {k: round(v[1] / 20, 4) for k, v in kern.items()}}
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    del qp, dp
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_learned(args, tqp, stream) -> dict:
     """Sort-merge join of two int64 key columns drawn from the lognormal /
-    cluster / Zipf mix: learned-CDF partition sort against the plain MSD radix
-    partition sort with the same bucket count, and against the full LSD radix
-    sort; the join ranges are taken over each method's output."""
+    cluster / Zipf mix, end to end (model training + both sides partition-
+    sorted + join ranges): the learned-CDF partitioner against the plain LSD
+    radix sort (the pipeline's own sort) and against the MSD radix
+    partitioner with the same bucket count."""
     import torch
     from tqp_datagen import device as dgd
 
@@ -225,8 +624,8 @@ def bench_learned(args, tqp, stream) -> dict:
     # into 2^(bits - 12) buckets of about 8 keys on average (at most 24 bits:
     # the model's float32 rank), sorted in registers or LDS after grouping
     bits = max(12, min(24, (max(nl, nr) // 8).bit_length()))
-    lo = min(int(left.min().item()), int(right.min().item()))
-    hi = max(int(left.max().item()), int(right.max().item()))
+    st_l, st_r = tqp.minmax(left), tqp.minmax(right)
+    lo, hi = min(st_l[0], st_r[0]), max(st_l[1], st_r[1])
     key_bits = (hi - lo).bit_length()
     reps = args.side_reps
 
@@ -256,47 +655,29 @@ def bench_learned(args, tqp, stream) -> dict:
 
     out = {"workload": f"sort-merge join of {nl} x {nr} int64 keys (lognormal sigma=2 / "
                        "64 dense clusters / Zipf s=1.2 mix)",
-           "partitions": 4096, "buckets": 1 << bits, "model": {"hidden": 32, "leaves": 4096, "sample": "1%",
-                                           "adam_steps": info["steps"],
-                                           "loss_first": info["loss_first"],
-                                           "loss_last": info["loss_last"],
-                                           "train_ms": round(train_ms, 3)}}
+           "partitions": 4096, "buckets": 1 << bits,
+           "model": {"hidden": 32, "leaves": 4096, "sample": "1%", "adam_steps": info["steps"],
+                     "loss_first": info["loss_first"], "loss_last": info["loss_last"],
+                     "train_ms": round(train_ms, 3)}}
     results = {}
     ideal = (nl + nr) / 2 / (1 << bits)
-
-    def partition_imbalance(tag):
-        # largest of the 4096 partitions over the mean partition, both sides
-        worst = 0.0
-        for t in sides:
-            if tag == "learned":
-                b = tqp.lcdf_buckets(model, t, 12).long()
-            else:
-                b = ((t - lo) >> max(key_bits - 12, 0)).clamp(0, 4095)
-            h = torch.bincount(b, minlength=4096)
-            worst = max(worst, float(h.max()) / (t.numel() / 4096))
-        return round(worst, 2)
+    jr = None
     for tag, mode, mdl in (("learned", tqp.PART_LEARNED, model), ("radix", tqp.PART_RADIX, None)):
         ms = _timed(part(mode, mdl, tag), reps, stream)
-        # one more run with per-kernel events, for the breakdown
-        tqp.profile_reset()
-        tqp.profile_enable(True)
-        part(mode, mdl, tag)()
-        torch.cuda.synchronize()
-        tqp.profile_enable(False)
-        kern = {k: round(v[1], 3) for k, v in tqp.profile_collect().items()}
-        tqp.profile_reset()
+        kern = {k: round(v[1], 3) for k, v in kernel_profile(part(mode, mdl, tag), 1).items()}
         jr = _timed(lambda: tqp.join_ranges(outk[0], outk[1]), 1, stream)
         results[tag] = (outk[0].clone(), outr[0].clone())
         s0, s1 = stats[(tag, 0)], stats[(tag, 1)]
+        total = ms + jr + (train_ms if tag == "learned" else 0.0)
         out[tag] = {"sort_ms": round(ms, 3), "join_ranges_ms": round(jr, 3),
-                    "rows_per_s": round((nl + nr) / ((ms + jr) * 1e-3), 1),
+                    "end_to_end_ms": round(total, 3),
+                    "rows_per_s": round((nl + nr) / (total * 1e-3), 1),
                     "max_bucket_over_ideal": round(max(s0["max_bucket"], s1["max_bucket"])
                                                    / ideal, 2),
                     "fallback_buckets": s0["fallback_buckets"] + s1["fallback_buckets"],
                     "fallback_key_frac": round((s0["fallback_keys"] + s1["fallback_keys"])
                                                / (nl + nr), 4),
                     "single_valued_big": s0["single_valued_big"] + s1["single_valued_big"],
-                    "partition_max_over_mean": partition_imbalance(tag),
                     "kernel_ms": kern}
         print(f"[bench] learned: {tag} {out[tag]}", file=sys.stderr, flush=True)
 
@@ -309,107 +690,28 @@ def bench_learned(args, tqp, stream) -> dict:
             tqp.sort_into(t, None, t.numel(), outk[i], outr[i], sws, key_bits=key_bits,
                           key_min=lo)
     ms = _timed(lsd, reps, stream)
+    prof = kernel_profile(lsd, 1)
     same = all(torch.equal(results[t][0], outk[0]) and torch.equal(results[t][1], outr[0])
                for t in results)
-    out["lsd_radix"] = {"sort_ms": round(ms, 3),
-                        "rows_per_s": round((nl + nr) / ((ms + out["radix"]["join_ranges_ms"])
-                                                         * 1e-3), 1)}
+    passes = _passes(key_bits)
+    ob = passes * (nl + nr) * 2.0 * (8 + 4)          # every pass reads and writes key + row id
+    cnt, tot = prof.get("onesweep", (passes * 2, ms))
+    achieved = ob / cnt / (tot / cnt * 1e-3) / 1e9
+    out["lsd_radix"] = {"sort_ms": round(ms, 3), "end_to_end_ms": round(ms + jr, 3),
+                        "rows_per_s": round((nl + nr) / ((ms + jr) * 1e-3), 1),
+                        "roofline": {"kernel": "onesweep", "bound": "hbm",
+                                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                     "algo_bytes_per_launch": int(ob / cnt),
+                                     "avg_launch_ms": round(tot / cnt, 5)}}
     out["outputs_identical"] = bool(same)
-    out["learned_speedup_vs_radix_partition"] = round(
-        out["radix"]["sort_ms"] / out["learned"]["sort_ms"], 3)
+    e2e = out["learned"]["end_to_end_ms"]
+    out["learned_end_to_end_speedup_vs_lsd"] = round(out["lsd_radix"]["end_to_end_ms"] / e2e, 3)
+    out["learned_end_to_end_speedup_vs_radix_partition"] = round(
+        out["radix"]["end_to_end_ms"] / e2e, 3)
+    out["learned_beats_plain_radix"] = bool(e2e < min(out["lsd_radix"]["end_to_end_ms"],
+                                                      out["radix"]["end_to_end_ms"]))
     del left, right, outk, outr, ws, sws, results
-    torch.cuda.empty_cache()
-    return out
-
-
-def bench_configs(args, tqp, stream) -> dict:
-    """Throughput of the other workloads: the small star query (1M fact rows,
-    launch-bound), the three-dimension star (600M fact rows, drawn on the
-    GPU), the Q6-shaped scan (60M rows), the Q14-shaped join (60M items,
-    2M parts) and the prediction query (20M reviews).  Their results are checked
-    against the oracle by the test suite (full-size cases included), not
-    here."""
-    import torch
-    import tqp_datagen as dg
-    from tqp_datagen import device as dgd
-    from paper_2209_04579_amd.pipeline import StarQuery, StarQuery3
-
-    out = {}
-    c1 = dg.config1(args.seed)
-    q = StarQuery({k: torch.from_numpy(v).cuda() for k, v in c1["fact"].items()},
-                  {k: torch.from_numpy(v).cuda() for k, v in c1["dim"].items()}, c1["day_cut"])
-    ms = _timed(q.run, 20, stream)
-    got = q.result()
-    out["small_star"] = {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat",
-                         "ms": round(ms, 4), "rows_per_s": round(1_000_000 / (ms * 1e-3), 1),
-                         "groups": int(len(got["key"]))}
-    del q
-    t0 = time.time()
-    c3 = dgd.config3(args.seed, device="cuda")
-    torch.cuda.synchronize()
-    print(f"[bench] star3: generated 600M fact rows in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-    q3 = StarQuery3(c3["fact"], c3["d1"], c3["d2"], c3["d3"], c3["attr_cut"])
-    ms = _timed(q3.run, max(args.side_reps, 1), stream)
-    got = q3.result()
-    n3 = int(c3["fact"]["fk1"].numel())
-    out["star3"] = {"workload": "fact 600M rows, three dims (1M, 100k, 25) filtered to ~20%; "
-                                "joins fk3, fk2, fk1; group by d1.cat*5+d2.cat: "
-                                "SUM(qty*price), COUNT",
-                    "ms": round(ms, 3), "rows_per_s": round(n3 / (ms * 1e-3), 1),
-                    "pairs": got["pairs"], "groups": int(len(got["key"]))}
-    del q3, c3
-    torch.cuda.empty_cache()
-    # Q6-shaped scan: 60M rows, five comparisons over int64 / int8 / int32
-    # columns, SUM(price * discount); one fused launch
-    from paper_2209_04579_amd.pipeline import Q6Scan
-    d6 = dgd.config_q6(args.seed, device="cuda")
-    q6 = Q6Scan(d6["items"], d6)
-    ms = _timed(q6.run, 20, stream)
-    got = q6.result()
-    n6 = q6.n
-    scan_bytes = n6 * (8 + 1 + 4 + 8)        # every referenced column read once
-    out["q6_scan"] = {"workload": "60M rows: ship int64 epoch-ns in one year, discount int8 "
-                                  "BETWEEN 5 AND 7, quantity int32 < 24; SUM(price * discount), "
-                                  "COUNT",
-                      "ms": round(ms, 4), "rows_per_s": round(n6 / (ms * 1e-3), 1),
-                      "scan_GBps": round(scan_bytes / (ms * 1e-3) / 1e9, 1),
-                      "count": got["count"]}
-    del q6, d6
-    torch.cuda.empty_cache()
-    # Q14-shaped join with a string predicate: 60M items, 2M parts
-    from paper_2209_04579_amd.pipeline import Q14Query
-    d14 = dgd.config_q14(args.seed, device="cuda")
-    q14 = Q14Query(d14["items"], d14["part"], d14["prefix"], d14["ship_lo"], d14["ship_hi"])
-    ms = _timed(q14.run, 20, stream)
-    got = q14.result()
-    n14 = q14.n
-    out["q14_join"] = {"workload": "60M items (one month of int64 epoch-ns ship dates kept), 2M "
-                                   "parts with (n x 24) byte-matrix types; LIKE prefix flag, "
-                                   "join partkey = pk, SUM(CASE promo THEN price*(100-discount)), "
-                                   "SUM(price*(100-discount))",
-                       "ms": round(ms, 4), "rows_per_s": round(n14 / (ms * 1e-3), 1),
-                       "pairs": got["pairs"],
-                       "promo_share": round(got["promo_rev"] / max(got["total_rev"], 1), 4)}
-    del q14, d14
-    torch.cuda.empty_cache()
-    # PREDICT inside a query: 20M reviews, 8 features, 8 -> 16 -> 2 fp32 model
-    from paper_2209_04579_amd.pipeline import PredictQuery
-    dp = dgd.config_predict(args.seed, device="cuda")
-    qp = PredictQuery(dp["reviews"], dp["model"], dp["nfeat"], dp["hidden"], dp["classes"],
-                      dp["year_min"], dp["nratings"])
-    ms = _timed(qp.run, 20, stream)
-    got = qp.result()
-    out["predict_query"] = {"workload": "20M reviews: WHERE year >= 2016, PREDICT with an fp32 "
-                                        "8 -> 16 -> 2 MLP over 8 int32 features, GROUP BY rating "
-                                        "with SUM(CASE class = 1) and COUNT",
-                            "ms": round(ms, 4), "rows_per_s": round(qp.n / (ms * 1e-3), 1),
-                            "rows_scored": got["rows_filtered"],
-                            "positive_share_by_rating": [round(float(p) / max(int(c), 1), 3)
-                                                         for p, c in zip(got["positive"][1:],
-                                                                         got["count"][1:])]}
-    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
-    del qp, dp
     torch.cuda.empty_cache()
     return out
 
@@ -454,6 +756,13 @@ def bench_batch(args, tqp, stream) -> dict:
     got = b.results()
     same = all(all(np.array_equal(g[k], w[k]) for k in ("key", "sum_qty", "count"))
                for g, w in zip(got, want))
+    # roofline of the batched plan's dominant kernel (eager run with events)
+    q = b.q
+    kept, pairs = int(q.cnt.item()), int(q.npairs.item())
+    st = {"n": q.n, "nd": q.nd, "kept": kept, "pairs": pairs, "groups_b": 0,
+          "passes": _passes(q.jk_bits), "uniq_l": q.nd, "uniq_r": q.nd, "pay": 12,
+          "gbv": 4 + 4 + 4 + 8}
+    kernels = kernel_table(kernel_profile(q.run, 3), 3, star_kernel_bytes, st)
     for k, v in defaults.items():
         tqp.tune_set(k, v)
     out = {"workload": f"{len(insts)} star queries (filter day<1278, join fk=pk, group by cat), "
@@ -466,6 +775,8 @@ def bench_batch(args, tqp, stream) -> dict:
            "graph_rows_per_s": round(rows / (graph_ms * 1e-3), 1),
            "sequential_rows_per_s": round(rows / (seq_ms * 1e-3), 1),
            "speedup_vs_sequential": round(seq_ms / graph_ms, 3),
+           "roofline": roofline_of(kernels, star_kernel_bytes, st, None,
+                                   "3 eager steps with per-kernel HIP events"),
            "tuned": best, "tuning_trials": len(timings),
            "results_match_sequential": bool(same)}
     print(f"[bench] batch: {out}", file=sys.stderr, flush=True)
@@ -477,167 +788,76 @@ def bench_batch(args, tqp, stream) -> dict:
 def main():
     args = parse()
     if args.record_traffic:
-        record_traffic(*args.record_traffic, args.record_command)
+        record_traffic(*args.record_traffic, args.traffic_tag, args.record_command)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import tqp_datagen as dg
     import paper_2209_04579_amd as tqp
-    from paper_2209_04579_amd.pipeline import StarQuery
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tqp.lib()
-    t0 = time.time()
-    cfg = dg.config2(args.seed, n_fact=args.n_fact, n_dim=args.n_dim)
-    print(f"[bench] generated {args.n_fact} fact rows in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    fact = {k: torch.from_numpy(v).cuda() for k, v in cfg["fact"].items()}
-    dim = {k: torch.from_numpy(v).cuda() for k, v in cfg["dim"].items()}
-    q = StarQuery(fact, dim, cfg["day_cut"], mode="q2")
     stream = torch.cuda.current_stream()
-
-    # plain-copy bandwidth on the same run (2 GiB), the scale for the HBM counters
-    src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-
-    for _ in range(args.warmup):
-        q.run()
-    res = q.result()
-    print(f"[bench] warmup done: {res['rows_filtered']} rows kept, {res['pairs']} pairs, "
-          f"{len(res['b_key'])} fk groups", file=sys.stderr, flush=True)
-
-    # the headline: K steps with nothing else on the stream
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        q.run()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    # per-kernel durations: K more steps, each library launch bracketed by HIP
-    # events on its stream (the events add a little time between kernels,
-    # which is why they stay out of the headline's timed region)
-    use_events = not args.no_kernel_events
-    prof = {}
-    if use_events:
-        tqp.profile_reset()
-        tqp.profile_enable(True)
-        for _ in range(args.steps):
-            q.run()
-        torch.cuda.synchronize()
-        tqp.profile_enable(False)
-        prof = tqp.profile_collect()
-        tqp.profile_reset()
-
-    st = {"n": args.n_fact, "nd": args.n_dim, "kept": res["rows_filtered"],
-          "pairs": res["pairs"], "groups_b": len(res["b_key"]),
-          "passes": (q.jk_bits + 7) // 8}
-    # distinct keys on each join side (for the per-kernel byte figures)
-    st["uniq_l"] = len(res["b_key"])
-    st["uniq_r"] = args.n_dim
-    kernels = {}
-    for name, (cnt, tot_ms) in prof.items():
-        per_step = cnt / args.steps
-        avg_ms = tot_ms / cnt
-        b = kernel_bytes(name, per_step, st)
-        kernels[name] = {"launches_per_step": per_step, "avg_ms": round(avg_ms, 5),
-                         "ms_per_step": round(tot_ms / args.steps, 5)}
-        if b is not None:
-            kernels[name]["algo_GBps"] = round(b / (tot_ms / args.steps * 1e-3) / 1e9, 1)
-    roofline = None
-    if kernels:
-        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-        d = kernels[dom]
-        b_step = kernel_bytes(dom, d["launches_per_step"], st)
-        per_launch = b_step / d["launches_per_step"]
-        achieved = per_launch / (d["avg_ms"] * 1e-3) / 1e9
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_for(dom),
-                    "algo_bytes_per_launch": int(per_launch),
-                    "avg_launch_ms": d["avg_ms"],
-                    "timed": f"{args.steps} further steps with per-kernel HIP events"}
-
-    # algorithmic bytes of the whole step, from the per-kernel figures
-    step_bytes = sum(kernel_bytes(k, kernels[k]["launches_per_step"], st) or 0 for k in kernels)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.lib()
-        times = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            want = oracle.q2(cfg["fact"], cfg["dim"], cfg["day_cut"])
-            times.append(time.perf_counter() - t0)
-        dt = sorted(times)[1]
-        ok = all(np.array_equal(res[k], want[k]) for k in
-                 ("a_key", "a_qty", "a_price", "a_count", "b_key", "b_qty", "b_count"))
-        cpu = {"value": round(args.n_fact / dt, 1), "unit": "rows/s", "cores": 1,
-               "kind": "oracle", "seconds": round(dt, 3), "matches_gpu": bool(ok),
-               "sample": f"the whole workload ({args.n_fact} fact rows), median of 3 runs, "
-                         "single-threaded C oracle (hash join + hash group-by)"}
-
-    # side comparisons on their own workloads (outside the headline's timed region)
-    del q, fact, dim
-    torch.cuda.empty_cache()
-    configs = None if args.no_configs else bench_configs(args, tqp, stream)
-    learned = None if args.no_learned else bench_learned(args, tqp, stream)
-    batch = None if args.no_batch else bench_batch(args, tqp, stream)
-
+    copy_gbs = stream_copy_gbs(stream)
+    if args.only == "star60m":
+        print(json.dumps({"star60m": bench_star60m(args, tqp, stream),
+                          "stream_copy_GBps": round(copy_gbs, 1)}), flush=True)
+        return
+    head = bench_star3(args, tqp, stream, copy_gbs)
+    ms = head["ms"]
+    n = head["n"]
     out = {
         "metric": METRIC,
-        "value": round(args.n_fact / (ms * 1e-3), 1),
+        "value": round(n / (ms * 1e-3), 1),
         "unit": "rows/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "median_ms_per_step": round(head["median_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "skewed star query: fact 60M rows (fk Zipf s=1 over 2M keys), "
-                               "dim 2M; day<1278; join fk=pk; group by (flag, cat mod 2) "
-                               "and by fk",
-                   "fact_rows": args.n_fact, "dim_rows": args.n_dim, "seed": args.seed,
+        "config": {"workload": "three-dimension star: fact 600M rows {fk1 U[0,1e6), fk2 "
+                               "U[0,1e5), fk3 U[0,25), qty, price int64 cents}; dims 1M / 100k "
+                               "/ 25 rows each filtered attr<20 (~20%); joins fk3=d3.pk, "
+                               "fk2=d2.pk, fk1=d1.pk; group by d1.cat*5+d2.cat: "
+                               "SUM(qty*price), COUNT",
+                   "fact_rows": n, "dim_rows": [1_000_000, 100_000, 25], "seed": args.seed,
+                   "plan": "semi-join reduction, then sort-merge joins on the kept rows",
                    "parallelism": "single GPU"},
-        "roofline": roofline,
-        "pipeline_hbm": {"algo_bytes_per_step": int(step_bytes),
-                         "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
-                         "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": head["roofline"],
+        "pipeline_hbm": head["pipeline_hbm"],
         "stream_copy_GBps": round(copy_gbs, 1),
-        "kernels": kernels,
-        "cpu_baseline": cpu,
-        "other_configs": configs,
-        "learned_vs_radix": learned,
-        "batch": batch,
-        # the paper reports ratios only, on other hardware and on TPC-H SF1
-        "paper_context": [
-            {"claim": "TQP on GPU vs Spark: about 20x on Q6, 6x on Q14 (TPC-H SF1)",
-             "hardware": "NVIDIA P100 16 GB vs Spark on 6-vCPU Xeon E5-2690 v4"},
-            {"claim": "TQP on CPU vs Spark: about 3x on Q6 and Q14 (TPC-H SF1)",
-             "hardware": "Azure NC6 v2, 6 vCPU Xeon E5-2690 v4"},
-            {"claim": "timing: median of 5 runs after 5 warm-up runs", "hardware": ""}],
+        "kernels": head["kernels"],
+        "result": {"rows_after_semijoin": head["res"]["reduced"],
+                   "pairs_per_join": head["res"]["pairs"], "groups": len(head["res"]["key"])},
+        "cpu_baseline": head["cpu_baseline"],
+        "catalog_statistics": "column min/max taken once per table at plan time (libtqp's "
+                              "min/max reduction), outside the timed steps",
     }
+    if args.only:
+        print(json.dumps(out), flush=True)
+        return
+    side = {}
+    if not args.no_configs:
+        side["star60m"] = bench_star60m(args, tqp, stream)
+        side.update(bench_configs(args, tqp, stream))
+    out["other_configs"] = side or None
+    out["learned_vs_radix"] = None if args.no_learned else bench_learned(args, tqp, stream)
+    out["batch"] = None if args.no_batch else bench_batch(args, tqp, stream)
+    # the paper reports ratios only, on other hardware and on TPC-H SF1
+    out["paper_context"] = [
+        {"claim": "TQP on GPU vs Spark: about 20x on Q6, 6x on Q14 (TPC-H SF1)",
+         "hardware": "NVIDIA P100 16 GB vs Spark on 6-vCPU Xeon E5-2690 v4"},
+        {"claim": "TQP on CPU vs Spark: about 3x on Q6 and Q14 (TPC-H SF1)",
+         "hardware": "Azure NC6 v2, 6 vCPU Xeon E5-2690 v4"},
+        {"claim": "timing: median of 5 runs after 5 warm-up runs", "hardware": ""}]
     print(json.dumps(out), flush=True)
 
 
