@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "libtqp_oracle.so")
 
 DT = {np.dtype(np.int8): 1, np.dtype(np.int32): 2, np.dtype(np.int64): 3}
 OPS = {"<": 0, "<=": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
-AGG_SUM, AGG_COUNT, AGG_SUM_PRODUCT = 0, 1, 2
+AGG_SUM, AGG_COUNT, AGG_SUM_PRODUCT, AGG_SUM_DIFF_PRODUCT = 0, 1, 2, 3
 
 _lib = None
 
@@ -65,7 +65,7 @@ def lib():
         _lib.orc_join_ranges.argtypes = [i64, vp, i64, vp, i32, i64, vp, vp, vp,
                                          vp, vp, vp, vp]
         _lib.orc_groupby.restype = i64
-        _lib.orc_groupby.argtypes = [i64, vp, i32, vp, vp, i32, vp, vp, vp, i64,
+        _lib.orc_groupby.argtypes = [i64, vp, i32, vp, vp, i32, vp, vp, vp, vp, i64,
                                      vp, vp, vp]
         _lib.orc_q1.restype = i64
         _lib.orc_q1.argtypes = [i64, vp, vp, vp, i64, i64, vp, vp, i64, vp, vp,
@@ -305,23 +305,26 @@ def join_ranges(lk: np.ndarray, rk: np.ndarray):
 
 
 def groupby(keys: np.ndarray, vals, aggs):
-    """GROUP BY keys.  aggs: list of ("sum", a) | ("count",) | ("sum_product", a, b).
+    """GROUP BY keys.  aggs: list of ("sum", a) | ("count",) | ("sum_product", a, b)
+    | ("sum_diff_product", a, b, c): SUM(vals[a] * (c - vals[b])).
 
     Returns (unique_keys int64, [agg arrays int64], overflow flag).
     """
     keys = _c(keys)
     vals = [_c(v) for v in vals]
     n = len(keys)
-    op = np.array([{"sum": AGG_SUM, "count": AGG_COUNT, "sum_product": AGG_SUM_PRODUCT}[a[0]]
+    op = np.array([{"sum": AGG_SUM, "count": AGG_COUNT, "sum_product": AGG_SUM_PRODUCT,
+                    "sum_diff_product": AGG_SUM_DIFF_PRODUCT}[a[0]]
                    for a in aggs], dtype=np.int32)
     aa = np.array([a[1] if len(a) > 1 else 0 for a in aggs], dtype=np.int32)
     ab = np.array([a[2] if len(a) > 2 else 0 for a in aggs], dtype=np.int32)
+    ac = np.array([a[3] if len(a) > 3 else 0 for a in aggs], dtype=np.int64)
     vdt = np.array([DT[v.dtype] for v in vals] or [3], dtype=np.int32)
     ok = np.empty(max(n, 1), dtype=np.int64)
     outs = [np.empty(max(n, 1), dtype=np.int64) for _ in aggs]
     ovf = ctypes.c_int(0)
     ng = lib().orc_groupby(n, _p(keys), DT[keys.dtype], _ptr_array(vals), _p(vdt),
-                           len(aggs), _p(op), _p(aa), _p(ab), n, _p(ok),
+                           len(aggs), _p(op), _p(aa), _p(ab), _p(ac), n, _p(ok),
                            _ptr_array(outs), ctypes.byref(ovf))
     return ok[:ng].copy(), [o[:ng].copy() for o in outs], bool(ovf.value)
 

@@ -26,7 +26,7 @@
 
 enum { DT_I8 = 1, DT_I32 = 2, DT_I64 = 3 };
 enum { OP_LT = 0, OP_LE = 1, OP_GT = 2, OP_GE = 3, OP_EQ = 4, OP_NE = 5 };
-enum { AGG_SUM = 0, AGG_COUNT = 1, AGG_SUM_PRODUCT = 2 };
+enum { AGG_SUM = 0, AGG_COUNT = 1, AGG_SUM_PRODUCT = 2, AGG_SUM_DIFF_PRODUCT = 3 };
 
 static int64_t value_at(const void *col, int dtype, int64_t i)
 {
@@ -379,12 +379,16 @@ int64_t orc_join_ranges(int64_t nl, const void *lk, int64_t nr, const void *rk,
  *   AGG_SUM(a)          = sum of vals[a][i]
  *   AGG_COUNT           = number of rows
  *   AGG_SUM_PRODUCT(a,b)= sum of vals[a][i] * vals[b][i]
+ *   AGG_SUM_DIFF_PRODUCT(a,b,c) = sum of vals[a][i] * (c - vals[b][i]), c a
+ *                         constant (Q14's revenue, price * (100 - discount)
+ *                         in cents and hundredths, Section 2.3)
  * Accumulated exactly in __int128; the stored int64 is the value mod 2^64.
  * *overflow is set if any exact value left the int64 range.
  * ---------------------------------------------------------------------- */
 int64_t orc_groupby(int64_t n, const void *keys, int kdtype,
                     const void *const *vals, const int *vdtypes,
                     int nagg, const int *aop, const int *aa, const int *ab,
+                    const int64_t *ac,
                     int64_t cap, int64_t *out_keys, int64_t *const *out_aggs,
                     int *overflow)
 {
@@ -402,8 +406,12 @@ int64_t orc_groupby(int64_t n, const void *keys, int kdtype,
             __int128 v;
             if (aop[a] == AGG_COUNT) v = 1;
             else if (aop[a] == AGG_SUM) v = value_at(vals[aa[a]], vdtypes[aa[a]], i);
-            else v = (__int128)value_at(vals[aa[a]], vdtypes[aa[a]], i) *
-                     (__int128)value_at(vals[ab[a]], vdtypes[ab[a]], i);
+            else if (aop[a] == AGG_SUM_PRODUCT)
+                v = (__int128)value_at(vals[aa[a]], vdtypes[aa[a]], i) *
+                    (__int128)value_at(vals[ab[a]], vdtypes[ab[a]], i);
+            else
+                v = (__int128)value_at(vals[aa[a]], vdtypes[aa[a]], i) *
+                    ((__int128)ac[a] - (__int128)value_at(vals[ab[a]], vdtypes[ab[a]], i));
             acc[g * nagg + a] += v;
         }
     }

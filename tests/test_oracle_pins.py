@@ -263,6 +263,33 @@ def test_groupby_brute_force_tiny():
     assert c.tolist() == [2, 1, 3]
 
 
+def test_groupby_sum_diff_product_brute_force():
+    # SUM(a * (c - b)): Python integers row by row, and the identity
+    # c * SUM(a) - SUM(a * b) (exact, no wrap at these sizes)
+    keys = np.array([3, 1, 3, 3, 1, -4, 1], np.int32)
+    a = np.array([900, 15, -7, 10 ** 7, 3, 0, 2 ** 40], np.int64)
+    b = np.array([5, 100, 11, 7, -3, 9, 99], np.int8)
+    c = 100
+    uk, (sdp, sa, sab, cnt), ovf = oracle.groupby(
+        keys, [a, b], [("sum_diff_product", 0, 1, c), ("sum", 0), ("sum_product", 0, 1),
+                       ("count",)])
+    assert not ovf
+    want = {}
+    for k, x, y in zip(keys.tolist(), a.tolist(), b.tolist()):
+        want[k] = want.get(k, 0) + x * (c - y)
+    assert uk.tolist() == sorted(want)
+    assert sdp.tolist() == [want[k] for k in sorted(want)]
+    assert (c * sa - sab).tolist() == sdp.tolist()
+    # the constant enters as given: a negative one, and c = 0 gives -SUM(a * b)
+    _, (neg,), _ = oracle.groupby(keys, [a, b], [("sum_diff_product", 0, 1, -3)])
+    assert neg.tolist() == [sum(x * (-3 - y) for kk, x, y in zip(keys.tolist(), a.tolist(),
+                                                                  b.tolist()) if kk == k)
+                            for k in sorted(want)]
+    _, (zero, sab2), _ = oracle.groupby(keys, [a, b], [("sum_diff_product", 0, 1, 0),
+                                                       ("sum_product", 0, 1)])
+    assert (zero == -sab2).all()
+
+
 def test_groupby_wraps_mod_2_64_and_flags_overflow():
     keys = np.zeros(3, np.int32)
     vals = np.array([I64_MAX, I64_MAX, 5], np.int64)
