@@ -70,14 +70,18 @@ typedef struct {
     int64_t literal;
 } tqp_pred;
 
-/* Aggregates over value columns: SUM(vals[a]), COUNT(*), SUM(vals[a]*vals[b]).
- * Sums are int64 two's complement, i.e. exact modulo 2^64. */
-typedef enum { TQP_AGG_SUM = 0, TQP_AGG_COUNT = 1, TQP_AGG_SUM_PRODUCT = 2 } tqp_agg_op;
+/* Aggregates over value columns: SUM(vals[a]), COUNT(*), SUM(vals[a]*vals[b]),
+ * SUM(vals[a] * (c - vals[b])) with c a constant (Section 2.3's Q14 revenue,
+ * price * (100 - discount) in cents and hundredths).  Sums are int64 two's
+ * complement, i.e. exact modulo 2^64.  c is read by SUM_DIFF_PRODUCT only. */
+typedef enum {
+    TQP_AGG_SUM = 0, TQP_AGG_COUNT = 1, TQP_AGG_SUM_PRODUCT = 2, TQP_AGG_SUM_DIFF_PRODUCT = 3
+} tqp_agg_op;
 typedef struct {
     int32_t op;
     int32_t a;
     int32_t b;
-    int32_t reserved;
+    int32_t c;
 } tqp_agg;
 
 /* One term of a packed key: mul * f(col[rows ? rows[i] : i]) where
@@ -430,6 +434,54 @@ int tqp_groupby_agg_terms(const tqp_keyterm *terms, int nterms, int64_t n, const
                           const tqp_agg *aggs, int nagg,
                           const tqp_col *out_key, int64_t *const *out_aggs,
                           int64_t *d_ngroups, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * tqp_lower_bound -- out[i] = the number of the first count keys of `sorted`
+ * (ascending; count = min(*d_n, sorted->len) with d_n, else sorted->len)
+ * that are below queries[i], for i < queries->len: where each query would be
+ * inserted.  sorted: int32 or int64; queries: any integer dtype; out: device
+ * int64, queries->len entries.  Splits a batched, sorted result by instance.
+ * ---------------------------------------------------------------------- */
+int tqp_lower_bound(const tqp_col *sorted, const int64_t *d_n, const tqp_col *queries,
+                    int64_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched execution (an extension of the executor of Section 2.2: many
+ * independent queries of one shape run as one plan).  The instances' tables
+ * are laid end to end in one columnar arena; every join key carries its
+ * instance number in its high bits (key' = i << key_shift | key) and every
+ * category likewise (cat' = i << cat_shift | cat), so keys of different
+ * instances never meet and instance i's groups precede instance i+1's.  The
+ * whole plan over the arena is then captured once and replayed as one graph.
+ *
+ * tqp_batch_plan: HOST only.  From k instances' fact and dimension row
+ *   counts and the largest join key and category over all of them (both
+ *   >= 0), writes the arena offsets out->fact_off[0..k] and dim_off[0..k]
+ *   (caller-owned host arrays of k + 1), the shifts and the arena's sizes.
+ *   TQP_EINVAL when the prefixed keys or categories would not fit int32.
+ * tqp_batch_capture_begin / tqp_batch_capture_end: every library call
+ *   enqueued on `stream` (not the null stream) in between is recorded into
+ *   one graph instead of running; end instantiates it and returns an opaque
+ *   handle in *graph.  Calls that synchronize (key-range derivation,
+ *   tqp_partition_sort) must not be captured.  Buffers and workspaces
+ *   named by the captured calls must stay allocated while the graph lives.
+ * tqp_batch_run: launches the captured graph on `stream` (one launch).
+ * tqp_batch_destroy: releases the handle (NULL is a no-op).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t *fact_off;      /* host, k + 1 entries (filled) */
+    int64_t *dim_off;       /* host, k + 1 entries (filled) */
+    int32_t  key_shift;     /* instance number position in join keys */
+    int32_t  cat_shift;     /* instance number position in categories */
+    int64_t  fact_rows;     /* arena sizes */
+    int64_t  dim_rows;
+} tqp_batch_layout;
+int tqp_batch_plan(int k, const int64_t *fact_rows, const int64_t *dim_rows, int64_t max_key,
+                   int64_t max_cat, tqp_batch_layout *out);
+int tqp_batch_capture_begin(void *stream);
+int tqp_batch_capture_end(void *stream, void **graph);
+int tqp_batch_run(void *graph, void *stream);
+int tqp_batch_destroy(void *graph);
 
 /* ------------------------------------------------------------------------
  * Learned CDF partitioner.  A model F maps a key to [0, 1], monotone

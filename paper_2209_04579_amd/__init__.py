@@ -23,7 +23,7 @@ __all__ = [
     "TqpError", "lib", "library_path", "filter", "filter_into", "gather_into", "gather",
     "pack_key_into", "sort", "sort_into", "filter_sort_into", "join", "join_into", "join_ranges",
     "groupby_agg", "groupby_agg_into", "keyset_build_into", "semijoin_into", "minmax",
-    "minmax_into", "OPS", "DTYPES",
+    "minmax_into", "lower_bound_into", "batch_plan", "batch_capture", "Graph", "OPS", "DTYPES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +32,7 @@ _LIB_PATH = os.path.join(_HERE, "libtqp.so")
 TQP_OK, TQP_EINVAL, TQP_ECAPACITY, TQP_EHIP = 0, 1, 2, 3
 DTYPES = {torch.int8: 1, torch.int32: 2, torch.int64: 3}
 OPS = {"<": 0, "<=": 1, ">": 2, ">=": 3, "==": 4, "!=": 5}
-AGGS = {"sum": 0, "count": 1, "sum_product": 2}
+AGGS = {"sum": 0, "count": 1, "sum_product": 2, "sum_diff_product": 3}
 JOIN_SORTED, JOIN_RANGES = 1, 2
 GB_SORTED, GB_DENSE = 1, 2
 GB_DENSE_MAX = 4096
@@ -55,7 +55,7 @@ class Pred(ctypes.Structure):
 
 class Agg(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("c", ctypes.c_int32)]
 
 
 class KeyTerm(ctypes.Structure):
@@ -67,6 +67,12 @@ class Ranges(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("lstart", ctypes.c_void_p),
                 ("lcnt", ctypes.c_void_p), ("rstart", ctypes.c_void_p),
                 ("rcnt", ctypes.c_void_p)]
+
+
+class BatchLayout(ctypes.Structure):
+    _fields_ = [("fact_off", ctypes.c_void_p), ("dim_off", ctypes.c_void_p),
+                ("key_shift", ctypes.c_int32), ("cat_shift", ctypes.c_int32),
+                ("fact_rows", ctypes.c_int64), ("dim_rows", ctypes.c_int64)]
 
 
 class KeySet(ctypes.Structure):
@@ -145,6 +151,18 @@ def lib():
         L.tqp_groupby_agg_terms.restype = i32
         L.tqp_groupby_agg_terms.argtypes = [P(KeyTerm), i32, i64, vp, i64, i64, P(Col), i32, vp,
                                             P(Agg), i32, P(Col), P(vp), vp, vp, sz, vp]
+        L.tqp_lower_bound.restype = i32
+        L.tqp_lower_bound.argtypes = [P(Col), vp, P(Col), vp, vp]
+        L.tqp_batch_plan.restype = i32
+        L.tqp_batch_plan.argtypes = [i32, vp, vp, i64, i64, P(BatchLayout)]
+        L.tqp_batch_capture_begin.restype = i32
+        L.tqp_batch_capture_begin.argtypes = [vp]
+        L.tqp_batch_capture_end.restype = i32
+        L.tqp_batch_capture_end.argtypes = [vp, P(vp)]
+        L.tqp_batch_run.restype = i32
+        L.tqp_batch_run.argtypes = [vp, vp]
+        L.tqp_batch_destroy.restype = i32
+        L.tqp_batch_destroy.argtypes = [vp]
         L.tqp_minmax.restype = i32
         L.tqp_minmax.argtypes = [P(Col), vp, vp, vp]
         L.tqp_keyset_build.restype = i32
@@ -288,6 +306,61 @@ def minmax(col):
     minmax_into(col, out)
     lo, hi = (int(v) for v in out.cpu().tolist())
     return None if lo > hi else (lo, hi)
+
+
+# ------------------------------------------------------------------ batch ----
+
+def lower_bound_into(sorted_keys, queries, out, d_n=None, stream=None):
+    """Enqueues out[i] = number of the (first d_n) sorted keys below queries[i]."""
+    _check(lib().tqp_lower_bound(ctypes.byref(_col(sorted_keys)), _ptr(d_n),
+                                 ctypes.byref(_col(queries)), _ptr(out), _stream(stream)))
+
+
+def batch_plan(fact_rows, dim_rows, max_key: int, max_cat: int) -> dict:
+    """The arena layout of k instances (libtqp's tqp_batch_plan, host only)."""
+    k = len(fact_rows)
+    if len(dim_rows) != k:
+        raise ValueError("one dimension size per instance")
+    fo, do = (ctypes.c_int64 * (k + 1))(), (ctypes.c_int64 * (k + 1))()
+    lay = BatchLayout(ctypes.cast(fo, ctypes.c_void_p), ctypes.cast(do, ctypes.c_void_p),
+                      0, 0, 0, 0)
+    fr = (ctypes.c_int64 * max(k, 1))(*[int(x) for x in fact_rows])
+    dr = (ctypes.c_int64 * max(k, 1))(*[int(x) for x in dim_rows])
+    _check(lib().tqp_batch_plan(k, fr, dr, int(max_key), int(max_cat), ctypes.byref(lay)))
+    return {"fact_off": list(fo), "dim_off": list(do), "key_shift": lay.key_shift,
+            "cat_shift": lay.cat_shift, "fact_rows": lay.fact_rows, "dim_rows": lay.dim_rows}
+
+
+class Graph:
+    """A captured plan (tqp_batch_capture_end's handle), replayed by run()."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def run(self, stream=None):
+        _check(lib().tqp_batch_run(self.handle, _stream(stream)))
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.tqp_batch_destroy(self.handle)
+            self.handle = None
+
+
+def batch_capture(fn, stream=None) -> Graph:
+    """Records every library call fn() enqueues into one graph (on a side
+    stream; fn must not allocate or synchronize) and returns it."""
+    s = stream or torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        _check(lib().tqp_batch_capture_begin(s.cuda_stream))
+        h = ctypes.c_void_p()
+        try:
+            fn()
+        finally:
+            rc = lib().tqp_batch_capture_end(s.cuda_stream, ctypes.byref(h))
+        _check(rc)
+    torch.cuda.current_stream().wait_stream(s)
+    return Graph(h.value)
 
 
 # -------------------------------------------------------------- semi-join ----
@@ -492,7 +565,10 @@ def groupby_workspace_bytes(n, dtype, nagg, flags, key_span=0) -> int:
 def _aggs(aggs):
     arr = (Agg * len(aggs))()
     for i, a in enumerate(aggs):
-        arr[i] = Agg(AGGS[a[0]], a[1] if len(a) > 1 else 0, a[2] if len(a) > 2 else 0, 0)
+        c = int(a[3]) if len(a) > 3 else 0
+        if not -(1 << 31) <= c < (1 << 31):
+            raise ValueError("the aggregate's constant must fit int32")
+        arr[i] = Agg(AGGS[a[0]], a[1] if len(a) > 1 else 0, a[2] if len(a) > 2 else 0, c)
     return arr
 
 

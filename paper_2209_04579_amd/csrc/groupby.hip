@@ -32,9 +32,17 @@ struct AggArgs {
     int32_t op[kMaxAgg];
     int32_t ia[kMaxAgg];
     int32_t ib[kMaxAgg];
+    int64_t ic[kMaxAgg];
     int32_t nagg;
     const int32_t *val_rows;
 };
+
+// The second factor of a product aggregate: vals[b] itself (SUM_PRODUCT) or
+// c - vals[b] (SUM_DIFF_PRODUCT), in wrapping int64 arithmetic, so the product
+// is the exact one modulo 2^64.
+__device__ __forceinline__ int64_t agg_second(const AggArgs &a, int g, int64_t y) {
+    return a.op[g] == TQP_AGG_SUM_PRODUCT ? y : int64_t(uint64_t(a.ic[g]) - uint64_t(y));
+}
 
 __device__ __forceinline__ int64_t agg_term(const AggArgs &a, int g, int64_t row) {
     if (a.op[g] == TQP_AGG_COUNT) return 1;
@@ -43,7 +51,7 @@ __device__ __forceinline__ int64_t agg_term(const AggArgs &a, int g, int64_t row
     if (a.op[g] == TQP_AGG_SUM) return vx;
     const int y = a.ib[g];
     const int64_t vy = (row >= 0 && row < a.vlen[y]) ? load_any(a.val[y], a.vdt[y], row) : 0;
-    return int64_t(uint64_t(vx) * uint64_t(vy));
+    return int64_t(uint64_t(vx) * uint64_t(agg_second(a, g, vy)));
 }
 
 // Look-back over kNV int64 values.  Each tile owns 2 * kNV status words; word
@@ -283,13 +291,13 @@ __global__ __launch_bounds__(kGbNT, 4) void k_gb_scan(const K *__restrict__ keys
         } else {
             const int x = a.ia[g];
             load_vals<R>(a.val[x], a.vdt[x], a.vlen[x], rows, valid, term[g]);
-            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+            if (a.op[g] >= TQP_AGG_SUM_PRODUCT) {
                 int64_t other[R];
                 const int y = a.ib[g];
                 load_vals<R>(a.val[y], a.vdt[y], a.vlen[y], rows, valid, other);
 #pragma unroll
                 for (int r = 0; r < R; r++)
-                    term[g][r] = int64_t(uint64_t(term[g][r]) * uint64_t(other[r]));
+                    term[g][r] = int64_t(uint64_t(term[g][r]) * uint64_t(agg_second(a, g, other[r])));
             }
         }
     }
@@ -429,11 +437,11 @@ __global__ __launch_bounds__(kGbNT) void k_gb_dense(KS ks, int64_t n,
             }
             int64_t v[R];
             load_vals<R>(a.val[a.ia[g]], a.vdt[a.ia[g]], a.vlen[a.ia[g]], row, ok, v);
-            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+            if (a.op[g] >= TQP_AGG_SUM_PRODUCT) {
                 int64_t vy[R];
                 load_vals<R>(a.val[a.ib[g]], a.vdt[a.ib[g]], a.vlen[a.ib[g]], row, ok, vy);
 #pragma unroll
-                for (int r = 0; r < R; r++) v[r] = int64_t(uint64_t(v[r]) * uint64_t(vy[r]));
+                for (int r = 0; r < R; r++) v[r] = int64_t(uint64_t(v[r]) * uint64_t(agg_second(a, g, vy[r])));
             }
 #pragma unroll
             for (int r = 0; r < R; r++)
@@ -496,12 +504,12 @@ __global__ __launch_bounds__(kGbNT) void k_gb_tiny(KS ks, int64_t n,
             }
             const int x = a.ia[g];
             load_vals<R>(a.val[x], a.vdt[x], a.vlen[x], row, ok, t[g]);
-            if (a.op[g] == TQP_AGG_SUM_PRODUCT) {
+            if (a.op[g] >= TQP_AGG_SUM_PRODUCT) {
                 const int y = a.ib[g];
                 int64_t vy[R];
                 load_vals<R>(a.val[y], a.vdt[y], a.vlen[y], row, ok, vy);
 #pragma unroll
-                for (int r = 0; r < R; r++) t[g][r] = int64_t(uint64_t(t[g][r]) * uint64_t(vy[r]));
+                for (int r = 0; r < R; r++) t[g][r] = int64_t(uint64_t(t[g][r]) * uint64_t(agg_second(a, g, vy[r])));
             }
         }
 #pragma unroll
@@ -740,16 +748,17 @@ static int agg_args(const tqp_col *vals, int nvals, const int32_t *val_rows, con
     }
     for (int g = 0; g < nagg; g++) {
         const tqp_agg &x = aggs[g];
-        if (x.op < TQP_AGG_SUM || x.op > TQP_AGG_SUM_PRODUCT)
+        if (x.op < TQP_AGG_SUM || x.op > TQP_AGG_SUM_DIFF_PRODUCT)
             return set_error(TQP_EINVAL, "%s: aggregate %d has a bad op", who, g);
         if (x.op != TQP_AGG_COUNT && (x.a < 0 || x.a >= nvals))
             return set_error(TQP_EINVAL, "%s: aggregate %d names a missing column", who, g);
-        if (x.op == TQP_AGG_SUM_PRODUCT && (x.b < 0 || x.b >= nvals))
+        if (x.op >= TQP_AGG_SUM_PRODUCT && (x.b < 0 || x.b >= nvals))
             return set_error(TQP_EINVAL, "%s: aggregate %d names a missing column", who, g);
         if (out_cap > 0 && !out_aggs[g]) return set_error(TQP_EINVAL, "%s: output %d is null", who, g);
         a->op[g] = x.op;
         a->ia[g] = x.a;
         a->ib[g] = x.b;
+        a->ic[g] = x.c;
     }
     if (val_rows && !col_aligned(val_rows, TQP_INT32))
         return set_error(TQP_EINVAL, "%s: val_rows must be 4-byte aligned", who);

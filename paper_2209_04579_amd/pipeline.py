@@ -492,13 +492,13 @@ class Q14Query:
 
     Plan: filter the month carrying partkey, price and discount; the LIKE over
     the part types (an (n, m) byte matrix) gives a 0/1 flag column; sort both
-    join sides (the part side carrying the flag); merge join; group by the
-    flag (two groups) with SUM(price), SUM(price * discount) and COUNT, so a
-    group's revenue is 100 * SUM(price) - SUM(price * discount), exact in
-    int64.
+    join sides (the part side carrying the flag); merge join; then two
+    aggregations of price * (100 - discount) and COUNT over the joined rows,
+    one grouped by the flag (the CASE: the group of flag 1) and one over all
+    rows (a single group), both exact in int64 on the device.
     """
 
-    AGGS = [("sum", 0), ("sum_product", 0, 1), ("count",)]
+    AGGS = [("sum_diff_product", 0, 1, 100), ("count",)]
 
     def __init__(self, items: dict, part: dict, prefix: bytes, ship_lo: int, ship_hi: int):
         self.items, self.part = items, part
@@ -531,9 +531,13 @@ class Q14Query:
         self.out_k = torch.empty(self.cap, dtype=torch.int32, device=dev)
         self.npairs = _i64(1, dev)
         self.ws_j = workspace(join_workspace_bytes(n, npart, torch.int32, JOIN_SORTED, self.cap), dev)
+        # by flag (2 groups) and over all rows (1 group)
         self.g_key = torch.empty(2, dtype=torch.int32, device=dev)
         self.g_out = [_i64(2, dev) for _ in self.AGGS]
         self.g_ng = _i64(1, dev)
+        self.t_key = torch.empty(1, dtype=torch.int32, device=dev)
+        self.t_out = [_i64(1, dev) for _ in self.AGGS]
+        self.t_ng = _i64(1, dev)
         self.ws_g = workspace(groupby_terms_workspace_bytes(len(self.AGGS), 2), dev)
 
     def run(self):
@@ -555,6 +559,9 @@ class Q14Query:
         groupby_agg_terms_into([(self.flag_s, self.out_r, 0, 1)], self.cap, self.fpay_s,
                                self.AGGS, self.g_key, self.g_out, self.g_ng, self.ws_g, 0, 2,
                                val_rows=self.out_l, d_n=self.npairs)
+        groupby_agg_terms_into([(None, None, 0, 0)], self.cap, self.fpay_s, self.AGGS,
+                               self.t_key, self.t_out, self.t_ng, self.ws_g, 0, 1,
+                               val_rows=self.out_l, d_n=self.npairs)
 
     def result(self) -> dict:
         torch.cuda.synchronize()
@@ -563,15 +570,14 @@ class Q14Query:
             raise RuntimeError(f"join produced {npairs} pairs, more than the {self.cap} planned")
         g = int(self.g_ng.item())
         keys = self.g_key[:g].cpu().tolist()
-        sp, spd, cnt = (o[:g].cpu().tolist() for o in self.g_out)
-
-        def wrap(x):
-            return (x + (1 << 63)) % (1 << 64) - (1 << 63)
-        rev = {k: wrap(100 * a - b) for k, a, b in zip(keys, sp, spd)}
-        count = dict(zip(keys, cnt))
+        rev, cnt = (o[:g].cpu().tolist() for o in self.g_out)
+        promo = keys.index(1) if 1 in keys else None
+        t = int(self.t_ng.item())
         return {"rows_filtered": int(self.cnt.item()), "pairs": npairs,
-                "promo_rev": rev.get(1, 0), "total_rev": wrap(sum(rev.values())),
-                "count": sum(count.values()), "promo_count": count.get(1, 0)}
+                "promo_rev": rev[promo] if promo is not None else 0,
+                "total_rev": int(self.t_out[0][0].item()) if t else 0,
+                "count": int(self.t_out[1][0].item()) if t else 0,
+                "promo_count": cnt[promo] if promo is not None else 0}
 
 
 class PredictQuery:
@@ -581,12 +587,15 @@ class PredictQuery:
         FROM reviews WHERE year >= year_min GROUP BY rating
 
     Plan: filter the years carrying the rating and the kept row ids; score
-    the kept rows (features read through the row ids); group by
-    rating * 2 + class, a dense domain, with COUNT.
+    the kept rows (features read through the row ids) with a two-class
+    model, whose class is 0 or 1, so the CASE is the class itself; group by
+    rating (a dense domain) with SUM(class) and COUNT.
     """
 
     def __init__(self, reviews: dict, model, nfeat: int, hidden: int, classes: int,
                  year_min: int, nratings: int):
+        if classes != 2:
+            raise ValueError("the prediction query's CASE over the class needs a two-class model")
         dev = reviews["rating"].device
         n = reviews["rating"].numel()
         self.n, self.hidden, self.classes, self.nratings = n, hidden, classes, nratings
@@ -599,19 +608,19 @@ class PredictQuery:
         self.cnt = _i64(1, dev)
         self.ws_f = workspace(filter_workspace_bytes(n), dev)
         self.cls = torch.empty(max(n, 1), dtype=torch.int8, device=dev)
-        self.span = nratings * classes
+        self.span = nratings
         self.g_key = torch.empty(self.span, dtype=torch.int32, device=dev)
-        self.g_cnt = [_i64(self.span, dev)]
+        self.g_out = [_i64(self.span, dev) for _ in range(2)]
         self.g_ng = _i64(1, dev)
-        self.ws_g = workspace(groupby_terms_workspace_bytes(1, self.span), dev)
+        self.ws_g = workspace(groupby_terms_workspace_bytes(2, self.span), dev)
 
     def run(self):
         filter_into([self.year], self.preds, [self.rating], [self.rating_f], self.rows, self.cnt,
                     self.ws_f)
         mlp_predict_into(self.feats, self.model, self.hidden, self.classes, self.cls, n=self.n,
                          rows=self.rows, d_n=self.cnt)
-        groupby_agg_terms_into([(self.rating_f, None, 0, self.classes), (self.cls, None, 0, 1)],
-                               self.n, [], [("count",)], self.g_key, self.g_cnt, self.g_ng,
+        groupby_agg_terms_into([(self.rating_f, None, 0, 1)], self.n, [self.cls],
+                               [("sum", 0), ("count",)], self.g_key, self.g_out, self.g_ng,
                                self.ws_g, 0, self.span, d_n=self.cnt)
 
     def result(self) -> dict:
@@ -619,9 +628,7 @@ class PredictQuery:
         g = int(self.g_ng.item())
         pos = np.zeros(self.nratings, np.int64)
         cnt = np.zeros(self.nratings, np.int64)
-        for k, c in zip(self.g_key[:g].cpu().tolist(), self.g_cnt[0][:g].cpu().tolist()):
-            r, cls = divmod(k, self.classes)
-            cnt[r] += c
-            if cls == 1:
-                pos[r] += c
+        keys = self.g_key[:g].cpu().numpy()
+        pos[keys] = self.g_out[0][:g].cpu().numpy()
+        cnt[keys] = self.g_out[1][:g].cpu().numpy()
         return {"rows_filtered": int(self.cnt.item()), "positive": pos, "count": cnt}

@@ -129,3 +129,22 @@ def test_filter_sort_argument_errors_without_a_gpu():
     short = (tqp.Col * 1)(tqp.Col(0x10000, 9, 2, 0))
     assert call(c=short) == tqp.TQP_EINVAL and b"column 0" in L.tqp_last_error()
     assert call(wsb=16) == tqp.TQP_ECAPACITY and b"workspace" in L.tqp_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
+def test_batch_plan_layout_and_limits_without_a_gpu():
+    import paper_2209_04579_amd as tqp
+    lay = tqp.batch_plan([10, 0, 25], [3, 1, 0], 999, 24)
+    assert lay["fact_off"] == [0, 10, 10, 35] and lay["dim_off"] == [0, 3, 4, 4]
+    assert lay["key_shift"] == 10 and lay["cat_shift"] == 5
+    assert (lay["fact_rows"], lay["dim_rows"]) == (35, 4)
+    # 256 instances need 8 prefix bits: 24-bit keys fit, 24-bit keys + 1 do not
+    assert tqp.batch_plan([1] * 256, [1] * 256, (1 << 23) - 1, 1)["key_shift"] == 23
+    with pytest.raises(tqp.TqpError):
+        tqp.batch_plan([1] * 256, [1] * 256, 1 << 23, 1)
+    with pytest.raises(tqp.TqpError):
+        tqp.batch_plan([1], [1], -1, 0)
+    L = tqp.lib()
+    assert L.tqp_batch_capture_begin(None) == tqp.TQP_EINVAL
+    assert L.tqp_batch_run(None, None) == tqp.TQP_EINVAL
+    assert L.tqp_batch_destroy(None) == tqp.TQP_OK

@@ -114,3 +114,18 @@ def test_batch_full_size_matches_oracle():
               "dim": {k: v.cpu().numpy() for k, v in i["dim"].items()},
               "day_cut": 1278} for i in dev]
     check_against_oracle(insts, got)
+
+
+@pytest.mark.parametrize("kdt", [np.int32, np.int64])
+@pytest.mark.parametrize("n", [0, 1, 5000, 1_000_003])
+def test_lower_bound_matches_searchsorted(kdt, n):
+    import paper_2209_04579_amd as tqp
+    keys = np.sort(dg.uniform_int(n + 1, 1, n, -1000, 1000, kdt))
+    q = np.concatenate([dg.uniform_int(n + 2, 2, 997, -1100, 1100, np.int64),
+                        np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0])])
+    out = torch.empty(len(q), dtype=torch.int64, device="cuda")
+    d_n = torch.tensor([n // 2], dtype=torch.int64, device="cuda")
+    tqp.lower_bound_into(torch.from_numpy(keys).cuda(), torch.from_numpy(q).cuda(), out, d_n=d_n)
+    assert np.array_equal(out.cpu().numpy(), np.searchsorted(keys[:n // 2], q, side="left"))
+    tqp.lower_bound_into(torch.from_numpy(keys).cuda(), torch.from_numpy(q).cuda(), out)
+    assert np.array_equal(out.cpu().numpy(), np.searchsorted(keys, q, side="left"))

@@ -349,3 +349,38 @@ def test_groupby_agg_terms_device_count_and_limits(tqp):
     with pytest.raises(tqp.TqpError):          # accumulators beyond the LDS budget
         tqp.groupby_agg_terms_into([(dev(cat), None, 0, 1)], n, [dev(qty)],
                                    [("sum", 0), ("count",)], out_key, outs, ng, ws, 0, 4000)
+
+
+DIFF_AGGS = [("sum_diff_product", 0, 1, 100), ("count",), ("sum_diff_product", 1, 0, -7),
+             ("sum", 0)]
+
+
+@pytest.mark.parametrize("path", ["sort", "sorted", "dense", "terms_tiny", "terms_dense"])
+@pytest.mark.parametrize("n", [0, 1, 4097, 300_001])
+def test_groupby_sum_diff_product_every_path(tqp, path, n):
+    """SUM(a * (c - b)) (Q14's revenue shape) through each group-by kernel,
+    against the oracle, including a negative constant and int8 b."""
+    span = 2 if path == "terms_tiny" else 125
+    keys = dg.uniform_int(n + 5, 1, n, 0, span, np.int32)
+    if path == "sorted":
+        keys = np.sort(keys)
+    a = dg.uniform_int(n + 5, 2, n, 90_000, 10_494_951, np.int64)
+    b = dg.uniform_int(n + 5, 3, n, 0, 11, np.int8)
+    wk, wa, ovf = oracle.groupby(keys, [a, b], DIFF_AGGS)
+    assert not ovf
+    if path in ("sort", "sorted", "dense"):
+        flags = {"sort": 0, "sorted": tqp.GB_SORTED, "dense": tqp.GB_DENSE}[path]
+        uk, aggs = tqp.groupby_agg(dev(keys), [dev(a), dev(b)], DIFF_AGGS, flags=flags,
+                                   key_lo=0, key_span=span if path == "dense" else 0)
+    else:
+        out_key = torch.empty(span, dtype=torch.int32, device="cuda")
+        aggs = [torch.empty(span, dtype=torch.int64, device="cuda") for _ in DIFF_AGGS]
+        ng = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ws = tqp.workspace(tqp.groupby_terms_workspace_bytes(len(DIFF_AGGS), span))
+        tqp.groupby_agg_terms_into([(dev(keys), None, 0, 1)], n, [dev(a), dev(b)], DIFF_AGGS,
+                                   out_key, aggs, ng, ws, 0, span)
+        g = int(ng.item())
+        uk, aggs = out_key[:g], [t[:g] for t in aggs]
+    assert np.array_equal(host(uk).astype(np.int64), wk)
+    for got, w in zip(aggs, wa):
+        assert np.array_equal(host(got), w)
