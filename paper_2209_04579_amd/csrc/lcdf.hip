@@ -51,11 +51,8 @@ namespace tqp {
 constexpr int kHidden = 32;
 constexpr int kKnots = 8;                    // spline knots per leaf
 constexpr int kNParam = 3 * kHidden + 1;     // centre offset, log-width, log-height per ramp; d
-constexpr int kTrainPoints = 16384;          // root training set (sample points, even ranks)
-constexpr int kGradBlocks = 64;
+constexpr int kTrainPoints = 4096;           // root training set (sample points, even ranks)
 constexpr int kLeafMax = 65536;
-constexpr int kBucketCap = 8192;             // keys sorted in LDS by one workgroup
-constexpr int kBucketNT = 256;
 constexpr int kHeavyMin = 4;                 // sample copies that make a key heavy
 constexpr int64_t kOvfCap = 65536;           // overflow buckets re-sorted one by one
 
@@ -71,18 +68,21 @@ struct LcdfModel {
     // log height, bias; Adam moments; the best parameters seen and their loss
     float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
     float c0[kHidden], s0[kHidden];
-    struct Leaf {
+    // 160 bytes in ten aligned 16-byte groups, so an evaluation loads a
+    // leaf with ten vector loads issued together
+    struct alignas(16) Leaf {
         int64_t kx[kKnots];                   // knot keys, ascending
-        float slope[kKnots - 1];              // rank per key unit on each segment
         float kr[kKnots];                     // knot ranks, ascending
+        float slope[kKnots];                  // rank per key unit on each segment (last unused)
         float lo, hi;                         // the leaf's rank range
+        float hlo, hhi;                       // ranks where the heavy key's copies start / end
         int64_t hkey;                         // heavy key, when hlo <= hhi
-        float hlo, hhi;                       // ranks where its copies start / end
         int32_t nk;                           // knots in use (0: constant lo)
         int32_t pad;
     } leaf[1];                                // nleaf entries
 };
 using Leaf = LcdfModel::Leaf;
+static_assert(sizeof(Leaf) == 160 && kKnots == 8, "leaf layout");
 
 static size_t model_bytes(int nleaf) {
     return sizeof(LcdfModel) + sizeof(Leaf) * size_t(nleaf > 0 ? nleaf - 1 : 0);
@@ -133,23 +133,82 @@ __device__ __forceinline__ int lcdf_leaf_of(const LcdfModel *m, int64_t key) {
     return lcdf_leaf(m, lcdf_root(m, lcdf_x(m, key)));
 }
 
-__device__ __forceinline__ float lcdf_leaf_eval(const Leaf &L, int64_t key) {
+// A leaf's fields in registers (ten 16-byte loads).
+struct LeafRegs {
+    int64_t kx[kKnots];
+    float kr[kKnots], slope[kKnots];
+    float lo, hi, hlo, hhi;
+    int64_t hkey;
+    int32_t nk;
+};
+
+__device__ __forceinline__ void leaf_load(const Leaf &Lm, LeafRegs &L) {
+    const int4 *q = reinterpret_cast<const int4 *>(&Lm);
+    int4 v[10];
+#pragma unroll
+    for (int i = 0; i < 10; i++) v[i] = q[i];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        L.kx[2 * i] = (int64_t(uint32_t(v[i].y)) << 32) | uint32_t(v[i].x);
+        L.kx[2 * i + 1] = (int64_t(uint32_t(v[i].w)) << 32) | uint32_t(v[i].z);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        L.kr[4 * i + 0] = __int_as_float(v[4 + i].x);
+        L.kr[4 * i + 1] = __int_as_float(v[4 + i].y);
+        L.kr[4 * i + 2] = __int_as_float(v[4 + i].z);
+        L.kr[4 * i + 3] = __int_as_float(v[4 + i].w);
+        L.slope[4 * i + 0] = __int_as_float(v[6 + i].x);
+        L.slope[4 * i + 1] = __int_as_float(v[6 + i].y);
+        L.slope[4 * i + 2] = __int_as_float(v[6 + i].z);
+        L.slope[4 * i + 3] = __int_as_float(v[6 + i].w);
+    }
+    L.lo = __int_as_float(v[8].x);
+    L.hi = __int_as_float(v[8].y);
+    L.hlo = __int_as_float(v[8].z);
+    L.hhi = __int_as_float(v[8].w);
+    L.hkey = (int64_t(uint32_t(v[9].y)) << 32) | uint32_t(v[9].x);
+    L.nk = v[9].z;
+}
+
+// F of one key in its leaf.  The spline segment is the last knot at or below
+// the key; each segment's value is clamped to its two knot ranks, so F is
+// monotone across segments even with rounding.
+__device__ __forceinline__ float lcdf_leaf_eval(const LeafRegs &L, int64_t key) {
     float f = L.lo;
     const int nk = L.nk;
     if (nk > 0) {
+        int64_t klast = L.kx[0];
+        float rlast = L.kr[0];
+#pragma unroll
+        for (int t = 1; t < kKnots; t++)
+            if (t == nk - 1) {
+                klast = L.kx[t];
+                rlast = L.kr[t];
+            }
         if (key <= L.kx[0]) {
             f = L.kr[0];
-        } else if (key >= L.kx[nk - 1]) {
-            f = L.kr[nk - 1];
+        } else if (key >= klast) {
+            f = rlast;
         } else {
             int j = 0;
 #pragma unroll
             for (int t = 1; t < kKnots - 1; t++)
                 if (t < nk - 1 && L.kx[t] <= key) j = t;
-            const float d = float(uint64_t(key) - uint64_t(L.kx[j]));   // in [0, 2^64)
-            float g = fmaf(L.slope[j], d, L.kr[j]);
-            g = g < L.kr[j] ? L.kr[j] : g;
-            f = g > L.kr[j + 1] ? L.kr[j + 1] : g;
+            int64_t kj = L.kx[0];
+            float rj = L.kr[0], rj1 = L.kr[1], sj = L.slope[0];
+#pragma unroll
+            for (int t = 1; t < kKnots - 1; t++)
+                if (t == j) {
+                    kj = L.kx[t];
+                    rj = L.kr[t];
+                    rj1 = L.kr[t + 1];
+                    sj = L.slope[t];
+                }
+            const float d = float(uint64_t(key) - uint64_t(kj));        // in [0, 2^64)
+            float g = fmaf(sj, d, rj);
+            g = g < rj ? rj : g;
+            f = g > rj1 ? rj1 : g;
         }
     }
     f = f < L.lo ? L.lo : (f > L.hi ? L.hi : f);
@@ -159,6 +218,12 @@ __device__ __forceinline__ float lcdf_leaf_eval(const Leaf &L, int64_t key) {
         else f = f > L.hhi ? f : L.hhi;
     }
     return f;
+}
+
+__device__ __forceinline__ float lcdf_leaf_eval(const Leaf &Lm, int64_t key) {
+    LeafRegs L;
+    leaf_load(Lm, L);
+    return lcdf_leaf_eval(L, key);
 }
 
 __device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
@@ -185,8 +250,11 @@ template <class K> struct LearnedOrd {
 #pragma unroll
         for (int r = 0; r < R; r++) x[r] = lcdf_x(m, int64_t(k[r]));
         lcdf_root_n<R>(m, x, y);
+        LeafRegs L[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) b[r] = bucket(lcdf_leaf_eval(m->leaf[lcdf_leaf(m, y[r])], int64_t(k[r])));
+        for (int r = 0; r < R; r++) leaf_load(m->leaf[lcdf_leaf(m, y[r])], L[r]);
+#pragma unroll
+        for (int r = 0; r < R; r++) b[r] = bucket(lcdf_leaf_eval(L[r], int64_t(k[r])));
     }
 };
 
@@ -256,102 +324,165 @@ __global__ __launch_bounds__(256) void k_lcdf_init(const int64_t *sorted, int64_
     }
 }
 
-// Partial gradients of the mean squared error over one slice of the
-// training points; part[block][p] (p = kNParam holds the partial loss).
-__global__ __launch_bounds__(256) void k_lcdf_grad(const LcdfModel *mod, const float *tx,
-                                                   const float *tq, int T, float *part) {
-    __shared__ float s_th[kNParam];
-    __shared__ float s_red[256 / kWave][kNParam + 1];
-    for (int p = threadIdx.x; p < kNParam; p += blockDim.x) s_th[p] = mod->theta[p];
-    // the centres themselves in the first kHidden slots
-    if (threadIdx.x < kHidden)
-        s_th[threadIdx.x] = mod->c0[threadIdx.x] + mod->s0[threadIdx.x] * mod->theta[threadIdx.x];
-    __syncthreads();
-    float g[kNParam + 1];
-#pragma unroll
-    for (int p = 0; p <= kNParam; p++) g[p] = 0.f;
-    const float inv_t = 2.0f / float(T);
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
-        const float x = tx[t];
-        float y = s_th[3 * kHidden];
-        float z[kHidden];
-#pragma unroll
-        for (int j = 0; j < kHidden; j++) {
-            const float w = __expf(-s_th[kHidden + j]);
-            z[j] = (x - s_th[j]) * w + 0.5f;
-            y += __expf(s_th[2 * kHidden + j]) * ramp(z[j]);
-        }
-        const float err = y - tq[t];
-        const float e = err * inv_t;
-        g[kNParam] += err * err / float(T);
-        g[3 * kHidden] += e;
-#pragma unroll
-        for (int j = 0; j < kHidden; j++) {
-            const float w = __expf(-s_th[kHidden + j]);
-            const float v = __expf(s_th[2 * kHidden + j]);
-            const bool act = z[j] > 0.f && z[j] < 1.f;
-            const float h = z[j] < 0.f ? 0.f : (z[j] > 1.f ? 1.f : z[j]);
-            if (act) {
-                g[j] += e * v * (-w) * mod->s0[j];           // d/du = s0 * d/dcentre
-                g[kHidden + j] += e * v * (-(z[j] - 0.5f));
-            }
-            g[2 * kHidden + j] += e * v * h;
-        }
-    }
-    const int w = wave_id();
-#pragma unroll
-    for (int p = 0; p <= kNParam; p++) {
-        float s = g[p];
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) s += __shfl_xor(s, o, kWave);
-        if (lane_id() == 0) s_red[w][p] = s;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p <= kNParam; p += blockDim.x) {
-        float s = 0.f;
-        for (int ww = 0; ww < 256 / kWave; ww++) s += s_red[ww][p];
-        part[blockIdx.x * (kNParam + 1) + p] = s;
-    }
-}
+// The whole training loop in one launch: one workgroup keeps the parameters,
+// Adam's moments and the training points on chip and runs `steps`
+// full-batch steps.  Each step: the per-ramp constants (inverse width,
+// height, centre) once; a forward pass (thread t: points t + k * 1024) that
+// leaves every point's scaled error in LDS; a backward pass in which thread
+// t accumulates the three gradients of ramp t mod 32 over the points
+// congruent to t / 32 mod 32; reductions in a fixed order (lanes by
+// shuffles, then the waves in turn); one Adam step per parameter (b1 = 0.9,
+// b2 = 0.999, bias-corrected).  The parameters with the lowest loss seen are
+// kept.  The gradient is that of the mean squared error between the root
+// and the sample ranks.
+constexpr int kFitNT = 1024;
+constexpr int kFitNW = kFitNT / kWave;
+constexpr int kFitPer = kTrainPoints / kFitNT;              // forward points per thread
+constexpr int kFitGroups = kFitNT / kHidden;                // threads per ramp in the backward pass
+static_assert(kTrainPoints % kFitNT == 0 && kFitNT % kHidden == 0, "training layout");
 
-// Sums the partial gradients in a fixed order, records the parameters if
-// their loss is the lowest so far, and takes one Adam step.
-__global__ __launch_bounds__(128) void k_lcdf_adam(LcdfModel *mod, const float *part, int nparts,
-                                                   float lr) {
-    __shared__ float s_loss;
-    __shared__ int s_better;
-    const int step = mod->steps_done + 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    if (threadIdx.x == 0) {
-        float l = 0.f;
-        for (int b = 0; b < nparts; b++) l += part[b * (kNParam + 1) + kNParam];
-        s_loss = l;
-        s_better = l < mod->loss_best;
+__global__ __launch_bounds__(kFitNT) void k_lcdf_fit(LcdfModel *mod, const float *tx,
+                                                     const float *tq, int T, int steps, float lr) {
+    __shared__ float s_th[kNParam], s_m1[kNParam], s_m2[kNParam], s_best[kNParam];
+    __shared__ float s_w[kHidden], s_v[kHidden], s_c[kHidden], s_c0[kHidden], s_s0[kHidden];
+    __shared__ float s_x[kTrainPoints], s_e[kTrainPoints];
+    __shared__ float s_red[kFitNW][3 * kHidden];
+    __shared__ float s_red1[kFitNW][2];
+    __shared__ float s_g[kNParam + 1];
+    __shared__ float s_lbest, s_lfirst, s_llast;
+    __shared__ int s_step;
+    const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
+    for (int p = tid; p < kNParam; p += kFitNT) {
+        s_th[p] = mod->theta[p];
+        s_m1[p] = mod->m1[p];
+        s_m2[p] = mod->m2[p];
+        s_best[p] = mod->theta[p];
     }
+    if (tid < kHidden) {
+        s_c0[tid] = mod->c0[tid];
+        s_s0[tid] = mod->s0[tid];
+    }
+    if (tid == 0) {
+        s_lbest = mod->loss_best;
+        s_lfirst = mod->loss_first;
+        s_llast = mod->loss_last;
+        s_step = mod->steps_done;
+    }
+    float pq[kFitPer];
+#pragma unroll
+    for (int k = 0; k < kFitPer; k++) {
+        const int t = tid + k * kFitNT;
+        s_x[t] = t < T ? tx[t] : 0.f;
+        pq[k] = t < T ? tq[t] : 0.f;
+    }
+    const float inv_t = 2.0f / float(T);
+    const int j = tid % kHidden, q = tid / kHidden;
     __syncthreads();
-    for (int p = threadIdx.x; p < kNParam; p += blockDim.x)
-        if (s_better) mod->best[p] = mod->theta[p];
-    for (int p = threadIdx.x; p <= kNParam; p += blockDim.x) {
-        float g = 0.f;
-        for (int b = 0; b < nparts; b++) g += part[b * (kNParam + 1) + p];
-        if (p == kNParam) {
-            if (step == 1) mod->loss_first = s_loss;
-            mod->loss_last = s_loss;
-            if (s_better) mod->loss_best = s_loss;
-            continue;
+    for (int it = 0; it < steps; it++) {
+        if (tid < kHidden) {
+            s_w[tid] = __expf(-s_th[kHidden + tid]);
+            s_v[tid] = __expf(s_th[2 * kHidden + tid]);
+            s_c[tid] = s_c0[tid] + s_s0[tid] * s_th[tid];
         }
-        const float m1 = b1 * mod->m1[p] + (1.f - b1) * g;
-        const float m2 = b2 * mod->m2[p] + (1.f - b2) * g * g;
-        mod->m1[p] = m1;
-        mod->m2[p] = m2;
-        const float mh = m1 / (1.f - powf(b1, float(step)));
-        const float vh = m2 / (1.f - powf(b2, float(step)));
-        float th = mod->theta[p] - lr * mh / (sqrtf(vh) + 1e-12f);
-        if (p >= kHidden && p < 2 * kHidden && th < -40.f) th = -40.f;    // width > 0
-        mod->theta[p] = th;
+        __syncthreads();
+        // forward: the root at this thread's points, their scaled errors
+        float loss = 0.f, esum = 0.f;
+#pragma unroll
+        for (int k = 0; k < kFitPer; k++) {
+            const int t = tid + k * kFitNT;
+            const float x = s_x[t];
+            float y = s_th[3 * kHidden];
+#pragma unroll
+            for (int r = 0; r < kHidden; r++) y += s_v[r] * ramp((x - s_c[r]) * s_w[r] + 0.5f);
+            const float err = t < T ? y - pq[k] : 0.f;
+            s_e[t] = err * inv_t;
+            loss += err * err / float(T);
+            esum += err * inv_t;
+        }
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            loss += __shfl_xor(loss, o, kWave);
+            esum += __shfl_xor(esum, o, kWave);
+        }
+        if (lane == 0) {
+            s_red1[w][0] = loss;
+            s_red1[w][1] = esum;
+        }
+        __syncthreads();
+        // backward: ramp j over the points q, q + 32, ...
+        {
+            const float wj = s_w[j], vj = s_v[j], cj = s_c[j], sj = s_s0[j];
+            float gc = 0.f, gw = 0.f, gv = 0.f;
+            for (int p = q; p < T; p += kFitGroups) {
+                const float z = (s_x[p] - cj) * wj + 0.5f;
+                const float e = s_e[p];
+                const float h = z < 0.f ? 0.f : (z > 1.f ? 1.f : z);
+                if (z > 0.f && z < 1.f) {
+                    gc += e * vj * (-wj) * sj;                    // d/du = s0 * d/dcentre
+                    gw += e * vj * (-(z - 0.5f));
+                }
+                gv += e * vj * h;
+            }
+            // lanes l and l + 32 of a wave hold the same ramp
+            gc += __shfl_xor(gc, kHidden, kWave);
+            gw += __shfl_xor(gw, kHidden, kWave);
+            gv += __shfl_xor(gv, kHidden, kWave);
+            if (lane < kHidden) {
+                s_red[w][j] = gc;
+                s_red[w][kHidden + j] = gw;
+                s_red[w][2 * kHidden + j] = gv;
+            }
+        }
+        __syncthreads();
+        if (tid <= kNParam) {
+            float sum = 0.f;
+            if (tid < 3 * kHidden) {
+                for (int ww = 0; ww < kFitNW; ww++) sum += s_red[ww][tid];
+            } else {
+                const int c = tid == 3 * kHidden ? 1 : 0;        // bias gradient, then the loss
+                for (int ww = 0; ww < kFitNW; ww++) sum += s_red1[ww][c];
+            }
+            s_g[tid] = sum;
+        }
+        __syncthreads();
+        const float lossv = s_g[kNParam];
+        const bool better = lossv < s_lbest;
+        const int step = s_step + 1;
+        if (tid < kNParam) {
+            const int p = tid;
+            if (better) s_best[p] = s_th[p];
+            const float b1 = 0.9f, b2 = 0.999f, gp = s_g[p];
+            const float m1 = b1 * s_m1[p] + (1.f - b1) * gp;
+            const float m2 = b2 * s_m2[p] + (1.f - b2) * gp * gp;
+            s_m1[p] = m1;
+            s_m2[p] = m2;
+            const float mh = m1 / (1.f - powf(b1, float(step)));
+            const float vh = m2 / (1.f - powf(b2, float(step)));
+            float th = s_th[p] - lr * mh / (sqrtf(vh) + 1e-12f);
+            if (p >= kHidden && p < 2 * kHidden && th < -40.f) th = -40.f;    // width > 0
+            s_th[p] = th;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (step == 1) s_lfirst = lossv;
+            s_llast = lossv;
+            if (better) s_lbest = lossv;
+            s_step = step;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x == 0) mod->steps_done = step;
+    for (int p = tid; p < kNParam; p += kFitNT) {
+        mod->theta[p] = s_th[p];
+        mod->m1[p] = s_m1[p];
+        mod->m2[p] = s_m2[p];
+        if (steps > 0) mod->best[p] = s_best[p];
+    }
+    if (tid == 0) {
+        mod->loss_best = s_lbest;
+        mod->loss_first = s_lfirst;
+        mod->loss_last = s_llast;
+        mod->steps_done = s_step;
+    }
 }
 
 // Effective root parameters from the best parameters seen (the starting ones
@@ -438,8 +569,8 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
         L.kx[j] = sorted[p];
         L.kr[j] = float((double(p) + 0.5) / double(m));
     }
-    for (int j = 0; j + 1 < nk; j++) {
-        const double dx = double(uint64_t(L.kx[j + 1]) - uint64_t(L.kx[j]));
+    for (int j = 0; j < kKnots; j++) {
+        const double dx = j + 1 < nk ? double(uint64_t(L.kx[j + 1]) - uint64_t(L.kx[j])) : 0.0;
         L.slope[j] = dx > 0 ? float((double(L.kr[j + 1]) - double(L.kr[j])) / dx) : 0.f;
     }
     L.nk = nk;
@@ -462,11 +593,34 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
 
 // Empty leaves take the rank reached by the leaves before them, so the
 // rank ranges stay ordered; the first leaf's range starts at 0, the last
-// one's ends at 1.
-__global__ void k_lcdf_leaf_fill(LcdfModel *mod) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one's ends at 1.  One workgroup: each thread takes a run of consecutive
+// leaves; the rank reached before a run is the last non-empty leaf's hi
+// among the runs before it (a prefix "last value" scan over the runs).
+constexpr int kFillNT = 256;
+
+__global__ __launch_bounds__(kFillNT) void k_lcdf_leaf_fill(LcdfModel *mod) {
+    __shared__ float s_last[kFillNT];
+    __shared__ int s_has[kFillNT];
+    const int nl = mod->nleaf;
+    const int per = (nl + kFillNT - 1) / kFillNT;
+    const int a = threadIdx.x * per, b = a + per < nl ? a + per : nl;
+    float last = 0.f;
+    int has = 0;
+    for (int k = a; k < b; k++)
+        if (mod->leaf[k].nk != 0) {
+            last = mod->leaf[k].hi;
+            has = 1;
+        }
+    s_last[threadIdx.x] = last;
+    s_has[threadIdx.x] = has;
+    __syncthreads();
     float prev = 0.f;
-    for (int k = 0; k < mod->nleaf; k++) {
+    for (int t = threadIdx.x - 1; t >= 0; t--)
+        if (s_has[t]) {
+            prev = s_last[t];
+            break;
+        }
+    for (int k = a; k < b; k++) {
         Leaf &L = mod->leaf[k];
         if (L.nk == 0) {
             L.lo = L.hi = prev;
@@ -475,7 +629,8 @@ __global__ void k_lcdf_leaf_fill(LcdfModel *mod) {
             prev = L.hi;
         }
     }
-    mod->leaf[mod->nleaf - 1].hi = 1.f;
+    __syncthreads();
+    if (threadIdx.x == 0) mod->leaf[nl - 1].hi = 1.f;
 }
 
 template <class K>
@@ -491,12 +646,8 @@ __global__ void k_lcdf_buckets(const LcdfModel *mod, const K *keys, int64_t n, i
 
 struct BucketStats {
     unsigned long long max_bucket;
-    unsigned long long nbig;            // buckets larger than the LDS tile
-    unsigned long long nmed;            // buckets sorted by a workgroup in LDS
-    unsigned long long nwave;           // buckets sorted by one wave
+    unsigned long long nbig;            // entries of the big-bucket list
 };
-
-constexpr int kSmallRun = 16;           // buckets up to this size sort in registers
 
 struct Overflow {
     int64_t start, len, kmin, kmax;
@@ -518,7 +669,7 @@ __device__ __forceinline__ void ord_many(const Ord &o, const K (&k)[R], uint32_t
 template <class K, class Ord>
 __global__ __launch_bounds__(256) void k_bucket_ids(const K *__restrict__ keys, int64_t n, Ord ord,
                                                     int32_t *__restrict__ ids) {
-    constexpr int R = 4;                // keys per thread per step, loads issued together
+    constexpr int R = 2;                // keys per thread per step, loads issued together
     const int64_t stride = int64_t(gridDim.x) * blockDim.x * R;
     for (int64_t base = blockIdx.x * int64_t(blockDim.x) * R + threadIdx.x; base < n;
          base += stride) {
@@ -545,77 +696,82 @@ __device__ __forceinline__ int64_t run_end(const int32_t *rs, int64_t nruns, int
     return r + 1 < nruns ? int64_t(rs[r + 1]) : n;
 }
 
-// One thread per bucket.  Buckets of at most kSmallRun keys are sorted in
-// registers by a bitonic network on (key, position), the stable order;
-// larger ones are listed for one wave (up to kWave keys), a workgroup (up to
-// kBucketCap keys) or the big-bucket path.
-template <class K>
-__global__ __launch_bounds__(256) void k_bucket_small(K *keys, int32_t *rows,
-                                                      const int32_t *__restrict__ rs,
-                                                      const int64_t *__restrict__ d_nruns,
-                                                      int64_t n, BucketStats *stats, int32_t *med,
-                                                      int32_t *wav, Overflow *big, int64_t big_cap) {
-    const K kMax = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
+// ---- windows: every bucket of at most kWinCap keys, sorted in LDS ------------
+//
+// The grouped keys are cut into windows of whole buckets: window w holds the
+// buckets that start in [w * kWin, (w + 1) * kWin), so it spans at most
+// kWinCap = 2 kWin positions when none of its buckets is larger than kWin.
+// Buckets are disjoint key ranges in key order, so sorting a window's keys
+// as one sequence sorts each of its buckets.  A window wider than kWinCap
+// (it holds a bucket of more than kWin keys) hands its buckets to the
+// big-bucket path instead: buckets of more than kWinCap keys one by one,
+// runs of smaller consecutive buckets as segments.
+constexpr int kWin = 4096;
+constexpr int kWinCap = 2 * kWin;
+constexpr int kWinNT = 1024;
+constexpr int kWinPer = kWinCap / kWinNT;        // elements per thread
+constexpr int kWinIdxBits = 13;                  // local index in a packed value
+static_assert((1 << kWinIdxBits) == kWinCap, "packed index width");
+
+__device__ __forceinline__ int64_t runs_lower_bound(const int32_t *rs, int64_t nruns, int64_t pos) {
+    int64_t lo = 0, hi = nruns;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (int64_t(rs[mid]) < pos) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void push_big(BucketStats *stats, Overflow *big, int64_t big_cap,
+                                         int64_t start, int64_t len) {
+    const unsigned long long slot = atomicAdd(&stats->nbig, 1ull);
+    if (int64_t(slot) < big_cap) big[slot] = Overflow{start, len, 0, 0, 0};
+}
+
+// One thread per window: its range [start, end), or the hand-off of its
+// buckets to the big-bucket path.  win[w] = {start, end}; end <= start means
+// nothing to sort.
+__global__ __launch_bounds__(256) void k_window_plan(const int32_t *__restrict__ rs,
+                                                     const int64_t *__restrict__ d_nruns, int64_t n,
+                                                     int64_t nwin, int2 *win, BucketStats *stats,
+                                                     Overflow *big, int64_t big_cap) {
     const int64_t nruns = *d_nruns;
-    unsigned long long mx = 0;
-    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nruns;
-         b += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t s0 = rs[b], len = run_end(rs, nruns, b, n) - s0;
-        if (len <= 1) continue;
-        mx = (unsigned long long)len > mx ? (unsigned long long)len : mx;
-        if (len > kSmallRun) {
-            if (len <= kWave) {
-                const unsigned long long slot = atomicAdd(&stats->nwave, 1ull);
-                wav[slot] = int32_t(b);
-            } else if (len <= kBucketCap) {
-                const unsigned long long slot = atomicAdd(&stats->nmed, 1ull);
-                med[slot] = int32_t(b);
-            } else {
-                const unsigned long long slot = atomicAdd(&stats->nbig, 1ull);
-                if (int64_t(slot) < big_cap) big[slot] = Overflow{s0, len, 0, 0, 0};
-            }
+    for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < nwin;
+         w += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t a = runs_lower_bound(rs, nruns, w * kWin);
+        const int64_t b = runs_lower_bound(rs, nruns, (w + 1) * kWin);
+        const int64_t s0 = a < nruns ? rs[a] : n, e0 = b < nruns ? rs[b] : n;
+        if (e0 - s0 <= kWinCap) {
+            win[w] = make_int2(int(s0), int(e0));
             continue;
         }
-        K k[kSmallRun];
-        int32_t r[kSmallRun];
-        uint32_t p[kSmallRun];
-#pragma unroll
-        for (int i = 0; i < kSmallRun; i++) {
-            k[i] = i < len ? keys[s0 + i] : kMax;
-            r[i] = i < len ? rows[s0 + i] : 0;
-            p[i] = uint32_t(i);
-        }
-#pragma unroll
-        for (int w = 2; w <= kSmallRun; w <<= 1) {
-#pragma unroll
-            for (int j = w >> 1; j > 0; j >>= 1) {
-#pragma unroll
-                for (int i = 0; i < kSmallRun; i++) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const bool up = (i & w) == 0;
-                        const bool gt = k[i] > k[l] || (k[i] == k[l] && p[i] > p[l]);
-                        if (gt == up) {
-                            const K tk = k[i];
-                            k[i] = k[l];
-                            k[l] = tk;
-                            const int32_t tr = r[i];
-                            r[i] = r[l];
-                            r[l] = tr;
-                            const uint32_t tp = p[i];
-                            p[i] = p[l];
-                            p[l] = tp;
-                        }
-                    }
-                }
+        win[w] = make_int2(int(s0), int(s0));
+        int64_t seg = -1;                        // start of the current run of small buckets
+        for (int64_t r = a; r < b; r++) {
+            const int64_t st = rs[r], len = run_end(rs, nruns, r, n) - st;
+            if (len > kWinCap) {
+                if (seg >= 0 && st - seg > 1) push_big(stats, big, big_cap, seg, st - seg);
+                seg = -1;
+                push_big(stats, big, big_cap, st, len);
+            } else if (seg < 0) {
+                seg = st;
             }
         }
-#pragma unroll
-        for (int i = 0; i < kSmallRun; i++)
-            if (i < len) {
-                keys[s0 + i] = k[i];
-                rows[s0 + i] = r[i];
-            }
+        if (seg >= 0 && e0 - seg > 1) push_big(stats, big, big_cap, seg, e0 - seg);
+    }
+}
+
+// The largest bucket (reported by the partition sort).
+__global__ __launch_bounds__(256) void k_run_max(const int32_t *__restrict__ rs,
+                                                 const int64_t *__restrict__ d_nruns, int64_t n,
+                                                 BucketStats *stats) {
+    const int64_t nruns = *d_nruns;
+    unsigned long long mx = 0;
+    for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < nruns;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        const unsigned long long len = (unsigned long long)(run_end(rs, nruns, r, n) - rs[r]);
+        mx = len > mx ? len : mx;
     }
     for (int o = 1; o < kWave; o <<= 1) {
         const unsigned long long om = __shfl_xor(mx, o, kWave);
@@ -624,120 +780,212 @@ __global__ __launch_bounds__(256) void k_bucket_small(K *keys, int32_t *rows,
     if (lane_id() == 0 && mx) atomicMax(&stats->max_bucket, mx);
 }
 
-// Buckets of kSmallRun + 1 to kWave keys: one wave each, one key per lane,
-// a bitonic network over the lanes (shuffles) on (key, position).
+// Compare-exchange of two registers (ascending).
+__device__ __forceinline__ void cx(uint64_t &a, uint64_t &b) {
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// LDS index of element i of a window buffer: one padding slot per 8, so the
+// 8 consecutive elements a thread reads or writes do not all fall on the
+// same banks as its neighbours'.
+__device__ __forceinline__ int wphys(int i) { return i + (i >> 3); }
+constexpr int kWinPhys = kWinCap + kWinCap / 8;
+
+// Persistent workgroups over the windows.  A window of m keys whose key span
+// (max - min) is below 2^51 is sorted as packed values
+// ((key - min) << 13 | local index), all distinct, by a merge sort in LDS:
+// runs of 8 sorted in registers, then merge levels 8, 16, ... where each
+// thread finds its 8 outputs by a merge-path search (the last run of a level
+// may be short: nothing is padded beyond a multiple of 8).  Ties cannot
+// occur, so the order is (key, position), the stable one.  A wider window is
+// sorted by a bitonic network on (key, local index) in LDS.  Row ids are read
+// through the local indices and written back in place.
 template <class K>
-__global__ __launch_bounds__(256) void k_bucket_wave(K *keys, int32_t *rows,
-                                                     const int32_t *__restrict__ rs,
-                                                     const int64_t *__restrict__ d_nruns, int64_t n,
-                                                     const int32_t *__restrict__ wav,
-                                                     const BucketStats *stats) {
-    const K kMax = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
-    const int64_t nw = int64_t(stats->nwave);
-    const int64_t nruns = *d_nruns;
-    const int lane = lane_id();
-    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / kWave);
-    for (int64_t m = blockIdx.x * int64_t(blockDim.x / kWave) + wave_id(); m < nw; m += waves) {
-        const int64_t b = wav[m];
-        const int64_t s0 = rs[b], len = run_end(rs, nruns, b, n) - s0;
-        const bool in = lane < len;
-        K k = in ? keys[s0 + lane] : kMax;
-        int32_t r = in ? rows[s0 + lane] : 0;
-        int32_t p = lane;                           // padding sorts after every key
+__device__ __forceinline__ void window_load(const K *keys, const int32_t *rows, const int2 *win,
+                                            int64_t w, int64_t nwin, int2 &se, K (&k)[kWinPer],
+                                            int32_t (&r)[kWinPer]) {
+    se = w < nwin ? win[w] : make_int2(0, 0);
+    const int m = se.y - se.x;
 #pragma unroll
-        for (int w = 2; w <= kWave; w <<= 1) {
-#pragma unroll
-            for (int j = w >> 1; j > 0; j >>= 1) {
-                const K ok = __shfl_xor(k, j, kWave);
-                const int32_t orow = __shfl_xor(r, j, kWave);
-                const int32_t op = __shfl_xor(p, j, kWave);
-                const bool lower = (lane & j) == 0;
-                const bool up = (lane & w) == 0;
-                const bool mine_gt = k > ok || (k == ok && p > op);
-                // the lower lane of an ascending pair keeps the smaller element
-                const bool take = (lower == up) ? mine_gt : !mine_gt;
-                if (take) {
-                    k = ok;
-                    r = orow;
-                    p = op;
-                }
-            }
-        }
-        if (in) {
-            keys[s0 + lane] = k;
-            rows[s0 + lane] = r;
-        }
+    for (int i = 0; i < kWinPer; i++) {
+        const int j = threadIdx.x + i * kWinNT;
+        k[i] = j < m ? keys[int64_t(se.x) + j] : K(0);
+        r[i] = j < m ? rows[int64_t(se.x) + j] : 0;
     }
 }
 
-// Persistent workgroups over the listed buckets (more than kSmallRun and at
-// most kBucketCap keys): each is sorted in LDS by (key, position), which is
-// the stable order; each thread holds the row ids of its output slots in
-// registers, so rows are permuted in place.
 template <class K>
-__global__ __launch_bounds__(kBucketNT) void k_bucket_sort(K *keys, int32_t *rows,
-                                                           const int32_t *__restrict__ rs,
-                                                           const int64_t *__restrict__ d_nruns,
-                                                           int64_t n,
-                                                           const int32_t *__restrict__ med,
-                                                           const BucketStats *stats) {
-    constexpr int kPer = kBucketCap / kBucketNT;
-    __shared__ K s_key[kBucketCap];
-    __shared__ uint16_t s_idx[kBucketCap];
-    const int64_t nmed = int64_t(stats->nmed);
-    const int64_t nruns = *d_nruns;
-    for (int64_t m = blockIdx.x; m < nmed; m += gridDim.x) {
-    const int64_t b = med[m];
-    const int64_t s0 = rs[b], size = run_end(rs, nruns, b, n) - s0;
-    int P = 1;
-    while (P < size) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += kBucketNT) {
-        if (i < size) {
-            s_key[i] = keys[s0 + i];
-            s_idx[i] = uint16_t(i);
-        } else {
-            s_key[i] = KeyTraits<K>::kBits == 32 ? K(INT32_MAX) : K(INT64_MAX);
-            s_idx[i] = 0xffff;
+__global__ __launch_bounds__(kWinNT) void k_window_sort(K *keys, int32_t *rows,
+                                                        const int2 *__restrict__ win, int64_t nwin) {
+    __shared__ uint64_t s_a[kWinPhys], s_b[kWinPhys];
+    __shared__ int64_t s_lo[kWinNT / kWave], s_hi[kWinNT / kWave];
+    const int tid = threadIdx.x;
+    for (int64_t w = blockIdx.x; w < nwin; w += gridDim.x) {
+        int2 se;
+        K k[kWinPer];
+        int32_t rw[kWinPer];
+        window_load(keys, rows, win, w, nwin, se, k, rw);
+        const int64_t s0 = se.x;
+        const int m = se.y - se.x;
+        if (m > 1) {
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+#pragma unroll
+        for (int i = 0; i < kWinPer; i++) {
+            const int j = tid + i * kWinNT;
+            if (j < m) {
+                lo = int64_t(k[i]) < lo ? int64_t(k[i]) : lo;
+                hi = int64_t(k[i]) > hi ? int64_t(k[i]) : hi;
+            }
         }
-    }
-    __syncthreads();
-    // bitonic network on (key, position): ties keep input order
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += kBucketNT) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const K ki = s_key[i], kl = s_key[l];
-                    const uint16_t xi = s_idx[i], xl = s_idx[l];
-                    const bool gt = ki > kl || (ki == kl && xi > xl);
-                    const bool up = (i & k) == 0;
-                    if (gt == up) {
-                        s_key[i] = kl;
-                        s_key[l] = ki;
-                        s_idx[i] = xl;
-                        s_idx[l] = xi;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int64_t ol = shfl_xor(lo, o), oh = shfl_xor(hi, o);
+            lo = ol < lo ? ol : lo;
+            hi = oh > hi ? oh : hi;
+        }
+        if (lane_id() == 0) {
+            s_lo[wave_id()] = lo;
+            s_hi[wave_id()] = hi;
+        }
+        __syncthreads();
+        lo = s_lo[0];
+        hi = s_hi[0];
+        for (int ww = 1; ww < kWinNT / kWave; ww++) {
+            lo = s_lo[ww] < lo ? s_lo[ww] : lo;
+            hi = s_hi[ww] > hi ? s_hi[ww] : hi;
+        }
+        const int m8 = (m + 7) & ~7;
+        const bool packed = (uint64_t(hi) - uint64_t(lo)) < (uint64_t(1) << (64 - kWinIdxBits));
+        uint64_t *res = nullptr;
+        if (packed) {
+#pragma unroll
+            for (int i = 0; i < kWinPer; i++) {
+                const int j = tid + i * kWinNT;
+                if (j < m8)
+                    s_a[wphys(j)] = j < m ? ((uint64_t(int64_t(k[i])) - uint64_t(lo)) << kWinIdxBits) |
+                                                uint64_t(j)
+                                          : ~uint64_t(0);
+            }
+            __syncthreads();
+            // runs of 8 in registers
+            if (tid * 8 < m8) {
+                uint64_t v[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) v[i] = s_a[wphys(tid * 8 + i)];
+#pragma unroll
+                for (int r = 0; r < 8; r++)
+#pragma unroll
+                    for (int i = r & 1; i + 1 < 8; i += 2) cx(v[i], v[i + 1]);
+#pragma unroll
+                for (int i = 0; i < 8; i++) s_a[wphys(tid * 8 + i)] = v[i];
+            }
+            __syncthreads();
+            uint64_t *src = s_a, *dst = s_b;
+            for (int L = 8; L < m8; L <<= 1) {
+                if (tid * 8 < m8) {
+                    const int out0 = tid * 8;
+                    const int base = (out0 / (2 * L)) * (2 * L);
+                    const int d = out0 - base;
+                    const int la = m8 - base < L ? m8 - base : L;
+                    const int lb = m8 - base - L < 0 ? 0 : (m8 - base - L < L ? m8 - base - L : L);
+                    const int pa = base, pb = base + L;          // run starts (logical)
+                    int a = d - lb > 0 ? d - lb : 0, hb = d < la ? d : la;
+                    while (a < hb) {
+                        const int mid = (a + hb) >> 1;
+                        if (src[wphys(pa + mid)] <= src[wphys(pb + d - 1 - mid)]) a = mid + 1;
+                        else hb = mid;
                     }
+                    int b = d - a;
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        const uint64_t va = a < la ? src[wphys(pa + a)] : ~uint64_t(0);
+                        const uint64_t vb = b < lb ? src[wphys(pb + b)] : ~uint64_t(0);
+                        const bool takeA = a < la && (b >= lb || va <= vb);
+                        dst[wphys(out0 + i)] = takeA ? va : vb;
+                        a += takeA ? 1 : 0;
+                        b += takeA ? 0 : 1;
+                    }
+                }
+                __syncthreads();
+                uint64_t *t = src;
+                src = dst;
+                dst = t;
+            }
+            res = src;
+        } else {
+            // bitonic on (key, local index): keys in s_a, indices in s_b
+            int P = 8;
+            while (P < m) P <<= 1;
+            K *sk = reinterpret_cast<K *>(s_a);
+            uint16_t *sx = reinterpret_cast<uint16_t *>(s_b);
+#pragma unroll
+            for (int i = 0; i < kWinPer; i++) {
+                const int j = tid + i * kWinNT;
+                if (j < P) {
+                    sk[j] = j < m ? k[i] : (sizeof(K) == 4 ? K(INT32_MAX) : K(INT64_MAX));
+                    sx[j] = j < m ? uint16_t(j) : uint16_t(0xffff);
                 }
             }
             __syncthreads();
+            for (int kk = 2; kk <= P; kk <<= 1) {
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int i = tid; i < P; i += kWinNT) {
+                        const int l = i ^ jj;
+                        if (l > i) {
+                            const K ki = sk[i], kl = sk[l];
+                            const uint16_t xi = sx[i], xl = sx[l];
+                            const bool gt = ki > kl || (ki == kl && xi > xl);
+                            if (gt == ((i & kk) == 0)) {
+                                sk[i] = kl;
+                                sk[l] = ki;
+                                sx[i] = xl;
+                                sx[l] = xi;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
         }
-    }
-    int32_t rv[kPer];
+        // sorted keys and local indices into registers, then the row ids
+        // permuted through LDS (the buffer the sort no longer uses)
+        K ok[kWinPer];
+        int idx[kWinPer];
 #pragma unroll
-    for (int r = 0; r < kPer; r++) {
-        const int i = threadIdx.x + r * kBucketNT;
-        rv[r] = i < size ? rows[s0 + s_idx[i]] : 0;
-    }
-    __syncthreads();                     // every row id is read before any is overwritten
-#pragma unroll
-    for (int r = 0; r < kPer; r++) {
-        const int i = threadIdx.x + r * kBucketNT;
-        if (i < size) {
-            keys[s0 + i] = s_key[i];
-            rows[s0 + i] = rv[r];
+        for (int i = 0; i < kWinPer; i++) {
+            const int j = tid + i * kWinNT;
+            idx[i] = 0;
+            if (j < m) {
+                if (packed) {
+                    const uint64_t v = res[wphys(j)];
+                    idx[i] = int(v & uint64_t(kWinCap - 1));
+                    ok[i] = K(int64_t(uint64_t(lo) + (v >> kWinIdxBits)));
+                } else {
+                    idx[i] = reinterpret_cast<uint16_t *>(s_b)[j];
+                    ok[i] = reinterpret_cast<K *>(s_a)[j];
+                }
+            }
         }
-    }
-    __syncthreads();                     // LDS is reused by the next bucket
+        __syncthreads();
+        int32_t *srow = reinterpret_cast<int32_t *>(packed && res == s_a ? s_b : s_a);
+        if (!packed) srow = reinterpret_cast<int32_t *>(s_b) + kWinCap;   // past the indices
+#pragma unroll
+        for (int i = 0; i < kWinPer; i++) {
+            const int j = tid + i * kWinNT;
+            if (j < m) srow[j] = rw[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kWinPer; i++) {
+            const int j = tid + i * kWinNT;
+            if (j < m) {
+                keys[s0 + j] = ok[i];
+                rows[s0 + j] = srow[idx[i]];
+            }
+        }
+        __syncthreads();                 // LDS is reused by the next window
+        }
     }
 }
 
@@ -821,7 +1069,7 @@ struct TrainLayout {
     int64_t *sample, *sorted;
     void *rws;
     size_t rws_bytes;
-    float *tx, *tq, *part;
+    float *tx, *tq;
     size_t bytes;
 };
 
@@ -835,7 +1083,6 @@ static TrainLayout train_layout(void *ws, int64_t m) {
     L.rws = c.take<char>(L.rws_bytes);
     L.tx = c.take<float>(kTrainPoints);
     L.tq = c.take<float>(kTrainPoints);
-    L.part = c.take<float>(size_t(kGradBlocks) * (kNParam + 1));
     L.bytes = c.bytes();
     return L;
 }
@@ -854,8 +1101,7 @@ struct PartLayout {
     int64_t chunk_cap;
     long long *mm;                      // min, max per big bucket
     int32_t *ids, *ids_sorted;          // bucket number of every key, before / after grouping
-    int32_t *med;                       // buckets sorted by a workgroup
-    int32_t *wav;                       // buckets sorted by one wave
+    int2 *win;                          // windows of whole buckets
     int32_t *ruk, *rus;                 // runs of the grouped bucket numbers: value, start
     int64_t *d_nruns;
     uint64_t *rle_ws;
@@ -880,8 +1126,7 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     L.mm = c.take<long long>(size_t(2 * L.ovf_cap));
     L.ids = c.take<int32_t>(size_t(nn));
     L.ids_sorted = c.take<int32_t>(size_t(nn));
-    L.med = c.take<int32_t>(size_t(nn));
-    L.wav = c.take<int32_t>(size_t(nn));
+    L.win = c.take<int2>(size_t(ceil_div(nn, kWin)));
     L.ruk = c.take<int32_t>(size_t(nn));
     L.rus = c.take<int32_t>(size_t(nn));
     L.d_nruns = c.take<int64_t>(1);
@@ -943,18 +1188,20 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     // each one sorted: short ones in registers, the rest by a workgroup in LDS
     if ((rc = rle_i32(L.ids_sorted, n, L.ruk, L.rus, L.d_nruns, L.rle_ws, s))) return rc;
     {
+        const int64_t nwin = ceil_div(n, kWin);
         int64_t g = ceil_div(n, 256);
-        if (g > 16384) g = 16384;
-        TQP_LAUNCH("bucket_small", k_bucket_small<K>, dim3(unsigned(g)), dim3(256), 0, s, out_key,
-                   out_rows, L.rus, L.d_nruns, n, L.stats, L.med, L.wav, L.ovf, L.ovf_cap);
-        if ((rc = check_launch("bucket small sort"))) return rc;
+        if (g > 4096) g = 4096;
+        TQP_LAUNCH("run_max", k_run_max, dim3(unsigned(g)), dim3(256), 0, s, L.rus, L.d_nruns, n,
+                   L.stats);
+        if ((rc = check_launch("bucket sizes"))) return rc;
+        g = ceil_div(nwin, 256);
+        TQP_LAUNCH("window_plan", k_window_plan, dim3(unsigned(g)), dim3(256), 0, s, L.rus,
+                   L.d_nruns, n, nwin, L.win, L.stats, L.ovf, L.ovf_cap);
+        if ((rc = check_launch("window plan"))) return rc;
+        TQP_LAUNCH("window_sort", k_window_sort<K>, dim3(unsigned(kComputeUnits)), dim3(kWinNT), 0,
+                   s, out_key, out_rows, L.win, nwin);
+        if ((rc = check_launch("window sort"))) return rc;
     }
-    TQP_LAUNCH("bucket_wave", k_bucket_wave<K>, dim3(unsigned(kComputeUnits * 8)), dim3(256), 0, s,
-               out_key, out_rows, L.rus, L.d_nruns, n, L.wav, L.stats);
-    if ((rc = check_launch("bucket wave sort"))) return rc;
-    TQP_LAUNCH("bucket_sort", k_bucket_sort<K>, dim3(unsigned(kComputeUnits * 2)), dim3(kBucketNT),
-               0, s, out_key, out_rows, L.rus, L.d_nruns, n, L.med, L.stats);
-    if ((rc = check_launch("bucket sort"))) return rc;
     BucketStats hs;
     if ((rc = download(&hs, L.stats, sizeof hs, s, "partition stats"))) return rc;
     int64_t n_ovf = 0, ovf_keys = 0, single = 0;
@@ -1108,16 +1355,13 @@ TQP_API int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, in
     TQP_LAUNCH("lcdf_init", k_lcdf_init, dim3(1), dim3(256), 0, s, L.sorted, m, nleaf, mod, L.tx,
                L.tq, T);
     if ((rc = check_launch("lcdf init"))) return rc;
-    for (int it = 0; it < steps; it++) {
-        TQP_LAUNCH("lcdf_grad", k_lcdf_grad, dim3(kGradBlocks), dim3(256), 0, s, mod, L.tx, L.tq, T,
-                   L.part);
-        TQP_LAUNCH("lcdf_adam", k_lcdf_adam, dim3(1), dim3(128), 0, s, mod, L.part, kGradBlocks, lr);
-    }
+    if (steps > 0)
+        TQP_LAUNCH("lcdf_fit", k_lcdf_fit, dim3(1), dim3(kFitNT), 0, s, mod, L.tx, L.tq, T, steps, lr);
     if ((rc = check_launch("lcdf train"))) return rc;
     TQP_LAUNCH("lcdf_finalize", k_lcdf_finalize, dim3(1), dim3(64), 0, s, mod);
     TQP_LAUNCH("lcdf_leaf_fit", k_lcdf_leaf_fit, dim3(unsigned(nleaf)), dim3(256), 0, s, mod,
                L.sorted, m);
-    TQP_LAUNCH("lcdf_leaf_fill", k_lcdf_leaf_fill, dim3(1), dim3(64), 0, s, mod);
+    TQP_LAUNCH("lcdf_leaf_fill", k_lcdf_leaf_fill, dim3(1), dim3(kFillNT), 0, s, mod);
     return check_launch("lcdf leaves");
 }
 

@@ -41,7 +41,7 @@ def test_model_is_monotone_and_trains(tqp, mix):
     info = tqp.lcdf_model_info(model)
     assert info["nleaf"] == 4096 and info["steps"] == 100
     assert info["loss_best"] < info["loss_first"]        # training improved the root
-    assert info["loss_best"] <= info["loss_last"]
+    assert info["loss_last"] <= info["loss_first"]       # and did not diverge
     sk = np.sort(np.concatenate([left, right]))
     b = host(tqp.lcdf_buckets(model, dev(sk), 16))
     assert np.all(np.diff(b) >= 0), "bucket numbers must not decrease along sorted keys"
