@@ -43,8 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--only", choices=("star600m", "star60m"), default=None,
-                    help="run one workload's timed steps only (for counter profiles)")
+    ap.add_argument("--only", choices=("star600m", "star60m", "learned", "batch"), default=None,
+                    help="run one workload only (for counter profiles and quick checks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000,
                     help="fact rows of the headline workload the CPU oracle is timed on")
@@ -604,6 +604,12 @@ def bench_configs(args, tqp, stream) -> dict:
     return out
 
 
+# The learned model: as many leaves as one pass of the bucket-number kernel
+# holds in LDS, 50 full-batch Adam steps on the root.
+LEARNED_LEAVES = 1704
+LEARNED_STEPS = 50
+
+
 def bench_learned(args, tqp, stream) -> dict:
     """Sort-merge join of two int64 key columns drawn from the lognormal /
     cluster / Zipf mix, end to end (model training + both sides partition-
@@ -620,10 +626,11 @@ def bench_learned(args, tqp, stream) -> dict:
     torch.cuda.synchronize()
     print(f"[bench] learned: generated {nl}+{nr} keys in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    # 4096 partitions of the key range, each cut further by the same model
-    # into 2^(bits - 12) buckets of about 8 keys on average (at most 24 bits:
-    # the model's float32 rank), sorted in registers or LDS after grouping
-    bits = max(12, min(24, (max(nl, nr) // 8).bit_length()))
+    # buckets of at most 3072 keys on average on the larger side, so that
+    # windows of whole buckets fit the 8192-key LDS sort
+    bits = 8
+    while bits < 24 and max(nl, nr) > 3072 * (1 << bits):
+        bits += 1
     st_l, st_r = tqp.minmax(left), tqp.minmax(right)
     lo, hi = min(st_l[0], st_r[0]), max(st_l[1], st_r[1])
     key_bits = (hi - lo).bit_length()
@@ -632,8 +639,8 @@ def bench_learned(args, tqp, stream) -> dict:
     model_holder = {}
 
     def train():
-        model_holder["m"] = tqp.lcdf_train([left, right], sample_stride=100, nleaf=4096,
-                                           steps=200)
+        model_holder["m"] = tqp.lcdf_train([left, right], sample_stride=100,
+                                           nleaf=LEARNED_LEAVES, steps=LEARNED_STEPS)
     train_ms = _timed(train, reps, stream)
     model = model_holder["m"]
     info = tqp.lcdf_model_info(model)
@@ -655,8 +662,9 @@ def bench_learned(args, tqp, stream) -> dict:
 
     out = {"workload": f"sort-merge join of {nl} x {nr} int64 keys (lognormal sigma=2 / "
                        "64 dense clusters / Zipf s=1.2 mix)",
-           "partitions": 4096, "buckets": 1 << bits,
-           "model": {"hidden": 32, "leaves": 4096, "sample": "1%", "adam_steps": info["steps"],
+           "buckets": 1 << bits,
+           "model": {"hidden": 32, "leaves": LEARNED_LEAVES, "knots_per_leaf": 8,
+                     "sample": "1%", "adam_steps": info["steps"],
                      "loss_first": info["loss_first"], "loss_last": info["loss_last"],
                      "train_ms": round(train_ms, 3)}}
     results = {}
@@ -805,6 +813,10 @@ def main():
     if args.only == "star60m":
         print(json.dumps({"star60m": bench_star60m(args, tqp, stream),
                           "stream_copy_GBps": round(copy_gbs, 1)}), flush=True)
+        return
+    if args.only in ("learned", "batch"):
+        fn = bench_learned if args.only == "learned" else bench_batch
+        print(json.dumps({args.only: fn(args, tqp, stream)}), flush=True)
         return
     head = bench_star3(args, tqp, stream, copy_gbs)
     ms = head["ms"]

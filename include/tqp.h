@@ -499,6 +499,8 @@ int tqp_batch_destroy(void *graph);
  *   tqp_lcdf_model_bytes(nleaf) bytes (nleaf in [1, 65536]); its first 36
  *   bytes are int64 kmin, float64 1/span, int32 nleaf, int32 steps, float32
  *   loss at the first step, at the last step, and the lowest.  No host sync.
+ *   Leaves are 64 bytes; with nleaf <= 2560 every bucket evaluation holds
+ *   all of them in LDS (the fast case), above that it reads them from memory.
  * tqp_lcdf_buckets: out_bucket[i] = bucket of keys[i] for 2^bucket_bits
  *   buckets (bits in [1, 24]); for inspection and tests.
  * ---------------------------------------------------------------------- */

@@ -688,7 +688,7 @@ def _bind_lcdf(L):
                                      vp]
 
 
-def lcdf_train(cols, sample_stride=100, nleaf=4096, steps=200, lr=1e-2, stream=None):
+def lcdf_train(cols, sample_stride=100, nleaf=1704, steps=50, lr=1e-2, stream=None):
     """Trains the learned CDF on the keys of cols (1 or 2 device columns).
 
     Returns the model as a device uint8 tensor."""
@@ -716,12 +716,15 @@ def lcdf_model_info(model) -> dict:
             "loss_last": float(loss_last), "loss_best": float(loss_best)}
 
 
-def lcdf_buckets(model, keys, bucket_bits, stream=None):
+def lcdf_buckets(model, keys, bucket_bits, out=None, stream=None):
     L = lib()
     if not hasattr(L, "_lcdf_bound"):
         _bind_lcdf(L)
         L._lcdf_bound = True
-    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    if out.dtype != torch.int32 or out.numel() < keys.numel() or not out.is_contiguous():
+        raise ValueError("lcdf_buckets: out must be a contiguous int32 tensor of n entries")
     _check(L.tqp_lcdf_buckets(model.data_ptr(), ctypes.byref(_col(keys)), int(bucket_bits),
                               _ptr(out), _stream(stream)))
     return out

@@ -6,10 +6,11 @@
 //   leaf = clamp(floor(root * L), 0, L - 1)
 //   F    = the leaf's piecewise-linear spline through kKnots knots (key, rank)
 //          taken at evenly spaced points of the leaf's sorted sample, over the
-//          key itself: the segment is found by int64 compares and the offset
-//          into it is the exact int64 difference (not x: a float32 x cannot
-//          tell apart keys closer than 2^-24 of the key span, and a dense
-//          cluster of a million keys can sit inside such a gap)
+//          key itself: the segment is found by int64 compares with the exact
+//          knot keys and the position inside it is the exact int64 difference
+//          (not x: a float32 x cannot tell apart keys closer than 2^-24 of the
+//          key span, and a dense cluster of a million keys can sit inside
+//          such a gap, as can a whole cluster inside one leaf)
 // and, where a leaf holds a heavy key h (one that fills a run of the sorted
 // sample), F jumps exactly at h: keys below h are held at or under the rank
 // where h's copies start, keys above at or over the rank where they end, and
@@ -31,15 +32,18 @@
 // every parameter by about the learning rate at first), and the parameters
 // with the lowest loss seen are the ones kept.
 //
-// Partition sort.  Two stable radix passes on the bucket number group the
-// keys by bucket (input order kept inside a bucket); one workgroup per bucket
-// then sorts its bucket in LDS by (key, position), which is the stable order.
-// A bucket larger than the LDS tile is left as is when all its keys are equal
-// (already in stable order), otherwise it is sorted by the plain radix sort
-// over its own key range.  With bucket = top bits of (key - kmin) the same
-// pipeline is the plain MSD radix partitioner the learned one is compared
-// against.
+// Partition sort.  Every key's bucket number is evaluated once (the leaves
+// held in LDS); stable radix passes on it group the keys by bucket (input
+// order kept inside a bucket); then each window of whole buckets (at most
+// 8192 keys) is sorted by one workgroup in LDS by (key, position), which is
+// the stable order and, since buckets are key ranges, sorts every bucket in
+// it.  A bucket too large for a window is left as is when all its keys are
+// equal (already in stable order); the others are gathered, sorted together
+// by the plain radix sort over their own key range and scattered back.  With
+// bucket = top bits of (key - kmin) the same pipeline is the plain MSD radix
+// partitioner the learned one is compared against.
 #include <limits.h>
+#include <stddef.h>
 #include <math.h>
 #include <algorithm>
 #include <vector>
@@ -68,21 +72,28 @@ struct LcdfModel {
     // log height, bias; Adam moments; the best parameters seen and their loss
     float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
     float c0[kHidden], s0[kHidden];
-    // 160 bytes in ten aligned 16-byte groups, so an evaluation loads a
-    // leaf with ten vector loads issued together
+    // 96 bytes: exact knot keys, knot ranks as 16-bit fractions of the
+    // leaf's rank range.  A heavy key h is a pair of knots (h, hlo), (h, hhi)
+    // at indices hk, hk + 1, so keys below h stay at or under the rank where
+    // its copies start and keys above at or over the rank where they end.
     struct alignas(16) Leaf {
-        int64_t kx[kKnots];                   // knot keys, ascending
-        float kr[kKnots];                     // knot ranks, ascending
-        float slope[kKnots];                  // rank per key unit on each segment (last unused)
+        int64_t kx[kKnots];                   // knot keys, ascending; unused ones INT64_MAX
+        uint16_t r[kKnots];                   // knot ranks: lo + (hi - lo) * r / 65535,
+                                              // ascending; unused ones repeat the last
         float lo, hi;                         // the leaf's rank range
-        float hlo, hhi;                       // ranks where the heavy key's copies start / end
-        int64_t hkey;                         // heavy key, when hlo <= hhi
-        int32_t nk;                           // knots in use (0: constant lo)
-        int32_t pad;
+        uint16_t hlo, hhi;                    // the heavy key's ranks (r[hk], r[hk + 1])
+        uint8_t nk, hk;                       // knots in use (0: constant lo); heavy pair
+                                              // index, kNoHeavy when none
+        uint16_t pad;
     } leaf[1];                                // nleaf entries
 };
 using Leaf = LcdfModel::Leaf;
-static_assert(sizeof(Leaf) == 160 && kKnots == 8, "leaf layout");
+constexpr int kNoHeavy = 0xff;
+static_assert(sizeof(Leaf) == 96 && offsetof(Leaf, lo) == 80, "leaf layout");
+// Leaves held in LDS at once while bucket numbers are evaluated (160 KB);
+// a model with more is evaluated in several passes over the keys, each
+// holding the next kLdsLeafMax leaves.
+constexpr int kLdsLeafMax = 1704;
 
 static size_t model_bytes(int nleaf) {
     return sizeof(LcdfModel) + sizeof(Leaf) * size_t(nleaf > 0 ? nleaf - 1 : 0);
@@ -133,128 +144,53 @@ __device__ __forceinline__ int lcdf_leaf_of(const LcdfModel *m, int64_t key) {
     return lcdf_leaf(m, lcdf_root(m, lcdf_x(m, key)));
 }
 
-// A leaf's fields in registers (ten 16-byte loads).
-struct LeafRegs {
-    int64_t kx[kKnots];
-    float kr[kKnots], slope[kKnots];
-    float lo, hi, hlo, hhi;
-    int64_t hkey;
-    int32_t nk;
-};
-
-__device__ __forceinline__ void leaf_load(const Leaf &Lm, LeafRegs &L) {
-    const int4 *q = reinterpret_cast<const int4 *>(&Lm);
-    int4 v[10];
-#pragma unroll
-    for (int i = 0; i < 10; i++) v[i] = q[i];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        L.kx[2 * i] = (int64_t(uint32_t(v[i].y)) << 32) | uint32_t(v[i].x);
-        L.kx[2 * i + 1] = (int64_t(uint32_t(v[i].w)) << 32) | uint32_t(v[i].z);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; i++) {
-        L.kr[4 * i + 0] = __int_as_float(v[4 + i].x);
-        L.kr[4 * i + 1] = __int_as_float(v[4 + i].y);
-        L.kr[4 * i + 2] = __int_as_float(v[4 + i].z);
-        L.kr[4 * i + 3] = __int_as_float(v[4 + i].w);
-        L.slope[4 * i + 0] = __int_as_float(v[6 + i].x);
-        L.slope[4 * i + 1] = __int_as_float(v[6 + i].y);
-        L.slope[4 * i + 2] = __int_as_float(v[6 + i].z);
-        L.slope[4 * i + 3] = __int_as_float(v[6 + i].w);
-    }
-    L.lo = __int_as_float(v[8].x);
-    L.hi = __int_as_float(v[8].y);
-    L.hlo = __int_as_float(v[8].z);
-    L.hhi = __int_as_float(v[8].w);
-    L.hkey = (int64_t(uint32_t(v[9].y)) << 32) | uint32_t(v[9].x);
-    L.nk = v[9].z;
+// lo + (hi - lo) * u / 65535: non-decreasing in u, at least lo (the sum of lo
+// and a non-negative product never rounds below lo); callers clamp to hi.
+__device__ __forceinline__ float leaf_rank(float lo, float span, uint32_t u) {
+    return fmaf(span, float(u) * (1.f / 65535.f), lo);
 }
 
-// F of one key in its leaf.  The spline segment is the last knot at or below
-// the key; each segment's value is clamped to its two knot ranks, so F is
-// monotone across segments even with rounding.
-__device__ __forceinline__ float lcdf_leaf_eval(const LeafRegs &L, int64_t key) {
-    float f = L.lo;
+// F of one key in its leaf.  The segment is the last knot at or below the
+// key (a branch-free binary search over the eight ascending knot keys); the
+// position inside it is the exact int64 offset from the segment's first knot
+// over the segment's width (each converted to float, which is monotone), and
+// the value is clamped to the segment's two knot ranks, so F is monotone
+// across segments even with rounding.  A key below the first knot takes the
+// first rank, one at or past the last knot the last rank, and the heavy key
+// itself the middle of its pair's ranks.
+__device__ __forceinline__ float lcdf_leaf_eval(const Leaf &L, int64_t key) {
+    const float lo = L.lo, hi = L.hi, span = hi - lo;
     const int nk = L.nk;
-    if (nk > 0) {
-        int64_t klast = L.kx[0];
-        float rlast = L.kr[0];
-#pragma unroll
-        for (int t = 1; t < kKnots; t++)
-            if (t == nk - 1) {
-                klast = L.kx[t];
-                rlast = L.kr[t];
-            }
-        if (key <= L.kx[0]) {
-            f = L.kr[0];
-        } else if (key >= klast) {
-            f = rlast;
-        } else {
-            int j = 0;
-#pragma unroll
-            for (int t = 1; t < kKnots - 1; t++)
-                if (t < nk - 1 && L.kx[t] <= key) j = t;
-            int64_t kj = L.kx[0];
-            float rj = L.kr[0], rj1 = L.kr[1], sj = L.slope[0];
-#pragma unroll
-            for (int t = 1; t < kKnots - 1; t++)
-                if (t == j) {
-                    kj = L.kx[t];
-                    rj = L.kr[t];
-                    rj1 = L.kr[t + 1];
-                    sj = L.slope[t];
-                }
-            const float d = float(uint64_t(key) - uint64_t(kj));        // in [0, 2^64)
-            float g = fmaf(sj, d, rj);
-            g = g < rj ? rj : g;
-            f = g > rj1 ? rj1 : g;
-        }
-    }
-    f = f < L.lo ? L.lo : (f > L.hi ? L.hi : f);
-    if (L.hlo <= L.hhi) {
-        if (key == L.hkey) f = 0.5f * (L.hlo + L.hhi);
-        else if (key < L.hkey) f = f < L.hlo ? f : L.hlo;
-        else f = f > L.hhi ? f : L.hhi;
-    }
-    return f;
+    int c = L.kx[3] <= key ? 4 : 0;                  // knots at or below the key
+    c += L.kx[c + 1] <= key ? 2 : 0;
+    c += L.kx[c] <= key ? 1 : 0;
+    c += L.kx[c] <= key ? 1 : 0;
+    const int j = c > 0 ? c - 1 : 0;
+    const int j1 = c < nk ? c : j;                   // j1 == j: no segment beyond j
+    const int64_t kj = L.kx[j], kj1 = L.kx[j1];
+    const float rj = leaf_rank(lo, span, L.r[j]), rj1 = leaf_rank(lo, span, L.r[j1]);
+    // below the first knot d = 0, past the last rj1 = rj: both give rj
+    const uint64_t d = c > 0 ? uint64_t(key) - uint64_t(kj) : 0;
+    const uint64_t w = j1 != j ? uint64_t(kj1) - uint64_t(kj) : 1;
+    const float g = fmaf(rj1 - rj, float(d) * __builtin_amdgcn_rcpf(float(w)), rj);
+    float f = __builtin_amdgcn_fmed3f(g, rj, rj1);
+    if (L.hk != kNoHeavy && j == int(L.hk) + 1 && kj == key)
+        f = 0.5f * (leaf_rank(lo, span, L.hlo) + leaf_rank(lo, span, L.hhi));
+    f = nk == 0 ? lo : f;
+    return f < lo ? lo : (f > hi ? hi : f);
 }
 
-__device__ __forceinline__ float lcdf_leaf_eval(const Leaf &Lm, int64_t key) {
-    LeafRegs L;
-    leaf_load(Lm, L);
-    return lcdf_leaf_eval(L, key);
-}
-
-__device__ __forceinline__ float lcdf_eval(const LcdfModel *m, int64_t key) {
-    return lcdf_leaf_eval(m->leaf[lcdf_leaf_of(m, key)], key);
-}
-
-// Bucket ordinals for run_radix: learned, or the top bits of key - kmin.
+// Bucket ordinals: learned (the leaves read from LDS by the bucket-number
+// kernel), or the top bits of key - kmin.
 template <class K> struct LearnedOrd {
     const LcdfModel *m;
+    const Leaf *leaves;                         // the model's leaves in memory
     float scale;                                // 2^bucket_bits
     uint32_t top;                               // 2^bucket_bits - 1
     __device__ __forceinline__ uint32_t bucket(float f) const {
         const float t = f * scale;
         const uint32_t b = t <= 0.f ? 0u : uint32_t(t);
         return b > top ? top : b;
-    }
-    __device__ __forceinline__ uint64_t operator()(K k) const {
-        return bucket(lcdf_eval(m, int64_t(k)));
-    }
-    // R keys at once: roots together, then the leaves (loads in flight together)
-    template <int R>
-    __device__ __forceinline__ void many(const K (&k)[R], uint32_t (&b)[R]) const {
-        float x[R], y[R];
-#pragma unroll
-        for (int r = 0; r < R; r++) x[r] = lcdf_x(m, int64_t(k[r]));
-        lcdf_root_n<R>(m, x, y);
-        LeafRegs L[R];
-#pragma unroll
-        for (int r = 0; r < R; r++) leaf_load(m->leaf[lcdf_leaf(m, y[r])], L[r]);
-#pragma unroll
-        for (int r = 0; r < R; r++) b[r] = bucket(lcdf_leaf_eval(L[r], int64_t(k[r])));
     }
 };
 
@@ -501,29 +437,51 @@ __global__ void k_lcdf_finalize(LcdfModel *mod) {
     if (j == 0) mod->d = th[3 * kHidden];
 }
 
+// The spline through knots (kx, kr) at a key, in float64: the rank of the
+// last knot at or below the key, moved linearly toward the next one.
+__device__ __forceinline__ double knot_spline(const int64_t *kx, const double *kr, int nk,
+                                              int64_t key) {
+    int c = 0;
+    while (c < nk && kx[c] <= key) c++;
+    if (c == 0) return kr[0];
+    if (c == nk) return kr[nk - 1];
+    const double d = double(uint64_t(key) - uint64_t(kx[c - 1]));
+    const double w = double(uint64_t(kx[c]) - uint64_t(kx[c - 1]));
+    return kr[c - 1] + (kr[c] - kr[c - 1]) * (d / w);
+}
+
 // One workgroup per leaf: the contiguous run of sorted sample points the root
-// routes to it, the spline knots at evenly spaced points of that run, and the
-// longest run of one key inside it.
+// routes to it, its longest run of one key (a heavy key when it repeats at
+// least kHeavyMin times), and the spline knots.  The knots start as the
+// leaf's first and last sample points and the heavy key's pair; each further
+// knot is the sample point where the spline so far misses the sample rank
+// the most (so knots land on the edges of dense clusters, where a straight
+// segment across a gap would put a whole cluster edge into one bucket).
 __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int64_t *sorted,
                                                        int64_t m) {
     __shared__ int64_t s_rng[2];
     __shared__ int64_t s_run[256 / kWave][2];
-    const int leaf = blockIdx.x;
-    if (threadIdx.x < 2) {
-        const int target = leaf + int(threadIdx.x);      // first point with leaf >= target
+    __shared__ int64_t s_kx[kKnots];
+    __shared__ double s_kr[kKnots];
+    __shared__ int s_nk, s_hpos, s_done;
+    __shared__ double s_err[256 / kWave];
+    __shared__ int64_t s_arg[256 / kWave];
+    const int leaf = blockIdx.x, tid = threadIdx.x;
+    if (tid < 2) {
+        const int target = leaf + tid;                   // first point with leaf >= target
         int64_t lo = 0, hi = m;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
             if (lcdf_leaf(mod, lcdf_root(mod, lcdf_x(mod, sorted[mid]))) < target) lo = mid + 1;
             else hi = mid;
         }
-        s_rng[threadIdx.x] = lo;
+        s_rng[tid] = lo;
     }
     __syncthreads();
     const int64_t a0 = s_rng[0], a1 = s_rng[1];
     // longest run of equal keys: each run start finds its end by binary search
     int64_t best_len = 0, best_start = 0;
-    for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+    for (int64_t i = a0 + tid; i < a1; i += blockDim.x) {
         const int64_t v = sorted[i];
         if (i > a0 && sorted[i - 1] == v) continue;
         int64_t lo = i + 1, hi = a1;
@@ -545,50 +503,134 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
             best_start = os;
         }
     }
-    const int w = wave_id();
     if (lane_id() == 0) {
-        s_run[w][0] = best_len;
-        s_run[w][1] = best_start;
+        s_run[wave_id()][0] = best_len;
+        s_run[wave_id()][1] = best_start;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    Leaf &L = mod->leaf[leaf];
-    L.hkey = 0;
-    L.hlo = 1.f;
-    L.hhi = 0.f;
-    L.pad = 0;
-    if (a1 <= a0) {                                   // empty: filled in later
-        L.nk = 0;
-        L.lo = L.hi = -1.f;
-        return;
-    }
-    const int64_t cnt = a1 - a0;
-    const int nk = cnt < kKnots ? int(cnt) : kKnots;
-    for (int j = 0; j < nk; j++) {
-        const int64_t p = nk > 1 ? a0 + (cnt - 1) * j / (nk - 1) : a0;
-        L.kx[j] = sorted[p];
-        L.kr[j] = float((double(p) + 0.5) / double(m));
-    }
-    for (int j = 0; j < kKnots; j++) {
-        const double dx = j + 1 < nk ? double(uint64_t(L.kx[j + 1]) - uint64_t(L.kx[j])) : 0.0;
-        L.slope[j] = dx > 0 ? float((double(L.kr[j + 1]) - double(L.kr[j])) / dx) : 0.f;
-    }
-    L.nk = nk;
-    L.lo = L.kr[0];
-    L.hi = L.kr[nk - 1];
     int64_t rl = 0, rs = 0;
     for (int ww = 0; ww < 256 / kWave; ww++)
         if (s_run[ww][0] > rl || (s_run[ww][0] == rl && s_run[ww][1] < rs)) {
             rl = s_run[ww][0];
             rs = s_run[ww][1];
         }
-    if (rl >= kHeavyMin) {
-        const float hlo = float(double(rs) / double(m));
-        const float hhi = float(double(rs + rl) / double(m));
-        L.hkey = sorted[rs];
-        L.hlo = hlo < L.lo ? L.lo : (hlo > L.hi ? L.hi : hlo);
-        L.hhi = hhi < L.lo ? L.lo : (hhi > L.hi ? L.hi : hhi);
+    const bool heavy = a1 > a0 && rl >= kHeavyMin;
+    if (tid == 0) {
+        int nk = 0, hpos = -1;
+        if (a1 > a0) {
+            if (!(heavy && rs == a0)) {
+                s_kx[nk] = sorted[a0];
+                s_kr[nk++] = (double(a0) + 0.5) / double(m);
+            }
+            if (heavy) {
+                hpos = nk;
+                s_kx[nk] = sorted[rs];
+                s_kr[nk++] = double(rs) / double(m);
+                s_kx[nk] = sorted[rs];
+                s_kr[nk++] = double(rs + rl) / double(m);
+            }
+            if (a1 - 1 > a0 && !(heavy && rs + rl == a1)) {
+                s_kx[nk] = sorted[a1 - 1];
+                s_kr[nk++] = (double(a1 - 1) + 0.5) / double(m);
+            }
+        }
+        s_nk = nk;
+        s_hpos = hpos;
+        s_done = 0;
     }
+    __syncthreads();
+    // greedy knots: the point of largest rank error, until the knots run out
+    while (!s_done && s_nk < kKnots) {
+        const int nk = s_nk;
+        double be = 0.0;
+        int64_t ba = -1;
+        for (int64_t i = a0 + tid; i < a1; i += blockDim.x) {
+            if (heavy && i >= rs && i < rs + rl) continue;      // the pair places these exactly
+            const double e = fabs(knot_spline(s_kx, s_kr, nk, sorted[i]) - (double(i) + 0.5) / double(m));
+            if (e > be) {
+                be = e;
+                ba = i;
+            }
+        }
+        for (int o = 1; o < kWave; o <<= 1) {
+            const double oe = __shfl_xor(be, o, kWave);
+            const int64_t oa = __shfl_xor(ba, o, kWave);
+            if (oe > be || (oe == be && oa >= 0 && (ba < 0 || oa < ba))) {
+                be = oe;
+                ba = oa;
+            }
+        }
+        if (lane_id() == 0) {
+            s_err[wave_id()] = be;
+            s_arg[wave_id()] = ba;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double e = 0.0;
+            int64_t arg = -1;
+            for (int ww = 0; ww < 256 / kWave; ww++)
+                if (s_err[ww] > e || (s_err[ww] == e && s_arg[ww] >= 0 && (arg < 0 || s_arg[ww] < arg))) {
+                    e = s_err[ww];
+                    arg = s_arg[ww];
+                }
+            if (arg < 0 || !(e > 0.0)) {
+                s_done = 1;                                    // exact already
+            } else {
+                // insert (key, rank) in (key, rank) order
+                const int64_t key = sorted[arg];
+                const double rank = (double(arg) + 0.5) / double(m);
+                int at = nk;
+                while (at > 0 && (s_kx[at - 1] > key || (s_kx[at - 1] == key && s_kr[at - 1] > rank))) {
+                    s_kx[at] = s_kx[at - 1];
+                    s_kr[at] = s_kr[at - 1];
+                    at--;
+                }
+                s_kx[at] = key;
+                s_kr[at] = rank;
+                if (s_hpos >= at) s_hpos++;
+                s_nk = nk + 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    Leaf o;
+    o.hlo = o.hhi = 0;
+    o.hk = uint8_t(kNoHeavy);
+    o.pad = 0;
+    const int nk = s_nk, hpos = s_hpos;
+    if (nk == 0) {                                    // empty: range filled in later
+        for (int t = 0; t < kKnots; t++) {
+            o.kx[t] = INT64_MAX;
+            o.r[t] = 0;
+        }
+        o.nk = 0;
+        o.lo = o.hi = -1.f;
+        mod->leaf[leaf] = o;
+        return;
+    }
+    // the first leaf's range starts at 0 and the last one's ends at 1
+    const float lo = leaf == 0 ? 0.f : float(s_kr[0]);
+    const float hi = leaf == mod->nleaf - 1 ? 1.f : float(s_kr[nk - 1]);
+    const double dlo = double(lo), dspan = double(hi) - double(lo);
+    auto enc = [&](double v) -> uint16_t {          // nearest 16-bit fraction of [lo, hi]
+        if (!(dspan > 0)) return 0;
+        const double u = nearbyint((v - dlo) / dspan * 65535.0);
+        return uint16_t(u < 0 ? 0 : (u > 65535 ? 65535 : u));
+    };
+    for (int t = 0; t < kKnots; t++) {
+        o.kx[t] = t < nk ? s_kx[t] : INT64_MAX;
+        o.r[t] = enc(s_kr[t < nk ? t : nk - 1]);
+    }
+    o.lo = lo;
+    o.hi = hi;
+    o.nk = uint8_t(nk);
+    if (hpos >= 0) {
+        o.hk = uint8_t(hpos);
+        o.hlo = o.r[hpos];
+        o.hhi = o.r[hpos + 1];
+    }
+    mod->leaf[leaf] = o;
 }
 
 // Empty leaves take the rank reached by the leaves before them, so the
@@ -633,15 +675,6 @@ __global__ __launch_bounds__(kFillNT) void k_lcdf_leaf_fill(LcdfModel *mod) {
     if (threadIdx.x == 0) mod->leaf[nl - 1].hi = 1.f;
 }
 
-template <class K>
-__global__ void k_lcdf_buckets(const LcdfModel *mod, const K *keys, int64_t n, int bits,
-                               int32_t *out) {
-    LearnedOrd<K> ord{mod, float(1u << bits), (1u << bits) - 1};
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x)
-        out[i] = int32_t(ord(keys[i]));
-}
-
 // ---- per-bucket finishing sort -------------------------------------------------
 
 struct BucketStats {
@@ -653,17 +686,6 @@ struct Overflow {
     int64_t start, len, kmin, kmax;
     int64_t off;                        // position in the gathered overflow keys
 };
-
-// R ordinals at once: the learned model evaluates them together.
-template <int R, class K>
-__device__ __forceinline__ void ord_many(const LearnedOrd<K> &o, const K (&k)[R], uint32_t (&b)[R]) {
-    o.template many<R>(k, b);
-}
-template <int R, class K, class Ord>
-__device__ __forceinline__ void ord_many(const Ord &o, const K (&k)[R], uint32_t (&b)[R]) {
-#pragma unroll
-    for (int r = 0; r < R; r++) b[r] = uint32_t(o(k[r]));
-}
 
 // Bucket number of every key, evaluated once (int32, in [0, nb)).
 template <class K, class Ord>
@@ -679,14 +701,95 @@ __global__ __launch_bounds__(256) void k_bucket_ids(const K *__restrict__ keys, 
             const int64_t i = base + int64_t(r) * blockDim.x;
             k[r] = i < n ? keys[i] : K(0);
         }
-        uint32_t b[R];
-        ord_many<R>(ord, k, b);
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const int64_t i = base + int64_t(r) * blockDim.x;
-            if (i < n) ids[i] = int32_t(b[r]);
+            if (i < n) ids[i] = int32_t(ord(k[r]));
         }
     }
+}
+
+// The same for a learned model, its leaves read from LDS: a key's leaf is a
+// random one of thousands, and the handful of reads its evaluation makes
+// cost far less from LDS than from the caches.  One workgroup per compute unit copies leaves
+// [leaf0, leaf0 + kLdsLeafMax) into LDS and numbers the keys whose leaf is
+// among them; a model with more leaves takes one such pass per group of
+// leaves (the keys are read again, each number is written once).
+constexpr int kBidNT = 1024;
+
+template <class K>
+__global__ __launch_bounds__(kBidNT) void k_bucket_ids_lds(const K *__restrict__ keys, int64_t n,
+                                                           LearnedOrd<K> ord, int leaf0,
+                                                           int32_t *__restrict__ ids) {
+    extern __shared__ int4 s_leaf[];
+    constexpr int Q = int(sizeof(Leaf) / 16);
+    const int nl = ord.m->nleaf;
+    const int cnt = nl - leaf0 < kLdsLeafMax ? nl - leaf0 : kLdsLeafMax;
+    if (cnt <= 0) return;
+    const int4 *src = reinterpret_cast<const int4 *>(ord.leaves + leaf0);
+    for (int i = threadIdx.x; i < cnt * Q; i += kBidNT) s_leaf[i] = src[i];
+    __syncthreads();
+    const Leaf *lds = reinterpret_cast<const Leaf *>(s_leaf);
+    const LcdfModel *m = ord.m;
+    constexpr int R = 4;
+    const int64_t stride = int64_t(gridDim.x) * kBidNT * R;
+    for (int64_t base = blockIdx.x * int64_t(kBidNT) * R + threadIdx.x; base < n; base += stride) {
+        K k[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + int64_t(r) * kBidNT;
+            k[r] = i < n ? keys[i] : K(0);
+        }
+        float x[R], y[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) x[r] = lcdf_x(m, int64_t(k[r]));
+        lcdf_root_n<R>(m, x, y);
+        // all R evaluations issued together (their LDS reads overlap), then
+        // only the keys whose leaf is in this pass's group are written
+        int li[R];
+        float f[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            li[r] = lcdf_leaf(m, y[r]) - leaf0;
+            f[r] = lcdf_leaf_eval(lds[li[r] >= 0 && li[r] < cnt ? li[r] : 0], int64_t(k[r]));
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t i = base + int64_t(r) * kBidNT;
+            if (i < n && li[r] >= 0 && li[r] < cnt) ids[i] = int32_t(ord.bucket(f[r]));
+        }
+    }
+}
+
+template <class K, class Ord>
+static int launch_bucket_ids(const K *keys, int64_t n, const Ord &ord, int32_t *ids, hipStream_t s) {
+    int64_t g = ceil_div(n, 256);
+    if (g > 16384) g = 16384;
+    TQP_LAUNCH("bucket_ids", (k_bucket_ids<K, Ord>), dim3(unsigned(g)), dim3(256), 0, s, keys, n,
+               ord, ids);
+    return check_launch("bucket ids");
+}
+
+template <class K>
+static int launch_bucket_ids(const K *keys, int64_t n, const LearnedOrd<K> &ord, int32_t *ids,
+                             hipStream_t s) {
+    int32_t nl = 0;
+    hipError_t e = hipMemcpyAsync(&nl, &ord.m->nleaf, sizeof nl, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(TQP_EHIP, "bucket ids: model header: %s", hipGetErrorString(e));
+    if (nl < 1 || nl > kLeafMax) return set_error(TQP_EINVAL, "bucket ids: the model has %d leaves", nl);
+    const size_t lds = size_t(kLdsLeafMax) * sizeof(Leaf);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_ids_lds<K>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess)
+        return set_error(TQP_EHIP, "bucket ids: LDS of %zu bytes: %s", lds, hipGetErrorString(e));
+    for (int leaf0 = 0; leaf0 < nl; leaf0 += kLdsLeafMax) {
+        TQP_LAUNCH("bucket_ids", k_bucket_ids_lds<K>, dim3(unsigned(kComputeUnits)), dim3(kBidNT),
+                   lds, s, keys, n, ord, leaf0, ids);
+        int rc = check_launch("bucket ids");
+        if (rc) return rc;
+    }
+    return TQP_OK;
 }
 
 // The buckets that occur are the runs of the grouped bucket numbers: run r
@@ -698,14 +801,14 @@ __device__ __forceinline__ int64_t run_end(const int32_t *rs, int64_t nruns, int
 
 // ---- windows: every bucket of at most kWinCap keys, sorted in LDS ------------
 //
-// The grouped keys are cut into windows of whole buckets: window w holds the
-// buckets that start in [w * kWin, (w + 1) * kWin), so it spans at most
-// kWinCap = 2 kWin positions when none of its buckets is larger than kWin.
+// The grouped keys are cut into windows of whole buckets: slot w holds the
+// buckets that start in [w * kWin, (w + 1) * kWin).  All of them but the
+// last lie inside that range, so they span fewer than kWin positions; when
+// the last one makes the slot wider than kWinCap = 2 kWin, the slot becomes
+// two windows, the buckets before the last and the last one alone, and a
+// last bucket of more than kWinCap keys goes to the big-bucket path instead.
 // Buckets are disjoint key ranges in key order, so sorting a window's keys
-// as one sequence sorts each of its buckets.  A window wider than kWinCap
-// (it holds a bucket of more than kWin keys) hands its buckets to the
-// big-bucket path instead: buckets of more than kWinCap keys one by one,
-// runs of smaller consecutive buckets as segments.
+// as one sequence sorts each of its buckets.
 constexpr int kWin = 4096;
 constexpr int kWinCap = 2 * kWin;
 constexpr int kWinNT = 1024;
@@ -729,9 +832,9 @@ __device__ __forceinline__ void push_big(BucketStats *stats, Overflow *big, int6
     if (int64_t(slot) < big_cap) big[slot] = Overflow{start, len, 0, 0, 0};
 }
 
-// One thread per window: its range [start, end), or the hand-off of its
-// buckets to the big-bucket path.  win[w] = {start, end}; end <= start means
-// nothing to sort.
+// One thread per slot: its one or two windows, win[w] and win[nwin + w], as
+// {start, end} (end <= start: nothing to sort), and the hand-off of a bucket
+// of more than kWinCap keys to the big-bucket path.
 __global__ __launch_bounds__(256) void k_window_plan(const int32_t *__restrict__ rs,
                                                      const int64_t *__restrict__ d_nruns, int64_t n,
                                                      int64_t nwin, int2 *win, BucketStats *stats,
@@ -744,21 +847,17 @@ __global__ __launch_bounds__(256) void k_window_plan(const int32_t *__restrict__
         const int64_t s0 = a < nruns ? rs[a] : n, e0 = b < nruns ? rs[b] : n;
         if (e0 - s0 <= kWinCap) {
             win[w] = make_int2(int(s0), int(e0));
+            win[nwin + w] = make_int2(0, 0);
             continue;
         }
-        win[w] = make_int2(int(s0), int(s0));
-        int64_t seg = -1;                        // start of the current run of small buckets
-        for (int64_t r = a; r < b; r++) {
-            const int64_t st = rs[r], len = run_end(rs, nruns, r, n) - st;
-            if (len > kWinCap) {
-                if (seg >= 0 && st - seg > 1) push_big(stats, big, big_cap, seg, st - seg);
-                seg = -1;
-                push_big(stats, big, big_cap, st, len);
-            } else if (seg < 0) {
-                seg = st;
-            }
+        const int64_t sl = rs[b - 1];            // the last bucket: [sl, e0), longer than kWin
+        win[w] = make_int2(int(s0), int(sl));
+        if (e0 - sl <= kWinCap) {
+            win[nwin + w] = make_int2(int(sl), int(e0));
+        } else {
+            win[nwin + w] = make_int2(0, 0);
+            push_big(stats, big, big_cap, sl, e0 - sl);
         }
-        if (seg >= 0 && e0 - seg > 1) push_big(stats, big, big_cap, seg, e0 - seg);
     }
 }
 
@@ -1126,7 +1225,7 @@ static PartLayout part_layout(void *ws, int64_t n, int ksize, int bucket_bits) {
     L.mm = c.take<long long>(size_t(2 * L.ovf_cap));
     L.ids = c.take<int32_t>(size_t(nn));
     L.ids_sorted = c.take<int32_t>(size_t(nn));
-    L.win = c.take<int2>(size_t(ceil_div(nn, kWin)));
+    L.win = c.take<int2>(size_t(2 * ceil_div(nn, kWin)));
     L.ruk = c.take<int32_t>(size_t(nn));
     L.rus = c.take<int32_t>(size_t(nn));
     L.d_nruns = c.take<int64_t>(1);
@@ -1165,13 +1264,7 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
     int rc = fill_u64(L.stats, 0, sizeof(BucketStats) / 8, s);
     if (rc) return rc;
     // 1. every key's bucket number, once
-    {
-        int64_t g = ceil_div(n, 256);
-        if (g > 16384) g = 16384;
-        TQP_LAUNCH("bucket_ids", (k_bucket_ids<K, Ord>), dim3(unsigned(g)), dim3(256), 0, s, key, n,
-                   ord, L.ids);
-        if ((rc = check_launch("bucket ids"))) return rc;
-    }
+    if ((rc = launch_bucket_ids(key, n, ord, L.ids, s))) return rc;
     // 2. group the keys by bucket: stable radix passes over the bucket
     // number, the key and its row id moving along
     SortCols sc = {};
@@ -1199,7 +1292,7 @@ static int partition_sort_typed(const K *key, const int32_t *in_rows, int64_t n,
                    L.d_nruns, n, nwin, L.win, L.stats, L.ovf, L.ovf_cap);
         if ((rc = check_launch("window plan"))) return rc;
         TQP_LAUNCH("window_sort", k_window_sort<K>, dim3(unsigned(kComputeUnits)), dim3(kWinNT), 0,
-                   s, out_key, out_rows, L.win, nwin);
+                   s, out_key, out_rows, L.win, 2 * nwin);
         if ((rc = check_launch("window sort"))) return rc;
     }
     BucketStats hs;
@@ -1373,18 +1466,15 @@ TQP_API int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_
         (keys->len > 0 && (!keys->data || !out_bucket)))
         return set_error(TQP_EINVAL, "tqp_lcdf_buckets: bad argument");
     if (keys->len == 0) return TQP_OK;
-    int64_t g = ceil_div(keys->len, 256);
-    if (g > 8192) g = 8192;
     hipStream_t s = as_stream(stream);
+    const LcdfModel *m = static_cast<const LcdfModel *>(model);
+    const float scale = float(1u << bucket_bits);
+    const uint32_t top = (1u << bucket_bits) - 1;
     if (keys->dtype == TQP_INT32)
-        TQP_LAUNCH("lcdf_buckets", k_lcdf_buckets<int32_t>, dim3(unsigned(g)), dim3(256), 0, s,
-                   static_cast<const LcdfModel *>(model), static_cast<const int32_t *>(keys->data),
-                   keys->len, bucket_bits, out_bucket);
-    else
-        TQP_LAUNCH("lcdf_buckets", k_lcdf_buckets<int64_t>, dim3(unsigned(g)), dim3(256), 0, s,
-                   static_cast<const LcdfModel *>(model), static_cast<const int64_t *>(keys->data),
-                   keys->len, bucket_bits, out_bucket);
-    return check_launch("tqp_lcdf_buckets");
+        return launch_bucket_ids(static_cast<const int32_t *>(keys->data), keys->len,
+                                 LearnedOrd<int32_t>{m, m->leaf, scale, top}, out_bucket, s);
+    return launch_bucket_ids(static_cast<const int64_t *>(keys->data), keys->len,
+                             LearnedOrd<int64_t>{m, m->leaf, scale, top}, out_bucket, s);
 }
 
 TQP_API size_t tqp_partition_sort_workspace_bytes(int64_t n, int dtype, int bucket_bits) {
@@ -1436,6 +1526,7 @@ TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint3
         if (mode == TQP_PART_LEARNED)
             return partition_sort_typed(k, in_rows, n,
                                         LearnedOrd<int32_t>{static_cast<const LcdfModel *>(model),
+                                                            static_cast<const LcdfModel *>(model)->leaf,
                                                             float(1u << bucket_bits),
                                                             (1u << bucket_bits) - 1},
                                         bucket_bits, ok, out_rows, h_stats, pws, s);
@@ -1447,6 +1538,7 @@ TQP_API int tqp_partition_sort(const tqp_col *key, const int32_t *in_rows, uint3
     if (mode == TQP_PART_LEARNED)
         return partition_sort_typed(k, in_rows, n,
                                     LearnedOrd<int64_t>{static_cast<const LcdfModel *>(model),
+                                                        static_cast<const LcdfModel *>(model)->leaf,
                                                         float(1u << bucket_bits),
                                                         (1u << bucket_bits) - 1},
                                     bucket_bits, ok, out_rows, h_stats, pws, s);

@@ -52,6 +52,24 @@ def test_model_is_monotone_and_trains(tqp, mix):
     assert np.all(np.diff(eb) >= 0) and eb.min() >= 0 and eb.max() < 65536
 
 
+@pytest.mark.parametrize("nleaf", [1, 1704, 1705, 3 * 1704 + 5])
+def test_bucket_numbers_every_leaf_group(tqp, mix, nleaf):
+    """Bucket numbers are evaluated with the leaves in LDS, one group of 1704
+    leaves per pass over the keys: every key gets its number in exactly one
+    pass (a pre-filled output is overwritten everywhere), numbers do not
+    decrease along sorted keys, and the partition sort is the stable sort."""
+    left, right = mix
+    model = tqp.lcdf_train([dev(left), dev(right)], sample_stride=50, nleaf=nleaf, steps=20)
+    sk = np.sort(np.concatenate([left, right]))
+    out = torch.full((sk.size,), -1, dtype=torch.int32, device="cuda")
+    b = host(tqp.lcdf_buckets(model, dev(sk), 16, out=out))
+    assert b.min() >= 0 and b.max() < 65536
+    assert np.all(np.diff(b) >= 0)
+    got, rows, _ = tqp.partition_sort(dev(right), tqp.PART_LEARNED, model, bucket_bits=14)
+    ok, perm = oracle.sort(right)
+    assert np.array_equal(host(got), ok) and np.array_equal(host(rows), perm)
+
+
 @pytest.mark.parametrize("bits", [8, 12, 16, 20, 24])
 def test_learned_partition_sort_matches_sort_and_oracle(tqp, mix, bits):
     left, right = mix
@@ -136,16 +154,19 @@ def assert_stable_sort(keys, sk, rows):
 
 @pytest.mark.timeout(900)
 def test_full_size_learned_join_matches_oracle(tqp):
-    """200M x 50M int64 keys at full size: the learned partition sort of each
-    side is the stable sort (property check on the device), and the join
-    ranges over the sorted sides equal the oracle's on host copies."""
+    """200M x 50M int64 keys at full size, in the benchmark's setting: the
+    learned partition sort of each side is the stable sort (property check on
+    the device), and the join ranges over the sorted sides equal the oracle's
+    on host copies."""
     from tqp_datagen import device as dgd
     c = dgd.config4(0, device="cuda")
     left, right = c["left"], c["right"]
-    model = tqp.lcdf_train([left, right], sample_stride=100, nleaf=4096, steps=200)
+    # the benchmark's setting: 1704 leaves, 50 steps, 2^16 buckets
+    model = tqp.lcdf_train([left, right], sample_stride=100, nleaf=1704, steps=50)
     sides = []
     for keys in (left, right):
-        sk, rows, st = tqp.partition_sort(keys, tqp.PART_LEARNED, model, bucket_bits=18)
+        sk, rows, st = tqp.partition_sort(keys, tqp.PART_LEARNED, model, bucket_bits=16)
+        assert st["fallback_keys"] < 0.01 * keys.numel()
         assert_stable_sort(keys, sk, rows)
         del rows
         sides.append(sk)
