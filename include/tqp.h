@@ -499,10 +499,12 @@ int tqp_batch_destroy(void *graph);
  *   tqp_lcdf_model_bytes(nleaf) bytes (nleaf in [1, 65536]); its first 36
  *   bytes are int64 kmin, float64 1/span, int32 nleaf, int32 steps, float32
  *   loss at the first step, at the last step, and the lowest.  No host sync.
- *   Leaves are 64 bytes; with nleaf <= 2560 every bucket evaluation holds
- *   all of them in LDS (the fast case), above that it reads them from memory.
+ *   Leaves are 96 bytes (eight exact int64 knots); bucket numbers are
+ *   evaluated with the leaves held in LDS, 1704 leaves per pass over the
+ *   keys, so nleaf <= 1704 takes one pass (the fast case).
  * tqp_lcdf_buckets: out_bucket[i] = bucket of keys[i] for 2^bucket_bits
- *   buckets (bits in [1, 24]); for inspection and tests.
+ *   buckets (bits in [1, 24]); for inspection and tests.  Synchronizes the
+ *   stream once (to read the model's leaf count).
  * ---------------------------------------------------------------------- */
 size_t tqp_lcdf_model_bytes(int nleaf);
 size_t tqp_lcdf_train_workspace_bytes(int64_t total_keys, int sample_stride);
@@ -515,8 +517,9 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
 /* ------------------------------------------------------------------------
  * tqp_partition_sort -- the same stable ascending sort as tqp_sort (same
  * out_key and out_rows bytes), by partitioning into 2^bucket_bits key-range
- * buckets (bucket_bits in [1, 24]; about n / 8 buckets keeps most of them
- * small enough to sort in registers) and sorting each bucket on its own.
+ * buckets (bucket_bits in [1, 24]; at most about 3000 keys per bucket on
+ * average, so that windows of whole buckets fit the 8192-key LDS sort) and
+ * sorting windows of whole buckets in LDS.
  *   mode TQP_PART_LEARNED: buckets from `model` (trained by tqp_lcdf_train);
  *   mode TQP_PART_RADIX:   buckets = top bucket_bits of key - key_min over
  *                          key_bits bits (key_bits 0 = derive on the device).
@@ -527,7 +530,7 @@ int tqp_lcdf_buckets(const void *model, const tqp_col *keys, int bucket_bits,
  * sort over their own key range (all of them gathered into one sort); if
  * more than 65536 buckets (the "part.ovf_cap" knob) overflow, the whole input
  * is sorted by the radix sort instead.  SYNCHRONIZES the stream
- * once (to read the fallback list).  Workspace:
+ * (to read the model's leaf count and the fallback list).  Workspace:
  * tqp_partition_sort_workspace_bytes.
  * ---------------------------------------------------------------------- */
 #define TQP_PART_LEARNED 1u
