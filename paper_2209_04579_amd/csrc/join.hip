@@ -22,7 +22,7 @@ constexpr int kJoinIPT = 16;
 constexpr int kJoinTile = kJoinNT * kJoinIPT;
 constexpr int kExpandPer = 8;
 constexpr int kExpandTile = kJoinNT * kExpandPer;   // output pairs per expand tile
-constexpr int kMatchIPT = 4;
+constexpr int kMatchIPT = 16;          // consecutive left runs per thread
 constexpr int kMatchTile = kJoinNT * kMatchIPT;
 constexpr int kMatchWindow = 4096;      // right keys staged in LDS per match tile
 constexpr int kRleNT = 1024;
@@ -148,11 +148,70 @@ struct MatchArgs {
     int64_t *d_count;
     int64_t *tile_first;     // optional: range holding the first pair of each output tile
     int64_t ntiles_out;
+    const int64_t *bounds;   // per match tile: its window [bounds[2t], bounds[2t + 1]) of right runs
     uint32_t *ticket;
     uint64_t *status_m;
     uint64_t *status_p;
 };
 
+// The right runs a match tile can meet lie in [lower_bound of its first left
+// key, upper_bound of its last): one thread per tile, all tiles at once, so no
+// tile waits on a search over the whole right side.
+template <class K>
+__global__ __launch_bounds__(256) void k_match_bounds(const K *__restrict__ uL,
+                                                      const int64_t *d_nuL, const K *__restrict__ uR,
+                                                      const int64_t *d_nuR, int64_t cap_tiles,
+                                                      int64_t *bounds) {
+    const int64_t nuL = *d_nuL, nuR = *d_nuR;
+    const int64_t ntiles = ceil_div(nuL, kMatchTile);
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntiles && t < cap_tiles;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t u0 = t * kMatchTile;
+        const int64_t u1 = (u0 + kMatchTile < nuL ? u0 + kMatchTile : nuL) - 1;
+        const K k0 = uL[u0], k1 = uL[u1];
+        int64_t lo = 0, hi = nuR;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (uR[mid] < k0) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t wl = lo;
+        hi = nuR;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (!(k1 < uR[mid])) lo = mid + 1;
+            else hi = mid;
+        }
+        bounds[2 * t] = wl;
+        bounds[2 * t + 1] = lo;
+    }
+}
+
+// Lower bound of k among wkeys[pos, wn), keys at or after pos: a gallop from
+// pos, then a binary search inside the last step (a few reads when the two
+// sides' keys interleave evenly).
+template <class K, class P>
+__device__ __forceinline__ int64_t gallop_lower(P wkeys, int64_t pos, int64_t wn, K k) {
+    int64_t lo = pos, hi = pos, step = 1;
+    while (hi < wn && wkeys[hi] < k) {
+        lo = hi + 1;
+        hi = lo + step;
+        step <<= 1;
+    }
+    if (hi > wn) hi = wn;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (wkeys[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Each thread takes kMatchIPT consecutive left runs and finds each one's key
+// among the tile's right window (staged in LDS when it fits) by galloping
+// from the previous key's position.  A first sweep counts the matched runs
+// and their pairs; after the two look-backs, a second sweep writes the
+// ranges of the matched runs from the window positions kept in registers.
 template <class K>
 __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     __shared__ int64_t s_tile, s_pm, s_pp;
@@ -177,60 +236,41 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
         }
         break;
     }
-    // The right keys this tile can match lie in [w_lo, w_hi): the lower bound
-    // of the tile's first left key and the upper bound of its last.  Two
-    // threads find them; a window that fits is staged in LDS and searched
-    // there, a larger one is searched in place.
-    const int64_t tile_u0 = tile * kMatchTile;
-    const int64_t tile_u1 = (tile_u0 + kMatchTile < nuL ? tile_u0 + kMatchTile : nuL) - 1;
-    if (threadIdx.x < 2) {
-        const K k = uL[threadIdx.x == 0 ? tile_u0 : tile_u1];
-        int64_t lo = 0, hi = nuR;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (threadIdx.x == 0 ? (uR[mid] < k) : !(k < uR[mid])) lo = mid + 1;
-            else hi = mid;
-        }
-        s_win[threadIdx.x] = lo;
-    }
+    if (threadIdx.x < 2) s_win[threadIdx.x] = a.bounds[2 * tile + threadIdx.x];
     __syncthreads();
     const int64_t w_lo = s_win[0], w_hi = s_win[1];
-    const bool in_lds = w_hi - w_lo <= kMatchWindow;
-    if (in_lds)
-        for (int64_t i = threadIdx.x; i < w_hi - w_lo; i += kJoinNT)
-            s_rkeys[i] = static_cast<const K *>(a.uR)[w_lo + i];
-    __syncthreads();
-    const K *wkeys = in_lds ? reinterpret_cast<const K *>(s_rkeys) : uR + w_lo;
     const int64_t wn = w_hi - w_lo;
+    const bool in_lds = wn <= kMatchWindow;
+    if (in_lds)
+        for (int64_t i = threadIdx.x; i < wn; i += kJoinNT) s_rkeys[i] = uR[w_lo + i];
+    // this thread's left runs: keys and starts (one more start for the counts)
     const int64_t u0 = tile * kMatchTile + int64_t(threadIdx.x) * kMatchIPT;
-    int64_t ls[kMatchIPT], lc[kMatchIPT], rs[kMatchIPT], rc[kMatchIPT];
     K key[kMatchIPT];
+    load_keys16(uL, u0, nuL, key);
+    int32_t st[kMatchIPT + 1];
+#pragma unroll
+    for (int r = 0; r <= kMatchIPT; r++) st[r] = u0 + r < nuL ? a.sL[u0 + r] : int32_t(nl);
+    __syncthreads();
     uint32_t hit = 0;
+    int32_t widx[kMatchIPT];
     int64_t pairs = 0;
-    int64_t from = 0;                         // keys ascend: each search starts at the last
+    int64_t from = 0;
 #pragma unroll
     for (int r = 0; r < kMatchIPT; r++) {
-        const int64_t u = u0 + r;
-        ls[r] = lc[r] = rs[r] = rc[r] = 0;
-        key[r] = K(0);
-        if (u < nuL) {
-            const K k = uL[u];
-            key[r] = k;
-            ls[r] = a.sL[u];
-            lc[r] = (u + 1 < nuL ? int64_t(a.sL[u + 1]) : nl) - ls[r];
-            int64_t lo = from, hi = wn;           // lower_bound of k in the window
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (wkeys[mid] < k) lo = mid + 1;
-                else hi = mid;
-            }
+        widx[r] = 0;
+        if (u0 + r < nuL) {
+            const K k = key[r];
+            const int64_t lo = in_lds ? gallop_lower(static_cast<const K *>(s_rkeys), from, wn, k)
+                                      : gallop_lower(uR + w_lo, from, wn, k);
             from = lo;
-            if (lo < wn && wkeys[lo] == k) {
-                lo += w_lo;
+            const K rk = lo < wn ? (in_lds ? s_rkeys[lo] : uR[w_lo + lo]) : k;
+            if (lo < wn && rk == k) {
                 hit |= 1u << r;
-                rs[r] = a.sR[lo];
-                rc[r] = (lo + 1 < nuR ? int64_t(a.sR[lo + 1]) : nr) - rs[r];
-                pairs += lc[r] * rc[r];
+                widx[r] = int32_t(lo);
+                const int64_t g = w_lo + lo;
+                const int64_t rs = a.sR[g];
+                const int64_t rc = (g + 1 < nuR ? int64_t(a.sR[g + 1]) : nr) - rs;
+                pairs += int64_t(st[r + 1] - st[r]) * rc;
             }
         }
     }
@@ -254,20 +294,26 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
 #pragma unroll
     for (int r = 0; r < kMatchIPT; r++) {
         if (!(hit & (1u << r))) continue;
-        a.rkey[q] = int64_t(key[r]);
-        a.rls[q] = ls[r];
-        a.rlc[q] = lc[r];
-        a.rrs[q] = rs[r];
-        a.rrc[q] = rc[r];
-        a.off[q] = o;
+        const int64_t g = w_lo + widx[r];
+        const int64_t rs = a.sR[g];
+        const int64_t rc = (g + 1 < nuR ? int64_t(a.sR[g + 1]) : nr) - rs;
+        const int64_t ls = st[r], lc = int64_t(st[r + 1]) - ls;
+        if (a.rkey) {
+            a.rkey[q] = int64_t(key[r]);
+            a.rls[q] = ls;
+            a.rlc[q] = lc;
+            a.rrs[q] = rs;
+            a.rrc[q] = rc;
+            a.off[q] = o;
+        }
         if (a.ukey && q < a.ucap) {
             a.ukey[q] = int64_t(key[r]);
-            a.uls[q] = ls[r];
-            a.ulc[q] = lc[r];
-            a.urs[q] = rs[r];
-            a.urc[q] = rc[r];
+            a.uls[q] = ls;
+            a.ulc[q] = lc;
+            a.urs[q] = rs;
+            a.urc[q] = rc;
         }
-        const int64_t p = lc[r] * rc[r];
+        const int64_t p = lc * rc;
         if (a.tile_first) {
             // this range holds the first pair of every output tile starting in it
             for (int64_t t = ceil_div(o, kExpandTile); t * kExpandTile < o + p && t < a.ntiles_out; t++)
@@ -351,6 +397,8 @@ struct JoinLayout {
     int64_t *off;
     int64_t *tile_first;     // per output tile of the expand: its first range
     int64_t ntiles_out;
+    int64_t *bounds;         // per match tile: its window of right runs
+    int64_t ntiles_match;
     int64_t *counters;       // nuL, nuR, nranges
     uint64_t *words;         // tickets + statuses
     int64_t nwords;
@@ -381,6 +429,8 @@ static JoinLayout join_layout(void *ws, int64_t nl, int64_t nr, int dtype, uint3
     L.off = c.take<int64_t>(size_t(nm));
     L.ntiles_out = ceil_div(cap > 0 ? cap : 1, kExpandTile);
     L.tile_first = c.take<int64_t>(size_t(L.ntiles_out));
+    L.ntiles_match = ceil_div(nl > 0 ? nl : 1, kMatchTile);
+    L.bounds = c.take<int64_t>(size_t(2 * L.ntiles_match));
     L.counters = c.take<int64_t>(4);
     const int64_t tl = ceil_div(nl > 0 ? nl : 1, kRleTile);
     const int64_t tr = ceil_div(nr > 0 ? nr : 1, kRleTile);
@@ -470,9 +520,19 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
         a.tile_first = L.tile_first;
         a.ntiles_out = L.ntiles_out;
     }
+    if (!want_pairs) a.rkey = nullptr;      // only the expand reads the workspace copy
     a.ticket = tickets + 4;
     a.status_m = L.stM;
     a.status_p = L.stP;
+    a.bounds = L.bounds;
+    {
+        int64_t g = ceil_div(L.ntiles_match, 256);
+        if (g > 1024) g = 1024;
+        TQP_LAUNCH("match_bounds", k_match_bounds<K>, dim3(unsigned(g)), dim3(256), 0, s,
+                   static_cast<const K *>(L.uL), &L.counters[0], static_cast<const K *>(L.uR),
+                   &L.counters[1], L.ntiles_match, L.bounds);
+        if ((rc = check_launch("join match bounds"))) return rc;
+    }
     const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, kMatchTile), tune(kTuneMatchPerCu));
     TQP_LAUNCH("join_match", k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
     if ((rc = check_launch("join match"))) return rc;
