@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--learned-right", type=int, default=50_000_000)
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-fact-hi", type=int, default=20_000_000)
+    ap.add_argument("--tune-cache", default=os.environ.get("TQP_TUNE_CACHE", ""),
+                    help="JSON file of tuned settings (read, and written after tuning); "
+                         "empty: tune every run")
     ap.add_argument("--side-reps", type=int, default=5,
                     help="timed repetitions of each side comparison (median reported)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -618,6 +621,7 @@ def bench_learned(args, tqp, stream) -> dict:
     partitioner with the same bucket count."""
     import torch
     from tqp_datagen import device as dgd
+    from paper_2209_04579_amd import autotune
 
     nl, nr = args.learned_left, args.learned_right
     t0 = time.time()
@@ -635,22 +639,55 @@ def bench_learned(args, tqp, stream) -> dict:
     lo, hi = min(st_l[0], st_r[0]), max(st_l[1], st_r[1])
     key_bits = (hi - lo).bit_length()
     reps = args.side_reps
+    sides = [left, right]
+    outk = [torch.empty_like(t) for t in sides]
+    outr = [torch.empty(t.numel(), dtype=torch.int32, device=t.device) for t in sides]
+    stats = {}
+
+    # the learned plan's own parameters, tuned (or taken from the cache):
+    # bucket count, the model's leaf count and its training steps
+    space = {"bits": [b for b in (bits - 1, bits, bits + 1) if 8 <= b <= 24],
+             "leaves": [LEARNED_LEAVES // 2, LEARNED_LEAVES, 2 * LEARNED_LEAVES],
+             "steps": [LEARNED_STEPS // 2, LEARNED_STEPS, 2 * LEARNED_STEPS]}
+    default = {"bits": bits, "leaves": LEARNED_LEAVES, "steps": LEARNED_STEPS}
+    tws = tqp.workspace(max(tqp.partition_sort_workspace_bytes(t.numel(), t.dtype, b)
+                            for t in sides for b in space["bits"]), left.device)
+
+    class LearnedPlan:
+        """Training plus both sides' partition sorts with one setting."""
+        def __init__(self, t):
+            self.t = t
+
+        def run(self):
+            m = tqp.lcdf_train([left, right], sample_stride=100, nleaf=self.t["leaves"],
+                               steps=self.t["steps"])
+            for i, t in enumerate(sides):
+                tqp.partition_sort_into(t, None, tqp.PART_LEARNED, m, self.t["bits"], outk[i],
+                                        outr[i], tws, key_bits=key_bits, key_min=lo)
+
+    key = autotune.cache_key("learned_partition_sort", nl + nr,
+                             "lognormal-clusters-zipf1.2", "int64")
+    tuned, _, cache_hit = autotune.tune_cached(
+        args.tune_cache, key,
+        lambda: autotune.tune_params(LearnedPlan, space, default, reps=3, rounds=1,
+                                     log=lambda m: print(m, file=sys.stderr, flush=True)))
+    default_ms = _timed(LearnedPlan(default).run, reps, stream)
+    tuned_ms = _timed(LearnedPlan(tuned).run, reps, stream)
+    del tws
+    torch.cuda.empty_cache()
+    bits = tuned["bits"]
 
     model_holder = {}
 
     def train():
         model_holder["m"] = tqp.lcdf_train([left, right], sample_stride=100,
-                                           nleaf=LEARNED_LEAVES, steps=LEARNED_STEPS)
+                                           nleaf=tuned["leaves"], steps=tuned["steps"])
     train_ms = _timed(train, reps, stream)
     model = model_holder["m"]
     info = tqp.lcdf_model_info(model)
 
-    sides = [left, right]
-    outk = [torch.empty_like(t) for t in sides]
-    outr = [torch.empty(t.numel(), dtype=torch.int32, device=t.device) for t in sides]
     ws = tqp.workspace(max(tqp.partition_sort_workspace_bytes(t.numel(), t.dtype, bits)
                            for t in sides), left.device)
-    stats = {}
 
     def part(mode, mdl, tag):
         def fn():
@@ -663,7 +700,11 @@ def bench_learned(args, tqp, stream) -> dict:
     out = {"workload": f"sort-merge join of {nl} x {nr} int64 keys (lognormal sigma=2 / "
                        "64 dense clusters / Zipf s=1.2 mix)",
            "buckets": 1 << bits,
-           "model": {"hidden": 32, "leaves": LEARNED_LEAVES, "knots_per_leaf": 8,
+           "tuned": {"setting": tuned, "from_cache": cache_hit, "cache_key": key,
+                     "default": default, "space": space,
+                     "train_and_sort_ms_default": round(default_ms, 3),
+                     "train_and_sort_ms_tuned": round(tuned_ms, 3)},
+           "model": {"hidden": 32, "leaves": tuned["leaves"], "knots_per_leaf": 8,
                      "sample": "1%", "adam_steps": info["steps"],
                      "loss_first": info["loss_first"], "loss_last": info["loss_last"],
                      "train_ms": round(train_ms, 3)}}
@@ -756,8 +797,21 @@ def bench_batch(args, tqp, stream) -> dict:
     def plan_for(t):
         b.q.tuning = dict(t)
         return b
-    best, best_ms, timings = autotune.tune(plan_for, reps=3, rounds=1, include_dense=False,
-                                           log=lambda m: print(m, file=sys.stderr, flush=True))
+    plan_knobs = ("filter.per_cu", "sort.per_cu", "rle.per_cu", "match.per_cu",
+                  "gbscan.per_cu", "sort.mode")
+    key = autotune.cache_key("batch_star", rows, "zipf0-1.5", "int32")
+    timings = {}
+
+    def run_tuner():
+        r = autotune.tune(plan_for, reps=3, rounds=1, include_dense=False, only=plan_knobs,
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+        timings.update(r[2])
+        return r
+    best, _, cache_hit = autotune.tune_cached(args.tune_cache, key, run_tuner)
+    b.q.tuning = dict(defaults)
+    b.capture()
+    default_graph_ms = _timed(b.run, reps, stream)
+    b.graph = None
     b.q.tuning = dict(best)
     b.capture()
     graph_ms = _timed(b.run, reps, stream)
@@ -785,7 +839,9 @@ def bench_batch(args, tqp, stream) -> dict:
            "speedup_vs_sequential": round(seq_ms / graph_ms, 3),
            "roofline": roofline_of(kernels, star_kernel_bytes, st, None,
                                    "3 eager steps with per-kernel HIP events"),
-           "tuned": best, "tuning_trials": len(timings),
+           "default_graph_ms": round(default_graph_ms, 3),
+           "tuned": best, "tuning_trials": len(timings), "tuning_from_cache": cache_hit,
+           "tuning_cache_key": key,
            "results_match_sequential": bool(same)}
     print(f"[bench] batch: {out}", file=sys.stderr, flush=True)
     del b, insts
