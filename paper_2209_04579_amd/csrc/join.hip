@@ -59,54 +59,67 @@ __device__ __forceinline__ void load_keys16(const K *p, int64_t row0, int64_t cn
 // Run heads of a sorted column -> (unique key, run start), count in *d_nu.
 // Tiles of 1024 threads x 16 keys: the keys are only 4-8 bytes each, so a
 // large tile keeps the per-tile ticket and look-back cost small next to the
-// tile's own traffic.
+// tile's own traffic.  A wave takes 16 rows of 64 consecutive keys, one key
+// per lane and row, and compacts each row's heads by ballot, so the heads of
+// a row are written by consecutive lanes to consecutive places (per-thread
+// runs of 16 keys made each store touch 64 cache lines).
 template <class K>
 __global__ __launch_bounds__(kRleNT) void k_rle(const K *__restrict__ keys, int64_t n,
                                                 const int64_t *d_n, K *__restrict__ ukey,
                                                 int32_t *__restrict__ ustart, int64_t *d_nu,
                                                 uint32_t *ticket, uint64_t *status) {
     __shared__ int64_t s_tile, s_prefix;
-    __shared__ int32_t s_scan[kRleNT / kWave];
+    __shared__ int32_t s_wcnt[kRleNT / kWave];
     const int64_t cnt = count_of(d_n, n);
     const int64_t ntiles = ceil_div(cnt, kRleTile);
+    const int w = wave_id(), lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     for (;;) {
     const int64_t tile = take_tile(ticket, &s_tile);
     if (tile >= ntiles) {
         if (tile == 0 && threadIdx.x == 0) *d_nu = 0;
         break;
     }
-    const int64_t row0 = tile * kRleTile + int64_t(threadIdx.x) * kJoinIPT;
-    K v[16];
-    if (reinterpret_cast<uintptr_t>(keys) % 16 == 0) {
-        load_keys16(keys, row0, cnt, v);
-    } else {
+    const int64_t wbase = tile * kRleTile + int64_t(w) * (kWave * kJoinIPT);
+    K v[kJoinIPT], pv[kJoinIPT];
 #pragma unroll
-        for (int r = 0; r < 16; r++) v[r] = row0 + r < cnt ? keys[row0 + r] : K(0);
+    for (int r = 0; r < kJoinIPT; r++) {
+        const int64_t i = wbase + r * kWave + lane;
+        v[r] = i < cnt ? keys[i] : K(0);
+        pv[r] = i > 0 && i - 1 < cnt ? keys[i - 1] : K(0);
     }
-    uint32_t head = 0;
-    K prev = row0 > 0 && row0 - 1 < cnt ? keys[row0 - 1] : K(0);
+    uint64_t hm[kJoinIPT];
+    int32_t wc = 0;
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int64_t i = row0 + r;
-        if (i < cnt && (i == 0 || v[r] != prev)) head |= 1u << r;
-        prev = v[r];
+    for (int r = 0; r < kJoinIPT; r++) {
+        const int64_t i = wbase + r * kWave + lane;
+        hm[r] = ballot(i < cnt && (i == 0 || v[r] != pv[r]));
+        wc += __popcll(hm[r]);
     }
-    int32_t total;
-    const int32_t excl = block_excl_scan<kRleNT>(int32_t(__popc(head)), &total, s_scan);
-    if (wave_id() == 0) {
+    if (lane == 0) s_wcnt[w] = wc;
+    __syncthreads();
+    int32_t wex = 0, total = 0;
+#pragma unroll
+    for (int ww = 0; ww < kRleNT / kWave; ww++) {
+        const int32_t c = s_wcnt[ww];
+        wex += ww < w ? c : 0;
+        total += c;
+    }
+    if (w == 0) {
         int64_t pre = lookback_count(status, tile, total);
-        if (lane_id() == 0) s_prefix = pre;
+        if (lane == 0) s_prefix = pre;
     }
     __syncthreads();
     if (tile == ntiles - 1 && threadIdx.x == 0) *d_nu = s_prefix + total;
-    int64_t q = s_prefix + excl;
+    int64_t q = s_prefix + wex;
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        if (head & (1u << r)) {
-            ukey[q] = v[r];
-            ustart[q] = int32_t(row0 + r);
-            q++;
+    for (int r = 0; r < kJoinIPT; r++) {
+        if ((hm[r] >> lane) & 1) {
+            const int64_t pos = q + __popcll(hm[r] & lt);
+            ukey[pos] = v[r];
+            ustart[pos] = int32_t(wbase + r * kWave + lane);
         }
+        q += __popcll(hm[r]);
     }
     __syncthreads();
     }
