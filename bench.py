@@ -713,7 +713,8 @@ def bench_learned(args, tqp, stream) -> dict:
     jr = None
     for tag, mode, mdl in (("learned", tqp.PART_LEARNED, model), ("radix", tqp.PART_RADIX, None)):
         ms = _timed(part(mode, mdl, tag), reps, stream)
-        kern = {k: round(v[1], 3) for k, v in kernel_profile(part(mode, mdl, tag), 1).items()}
+        kp = kernel_profile(part(mode, mdl, tag), 1)
+        kern = {k: round(v[1], 3) for k, v in kp.items()}
         jr = _timed(lambda: tqp.join_ranges(outk[0], outk[1]), 1, stream)
         results[tag] = (outk[0].clone(), outr[0].clone())
         s0, s1 = stats[(tag, 0)], stats[(tag, 1)]
@@ -728,6 +729,29 @@ def bench_learned(args, tqp, stream) -> dict:
                                                / (nl + nr), 4),
                     "single_valued_big": s0["single_valued_big"] + s1["single_valued_big"],
                     "kernel_ms": kern}
+        if tag == "learned":
+            # algorithmic bytes per key: the bucket number (read 8 B key, write
+            # 4 B), each grouping pass (read and write 4 B number + 8 B key +
+            # 4 B row id; the first pass reads no row ids), the window sort
+            # (read and write 8 B key + 4 B row id)
+            nk = nl + nr
+            per_key = {"bucket_ids": 12.0, "onesweep": 12.0 + 16.0 + 16.0 + 16.0,
+                       "window_sort": 24.0}
+            lk = {}
+            for k, b in per_key.items():
+                if k in kp:
+                    c, t = kp[k]
+                    lk[k] = {"launches": c, "ms": round(t, 3),
+                             "algo_GBps": round(b * nk / (t * 1e-3) / 1e9, 1)}
+            dom = max(lk, key=lambda k: lk[k]["ms"])
+            c, t = kp[dom]
+            ach = per_key[dom] * nk / c / (t / c * 1e-3) / 1e9
+            out[tag]["kernels"] = lk
+            out[tag]["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                    "algo_bytes_per_launch": int(per_key[dom] * nk / c),
+                                    "avg_launch_ms": round(t / c, 5)}
         print(f"[bench] learned: {tag} {out[tag]}", file=sys.stderr, flush=True)
 
     # the plain LSD radix sort (the pipeline's own sort) on the same keys

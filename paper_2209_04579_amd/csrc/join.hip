@@ -22,8 +22,18 @@ constexpr int kJoinIPT = 16;
 constexpr int kJoinTile = kJoinNT * kJoinIPT;
 constexpr int kExpandPer = 8;
 constexpr int kExpandTile = kJoinNT * kExpandPer;   // output pairs per expand tile
-constexpr int kMatchIPT = 16;          // consecutive left runs per thread
-constexpr int kMatchTile = kJoinNT * kMatchIPT;
+// Consecutive left runs per thread of the match: 4 when either side is
+// below 2^25 rows (each lane's ranges 32 bytes apart, so a store covers few
+// cache lines when most left runs match, as against a dimension), 16 when
+// both sides are large (a quarter of the tiles, tickets and look-backs).  The
+// tile count and the workspace are sized for the smaller tile.
+constexpr int kMatchIPTSmall = 4;
+constexpr int kMatchIPTLarge = 16;
+constexpr int64_t kMatchLargeRows = int64_t(1) << 25;
+constexpr int kMatchTile = kJoinNT * kMatchIPTSmall;
+__host__ __device__ constexpr int match_ipt(int64_t nl) {
+    return nl >= kMatchLargeRows ? kMatchIPTLarge : kMatchIPTSmall;
+}
 constexpr int kMatchWindow = 4096;      // right keys staged in LDS per match tile
 constexpr int kRleNT = 1024;
 constexpr int kRleTile = kRleNT * kJoinIPT;
@@ -173,14 +183,14 @@ struct MatchArgs {
 template <class K>
 __global__ __launch_bounds__(256) void k_match_bounds(const K *__restrict__ uL,
                                                       const int64_t *d_nuL, const K *__restrict__ uR,
-                                                      const int64_t *d_nuR, int64_t cap_tiles,
-                                                      int64_t *bounds) {
+                                                      const int64_t *d_nuR, int64_t tile_runs,
+                                                      int64_t cap_tiles, int64_t *bounds) {
     const int64_t nuL = *d_nuL, nuR = *d_nuR;
-    const int64_t ntiles = ceil_div(nuL, kMatchTile);
+    const int64_t ntiles = ceil_div(nuL, tile_runs);
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntiles && t < cap_tiles;
          t += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t u0 = t * kMatchTile;
-        const int64_t u1 = (u0 + kMatchTile < nuL ? u0 + kMatchTile : nuL) - 1;
+        const int64_t u0 = t * tile_runs;
+        const int64_t u1 = (u0 + tile_runs < nuL ? u0 + tile_runs : nuL) - 1;
         const K k0 = uL[u0], k1 = uL[u1];
         int64_t lo = 0, hi = nuR;
         while (lo < hi) {
@@ -220,13 +230,14 @@ __device__ __forceinline__ int64_t gallop_lower(P wkeys, int64_t pos, int64_t wn
     return lo;
 }
 
-// Each thread takes kMatchIPT consecutive left runs and finds each one's key
+// Each thread takes IPT consecutive left runs and finds each one's key
 // among the tile's right window (staged in LDS when it fits) by galloping
 // from the previous key's position.  A first sweep counts the matched runs
 // and their pairs; after the two look-backs, a second sweep writes the
 // ranges of the matched runs from the window positions kept in registers.
-template <class K>
+template <class K, int IPT>
 __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
+    constexpr int kTileRuns = kJoinNT * IPT;
     __shared__ int64_t s_tile, s_pm, s_pp;
     __shared__ int64_t s_win[2];
     __shared__ K s_rkeys[kMatchWindow];
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     const int64_t nuR = count_of(a.d_nuR, a.nr);
     const int64_t nl = count_of(a.d_nl, a.nl);
     const int64_t nr = count_of(a.d_nr, a.nr);
-    const int64_t ntiles = ceil_div(nuL, kMatchTile);
+    const int64_t ntiles = ceil_div(nuL, kTileRuns);
     const K *uL = static_cast<const K *>(a.uL);
     const K *uR = static_cast<const K *>(a.uR);
     for (;;) {
@@ -257,19 +268,33 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     if (in_lds)
         for (int64_t i = threadIdx.x; i < wn; i += kJoinNT) s_rkeys[i] = uR[w_lo + i];
     // this thread's left runs: keys and starts (one more start for the counts)
-    const int64_t u0 = tile * kMatchTile + int64_t(threadIdx.x) * kMatchIPT;
-    K key[kMatchIPT];
-    load_keys16(uL, u0, nuL, key);
-    int32_t st[kMatchIPT + 1];
+    const int64_t u0 = tile * kTileRuns + int64_t(threadIdx.x) * IPT;
+    K key[IPT];
+    if (u0 + IPT <= nuL && reinterpret_cast<uintptr_t>(uL) % 16 == 0) {
+        // u0 is a multiple of IPT, so whole 16-byte groups
+        constexpr int kPer = 16 / sizeof(K);
+        const int4 *q = reinterpret_cast<const int4 *>(uL + u0);
 #pragma unroll
-    for (int r = 0; r <= kMatchIPT; r++) st[r] = u0 + r < nuL ? a.sL[u0 + r] : int32_t(nl);
+        for (int j = 0; j < IPT / kPer; j++) {
+            const int4 x = q[j];
+            const K *e = reinterpret_cast<const K *>(&x);
+#pragma unroll
+            for (int t = 0; t < kPer; t++) key[j * kPer + t] = e[t];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < IPT; r++) key[r] = u0 + r < nuL ? uL[u0 + r] : K(0);
+    }
+    int32_t st[IPT + 1];
+#pragma unroll
+    for (int r = 0; r <= IPT; r++) st[r] = u0 + r < nuL ? a.sL[u0 + r] : int32_t(nl);
     __syncthreads();
     uint32_t hit = 0;
-    int32_t widx[kMatchIPT];
+    int32_t widx[IPT];
     int64_t pairs = 0;
     int64_t from = 0;
 #pragma unroll
-    for (int r = 0; r < kMatchIPT; r++) {
+    for (int r = 0; r < IPT; r++) {
         widx[r] = 0;
         if (u0 + r < nuL) {
             const K k = key[r];
@@ -305,7 +330,7 @@ __global__ __launch_bounds__(kJoinNT) void k_join_match(MatchArgs a) {
     int64_t q = s_pm + ex_m;
     int64_t o = s_pp + ex_p;
 #pragma unroll
-    for (int r = 0; r < kMatchIPT; r++) {
+    for (int r = 0; r < IPT; r++) {
         if (!(hit & (1u << r))) continue;
         const int64_t g = w_lo + widx[r];
         const int64_t rs = a.sR[g];
@@ -543,11 +568,17 @@ static int join_typed(const tqp_col *lkey, const int32_t *lrows, const int64_t *
         if (g > 1024) g = 1024;
         TQP_LAUNCH("match_bounds", k_match_bounds<K>, dim3(unsigned(g)), dim3(256), 0, s,
                    static_cast<const K *>(L.uL), &L.counters[0], static_cast<const K *>(L.uR),
-                   &L.counters[1], L.ntiles_match, L.bounds);
+                   &L.counters[1], int64_t(kJoinNT) * match_ipt(nl < nr ? nl : nr), L.ntiles_match,
+                   L.bounds);
         if ((rc = check_launch("join match bounds"))) return rc;
     }
-    const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, kMatchTile), tune(kTuneMatchPerCu));
-    TQP_LAUNCH("join_match", k_join_match<K>, dim3(gm), dim3(kJoinNT), 0, s, a);
+    const int ipt = match_ipt(nl < nr ? nl : nr);
+    const unsigned gm = persistent_grid(ceil_div(nl > 0 ? nl : 1, int64_t(kJoinNT) * ipt),
+                                        tune(kTuneMatchPerCu));
+    if (ipt == kMatchIPTLarge)
+        TQP_LAUNCH("join_match", (k_join_match<K, kMatchIPTLarge>), dim3(gm), dim3(kJoinNT), 0, s, a);
+    else
+        TQP_LAUNCH("join_match", (k_join_match<K, kMatchIPTSmall>), dim3(gm), dim3(kJoinNT), 0, s, a);
     if ((rc = check_launch("join match"))) return rc;
     if (want_pairs) {
         int64_t g = L.ntiles_out;
