@@ -609,7 +609,7 @@ def bench_configs(args, tqp, stream) -> dict:
 
 # The learned model: as many leaves as one pass of the bucket-number kernel
 # holds in LDS, 50 full-batch Adam steps on the root.
-LEARNED_LEAVES = 1704
+LEARNED_LEAVES = 1688
 LEARNED_STEPS = 50
 
 

@@ -500,8 +500,8 @@ int tqp_batch_destroy(void *graph);
  *   bytes are int64 kmin, float64 1/span, int32 nleaf, int32 steps, float32
  *   loss at the first step, at the last step, and the lowest.  No host sync.
  *   Leaves are 96 bytes (eight exact int64 knots); bucket numbers are
- *   evaluated with the leaves held in LDS, 1704 leaves per pass over the
- *   keys, so nleaf <= 1704 takes one pass (the fast case).
+ *   evaluated with the leaves held in LDS, 1688 leaves per pass over the
+ *   keys, so nleaf <= 1688 takes one pass (the fast case).
  * tqp_lcdf_buckets: out_bucket[i] = bucket of keys[i] for 2^bucket_bits
  *   buckets (bits in [1, 24]); for inspection and tests.  Synchronizes the
  *   stream once (to read the model's leaf count).

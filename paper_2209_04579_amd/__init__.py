@@ -688,7 +688,7 @@ def _bind_lcdf(L):
                                      vp]
 
 
-def lcdf_train(cols, sample_stride=100, nleaf=1704, steps=50, lr=1e-2, stream=None):
+def lcdf_train(cols, sample_stride=100, nleaf=1688, steps=50, lr=1e-2, stream=None):
     """Trains the learned CDF on the keys of cols (1 or 2 device columns).
 
     Returns the model as a device uint8 tensor."""

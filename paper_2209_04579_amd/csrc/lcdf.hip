@@ -57,6 +57,10 @@ constexpr int kKnots = 8;                    // spline knots per leaf
 constexpr int kNParam = 3 * kHidden + 1;     // centre offset, log-width, log-height per ramp; d
 constexpr int kTrainPoints = 4096;           // root training set (sample points, even ranks)
 constexpr int kLeafMax = 65536;
+// The root as a table: its breakpoints in [0, 1] (every ramp starts and ends
+// at one), 0 and 1: at most 2 * kHidden + 2 points, searched as 128.
+constexpr int kRootPts = 2 * kHidden + 2;
+constexpr int kRootPad = 128;
 constexpr int kHeavyMin = 4;                 // sample copies that make a key heavy
 constexpr int64_t kOvfCap = 65536;           // overflow buckets re-sorted one by one
 
@@ -66,8 +70,13 @@ struct LcdfModel {
     int32_t nleaf;
     int32_t steps_done;
     float loss_first, loss_last, loss_best, pad0;
-    // effective root parameters used by inference
+    // effective root parameters
     float w[kHidden], c[kHidden], v[kHidden], d;
+    // the root as used for routing: points px (ascending, px[0] = 0, +inf past
+    // the last), the root's values py there (non-decreasing) and the slopes
+    // ps between them
+    int32_t npts, pad1;
+    float px[kRootPad], py[kRootPts], ps[kRootPts];
     // training state: ramp centre offset u (centre = c0 + s0 * u), log width,
     // log height, bias; Adam moments; the best parameters seen and their loss
     float theta[kNParam], m1[kNParam], m2[kNParam], best[kNParam];
@@ -90,10 +99,12 @@ struct LcdfModel {
 using Leaf = LcdfModel::Leaf;
 constexpr int kNoHeavy = 0xff;
 static_assert(sizeof(Leaf) == 96 && offsetof(Leaf, lo) == 80, "leaf layout");
-// Leaves held in LDS at once while bucket numbers are evaluated (160 KB);
-// a model with more is evaluated in several passes over the keys, each
-// holding the next kLdsLeafMax leaves.
-constexpr int kLdsLeafMax = 1704;
+// Leaves held in LDS at once while bucket numbers are evaluated (with the
+// root's table, 160 KB); a model with more is evaluated in several passes
+// over the keys, each holding the next kLdsLeafMax leaves.
+constexpr int kLdsLeafMax = 1688;
+constexpr int kRootTabBytes = int(sizeof(float)) * (kRootPad + 2 * kRootPts);   // 1040
+static_assert(kRootTabBytes % 16 == 0, "leaves after the table stay 16-byte aligned");
 
 static size_t model_bytes(int nleaf) {
     return sizeof(LcdfModel) + sizeof(Leaf) * size_t(nleaf > 0 ? nleaf - 1 : 0);
@@ -117,18 +128,22 @@ __device__ __forceinline__ float lcdf_root(const LcdfModel *m, float x) {
     return y;
 }
 
-// The root at R points, parameter by parameter, so each parameter is loaded
-// once for all R (they are wave-uniform scalar loads) and only a few are live.
-template <int R>
-__device__ __forceinline__ void lcdf_root_n(const LcdfModel *m, const float (&x)[R], float (&y)[R]) {
+// The root from its table: the last point at or below x (a branch-free
+// search over the 128 padded points), then the straight line to the next
+// point, clamped to the two points' values, so the result is monotone in x
+// whatever the rounding.  The same function as the ramp sum up to rounding.
+__device__ __forceinline__ float lcdf_root_tab(const float *px, const float *py, const float *ps,
+                                               int npts, float x) {
+    int k = 0;
 #pragma unroll
-    for (int r = 0; r < R; r++) y[r] = m->d;
-#pragma unroll 4
-    for (int j = 0; j < kHidden; j++) {
-        const float w = m->w[j], c = m->c[j], v = m->v[j];
-#pragma unroll
-        for (int r = 0; r < R; r++) y[r] = fmaf(v, ramp(fmaf(w, x[r], c)), y[r]);
-    }
+    for (int h = kRootPad / 2; h >= 1; h >>= 1) k += px[k + h] <= x ? h : 0;
+    if (k >= npts - 1) return py[npts - 1];
+    const float y0 = py[k], y1 = py[k + 1];
+    return __builtin_amdgcn_fmed3f(fmaf(ps[k], x - px[k], y0), y0, y1);
+}
+
+__device__ __forceinline__ float lcdf_root_tab(const LcdfModel *m, float x) {
+    return lcdf_root_tab(m->px, m->py, m->ps, m->npts, x);
 }
 
 __device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
@@ -141,7 +156,7 @@ __device__ __forceinline__ int lcdf_leaf(const LcdfModel *m, float root) {
 // the key; each segment's value is clamped to its two knot ranks, so F is
 // monotone across segments even with rounding.
 __device__ __forceinline__ int lcdf_leaf_of(const LcdfModel *m, int64_t key) {
-    return lcdf_leaf(m, lcdf_root(m, lcdf_x(m, key)));
+    return lcdf_leaf(m, lcdf_root_tab(m, lcdf_x(m, key)));
 }
 
 // lo + (hi - lo) * u / 65535: non-decreasing in u, at least lo (the sum of lo
@@ -422,7 +437,8 @@ __global__ __launch_bounds__(kFitNT) void k_lcdf_fit(LcdfModel *mod, const float
 }
 
 // Effective root parameters from the best parameters seen (the starting ones
-// when no step was taken): w = 1 / width, c = 0.5 - centre * w, v = height.
+// when no step was taken): w = 1 / width, c = 0.5 - centre * w, v = height;
+// then the root's table, which routing uses.
 __global__ void k_lcdf_finalize(LcdfModel *mod) {
     const int j = threadIdx.x;
     const bool trained = mod->loss_best < INFINITY;
@@ -435,6 +451,56 @@ __global__ void k_lcdf_finalize(LcdfModel *mod) {
         mod->v[j] = expf(th[2 * kHidden + j]);
     }
     if (j == 0) mod->d = th[3 * kHidden];
+    __syncthreads();
+    if (j != 0) return;
+    // the root's table: breakpoints inside (0, 1), then 0 and 1, sorted and
+    // without repeats; values from the ramp sum, made non-decreasing
+    float pts[kRootPts];
+    int np = 0;
+    pts[np++] = 0.f;
+    pts[np++] = 1.f;
+    for (int q = 0; q < kHidden; q++) {
+        const float a = -mod->c[q] / mod->w[q], b = (1.f - mod->c[q]) / mod->w[q];
+        if (a > 0.f && a < 1.f) pts[np++] = a;
+        if (b > 0.f && b < 1.f) pts[np++] = b;
+    }
+    for (int i = 1; i < np; i++)                  // insertion sort (at most 66 points)
+        for (int t = i; t > 0 && pts[t - 1] > pts[t]; t--) {
+            const float u = pts[t];
+            pts[t] = pts[t - 1];
+            pts[t - 1] = u;
+        }
+    int n = 0;
+    for (int i = 0; i < np; i++)
+        if (n == 0 || pts[i] > mod->px[n - 1]) mod->px[n++] = pts[i];
+    for (int i = n; i < kRootPad; i++) mod->px[i] = INFINITY;
+    float ymax = -INFINITY;
+    for (int i = 0; i < n; i++) {
+        const float y = lcdf_root(mod, mod->px[i]);
+        ymax = y > ymax ? y : ymax;
+        mod->py[i] = ymax;
+    }
+    for (int i = 0; i + 1 < n; i++)
+        mod->ps[i] = (mod->py[i + 1] - mod->py[i]) / (mod->px[i + 1] - mod->px[i]);
+    mod->ps[n - 1] = 0.f;
+    mod->npts = n;
+}
+
+// lstart[l] = the first sorted sample point the root routes to leaf l or
+// later (lstart[nleaf] = m): the routing is monotone along the sorted
+// sample, so each point writes the starts of the leaves its step from the
+// previous point passes, and every entry is written once.
+__global__ __launch_bounds__(256) void k_leaf_starts(const LcdfModel *mod, const int64_t *sorted,
+                                                     int64_t m, int64_t *lstart) {
+    const int nl = mod->nleaf;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < m;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int l = lcdf_leaf_of(mod, sorted[i]);
+        const int p = i > 0 ? lcdf_leaf_of(mod, sorted[i - 1]) : -1;
+        for (int t = p + 1; t <= l; t++) lstart[t] = i;
+        if (i == m - 1)
+            for (int t = l + 1; t <= nl; t++) lstart[t] = m;
+    }
 }
 
 // The spline through knots (kx, kr) at a key, in float64: the rank of the
@@ -451,15 +517,14 @@ __device__ __forceinline__ double knot_spline(const int64_t *kx, const double *k
 }
 
 // One workgroup per leaf: the contiguous run of sorted sample points the root
-// routes to it, its longest run of one key (a heavy key when it repeats at
+// routes to it (from lstart), its longest run of one key (a heavy key when it repeats at
 // least kHeavyMin times), and the spline knots.  The knots start as the
 // leaf's first and last sample points and the heavy key's pair; each further
 // knot is the sample point where the spline so far misses the sample rank
 // the most (so knots land on the edges of dense clusters, where a straight
 // segment across a gap would put a whole cluster edge into one bucket).
 __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int64_t *sorted,
-                                                       int64_t m) {
-    __shared__ int64_t s_rng[2];
+                                                       int64_t m, const int64_t *lstart) {
     __shared__ int64_t s_run[256 / kWave][2];
     __shared__ int64_t s_kx[kKnots];
     __shared__ double s_kr[kKnots];
@@ -467,18 +532,7 @@ __global__ __launch_bounds__(256) void k_lcdf_leaf_fit(LcdfModel *mod, const int
     __shared__ double s_err[256 / kWave];
     __shared__ int64_t s_arg[256 / kWave];
     const int leaf = blockIdx.x, tid = threadIdx.x;
-    if (tid < 2) {
-        const int target = leaf + tid;                   // first point with leaf >= target
-        int64_t lo = 0, hi = m;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (lcdf_leaf(mod, lcdf_root(mod, lcdf_x(mod, sorted[mid]))) < target) lo = mid + 1;
-            else hi = mid;
-        }
-        s_rng[tid] = lo;
-    }
-    __syncthreads();
-    const int64_t a0 = s_rng[0], a1 = s_rng[1];
+    const int64_t a0 = lstart[leaf], a1 = lstart[leaf + 1];
     // longest run of equal keys: each run start finds its end by binary search
     int64_t best_len = 0, best_start = 0;
     for (int64_t i = a0 + tid; i < a1; i += blockDim.x) {
@@ -721,16 +775,26 @@ template <class K>
 __global__ __launch_bounds__(kBidNT) void k_bucket_ids_lds(const K *__restrict__ keys, int64_t n,
                                                            LearnedOrd<K> ord, int leaf0,
                                                            int32_t *__restrict__ ids) {
-    extern __shared__ int4 s_leaf[];
+    extern __shared__ int4 s_dyn[];
     constexpr int Q = int(sizeof(Leaf) / 16);
-    const int nl = ord.m->nleaf;
+    const LcdfModel *m = ord.m;
+    const int nl = m->nleaf;
     const int cnt = nl - leaf0 < kLdsLeafMax ? nl - leaf0 : kLdsLeafMax;
     if (cnt <= 0) return;
+    // the root's table, then the leaves of this pass
+    float *s_px = reinterpret_cast<float *>(s_dyn);
+    float *s_py = s_px + kRootPad, *s_ps = s_py + kRootPts;
+    int4 *s_leaf = s_dyn + kRootTabBytes / 16;
+    for (int i = threadIdx.x; i < kRootPad; i += kBidNT) s_px[i] = m->px[i];
+    for (int i = threadIdx.x; i < kRootPts; i += kBidNT) {
+        s_py[i] = m->py[i];
+        s_ps[i] = m->ps[i];
+    }
     const int4 *src = reinterpret_cast<const int4 *>(ord.leaves + leaf0);
     for (int i = threadIdx.x; i < cnt * Q; i += kBidNT) s_leaf[i] = src[i];
     __syncthreads();
     const Leaf *lds = reinterpret_cast<const Leaf *>(s_leaf);
-    const LcdfModel *m = ord.m;
+    const int npts = m->npts;
     constexpr int R = 4;
     const int64_t stride = int64_t(gridDim.x) * kBidNT * R;
     for (int64_t base = blockIdx.x * int64_t(kBidNT) * R + threadIdx.x; base < n; base += stride) {
@@ -740,17 +804,14 @@ __global__ __launch_bounds__(kBidNT) void k_bucket_ids_lds(const K *__restrict__
             const int64_t i = base + int64_t(r) * kBidNT;
             k[r] = i < n ? keys[i] : K(0);
         }
-        float x[R], y[R];
-#pragma unroll
-        for (int r = 0; r < R; r++) x[r] = lcdf_x(m, int64_t(k[r]));
-        lcdf_root_n<R>(m, x, y);
         // all R evaluations issued together (their LDS reads overlap), then
         // only the keys whose leaf is in this pass's group are written
         int li[R];
         float f[R];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            li[r] = lcdf_leaf(m, y[r]) - leaf0;
+            const float y = lcdf_root_tab(s_px, s_py, s_ps, npts, lcdf_x(m, int64_t(k[r])));
+            li[r] = lcdf_leaf(m, y) - leaf0;
             f[r] = lcdf_leaf_eval(lds[li[r] >= 0 && li[r] < cnt ? li[r] : 0], int64_t(k[r]));
         }
 #pragma unroll
@@ -778,7 +839,7 @@ static int launch_bucket_ids(const K *keys, int64_t n, const LearnedOrd<K> &ord,
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_error(TQP_EHIP, "bucket ids: model header: %s", hipGetErrorString(e));
     if (nl < 1 || nl > kLeafMax) return set_error(TQP_EINVAL, "bucket ids: the model has %d leaves", nl);
-    const size_t lds = size_t(kLdsLeafMax) * sizeof(Leaf);
+    const size_t lds = size_t(kRootTabBytes) + size_t(kLdsLeafMax) * sizeof(Leaf);
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_ids_lds<K>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess)
@@ -1169,6 +1230,7 @@ struct TrainLayout {
     void *rws;
     size_t rws_bytes;
     float *tx, *tq;
+    int64_t *lstart;                    // kLeafMax + 1 leaf starts
     size_t bytes;
 };
 
@@ -1182,6 +1244,7 @@ static TrainLayout train_layout(void *ws, int64_t m) {
     L.rws = c.take<char>(L.rws_bytes);
     L.tx = c.take<float>(kTrainPoints);
     L.tq = c.take<float>(kTrainPoints);
+    L.lstart = c.take<int64_t>(size_t(kLeafMax) + 1);
     L.bytes = c.bytes();
     return L;
 }
@@ -1452,8 +1515,14 @@ TQP_API int tqp_lcdf_train(const tqp_col *cols, int ncols, int sample_stride, in
         TQP_LAUNCH("lcdf_fit", k_lcdf_fit, dim3(1), dim3(kFitNT), 0, s, mod, L.tx, L.tq, T, steps, lr);
     if ((rc = check_launch("lcdf train"))) return rc;
     TQP_LAUNCH("lcdf_finalize", k_lcdf_finalize, dim3(1), dim3(64), 0, s, mod);
+    {
+        int64_t g = ceil_div(m, 256);
+        if (g > 4096) g = 4096;
+        TQP_LAUNCH("lcdf_leaf_starts", k_leaf_starts, dim3(unsigned(g)), dim3(256), 0, s, mod,
+                   L.sorted, m, L.lstart);
+    }
     TQP_LAUNCH("lcdf_leaf_fit", k_lcdf_leaf_fit, dim3(unsigned(nleaf)), dim3(256), 0, s, mod,
-               L.sorted, m);
+               L.sorted, m, L.lstart);
     TQP_LAUNCH("lcdf_leaf_fill", k_lcdf_leaf_fill, dim3(1), dim3(kFillNT), 0, s, mod);
     return check_launch("lcdf leaves");
 }

@@ -52,9 +52,9 @@ def test_model_is_monotone_and_trains(tqp, mix):
     assert np.all(np.diff(eb) >= 0) and eb.min() >= 0 and eb.max() < 65536
 
 
-@pytest.mark.parametrize("nleaf", [1, 1704, 1705, 3 * 1704 + 5])
+@pytest.mark.parametrize("nleaf", [1, 1688, 1689, 3 * 1688 + 5])
 def test_bucket_numbers_every_leaf_group(tqp, mix, nleaf):
-    """Bucket numbers are evaluated with the leaves in LDS, one group of 1704
+    """Bucket numbers are evaluated with the leaves in LDS, one group of 1688
     leaves per pass over the keys: every key gets its number in exactly one
     pass (a pre-filled output is overwritten everywhere), numbers do not
     decrease along sorted keys, and the partition sort is the stable sort."""
@@ -161,8 +161,8 @@ def test_full_size_learned_join_matches_oracle(tqp):
     from tqp_datagen import device as dgd
     c = dgd.config4(0, device="cuda")
     left, right = c["left"], c["right"]
-    # the benchmark's setting: 1704 leaves, 50 steps, 2^16 buckets
-    model = tqp.lcdf_train([left, right], sample_stride=100, nleaf=1704, steps=50)
+    # the benchmark's setting: 1688 leaves, 50 steps, 2^16 buckets
+    model = tqp.lcdf_train([left, right], sample_stride=100, nleaf=1688, steps=50)
     sides = []
     for keys in (left, right):
         sk, rows, st = tqp.partition_sort(keys, tqp.PART_LEARNED, model, bucket_bits=16)
