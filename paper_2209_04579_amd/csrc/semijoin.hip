@@ -28,6 +28,13 @@ constexpr int kSjMaxPay = 4;
 // Words of key sets staged in LDS per 256 threads of workgroup (36 KiB): a
 // 1024-thread workgroup, alone on its compute unit, stages up to 144 KiB.
 constexpr int kSjLdsWordsPer256 = 9216;
+// Kept rows of a tile staged in LDS (row ids and keys) so that the tile's
+// look-back and writes can wait until the next tile's loads are in flight;
+// a tile keeping more is written at once from registers instead.
+constexpr int kSjStage = 256;
+template <class K> constexpr int sj_stage_words(int ns) {
+    return 2 * kSjStage * (1 + ns * int(sizeof(K) / 4));     // two buffers, in 4-byte words
+}
 // Tiles are handed out in groups of kSjGroup consecutive tiles per XCD
 // counter (workgroup b draws from counter b % kSjXcds), so that no single
 // ticket address takes every workgroup's atomic.
@@ -55,12 +62,13 @@ struct SemiArgs {
     uint64_t *status;                // one look-back status per tile
 };
 
-// Rows per thread per tile: up to 16, fewer with more sets or wider keys, so
-// that one tile's keys take at most 192 bytes of registers per thread (two
-// tiles' keys are held at once).  Each step is one 16-byte load per set.
+// Rows per thread per tile: up to 16, fewer with more sets or wider keys
+// (three steps of 16-byte loads per set with three or four sets), so that a
+// tile's keys and the staging of the previous tile's kept rows fit the
+// registers.  Each step is one 16-byte load per set.
 template <class K, int NS> struct SjShape {
     static constexpr int V = 16 / int(sizeof(K));     // keys per 16-byte load
-    static constexpr int Steps = (16 / V) < (12 / NS) ? (16 / V) : (12 / NS);
+    static constexpr int Steps = (16 / V) < (NS >= 3 ? 3 : 12 / NS) ? (16 / V) : (NS >= 3 ? 3 : 12 / NS);
     static constexpr int R = V * Steps;               // rows per thread per tile
 };
 // the smallest tile of any set count and workgroup size (sizes the
@@ -81,6 +89,29 @@ __device__ __forceinline__ int64_t sj_tile_of(int64_t ticket, int xcd) {
     return ((ticket / kSjGroup) * kSjXcds + xcd) * kSjGroup + ticket % kSjGroup;
 }
 
+// Writes a staged tile's kept rows (row ids, keys, then the payload read
+// through the row ids) to their slots from base, consecutive threads taking
+// consecutive slots.  The staging writes and the prefix in LDS must be
+// visible: callers come here after a barrier that follows both.
+template <class K, int NS, int NT>
+__device__ __forceinline__ void sj_write_staged(const SemiArgs &a, const int32_t *srow,
+                                                int64_t base, int cnt, bool last_tile) {
+    const K *skey = reinterpret_cast<const K *>(srow + kSjStage);
+    if (last_tile && threadIdx.x == 0) *a.d_count = base + cnt;
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+        const int32_t row = srow[i];
+        if (a.out_rows) a.out_rows[base + i] = row;
+#pragma unroll
+        for (int s = 0; s < NS; s++)
+            if (a.key_out[s]) static_cast<K *>(a.key_out[s])[base + i] = skey[s * kSjStage + i];
+#pragma unroll 1
+        for (int c = 0; c < a.npay; c++) {
+            const int lg = a.paylg[c];
+            sj_store(a.pout[c], lg, base + i, from_word(word_of(a.pin[c], lg, row), a.pin[c], lg, row));
+        }
+    }
+}
+
 // NT threads per workgroup; a tile is NT * R rows.  Larger workgroups take
 // larger tiles, so the per-tile ticket, scan and look-back are paid over
 // more rows.
@@ -94,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
     constexpr int NW = S::Steps > 4 ? 2 : 1;       // words of packed step counts
     static_assert(R <= 32, "keep bits of a thread fit one word");
     __shared__ int64_t s_tile;
-    __shared__ int64_t s_prefix;
+    __shared__ int64_t s_prefix, s_pprefix;
     __shared__ uint64_t s_scan[NT / kWave];
     extern __shared__ uint32_t s_sets[];
 
@@ -112,15 +143,20 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
         for (int i = tid; i < a.lds_len[s]; i += NT) dst[i] = a.bits[s][i];
     }
     __syncthreads();
+    // the kept rows waiting to be written, after the sets: two buffers, each
+    // row ids then each set's keys.  A tile stages into one while the
+    // previous tile's rows are written from the other.
+    int32_t *s_stage = reinterpret_cast<int32_t *>(s_sets + ((a.lds_words + 3) & ~3));
+    const int stage_half = sj_stage_words<K>(NS) / 2;
+    int64_t pend_tile = -1;              // the tile whose kept rows wait in LDS
+    int pend_total = 0, pb = 0;
     // A tile's ticket is drawn only when the workgroup is ready to work on
     // it: every tile handed out is in progress, so the look-backs of later
     // tiles never wait on a tile that is merely reserved.
     for (;;) {
         const int64_t tile = sj_tile_of(take_tile(a.ticket + xcd, &s_tile), xcd);
-        if (tile >= ntiles) {
-            if (tile == 0 && tid == 0) *a.d_count = 0;    // empty input
-            break;
-        }
+        const bool last = tile >= ntiles;
+        if (last && tile == 0 && tid == 0) *a.d_count = 0;    // empty input
         const int64_t row0 = tile * Tile;
         // item r = k * V + jj of this thread is row trow + k * Step + jj
         const int64_t trow = row0 + int64_t(tid) * V;
@@ -158,6 +194,21 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
 #pragma unroll
             for (int r = 0; r < R; r++)
                 if (trow + (r / V) * Step + (r % V) < n) alive |= 1u << r;
+        }
+        // the previous tile's look-back while these loads are in flight (its
+        // predecessors have long posted their counts); its rows are written
+        // at the end of this tile, once this tile's keys are no longer held
+        if (pend_tile >= 0 && wave_id() == 0) {
+            const int64_t pre = lookback_resolve(a.status, pend_tile, pend_total);
+            if (lane_id() == 0) s_pprefix = pre;
+        }
+        if (last) {
+            if (pend_tile >= 0) {
+                __syncthreads();
+                sj_write_staged<K, NS, NT>(a, s_stage + pb * stage_half, s_pprefix, pend_total,
+                                           pend_tile == ntiles - 1);
+            }
+            break;
         }
         // sets in LDS: every row tested (LDS reads are cheap)
 #pragma unroll
@@ -221,53 +272,78 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
             first[k] = total + int((excl[k / 4] >> (16 * (k % 4))) & 0xffff);
             total += int((tot[k / 4] >> (16 * (k % 4))) & 0xffff);
         }
-        if (wave_id() == 0) {
-            const int64_t pre = lookback_count(a.status, tile, total);
-            if (lane_id() == 0) s_prefix = pre;
-        }
-        __syncthreads();
-        const int64_t base = s_prefix;
-        if (tile == ntiles - 1 && tid == 0) *a.d_count = base + total;
-        if (!alive) continue;
-
-        // Outputs go straight from registers: kept rows are written in slot
-        // order, so each column's writes of a tile cover one contiguous run
-        // (the L2 merges them into whole lines).
+        if (wave_id() == 0) lookback_publish(a.status, tile, total);
+        const bool stage = total <= kSjStage;
+        const int cb = pend_tile >= 0 ? pb ^ 1 : pb;
+        if (stage) {
+            // stage the kept rows in slot order; written during the next tile
+            int32_t *srow = s_stage + cb * stage_half;
+            K *skey = reinterpret_cast<K *>(srow + kSjStage);
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int k = r / V, jj = r % V;
-            const uint32_t mk = (alive >> (k * V)) & ((1u << V) - 1u);
-            if (!((mk >> jj) & 1u)) continue;
-            const int64_t slot = base + first[k] + __popc(mk & ((1u << jj) - 1u));
-            if (a.out_rows) a.out_rows[slot] = int32_t(trow + k * Step + jj);
+            for (int r = 0; r < R; r++) {
+                const int k = r / V, jj = r % V;
+                const uint32_t mk = (alive >> (k * V)) & ((1u << V) - 1u);
+                if (!((mk >> jj) & 1u)) continue;
+                const int local = first[k] + __popc(mk & ((1u << jj) - 1u));
+                srow[local] = int32_t(trow + k * Step + jj);
 #pragma unroll
-            for (int s = 0; s < NS; s++)
-                if (a.key_out[s]) static_cast<K *>(a.key_out[s])[slot] = v[s][r];
-        }
-        // payload: only kept rows are read, four loads in flight at a time
-        for (int c = 0; c < a.npay; c++) {
-            const int lg = a.paylg[c];
-            const void *src = a.pin[c];
+                for (int s = 0; s < NS; s++) skey[s * kSjStage + local] = v[s][r];
+            }
+        } else {
+            // too many kept rows to stage: this tile's prefix now, its rows
+            // straight from registers (each column's writes of a tile cover
+            // one contiguous run, which the L2 merges into whole lines)
+            if (wave_id() == 0) {
+                const int64_t pre = lookback_resolve(a.status, tile, total);
+                if (lane_id() == 0) s_prefix = pre;
+            }
+            __syncthreads();
+            const int64_t base = s_prefix;
+            if (tile == ntiles - 1 && tid == 0) *a.d_count = base + total;
 #pragma unroll
-            for (int r0 = 0; r0 < R; r0 += 4) {
-                uint64_t val[4];
+            for (int r = 0; r < R; r++) {
+                const int k = r / V, jj = r % V;
+                const uint32_t mk = (alive >> (k * V)) & ((1u << V) - 1u);
+                if (!((mk >> jj) & 1u)) continue;
+                const int64_t slot = base + first[k] + __popc(mk & ((1u << jj) - 1u));
+                if (a.out_rows) a.out_rows[slot] = int32_t(trow + k * Step + jj);
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int r = r0 + q;
-                    const int64_t row = trow + (r / V) * Step + (r % V);
-                    val[q] = ((alive >> r) & 1u) ? word_of(src, lg, row) : 0;
-                }
+                for (int s = 0; s < NS; s++)
+                    if (a.key_out[s]) static_cast<K *>(a.key_out[s])[slot] = v[s][r];
+            }
+            // payload: only kept rows are read, four loads in flight at a time
+            for (int c = 0; c < a.npay; c++) {
+                const int lg = a.paylg[c];
+                const void *src = a.pin[c];
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int r = r0 + q, k = r / V, jj = r % V;
-                    if (!((alive >> r) & 1u)) continue;
-                    const uint32_t mk = (alive >> (k * V)) & ((1u << V) - 1u);
-                    const int64_t row = trow + k * Step + jj;
-                    const int64_t slot = base + first[k] + __popc(mk & ((1u << jj) - 1u));
-                    sj_store(a.pout[c], lg, slot, from_word(val[q], src, lg, row));
+                for (int r0 = 0; r0 < R; r0 += 4) {
+                    uint64_t val[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int r = r0 + q;
+                        const int64_t row = trow + (r / V) * Step + (r % V);
+                        val[q] = ((alive >> r) & 1u) ? word_of(src, lg, row) : 0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int r = r0 + q, k = r / V, jj = r % V;
+                        if (!((alive >> r) & 1u)) continue;
+                        const uint32_t mk = (alive >> (k * V)) & ((1u << V) - 1u);
+                        const int64_t row = trow + k * Step + jj;
+                        const int64_t slot = base + first[k] + __popc(mk & ((1u << jj) - 1u));
+                        sj_store(a.pout[c], lg, slot, from_word(val[q], src, lg, row));
+                    }
                 }
             }
         }
+        // the previous tile's rows, now that this tile's keys are no longer
+        // needed (its prefix was posted before this tile's block scan)
+        if (pend_tile >= 0)
+            sj_write_staged<K, NS, NT>(a, s_stage + pb * stage_half, s_pprefix, pend_total,
+                                       pend_tile == ntiles - 1);
+        pend_tile = stage ? tile : -1;
+        pend_total = total;
+        pb = cb;
     }
 }
 
@@ -323,12 +399,13 @@ static int launch_semijoin_nt(int ns, unsigned grid, size_t lds, hipStream_t s, 
 }
 
 // The workgroup size in units of kSjNT threads (1, 2 or 4) from the
-// "semijoin.wg" knob.  8-byte keys of one or two sets take 16 rows per
-// thread, more registers than a 1024-thread workgroup allows, so they stop
-// at 512.
+// "semijoin.wg" knob.  A 1024-thread workgroup allows 128 registers per
+// thread; only three 4-byte key sets and three or four 8-byte ones (12 and
+// 6 rows per thread) fit it without spilling, the other shapes stop at 512.
 static int sj_wg(int dtype, int ns) {
     const int wg = tune(kTuneSemiWg);
-    if (wg >= 4) return (dtype == TQP_INT64 && ns <= 2) ? 2 : 4;
+    const bool fits = dtype == TQP_INT32 ? ns == 3 : ns >= 3;
+    if (wg >= 4) return fits ? 4 : 2;
     return wg >= 2 ? 2 : 1;
 }
 
@@ -454,7 +531,10 @@ static int semijoin_run(const char *who, const tqp_col *keys, const tqp_keyset *
     // workgroups per CU count 256-thread units: a 1024-thread workgroup takes four
     const int per_cu = tune(kTuneSemiPerCu) / wg > 0 ? tune(kTuneSemiPerCu) / wg : 1;
     const unsigned grid = persistent_grid(ntiles, per_cu);
-    const size_t lds = size_t(lds_words) * 4;
+    // the sets, then (16-byte aligned) the staging of kept rows
+    const int stage_words = dt == TQP_INT32 ? sj_stage_words<int32_t>(nsets)
+                                            : sj_stage_words<int64_t>(nsets);
+    const size_t lds = size_t(((lds_words + 3) & ~3) + stage_words) * 4;
     rc = dt == TQP_INT32 ? launch_semijoin<int32_t>(nsets, wg, grid, lds, s, a)
                          : launch_semijoin<int64_t>(nsets, wg, grid, lds, s, a);
     if (rc) return rc;

@@ -269,6 +269,41 @@ __device__ __forceinline__ int64_t lookback_count(uint64_t *status, int64_t tile
     return excl;
 }
 
+// The same look-back in two halves, for a tile whose prefix is wanted later
+// than its count is known: lookback_publish posts the tile's aggregate (the
+// inclusive prefix for tile 0) as soon as it is counted; lookback_resolve,
+// called later by one whole wave, walks back to the exclusive prefix and
+// posts the inclusive one.  A successor only ever needs aggregates, which
+// are posted before any wait, so deferring the resolution cannot deadlock.
+__device__ __forceinline__ void lookback_publish(uint64_t *status, int64_t tile, int64_t agg) {
+    if (lane_id() == 0) st_relaxed(&status[tile], (tile == 0 ? kFlagInc : kFlagAgg) | uint64_t(agg));
+}
+
+__device__ __forceinline__ int64_t lookback_resolve(uint64_t *status, int64_t tile, int64_t agg) {
+    if (tile == 0) return 0;
+    int64_t excl = 0;
+    int64_t base = tile - 1;
+    while (true) {
+        const int64_t idx = base - lane_id();
+        uint64_t s = kFlagInc;
+        if (idx >= 0) {
+            s = ld_relaxed(&status[idx]);
+            while ((s >> 62) == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                s = ld_relaxed(&status[idx]);
+            }
+        }
+        const uint64_t inc = ballot((s >> 62) == 2);
+        const int stop = inc ? (__ffsll(static_cast<long long>(inc)) - 1) : (kWave - 1);
+        int64_t v = lane_id() <= stop ? int64_t(s & kValMask) : 0;
+        excl += wave_sum(v);
+        if (inc) break;
+        base -= kWave;
+    }
+    if (lane_id() == 0) st_relaxed(&status[tile], kFlagInc | uint64_t(excl + agg));
+    return excl;
+}
+
 // ---- key/value element access ------------------------------------------------
 
 template <class T> struct KeyTraits;
