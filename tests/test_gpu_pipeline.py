@@ -162,6 +162,27 @@ def test_q3_replay_is_identical(plan):
             assert np.array_equal(again[k], first[k])
 
 
+@pytest.mark.parametrize("plan", PLANS3)
+def test_q3_graph_replays_match_eager(plan):
+    """The whole star query captured through the library into one HIP graph:
+    every replay gives the eager run's (and the oracle's) groups, with eager
+    work and synchronizations between the replays and the outputs cleared
+    first, so each replay recomputes them."""
+    import paper_2209_04579_amd as tqp
+    cfg = dg.config3(6, n_fact=1_500_000, dims=(60_000, 6_000, 25))
+    q, first = check_q3(cfg, plan=plan)
+    g = tqp.batch_capture(q.run)
+    for i in range(3):
+        for t in q.g_out:
+            t.zero_()
+        g.run()
+        again = q.result()
+        for k in ("key", "sum_qp", "count"):
+            assert np.array_equal(again[k], first[k]), (i, k)
+        q.run()                                  # eager work between replays
+        torch.cuda.synchronize()
+
+
 @pytest.mark.timeout(400)
 def test_q3_full_size():
     """The 600M-row three-dimension star at full size, both plans: tables
