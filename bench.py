@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--only", choices=("star600m", "star60m", "learned", "batch"), default=None,
+    ap.add_argument("--only", choices=("star600m", "star60m", "learned", "batch", "configs"),
+                    default=None,
                     help="run one workload only (for counter profiles and quick checks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000,
@@ -516,6 +517,7 @@ def bench_configs(args, tqp, stream) -> dict:
     Q14-shaped join (60M items, 2M parts) and the prediction query (20M
     reviews).  Their results are checked against the oracle by the test suite
     (full-size cases included), not here."""
+    import numpy as np
     import torch
     import tqp_datagen as dg
     from tqp_datagen import device as dgd
@@ -525,8 +527,14 @@ def bench_configs(args, tqp, stream) -> dict:
     c1 = dg.config1(args.seed)
     q = StarQuery({k: torch.from_numpy(v).cuda() for k, v in c1["fact"].items()},
                   {k: torch.from_numpy(v).cuda() for k, v in c1["dim"].items()}, c1["day_cut"])
-    ms = _timed(q.run, 20, stream)
+    eager_ms = _timed(q.run, 20, stream)
     got = q.result()
+    # launch-bound: the whole query as one graph replay (library capture)
+    graph = tqp.batch_capture(q.run)
+    ms = _timed(graph.run, 20, stream)
+    again = q.result()
+    graph_ok = all(np.array_equal(again[k], got[k]) for k in ("key", "sum_qty", "count"))
+    del graph
     st = {"n": 1_000_000, "nd": 10_000, "kept": got["rows_filtered"], "pairs": got["pairs"],
           "groups_b": 0, "passes": _passes(q.jk_bits), "uniq_l": 10_000, "uniq_r": 10_000,
           "pay": 12, "gbv": 4 + 4 + 4 + 8}
@@ -534,6 +542,9 @@ def bench_configs(args, tqp, stream) -> dict:
     out["small_star"] = {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat "
                                      "(16 MB of input: cache-resident, launch-bound)",
                          "ms": round(ms, 4), "rows_per_s": round(1_000_000 / (ms * 1e-3), 1),
+                         "eager_ms": round(eager_ms, 4),
+                         "step": "one replay of the query captured as a HIP graph",
+                         "graph_results_match_eager": bool(graph_ok),
                          "groups": int(len(got["key"])),
                          "roofline": roofline_of(kernels, star_kernel_bytes, st, None,
                                                  "20 steps with per-kernel HIP events"),
@@ -910,6 +921,9 @@ def main():
     if args.only in ("learned", "batch"):
         fn = bench_learned if args.only == "learned" else bench_batch
         print(json.dumps({args.only: fn(args, tqp, stream)}), flush=True)
+        return
+    if args.only == "configs":
+        print(json.dumps(bench_configs(args, tqp, stream)), flush=True)
         return
     head = bench_star3(args, tqp, stream, copy_gbs)
     ms = head["ms"]
