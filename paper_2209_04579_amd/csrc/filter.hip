@@ -2,10 +2,12 @@
 //
 // Each workgroup takes a 4096-row tile (256 threads x 16 consecutive rows),
 // evaluates the predicate conjunction with wide vector loads, counts its kept
-// rows with a block scan, gets the tile's output offset from a decoupled
-// look-back over the tiles before it, and writes the kept row ids and the
-// payload columns at those offsets.  Every input byte is read once; output is
-// written once; the order of kept rows is ascending row id.
+// rows with a block scan and stages their row ids in LDS in ascending order.
+// The tile's output offset comes from a decoupled look-back over the tiles
+// before it, resolved while the workgroup's next tile is loading; the staged
+// row ids, and the payload columns read through them, are written at that
+// offset by consecutive threads.  Every predicate byte is read once, payload
+// only for kept rows; output is written once, in ascending row id order.
 #include "tqp_internal.hpp"
 
 namespace tqp {
@@ -109,99 +111,193 @@ __device__ __forceinline__ void load8(const void *p, int dt, int64_t row0, int64
     }
 }
 
+// Element v (zero-extended) of a column of element size 1 << lg, stored at i.
+__device__ __forceinline__ void store_lg(void *out, int lg, int64_t i, uint64_t v) {
+    if (lg == 0) static_cast<uint8_t *>(out)[i] = uint8_t(v);
+    else if (lg == 2) static_cast<uint32_t *>(out)[i] = uint32_t(v);
+    else static_cast<uint64_t *>(out)[i] = v;
+}
+
+// Writes a staged tile's kept rows from slot base on: the row ids, then
+// every payload column read through them, consecutive threads taking
+// consecutive slots (so the writes are coalesced, and so are the payload
+// reads where the kept rows are dense).  Each thread takes kWriteU slots per
+// pass with every column's loads issued before the first store, so a dense
+// tile costs few memory round trips.  The staging writes and the prefix in
+// LDS must be visible: callers come here after a barrier that follows both.
+constexpr int kWriteU = 2;
+__device__ __forceinline__ void filter_write_staged(const FilterArgs &a, const int32_t *srow,
+                                                    int64_t base, int cnt, bool last_tile) {
+    if (last_tile && threadIdx.x == 0) *a.d_count = base + cnt;
+    int lg[kMaxPay];
+#pragma unroll
+    for (int c = 0; c < kMaxPay; c++) lg[c] = c < a.npay ? dtype_lg(a.paydt[c]) : 0;
+    for (int i0 = threadIdx.x; i0 < cnt; i0 += kWriteU * kFilterNT) {
+        int32_t row[kWriteU];
+#pragma unroll
+        for (int u = 0; u < kWriteU; u++) {
+            const int i = i0 + u * kFilterNT;
+            row[u] = i < cnt ? srow[i] : -1;
+        }
+        uint64_t w[kWriteU][kMaxPay];
+#pragma unroll
+        for (int c = 0; c < kMaxPay; c++)
+#pragma unroll
+            for (int u = 0; u < kWriteU; u++)
+                if (c < a.npay && row[u] >= 0) w[u][c] = word_of(a.pin[c], lg[c], row[u]);
+#pragma unroll
+        for (int u = 0; u < kWriteU; u++) {
+            if (row[u] < 0) continue;
+            const int64_t slot = base + i0 + u * kFilterNT;
+            if (a.out_rows) a.out_rows[slot] = row[u];
+#pragma unroll
+            for (int c = 0; c < kMaxPay; c++)
+                if (c < a.npay) store_lg(a.pout[c], lg[c], slot, from_word(w[u][c], a.pin[c], lg[c], row[u]));
+        }
+    }
+}
+
+// A tile keeping at most this many rows defers its look-back and writes
+// (its row ids wait in LDS); a denser one resolves its offset at once and
+// writes each column from LDS, where a column's values are staged straight
+// from its vector loads.
+constexpr int kFilterDefer = 1024;
+
 __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
     __shared__ int64_t s_tile;
-    __shared__ int64_t s_prefix;
+    __shared__ int64_t s_prefix, s_pprefix;
     __shared__ int32_t s_scan[kFilterNT / kWave];
+    // Two buffers of a tile's kept row ids (ascending): one filled by the
+    // current tile while the previous tile's rows are written from the
+    // other.  A dense tile uses the whole array for one column at a time.
     __shared__ int64_t s_stage[kFilterTile];
+    int32_t *const s_rows = reinterpret_cast<int32_t *>(s_stage);
 
     const int64_t n = a.n;
     const int64_t ntiles = ceil_div(n, kFilterTile);
     const bool vec = a.vec != 0;
-    // Persistent workgroups: each takes tiles in ticket order until none are left.
+    int64_t pend_tile = -1;      // the tile whose kept rows wait in LDS
+    int pend_total = 0, pb = 0;
+    // Persistent workgroups: each takes tiles in ticket order until none are
+    // left.  A sparse tile publishes its count as soon as it is known; its
+    // prefix is resolved while the workgroup's next tile is being loaded, and
+    // its rows are written after that tile's scan.
     for (;;) {
-    const int64_t tile = take_tile(a.ticket, &s_tile);
-    if (tile >= ntiles) {
-        if (tile == 0 && threadIdx.x == 0) *a.d_count = 0;   // empty input
-        break;
-    }
-    const int64_t row0 = tile * kFilterTile + int64_t(threadIdx.x) * kFilterIPT;
-
-    uint32_t mask = 0;
-#pragma unroll
-    for (int r = 0; r < 16; r++)
-        if (row0 + r < n) mask |= 1u << r;
-
-    int64_t v[16];
-    int loaded = -1;
-    for (int p = 0; p < a.npred; p++) {
-        if (a.pcolid[p] != loaded) {
-            load16(a.pcol[p], a.pdt[p], row0, n, vec, v);
-            loaded = a.pcolid[p];
+        const int64_t tile = take_tile(a.ticket, &s_tile);
+        const bool last = tile >= ntiles;
+        if (last && tile == 0 && threadIdx.x == 0) *a.d_count = 0;   // empty input
+        const int64_t row0 = tile * kFilterTile + int64_t(threadIdx.x) * kFilterIPT;
+        int64_t v[16];
+        if (!last) load16(a.pcol[0], a.pdt[0], row0, n, vec, v);
+        if (pend_tile >= 0 && wave_id() == 0) {
+            const int64_t pre = lookback_resolve(a.status, pend_tile, pend_total);
+            if (lane_id() == 0) s_pprefix = pre;
         }
-        const int op = a.pop[p];
-        const int64_t lit = a.plit[p];
-        uint32_t m = 0;
-#pragma unroll
-        for (int r = 0; r < 16; r++)
-            if (cmp_holds(v[r], op, lit)) m |= 1u << r;
-        mask &= m;
-    }
-
-    int32_t total;
-    const int32_t excl = block_excl_scan<kFilterNT>(int32_t(__popc(mask)), &total, s_scan);
-    if (wave_id() == 0) {
-        int64_t pre = lookback_count(a.status, tile, total);
-        if (lane_id() == 0) s_prefix = pre;
-    }
-    __syncthreads();
-    const int64_t base = s_prefix;
-    if (tile == ntiles - 1 && threadIdx.x == 0) *a.d_count = s_prefix + total;
-
-    // Each output column goes through LDS in kept order, then out with
-    // consecutive threads on consecutive addresses.
-    if (a.out_rows) {
-        int32_t *st = reinterpret_cast<int32_t *>(s_stage);
-        int q = excl;
-#pragma unroll
-        for (int r = 0; r < 16; r++)
-            if (mask & (1u << r)) st[q++] = static_cast<int32_t>(row0 + r);
-        __syncthreads();
-        for (int i = threadIdx.x; i < total; i += kFilterNT) a.out_rows[base + i] = st[i];
-        __syncthreads();
-    }
-    for (int c = 0; c < a.npay; c++) {
-        const int dt = a.paydt[c];
-        if (mask) load16(a.pin[c], dt, row0, n, vec, v);
-        int q = excl;
-        if (dt == TQP_INT8) {
-            int8_t *st = reinterpret_cast<int8_t *>(s_stage);
+        uint32_t mask = 0;
+        int32_t total = 0, excl = 0;
+        bool defer = true;
+        int cb = pb;
+        if (!last) {       // (uniform across the workgroup)
 #pragma unroll
             for (int r = 0; r < 16; r++)
-                if (mask & (1u << r)) st[q++] = static_cast<int8_t>(v[r]);
-            __syncthreads();
-            int8_t *out = static_cast<int8_t *>(a.pout[c]);
-            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
-        } else if (dt == TQP_INT32) {
-            int32_t *st = reinterpret_cast<int32_t *>(s_stage);
+                if (row0 + r < n) mask |= 1u << r;
+            int loaded = a.pcolid[0];
+            for (int p = 0; p < a.npred; p++) {
+                if (a.pcolid[p] != loaded) {
+                    load16(a.pcol[p], a.pdt[p], row0, n, vec, v);
+                    loaded = a.pcolid[p];
+                }
+                const int op = a.pop[p];
+                const int64_t lit = a.plit[p];
+                uint32_t m = 0;
 #pragma unroll
-            for (int r = 0; r < 16; r++)
-                if (mask & (1u << r)) st[q++] = static_cast<int32_t>(v[r]);
-            __syncthreads();
-            int32_t *out = static_cast<int32_t *>(a.pout[c]);
-            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+                for (int r = 0; r < 16; r++)
+                    if (cmp_holds(v[r], op, lit)) m |= 1u << r;
+                mask &= m;
+            }
+            excl = block_excl_scan<kFilterNT>(int32_t(__popc(mask)), &total, s_scan);
+            defer = total <= kFilterDefer;
+            if (defer) {
+                if (wave_id() == 0) lookback_publish(a.status, tile, total);
+                cb = pend_tile >= 0 ? pb ^ 1 : pb;
+                int32_t *st = s_rows + cb * kFilterTile;
+                int q = excl;
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (mask & (1u << r)) st[q++] = static_cast<int32_t>(row0 + r);
+            } else if (wave_id() == 0) {
+                // dense tile: its offset now
+                const int64_t pre = lookback_count(a.status, tile, total);
+                if (lane_id() == 0) s_prefix = pre;
+            }
         } else {
-            int64_t *st = reinterpret_cast<int64_t *>(s_stage);
+            __syncthreads();     // s_pprefix
+        }
+        if (pend_tile >= 0)
+            filter_write_staged(a, s_rows + pb * kFilterTile, s_pprefix, pend_total,
+                                pend_tile == ntiles - 1);
+        if (last) break;
+        if (defer) {
+            pend_tile = tile;
+            pend_total = total;
+            pb = cb;
+            continue;
+        }
+
+        // dense tile, with the pending tile's rows out: every column through LDS
+        pend_tile = -1;
+        __syncthreads();
+        const int64_t base = s_prefix;
+        if (tile == ntiles - 1 && threadIdx.x == 0) *a.d_count = base + total;
+        // each output column goes through LDS in kept order, then out with
+        // consecutive threads on consecutive addresses
+        if (a.out_rows) {
+            int q = excl;
 #pragma unroll
             for (int r = 0; r < 16; r++)
-                if (mask & (1u << r)) st[q++] = v[r];
+                if (mask & (1u << r)) s_rows[q++] = static_cast<int32_t>(row0 + r);
             __syncthreads();
-            int64_t *out = static_cast<int64_t *>(a.pout[c]);
-            for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+            for (int i = threadIdx.x; i < total; i += kFilterNT) a.out_rows[base + i] = s_rows[i];
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    __syncthreads();
+        for (int c = 0; c < a.npay; c++) {
+            const int dt = a.paydt[c];
+            // only threads with kept rows read the column (v is overwritten
+            // either way, so the predicate values are dead by now)
+            if (mask) {
+                load16(a.pin[c], dt, row0, n, vec, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; r++) v[r] = 0;
+            }
+            int q = excl;
+            if (dt == TQP_INT8) {
+                int8_t *st = reinterpret_cast<int8_t *>(s_stage);
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (mask & (1u << r)) st[q++] = static_cast<int8_t>(v[r]);
+                __syncthreads();
+                int8_t *out = static_cast<int8_t *>(a.pout[c]);
+                for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+            } else if (dt == TQP_INT32) {
+                int32_t *st = reinterpret_cast<int32_t *>(s_stage);
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (mask & (1u << r)) st[q++] = static_cast<int32_t>(v[r]);
+                __syncthreads();
+                int32_t *out = static_cast<int32_t *>(a.pout[c]);
+                for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+            } else {
+                int64_t *st = s_stage;
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    if (mask & (1u << r)) st[q++] = v[r];
+                __syncthreads();
+                int64_t *out = static_cast<int64_t *>(a.pout[c]);
+                for (int i = threadIdx.x; i < total; i += kFilterNT) out[base + i] = st[i];
+            }
+            __syncthreads();
+        }
     }
 }
 

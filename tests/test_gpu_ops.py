@@ -70,6 +70,32 @@ def test_filter_all_none_and_extremes(tqp):
     assert np.array_equal(host(rows), oracle.filter_rows([y], [(0, "<", I64.max)]))
 
 
+@pytest.mark.parametrize("seed,offset", [(0, 0), (1, 0), (2, 1)])
+def test_filter_runs_of_mixed_density_with_payload(tqp, seed, offset):
+    """Runs of rows whose kept share swings between none, a few and all, at
+    run lengths aligned with nothing, so sparse and dense stretches follow
+    each other in every pattern; payload columns of every dtype, 16-byte
+    aligned or not (offset 1 starts each column one element in)."""
+    n = 1_500_000 + 9_871 * seed
+    lens = dg.uniform_int(seed, 1, 4000, 1, 20_000, np.int64)
+    ends = np.minimum(np.cumsum(lens), n)
+    share = np.array([0, 1, 20, 250, 600, 999, 1000], np.int64)
+    pick = dg.uniform_int(seed, 2, len(ends), 0, len(share), np.int64)
+    per_row = share[pick][np.searchsorted(ends, np.arange(n), side="right").clip(0, len(ends) - 1)]
+    u = dg.uniform_int(seed, 3, n, 0, 1000, np.int64)
+    flag = (u >= per_row).astype(np.int8)          # 0 where the row is kept
+    pays = [dg.uniform_int(seed, 4, n + offset, -128, 128, np.int8),
+            dg.uniform_int(seed, 5, n + offset, I32.min, I32.max, np.int32),
+            (dg.uniform_int(seed, 6, n + offset, -2 ** 31, 2 ** 31, np.int64) << 32)
+            + dg.uniform_int(seed, 7, n + offset, 0, 2 ** 32, np.int64)]
+    dpays = [dev(p)[offset:] for p in pays]
+    rows, got = tqp.filter([dev(flag)], [(0, "==", 0)], payload=dpays)
+    want = oracle.filter_rows([flag], [(0, "==", 0)])
+    assert np.array_equal(host(rows), want)
+    for p, g in zip(pays, got):
+        assert np.array_equal(host(g), oracle.gather(p[offset:], want))
+
+
 def test_filter_is_deterministic_across_runs(tqp):
     n = 3_000_000
     day = dev(dg.uniform_int(11, 3, n, 0, dg.DAY_DOMAIN, np.int32))
