@@ -71,27 +71,35 @@ int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s) {
     return check_launch("fill_u32");
 }
 
-// Clears nsec sections of words: section k starts at p + k * stride and is
-// cleared over its first ceil(count / per) * width words, count =
-// min(*d_n, n).  Lets a call planned for capacity n clear only what its
-// actual count will touch.
-__global__ void k_clear_sections(uint32_t *p, int nsec, int64_t stride, const int64_t *d_n,
-                                 int64_t n, int64_t per, int64_t width) {
+// Clears the head words before p, then nsec sections of words: section k
+// starts at p + k * stride and is cleared over its first ceil(count / per) *
+// width words, count = min(*d_n, n).  Lets a call planned for capacity n
+// clear only what its actual count will touch, together with the counters
+// in front of the sections, in one launch.
+__global__ void k_clear_sections(uint32_t *p, int64_t head, int nsec, int64_t stride,
+                                 const int64_t *d_n, int64_t n, int64_t per, int64_t width) {
     const int64_t cnt = count_of(d_n, n);
     int64_t need = ceil_div(cnt > 0 ? cnt : 1, per) * width;
     if (need > stride) need = stride;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < need * nsec;
-         i += int64_t(gridDim.x) * blockDim.x)
-        p[(i / need) * stride + i % need] = 0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < head + need * nsec;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        if (i < head) {
+            p[i - head] = 0;
+        } else {
+            const int64_t j = i - head;
+            p[(j / need) * stride + j % need] = 0;
+        }
+    }
 }
 
-int clear_sections(uint32_t *dst, int nsec, int64_t stride, const int64_t *d_n, int64_t n,
-                   int64_t per, int64_t width, hipStream_t s) {
-    if (nsec <= 0 || stride <= 0) return TQP_OK;
-    int64_t blocks = ceil_div(int64_t(nsec) * stride, 256);
+int clear_sections(uint32_t *dst, int64_t head, int nsec, int64_t stride, const int64_t *d_n,
+                   int64_t n, int64_t per, int64_t width, hipStream_t s) {
+    if (head < 0) head = 0;
+    if (nsec <= 0 || stride <= 0) return fill_u32(dst - head, 0, head, s);
+    int64_t blocks = ceil_div(head + int64_t(nsec) * stride, 256);
     if (blocks > 2048) blocks = 2048;
     TQP_LAUNCH("clear_sections", k_clear_sections, dim3(unsigned(blocks)), dim3(256), 0, s, dst,
-               nsec, stride, d_n, n, per, width);
+               head, nsec, stride, d_n, n, per, width);
     return check_launch("clear_sections");
 }
 

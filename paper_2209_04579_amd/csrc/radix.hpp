@@ -738,15 +738,13 @@ int run_radix(const K *key_in, int64_t n, const int64_t *d_n, int bits, Ord ord,
     uint32_t *tickets = words + npass * kBins;
     uint32_t *status = tickets + npass * kXcds;
     uint64_t *keep_bits = cv.take<uint64_t>(size_t(ceil_div(n > 0 ? n : 1, 64)));
-    // histograms and tickets, then the per-pass tile statuses over the tiles
-    // the actual count needs (a plan sized for a large capacity does not pay
-    // for clearing all of it)
-    int rc = fill_u32(words, 0, int64_t(npass) * (kBins + kXcds), s);
-    if (rc) return rc;
-    if (d_n && !pred)
-        rc = clear_sections(status, npass, ntiles * kBins, d_n, n, kSortTile, kBins, s);
-    else
-        rc = fill_u32(status, 0, int64_t(npass) * ntiles * kBins, s);
+    // histograms and tickets, then (contiguous with them) the per-pass tile
+    // statuses over the tiles the actual count needs (a plan sized for a
+    // large capacity does not pay for clearing all of it), in one launch
+    const int64_t head = int64_t(npass) * (kBins + kXcds);
+    int rc = (d_n && !pred)
+                 ? clear_sections(status, head, npass, ntiles * kBins, d_n, n, kSortTile, kBins, s)
+                 : fill_u32(words, 0, head + int64_t(npass) * ntiles * kBins, s);
     if (rc) return rc;
     if (pred && (rc = fill_u64(reinterpret_cast<uint64_t *>(d_kept), 0, 1, s))) return rc;
     {

@@ -103,11 +103,12 @@ size_t rle_words(int64_t n);
 int rle_i32(const int32_t *keys, int64_t n, int32_t *ukey, int32_t *ustart, int64_t *d_nu,
             uint64_t *words, hipStream_t s);
 int fill_u32(void *dst, uint32_t value, int64_t count, hipStream_t s);
-// Zeroes nsec sections (section k at dst + k * stride words), each over its
-// first ceil(count / per) * width words with count = min(*d_n, n) read on
-// the device (d_n NULL: count = n).
-int clear_sections(uint32_t *dst, int nsec, int64_t stride, const int64_t *d_n, int64_t n,
-                   int64_t per, int64_t width, hipStream_t s);
+// Zeroes the head words before dst, then nsec sections (section k at dst +
+// k * stride words), each over its first ceil(count / per) * width words
+// with count = min(*d_n, n) read on the device (d_n NULL: count = n).  One
+// launch for both.
+int clear_sections(uint32_t *dst, int64_t head, int nsec, int64_t stride, const int64_t *d_n,
+                   int64_t n, int64_t per, int64_t width, hipStream_t s);
 
 // Device-side min / max of a key column over min(*d_n, n) entries, written to
 // out[0] = min, out[1] = max (int64).
