@@ -1,13 +1,15 @@
 // WHERE with stream compaction, single pass.
 //
 // Each workgroup takes a 4096-row tile (256 threads x 16 consecutive rows),
-// evaluates the predicate conjunction with wide vector loads, counts its kept
-// rows with a block scan and stages their row ids in LDS in ascending order.
-// The tile's output offset comes from a decoupled look-back over the tiles
-// before it, resolved while the workgroup's next tile is loading; the staged
-// row ids, and the payload columns read through them, are written at that
-// offset by consecutive threads.  Every predicate byte is read once, payload
-// only for kept rows; output is written once, in ascending row id order.
+// evaluates the predicate conjunction with wide vector loads and counts its
+// kept rows with a block scan.  A sparse tile stages its kept row ids in LDS
+// in ascending order; its output offset comes from a decoupled look-back over
+// the tiles before it, resolved while the workgroup's next tile is loading,
+// and the staged row ids, with the payload columns read through them, are
+// written at that offset by consecutive threads.  A dense tile resolves its
+// offset at once and writes each column through LDS.  Every predicate byte is
+// read once, payload only where rows are kept; output is written once, in
+// ascending row id order.
 #include "tqp_internal.hpp"
 
 namespace tqp {
@@ -427,6 +429,8 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
     for (int c = 0; c < ncols; c++) {
         if (!dtype_ok(cols[c].dtype) || cols[c].len != n || (n > 0 && !cols[c].data))
             return set_error(TQP_EINVAL, "tqp_filter: column %d has a bad dtype, length or pointer", c);
+        if (!col_aligned(cols[c].data, cols[c].dtype))
+            return set_error(TQP_EINVAL, "tqp_filter: column %d is unaligned", c);
         vec = vec && (reinterpret_cast<uintptr_t>(cols[c].data) % 16 == 0);
     }
     for (int p = 0; p < npred; p++) {
@@ -442,6 +446,9 @@ TQP_API int tqp_filter(const tqp_col *cols, int ncols, const tqp_pred *preds, in
         if (!dtype_ok(pay_in[c].dtype) || pay_in[c].dtype != pay_out[c].dtype ||
             pay_in[c].len != n || pay_out[c].len < n || (n > 0 && (!pay_in[c].data || !pay_out[c].data)))
             return set_error(TQP_EINVAL, "tqp_filter: payload %d has a bad dtype, length or pointer", c);
+        // (kept rows' payload is read as the aligned 8-byte word holding it)
+        if (!col_aligned(pay_in[c].data, pay_in[c].dtype) || !col_aligned(pay_out[c].data, pay_out[c].dtype))
+            return set_error(TQP_EINVAL, "tqp_filter: payload %d is unaligned", c);
         vec = vec && (reinterpret_cast<uintptr_t>(pay_in[c].data) % 16 == 0);
         a.pin[c] = pay_in[c].data;
         a.pout[c] = pay_out[c].data;

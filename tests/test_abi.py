@@ -74,6 +74,18 @@ def test_unaligned_columns_are_rejected_without_a_gpu():
     rc = L.tqp_gather(ctypes.byref(src), ctypes.c_void_p(0xA0000), 10, None,
                       ctypes.byref(out64), None)
     assert rc == tqp.TQP_EINVAL and b"aligned to their dtype" in L.tqp_last_error()
+    # filter: a predicate column, then a payload column, off their element size
+    col = (tqp.Col * 1)(tqp.Col(0xB0002, 10, 2, 0))
+    pred = (tqp.Pred * 1)(tqp.Pred(0, 0, 5))
+    cnt = ctypes.c_void_p(0xC0000)
+    ws = ctypes.c_void_p(0xD0000)
+    rc = L.tqp_filter(col, 1, pred, 1, None, None, 0, None, cnt, ws, 1 << 20, None)
+    assert rc == tqp.TQP_EINVAL and b"unaligned" in L.tqp_last_error()
+    col = (tqp.Col * 1)(tqp.Col(0xB0000, 10, 2, 0))
+    pin = (tqp.Col * 1)(tqp.Col(0xE0004, 10, 3, 0))
+    pout = (tqp.Col * 1)(tqp.Col(0xF0000, 10, 3, 0))
+    rc = L.tqp_filter(col, 1, pred, 1, pin, pout, 1, None, cnt, ws, 1 << 20, None)
+    assert rc == tqp.TQP_EINVAL and b"payload 0 is unaligned" in L.tqp_last_error()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libtqp.so not built")
