@@ -210,7 +210,8 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
             }
             break;
         }
-        // sets in LDS: every row tested (LDS reads are cheap)
+        // sets in LDS: every row tested (LDS reads are cheap); a set of at
+        // most 64 keys is held in a register instead
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             if (a.lds_off[s] < 0) continue;
@@ -218,12 +219,21 @@ __global__ __launch_bounds__(NT) void k_semijoin(SemiArgs a) {
             const uint64_t lo = uint64_t(a.lo[s]);
             const uint64_t nb = a.nbits[s];
             uint32_t m = 0;
+            if (nb <= 64) {
+                const uint64_t bits = uint64_t(w[0]) | (nb > 32 ? uint64_t(w[1]) << 32 : 0);
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                const uint64_t idx = uint64_t(int64_t(v[s][r])) - lo;
-                const bool in = idx < nb;
-                const uint32_t word = w[in ? uint32_t(idx >> 5) : 0u];
-                if (in && ((word >> (idx & 31)) & 1u)) m |= 1u << r;
+                for (int r = 0; r < R; r++) {
+                    const uint64_t idx = uint64_t(int64_t(v[s][r])) - lo;
+                    if (idx < nb && ((bits >> idx) & 1u)) m |= 1u << r;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const uint64_t idx = uint64_t(int64_t(v[s][r])) - lo;
+                    const bool in = idx < nb;
+                    const uint32_t word = w[in ? uint32_t(idx >> 5) : 0u];
+                    if (in && ((word >> (idx & 31)) & 1u)) m |= 1u << r;
+                }
             }
             alive &= m;
         }

@@ -97,6 +97,21 @@ def test_semijoin_set_counts(tqp, nsets):
     check(tqp, keys, set_keys, ranges)
 
 
+@pytest.mark.parametrize("kdt", [np.int32, np.int64])
+@pytest.mark.parametrize("nb", [1, 31, 32, 33, 63, 64, 65])
+def test_semijoin_tiny_sets(tqp, nb, kdt):
+    """Sets of a few keys around one and two words, over ranges not starting
+    at zero, with keys below, inside and beyond each range; beside a larger
+    set so both kinds of test run in one scan."""
+    n = 70_001
+    lo = -17
+    keys = [dg.uniform_int(nb, 60, n, lo - 5, lo + nb + 5, kdt),
+            dg.uniform_int(nb, 61, n, 0, 5000, kdt)]
+    set_keys = [dg.uniform_int(nb, 62, max(nb // 2, 1), lo - 3, lo + nb + 3, kdt),
+                dg.permutation(nb, 63, 5000)[:1200].astype(kdt)]
+    check(tqp, keys, set_keys, [(lo, nb), (0, 5000)])
+
+
 def test_semijoin_keys_outside_every_range(tqp):
     n = 20_000
     k = dg.uniform_int(3, 1, n, -10 ** 9, 10 ** 9, np.int64)
