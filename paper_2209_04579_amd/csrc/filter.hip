@@ -306,18 +306,28 @@ __global__ __launch_bounds__(kFilterNT) void k_filter(FilterArgs a) {
 // WHERE + aggregate without compaction: the predicate pass of k_filter (8
 // consecutive rows per thread here, which halves the registers a column
 // takes and doubles the loads in flight), then SUM(a * b) and COUNT over the
-// kept rows.  a and b are read only by threads holding a kept row, so at low
-// selectivity most of their cache lines are never fetched.  Partial sums are reduced per
-// workgroup and added with one device atomic each; int64 addition wraps
-// modulo 2^64, so every order gives the same bytes.
+// kept rows.  The predicates come grouped by column; with at most
+// kSumMaxCols distinct columns, every column of a tile is loaded before the
+// first test (one memory round trip per tile instead of one per column), and
+// a value operand that is also a predicate column is taken from those loads.
+// Other value columns are read only by threads holding a kept row, so at low
+// selectivity most of their cache lines are never fetched.  Partial sums are
+// reduced per workgroup and added with one device atomic each; int64
+// addition wraps modulo 2^64, so every order gives the same bytes.
+constexpr int kSumMaxCols = 4;
 struct FilterSumArgs {
-    const void *pcol[kMaxPred];
+    const void *pcol[kMaxPred];      // per predicate, grouped by column
     int64_t plit[kMaxPred];
     int32_t pdt[kMaxPred];
     int32_t pop[kMaxPred];
     int32_t pcolid[kMaxPred];
     int32_t npred;
     int32_t vec;
+    const void *dcol[kMaxPred];      // the distinct predicate columns
+    int32_t ddt[kMaxPred];
+    int32_t pbeg[kMaxPred + 1];      // column d's predicates: pbeg[d] .. pbeg[d + 1] - 1
+    int32_t nd;
+    int32_t aslot, bslot;            // the distinct column that a / b is, or -1
     const void *a;        // null: the sum is 0
     const void *b;        // null: SUM(a)
     int32_t adt, bdt;
@@ -336,6 +346,9 @@ __global__ void k_zero2(unsigned long long *p, unsigned long long *q) {
 constexpr int kSumIPT = 8;
 constexpr int kSumTile = kFilterNT * kSumIPT;
 
+// ND distinct predicate columns (1 .. kSumMaxCols) loaded together; ND = 0:
+// each column loaded when its first predicate is reached.
+template <int ND>
 __global__ __launch_bounds__(kFilterNT) void k_filter_sum(FilterSumArgs f) {
     __shared__ unsigned long long s_red[2][kFilterNT / kWave];
     const int64_t n = f.n;
@@ -348,6 +361,57 @@ __global__ __launch_bounds__(kFilterNT) void k_filter_sum(FilterSumArgs f) {
 #pragma unroll
         for (int r = 0; r < kSumIPT; r++)
             if (row0 + r < n) mask |= 1u << r;
+        if constexpr (ND > 0) {
+            int64_t d[ND][kSumIPT];
+#pragma unroll
+            for (int c = 0; c < ND; c++) load8(f.dcol[c], f.ddt[c], row0, n, vec, d[c]);
+#pragma unroll
+            for (int c = 0; c < ND; c++) {
+                for (int p = f.pbeg[c]; p < f.pbeg[c + 1]; p++) {
+                    const int op = f.pop[p];
+                    const int64_t lit = f.plit[p];
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int r = 0; r < kSumIPT; r++)
+                        if (cmp_holds(d[c][r], op, lit)) m |= 1u << r;
+                    mask &= m;
+                }
+            }
+            cnt += __popc(mask);
+            if (mask && f.a) {
+                int64_t x[kSumIPT], y[kSumIPT];
+                if (f.aslot >= 0) {
+#pragma unroll
+                    for (int c = 0; c < ND; c++)
+                        if (c == f.aslot) {
+#pragma unroll
+                            for (int r = 0; r < kSumIPT; r++) x[r] = d[c][r];
+                        }
+                } else {
+                    load8(f.a, f.adt, row0, n, vec, x);
+                }
+                if (f.b) {
+                    if (f.bslot >= 0) {
+#pragma unroll
+                        for (int c = 0; c < ND; c++)
+                            if (c == f.bslot) {
+#pragma unroll
+                                for (int r = 0; r < kSumIPT; r++) y[r] = d[c][r];
+                            }
+                    } else {
+                        load8(f.b, f.bdt, row0, n, vec, y);
+                    }
+#pragma unroll
+                    for (int r = 0; r < kSumIPT; r++)
+                        if (mask & (1u << r)) sum += uint64_t(x[r]) * uint64_t(y[r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < kSumIPT; r++)
+                        if (mask & (1u << r)) sum += uint64_t(x[r]);
+                }
+            }
+            continue;
+        }
         int64_t v[kSumIPT];
         int loaded = -1;
         for (int p = 0; p < f.npred; p++) {
@@ -396,6 +460,27 @@ __global__ __launch_bounds__(kFilterNT) void k_filter_sum(FilterSumArgs f) {
         if (ts) atomicAdd(f.d_sum, ts);
         if (tc) atomicAdd(f.d_count, tc);
     }
+}
+
+// Tiles are dealt to workgroups statically, so the grid holds no more
+// workgroups than can be resident at once (their count depends on the
+// variant's registers; looked up once per variant): a second round of
+// late-starting workgroups would each still take a full share of tiles.
+template <class Kern>
+static int launch_filter_sum(Kern kern, int nd, int64_t n, hipStream_t s, const FilterSumArgs &f) {
+    static int resident[kSumMaxCols + 1] = {};
+    if (resident[nd] == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
+                                                         kFilterNT, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        resident[nd] = per_cu;
+    }
+    int per_cu = 2 * tune(kTuneFilterPerCu);
+    if (per_cu > resident[nd]) per_cu = resident[nd];
+    const unsigned grid = persistent_grid(ceil_div(n, kSumTile), per_cu);
+    TQP_LAUNCH("filter_sum", kern, dim3(grid), dim3(kFilterNT), 0, s, f);
+    return check_launch("tqp_filter_sum");
 }
 
 static size_t filter_ws(int64_t n) {
@@ -496,15 +581,33 @@ TQP_API int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds
             return set_error(TQP_EINVAL, "tqp_filter_sum: column %d has a bad dtype, length or pointer", c);
         vec = vec && (reinterpret_cast<uintptr_t>(cols[c].data) % 16 == 0);
     }
-    for (int p = 0; p < npred; p++) {
+    for (int p = 0; p < npred; p++)
         if (preds[p].col < 0 || preds[p].col >= ncols || preds[p].op < TQP_LT || preds[p].op > TQP_NE)
             return set_error(TQP_EINVAL, "tqp_filter_sum: predicate %d is invalid", p);
-        f.pcol[p] = cols[preds[p].col].data;
-        f.pdt[p] = cols[preds[p].col].dtype;
-        f.pcolid[p] = preds[p].col;
-        f.pop[p] = preds[p].op;
-        f.plit[p] = preds[p].literal;
+    // predicates grouped by column, columns in order of first use (a
+    // conjunction does not depend on the order of its terms)
+    int np = 0;
+    f.nd = 0;
+    for (int p = 0; p < npred; p++) {
+        const int col = preds[p].col;
+        bool seen = false;
+        for (int q = 0; q < p; q++) seen = seen || preds[q].col == col;
+        if (seen) continue;
+        f.dcol[f.nd] = cols[col].data;
+        f.ddt[f.nd] = cols[col].dtype;
+        f.pbeg[f.nd] = np;
+        f.nd++;
+        for (int q = p; q < npred; q++) {
+            if (preds[q].col != col) continue;
+            f.pcol[np] = cols[col].data;
+            f.pdt[np] = cols[col].dtype;
+            f.pcolid[np] = col;
+            f.pop[np] = preds[q].op;
+            f.plit[np] = preds[q].literal;
+            np++;
+        }
     }
+    f.pbeg[f.nd] = np;
     const tqp_col *vals[2] = {a, b};
     for (int k = 0; k < 2; k++) {
         const tqp_col *v = vals[k];
@@ -520,6 +623,12 @@ TQP_API int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds
     f.b = b ? b->data : nullptr;
     f.adt = a ? a->dtype : 0;
     f.bdt = b ? b->dtype : 0;
+    // a value operand that is one of the loaded predicate columns
+    f.aslot = f.bslot = -1;
+    for (int c = 0; c < f.nd; c++) {
+        if (a && f.aslot < 0 && f.dcol[c] == a->data && f.ddt[c] == a->dtype) f.aslot = c;
+        if (b && f.bslot < 0 && f.dcol[c] == b->data && f.ddt[c] == b->dtype) f.bslot = c;
+    }
     f.n = n;
     f.d_sum = reinterpret_cast<unsigned long long *>(d_sum);
     f.d_count = reinterpret_cast<unsigned long long *>(d_count);
@@ -527,7 +636,12 @@ TQP_API int tqp_filter_sum(const tqp_col *cols, int ncols, const tqp_pred *preds
     TQP_LAUNCH("filter_sum_init", k_zero2, dim3(1), dim3(64), 0, s, f.d_sum, f.d_count);
     int rc = check_launch("tqp_filter_sum");
     if (rc || n == 0) return rc;
-    const unsigned grid = persistent_grid(ceil_div(n, kSumTile), 2 * tune(kTuneFilterPerCu));
-    TQP_LAUNCH("filter_sum", k_filter_sum, dim3(grid), dim3(kFilterNT), 0, s, f);
-    return check_launch("tqp_filter_sum");
+    const int nd = f.nd <= kSumMaxCols ? f.nd : 0;
+    switch (nd) {
+    case 1: return launch_filter_sum(k_filter_sum<1>, nd, n, s, f);
+    case 2: return launch_filter_sum(k_filter_sum<2>, nd, n, s, f);
+    case 3: return launch_filter_sum(k_filter_sum<3>, nd, n, s, f);
+    case 4: return launch_filter_sum(k_filter_sum<4>, nd, n, s, f);
+    default: return launch_filter_sum(k_filter_sum<0>, nd, n, s, f);
+    }
 }

@@ -86,6 +86,44 @@ def test_filter_sum_none_all_and_outside_literals(tqp):
     assert run(tqp, [c8], [], a, c8) == oracle.filter_sum([c8], [], a, c8)[:2]
 
 
+@pytest.mark.parametrize("ncols", [2, 3, 4, 5])
+def test_filter_sum_columns_loaded_together(tqp, ncols):
+    """Predicates interleaved over up to five columns of mixed dtypes (up to
+    four are loaded together per tile, five take the per-column path), with
+    the value operands among the predicate columns, outside them, or both."""
+    n = 300_007
+    dts = [np.int64, np.int8, np.int32, np.int64, np.int32]
+    spans = [(-10 ** 6, 10 ** 6), (-100, 100), (-1000, 1000), (0, 50), (-7, 7)]
+    cols = [dg.uniform_int(ncols, 30 + c, n, lo, hi, dts[c]) for c, (lo, hi) in
+            enumerate(spans[:ncols])]
+    cuts = [(">=", -600_000), ("<", 90), (">", -900), ("!=", 13), ("<=", 5)]
+    preds = []
+    for rep in range(2):          # each column's predicates far apart in the list
+        for c in range(ncols):
+            op, lit = cuts[c]
+            if len(preds) < 8:        # the most a call takes
+                preds.append((c, op, lit + rep * (1 if op in ("<", "<=") else -1)))
+    price = dg.uniform_int(ncols, 40, n, -(1 << 31), 1 << 31, np.int64)
+    for a, b in ((price, cols[1]), (cols[0], cols[ncols - 1]), (price, None), (cols[2 % ncols], None),
+                 (cols[1], cols[1])):
+        want = oracle.filter_sum(cols, preds, a, b)[:2]
+        assert run(tqp, cols, preds, a, b) == want
+    # the same predicate columns through their own device tensors as a and b
+    dcols = [dev(x) for x in cols]
+    s_ = torch.empty(1, dtype=torch.int64, device="cuda")
+    c_ = torch.empty(1, dtype=torch.int64, device="cuda")
+    old = tqp.tune_knobs()["filter.per_cu"][0]
+    try:
+        for per_cu in (1, old, 8):
+            tqp.tune_set("filter.per_cu", per_cu)
+            tqp.filter_sum_into(dcols, preds, s_, c_, dcols[0], dcols[ncols - 1])
+            torch.cuda.synchronize()
+            assert (int(s_.item()), int(c_.item())) == oracle.filter_sum(cols, preds, cols[0],
+                                                                         cols[ncols - 1])[:2]
+    finally:
+        tqp.tune_set("filter.per_cu", old)
+
+
 def test_filter_sum_repeatable_and_knob_independent(tqp):
     cfg = dg.config_q6(5, 3_000_000)
     t = cfg["items"]
