@@ -37,15 +37,20 @@ METRIC = "rows/s filter→join→group-by, % peak HBM GB/s; learned vs radix par
 COPY_BYTES = 1 << 31           # the plain copy this script times (2 GiB read, 2 GiB written)
 
 
+# the entries of bench_configs, each runnable alone with --only
+CONFIG_PARTS = ("small", "q6", "q14", "predict")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--only", choices=("star600m", "star60m", "learned", "batch", "configs"),
-                    default=None,
-                    help="run one workload only (for counter profiles and quick checks)")
+    ap.add_argument("--only", choices=("star600m", "star60m", "learned", "batch", "configs")
+                    + CONFIG_PARTS, default=None,
+                    help="run one workload only (for counter profiles and quick checks); "
+                         "small, q6, q14, predict: one of the configs entries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=60_000_000,
                     help="fact rows of the headline workload the CPU oracle is timed on")
@@ -70,7 +75,8 @@ def parse():
                     help="no GPU work: turn two rocprofv3 counter_collection.csv files "
                          "(--pmc FETCH_SIZE, --pmc WRITE_SIZE of this script with --only TAG) "
                          "into profiles/<kernel>_<TAG>_traffic.json")
-    ap.add_argument("--traffic-tag", choices=("star600m", "star60m"), default="star600m")
+    ap.add_argument("--traffic-tag", choices=("star600m", "star60m", "q6", "q14", "predict"),
+                    default="star600m")
     ap.add_argument("--record-command", default="",
                     help="the rocprofv3 command lines, stored with the traffic figures")
     return ap.parse_args()
@@ -82,7 +88,8 @@ KERNEL_FILE = {"semijoin": "semijoin.hip", "filter": "filter.hip", "onesweep": "
                "radix_hist": "radix.hpp", "rle": "join.hip", "join_match": "join.hip",
                "join_expand": "join.hip", "pack_key": "gather.hip", "gather": "gather.hip",
                "gb_dense": "groupby.hip", "gb_scan": "groupby.hip", "gb_tiny": "groupby.hip",
-               "gb_diff": "groupby.hip", "keyset_set": "semijoin.hip"}
+               "gb_diff": "groupby.hip", "keyset_set": "semijoin.hip",
+               "filter_sum": "filter.hip", "mlp_predict": "predict.hip"}
 # kernels timed under one name (the filtered histogram of tqp_filter_sort
 # and the plain one both launch as "radix_hist")
 KERNEL_ALIASES = {"radix_hist": ("radix_hist", "radix_hist_filt")}
@@ -511,19 +518,31 @@ def bench_star60m(args, tqp, stream) -> dict:
     return out
 
 
-def bench_configs(args, tqp, stream) -> dict:
+def bench_configs(args, tqp, stream, parts=CONFIG_PARTS) -> dict:
     """Throughput of the other query workloads: the small star query (1M fact
     rows, cache-resident and launch-bound), the Q6-shaped scan (60M rows), the
     Q14-shaped join (60M items, 2M parts) and the prediction query (20M
     reviews).  Their results are checked against the oracle by the test suite
     (full-size cases included), not here."""
+    out = {}
+    if "small" in parts:
+        out["small_star"] = _bench_small(args, tqp, stream)
+    if "q6" in parts:
+        out["q6_scan"] = _bench_q6(args, tqp, stream)
+    if "q14" in parts:
+        out["q14_join"] = _bench_q14(args, tqp, stream)
+    if "predict" in parts:
+        out["predict_query"] = _bench_predict(args, tqp, stream)
+    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def _bench_small(args, tqp, stream) -> dict:
     import numpy as np
     import torch
     import tqp_datagen as dg
-    from tqp_datagen import device as dgd
-    from paper_2209_04579_amd.pipeline import PredictQuery, Q6Scan, Q14Query, StarQuery
+    from paper_2209_04579_amd.pipeline import StarQuery
 
-    out = {}
     c1 = dg.config1(args.seed)
     q = StarQuery({k: torch.from_numpy(v).cuda() for k, v in c1["fact"].items()},
                   {k: torch.from_numpy(v).cuda() for k, v in c1["dim"].items()}, c1["day_cut"])
@@ -539,7 +558,7 @@ def bench_configs(args, tqp, stream) -> dict:
           "groups_b": 0, "passes": _passes(q.jk_bits), "uniq_l": 10_000, "uniq_r": 10_000,
           "pay": 12, "gbv": 4 + 4 + 4 + 8}
     kernels = kernel_table(kernel_profile(q.run, 20), 20, star_kernel_bytes, st)
-    out["small_star"] = {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat "
+    return {"workload": "fact 1M rows, dim 10k; day<1278; join; group by cat "
                                      "(16 MB of input: cache-resident, launch-bound)",
                          "ms": round(ms, 4), "rows_per_s": round(1_000_000 / (ms * 1e-3), 1),
                          "eager_ms": round(eager_ms, 4),
@@ -550,7 +569,13 @@ def bench_configs(args, tqp, stream) -> dict:
                                                  "20 steps with per-kernel HIP events"),
                          "launches_per_step": sum(k["launches_per_step"]
                                                   for k in kernels.values())}
-    del q
+
+
+def _bench_q6(args, tqp, stream) -> dict:
+    import torch
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import Q6Scan
+
     # Q6-shaped scan: 60M rows, five comparisons over int64 / int8 / int32
     # columns, SUM(price * discount); one fused launch
     d6 = dgd.config_q6(args.seed, device="cuda")
@@ -562,7 +587,7 @@ def bench_configs(args, tqp, stream) -> dict:
     kern = kernel_profile(q6.run, 20)
     fs = kern.get("filter_sum", (20, ms * 20))
     achieved = scan_bytes / (fs[1] / fs[0] * 1e-3) / 1e9
-    out["q6_scan"] = {"workload": "60M rows: ship int64 epoch-ns in one year, discount int8 "
+    out = {"workload": "60M rows: ship int64 epoch-ns in one year, discount int8 "
                                   "BETWEEN 5 AND 7, quantity int32 < 24; SUM(price * discount), "
                                   "COUNT",
                       "ms": round(ms, 4), "rows_per_s": round(n6 / (ms * 1e-3), 1),
@@ -570,10 +595,19 @@ def bench_configs(args, tqp, stream) -> dict:
                       "roofline": {"kernel": "filter_sum", "bound": "hbm",
                                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "traffic": traffic_for("filter_sum", "q6"),
                                    "algo_bytes_per_launch": int(scan_bytes),
                                    "avg_launch_ms": round(fs[1] / fs[0], 5)}}
     del q6, d6
     torch.cuda.empty_cache()
+    return out
+
+
+def _bench_q14(args, tqp, stream) -> dict:
+    import torch
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import Q14Query
+
     # Q14-shaped join with a string predicate: 60M items, 2M parts
     d14 = dgd.config_q14(args.seed, device="cuda")
     q14 = Q14Query(d14["items"], d14["part"], d14["prefix"], d14["ship_lo"], d14["ship_hi"])
@@ -585,7 +619,7 @@ def bench_configs(args, tqp, stream) -> dict:
     # the filter reads ship (8 B) of every row and the payload lines of kept rows
     fbytes = n14 * 8 + got["rows_filtered"] * (4 + 8 + 1) * 2
     achieved = fbytes / (fl[1] / fl[0] * 1e-3) / 1e9
-    out["q14_join"] = {"workload": "60M items (one month of int64 epoch-ns ship dates kept), 2M "
+    out = {"workload": "60M items (one month of int64 epoch-ns ship dates kept), 2M "
                                    "parts with (n x 24) byte-matrix types; LIKE prefix flag, "
                                    "join partkey = pk, SUM(CASE promo THEN price*(100-discount)), "
                                    "SUM(price*(100-discount))",
@@ -595,11 +629,20 @@ def bench_configs(args, tqp, stream) -> dict:
                        "roofline": {"kernel": "filter", "bound": "hbm",
                                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                    "traffic": traffic_for("filter", "q14"),
                                     "algo_bytes_per_launch": int(fbytes),
                                     "avg_launch_ms": round(fl[1] / fl[0], 5)},
                        "kernel_ms": {k: round(v[1] / 20, 4) for k, v in kern.items()}}
     del q14, d14
     torch.cuda.empty_cache()
+    return out
+
+
+def _bench_predict(args, tqp, stream) -> dict:
+    import torch
+    from tqp_datagen import device as dgd
+    from paper_2209_04579_amd.pipeline import PredictQuery
+
     # PREDICT inside a query: 20M reviews, 8 features, 8 -> 16 -> 2 fp32 model
     dp = dgd.config_predict(args.seed, device="cuda")
     qp = PredictQuery(dp["reviews"], dp["model"], dp["nfeat"], dp["hidden"], dp["classes"],
@@ -610,7 +653,7 @@ def bench_configs(args, tqp, stream) -> dict:
     mp = kern.get("mlp_predict", (20, ms * 20))
     pbytes = got["rows_filtered"] * (4 + 8 * 4 + 1)
     achieved = pbytes / (mp[1] / mp[0] * 1e-3) / 1e9
-    out["predict_query"] = {"workload": "20M reviews: WHERE year >= 2016, PREDICT with an fp32 "
+    out = {"workload": "20M reviews: WHERE year >= 2016, PREDICT with an fp32 "
                                         "8 -> 16 -> 2 MLP over 8 int32 features, GROUP BY rating "
                                         "with SUM(CASE class = 1) and COUNT",
                             "ms": round(ms, 4), "rows_per_s": round(qp.n / (ms * 1e-3), 1),
@@ -622,10 +665,10 @@ def bench_configs(args, tqp, stream) -> dict:
                                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s",
                                          "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                         "traffic": traffic_for("mlp_predict", "predict"),
                                          "algo_bytes_per_launch": int(pbytes),
                                          "avg_launch_ms": round(mp[1] / mp[0], 5)},
                             "kernel_ms": {k: round(v[1] / 20, 4) for k, v in kern.items()}}
-    print(f"[bench] configs: {out}", file=sys.stderr, flush=True)
     del qp, dp
     torch.cuda.empty_cache()
     return out
@@ -924,6 +967,9 @@ def main():
         return
     if args.only == "configs":
         print(json.dumps(bench_configs(args, tqp, stream)), flush=True)
+        return
+    if args.only in CONFIG_PARTS:
+        print(json.dumps(bench_configs(args, tqp, stream, parts=(args.only,))), flush=True)
         return
     head = bench_star3(args, tqp, stream, copy_gbs)
     ms = head["ms"]
